@@ -1,0 +1,208 @@
+"""ORACLE for the constrained Delaunay refinement loop -- test infrastructure.
+
+A plain sequential C implementation (``qmo.c``, ``qmo_exact.h``) of the
+round rule the GPU library executes, with its own exact big-integer
+predicates.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package; the product
+path never does.  It shares no code with ``paper_1903_03406_amd``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_qmo.so")
+_lib = None
+
+NSTAT = 16
+STAT_FIELDS = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
+               "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
+               "ex_face", "ex_edge2d", "ex_manifold", "nv_after", "nt_after")
+
+
+def build() -> str:
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-o", _SO + ".tmp", os.path.join(_HERE, "qmo.c"), "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is not built; run oracle.build()")
+        lib = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        lib.qmo_refine.restype = ctypes.c_int
+        lib.qmo_refine.argtypes = [ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int, P, P,
+                                   ctypes.c_int, P, P, ctypes.c_int, P, P,
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(P)]
+        lib.qmo_result_counts.argtypes = [P, P]
+        lib.qmo_result_seconds.argtypes = [P]
+        lib.qmo_result_seconds.restype = ctypes.c_double
+        lib.qmo_result_copy.argtypes = [P] * 8
+        lib.qmo_result_free.argtypes = [P]
+        for name in ("qmo_p_orient3d", "qmo_p_insphere", "qmo_p_segdot", "qmo_p_facedot"):
+            getattr(lib, name).restype = ctypes.c_int
+        lib.qmo_p_orient2d.restype = ctypes.c_int
+        lib.qmo_p_orient2d.argtypes = [ctypes.c_int, P, P, P]
+        lib.qmo_c_is_bad.restype = ctypes.c_int
+        lib.qmo_c_is_bad.argtypes = [P, P, P, P, ctypes.c_double]
+        lib.qmo_c_key.restype = ctypes.c_uint64
+        lib.qmo_c_key.argtypes = [ctypes.c_int, P, ctypes.c_int]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data
+
+
+@dataclass
+class OracleResult:
+    xyz: np.ndarray
+    tets: np.ndarray
+    sf: np.ndarray
+    sf_facet: np.ndarray
+    ss: np.ndarray
+    ss_seg: np.ndarray
+    rstats: np.ndarray        # (rounds, 16)
+    rounds: int
+    status: int               # 0 done, 1 round guard reached
+    seconds: float
+
+
+def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0) -> OracleResult:
+    """Run the oracle on a workload (qm_inputs.Workload or compatible)."""
+    lib = _load()
+    c = lambda a, t: np.ascontiguousarray(a, dtype=t)
+    xyz = c(w.xyz, np.float64); tets = c(w.tets, np.int32)
+    sf = c(w.sf, np.int32); sff = c(w.sf_facet, np.int32)
+    ss = c(w.ss, np.int32); sss = c(w.ss_seg, np.int32)
+    ft = c(w.ftri, np.int32); ftf = c(w.ftri_facet, np.int32)
+    res = ctypes.c_void_p()
+    rc = lib.qmo_refine(len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(sf), _ptr(sf), _ptr(sff),
+                        len(ss), _ptr(ss), _ptr(sss), len(ft), _ptr(ft), _ptr(ftf),
+                        float(w.B if B is None else B), float(hmin_factor), int(max_rounds),
+                        int(max_kept), ctypes.byref(res))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (code {rc})")
+    cnt = np.zeros(6, dtype=np.int32)
+    lib.qmo_result_counts(res, _ptr(cnt))
+    nv, nt, nsf, nss, rounds, status = (int(x) for x in cnt)
+    out = OracleResult(np.empty((nv, 3)), np.empty((nt, 4), np.int32), np.empty((nsf, 3), np.int32),
+                       np.empty(nsf, np.int32), np.empty((nss, 2), np.int32), np.empty(nss, np.int32),
+                       np.empty((rounds, NSTAT), np.int32), rounds, status,
+                       float(lib.qmo_result_seconds(res)))
+    lib.qmo_result_copy(res, _ptr(out.xyz), _ptr(out.tets), _ptr(out.sf), _ptr(out.sf_facet),
+                        _ptr(out.ss), _ptr(out.ss_seg), _ptr(out.rstats))
+    lib.qmo_result_free(res)
+    return out
+
+
+# --- the oracle's predicates and constructions, for its own pin tests -------
+def _v3(p):
+    return np.ascontiguousarray(p, dtype=np.float64)
+
+
+def orient3d(a, b, c, d) -> int:
+    L = _load(); a, b, c, d = map(_v3, (a, b, c, d))
+    return L.qmo_p_orient3d(*(ctypes.c_void_p(_ptr(x)) for x in (a, b, c, d)))
+
+
+def insphere(a, b, c, d, e) -> int:
+    L = _load(); xs = list(map(_v3, (a, b, c, d, e)))
+    return L.qmo_p_insphere(*(ctypes.c_void_p(_ptr(x)) for x in xs))
+
+
+def orient2d(axis, a, b, c) -> int:
+    L = _load(); xs = list(map(_v3, (a, b, c)))
+    return L.qmo_p_orient2d(int(axis), *(_ptr(x) for x in xs))
+
+
+def segdot(a, b, v) -> int:
+    L = _load(); xs = list(map(_v3, (a, b, v)))
+    return L.qmo_p_segdot(*(ctypes.c_void_p(_ptr(x)) for x in xs))
+
+
+def facedot(a, b, c, v) -> int:
+    L = _load(); xs = list(map(_v3, (a, b, c, v)))
+    return L.qmo_p_facedot(*(ctypes.c_void_p(_ptr(x)) for x in xs))
+
+
+def midpoint(a, b):
+    L = _load(); a, b = _v3(a), _v3(b); p = np.empty(3)
+    L.qmo_c_midpoint(ctypes.c_void_p(_ptr(a)), ctypes.c_void_p(_ptr(b)), ctypes.c_void_p(_ptr(p)))
+    return p
+
+
+def tri_cc(a, b, c):
+    L = _load(); xs = list(map(_v3, (a, b, c))); p = np.empty(3)
+    L.qmo_c_tri_cc(*(ctypes.c_void_p(_ptr(x)) for x in xs), ctypes.c_void_p(_ptr(p)))
+    return p
+
+
+def tet_cc(a, b, c, d):
+    L = _load(); xs = list(map(_v3, (a, b, c, d))); p = np.empty(3); r2 = np.empty(1)
+    L.qmo_c_tet_cc(*(ctypes.c_void_p(_ptr(x)) for x in xs), ctypes.c_void_p(_ptr(p)),
+                   ctypes.c_void_p(_ptr(r2)))
+    return p, float(r2[0])
+
+
+def is_bad(a, b, c, d, B) -> bool:
+    L = _load(); xs = list(map(_v3, (a, b, c, d)))
+    return bool(L.qmo_c_is_bad(*(_ptr(x) for x in xs), float(B)))
+
+
+def key(cls, ids) -> int:
+    L = _load(); ids = np.ascontiguousarray(ids, dtype=np.int32)
+    return int(L.qmo_c_key(int(cls), _ptr(ids), len(ids)))
+
+
+CHECK_FIELDS = ("neg_orient", "face_overuse", "hull_not_subface", "nonlocal_delaunay",
+                "sf_missing", "ss_missing", "euler", "bad_tets", "chain_broken",
+                "nonlocal_unexcused")
+
+
+def check(xyz, tets, sf, ss, ss_seg, B) -> dict:
+    """Mesh property checks (see qmo_check in qmo.c)."""
+    L = _load()
+    c = lambda a, t: np.ascontiguousarray(a, dtype=t)
+    xyz = c(xyz, np.float64); tets = c(tets, np.int32); sf = c(sf, np.int32)
+    ss = c(ss, np.int32); ss_seg = c(ss_seg, np.int32)
+    out = np.zeros(10, dtype=np.int32); vol = np.zeros(1)
+    L.qmo_check.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+    L.qmo_check(len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(sf), _ptr(sf), len(ss), _ptr(ss),
+                _ptr(ss_seg), float(B), _ptr(out), _ptr(vol))
+    d = dict(zip(CHECK_FIELDS, (int(x) for x in out)))
+    d["volume"] = float(vol[0])
+    return d
+
+
+def check_global(xyz, tets) -> int:
+    """Brute force: tets whose circumsphere strictly encloses a mesh vertex."""
+    L = _load()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64); tets = np.ascontiguousarray(tets, dtype=np.int32)
+    L.qmo_check_global.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]
+    L.qmo_check_global.restype = ctypes.c_int
+    return int(L.qmo_check_global(len(xyz), _ptr(xyz), len(tets), _ptr(tets)))
+
+
+def facet_areas(xyz, tri, tri_facet) -> dict:
+    """Sum of triangle areas per facet id (FP64)."""
+    a, b, c = (xyz[tri[:, k]] for k in range(3))
+    ar = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+    out = {}
+    for f, x in zip(tri_facet.tolist(), ar.tolist()):
+        out[f] = out.get(f, 0.0) + x
+    return out

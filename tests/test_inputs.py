@@ -1,0 +1,46 @@
+"""The seeded workload generator: Delaunay input, PLC structure."""
+import numpy as np
+import pytest
+
+import oracle
+import qm_inputs as qi
+
+
+@pytest.mark.parametrize("n,seed", [(30, 1), (500, 2), (2000, 3)])
+def test_delaunay_is_empty_sphere(n, seed):
+    w = qi.uniform_cube(n, seed=seed)
+    assert oracle.check_global(w.xyz, w.tets) == 0
+    c = oracle.check(w.xyz, w.tets, w.sf, w.ss, w.ss_seg, w.B)
+    assert c["neg_orient"] == 0 and c["face_overuse"] == 0 and c["euler"] == 1
+    assert c["hull_not_subface"] == 0 and abs(c["volume"] - 1) < 1e-12
+
+
+def test_delaunay_independent_of_point_order_within_ties():
+    """The generator's symbolic perturbation makes the result a function of
+    the point set and ids only: rebuilding gives the same tets."""
+    w = qi.uniform_cube(400, seed=4)
+    t2, _ = qi.delaunay(w.xyz)
+    a = np.sort(np.sort(w.tets, axis=1), axis=0)
+    b = np.sort(np.sort(t2, axis=1), axis=0)
+    assert np.array_equal(a, b)
+
+
+def test_workload_structure():
+    w = qi.uniform_cube(200, seed=5, spheres=(0.3,))
+    assert np.all(w.xyz[:8] == qi.corners())
+    assert np.all((w.xyz[8:] > 0) & (w.xyz[8:] < 1))
+    assert np.all(np.ldexp(w.xyz, 53) == np.rint(np.ldexp(w.xyz, 53)))     # lattice
+    hull = w.ftri_facet < 6
+    assert hull.sum() == 12 and np.bincount(w.ftri_facet[hull]).tolist() == [2] * 6
+    assert len(w.seg) >= 12
+    # each internal facet is one Delaunay face and its edges are segments
+    segs = set(map(tuple, np.sort(w.seg, axis=1).tolist()))
+    for tri in w.ftri[~hull]:
+        a, b, c = sorted(tri.tolist())
+        assert {(a, b), (a, c), (b, c)} <= segs
+
+
+def test_configs_are_seeded():
+    a, b = qi.config(1), qi.config(1)
+    assert a.sha256() == b.sha256()
+    assert len(a.xyz) == 1008

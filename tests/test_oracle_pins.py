@@ -1,0 +1,356 @@
+"""Pins for the oracle: its predicates, constructions and round rule checked
+against independent statements of the mathematics (exact rationals,
+closed forms, global Delaunay emptiness, conservation laws)."""
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+import qm_inputs as qi
+
+
+# ---------------------------------------------------------------- helpers
+def fr3(p):
+    return [Fr(float(x)) for x in p]
+
+
+def det_gauss(m):
+    """Determinant by fraction Gaussian elimination (independent of any
+    cofactor formula)."""
+    m = [row[:] for row in m]
+    n, sign, d = len(m), 1, Fr(1)
+    for c in range(n):
+        piv = next((r for r in range(c, n) if m[r][c] != 0), None)
+        if piv is None:
+            return Fr(0)
+        if piv != c:
+            m[c], m[piv] = m[piv], m[c]
+            sign = -sign
+        d *= m[c][c]
+        for r in range(c + 1, n):
+            f = m[r][c] / m[c][c]
+            for k in range(c, n):
+                m[r][k] -= f * m[c][k]
+    return sign * d
+
+
+def sgn(x):
+    return (x > 0) - (x < 0)
+
+
+def solve(A, b):
+    """Solve A x = b in fractions (Cramer through det_gauss)."""
+    D = det_gauss(A)
+    out = []
+    for i in range(len(A)):
+        Ai = [row[:] for row in A]
+        for r in range(len(A)):
+            Ai[r][i] = b[r]
+        out.append(det_gauss(Ai) / D)
+    return out
+
+
+def exact_orient3d(a, b, c, d):
+    a, b, c, d = map(fr3, (a, b, c, d))
+    return sgn(det_gauss([[b[k] - a[k] for k in range(3)], [c[k] - a[k] for k in range(3)],
+                          [d[k] - a[k] for k in range(3)]]))
+
+
+def exact_sphere_centre(a, b, c, d):
+    a, b, c, d = map(fr3, (a, b, c, d))
+    A = [[2 * (p[k] - a[k]) for k in range(3)] for p in (b, c, d)]
+    rhs = [sum(p[k] * p[k] - a[k] * a[k] for k in range(3)) for p in (b, c, d)]
+    return solve(A, rhs)
+
+
+def exact_insphere(a, b, c, d, e):
+    """+1 inside, 0 on, -1 outside: distance to the exact centre."""
+    cen = exact_sphere_centre(a, b, c, d)
+    A, E = fr3(a), fr3(e)
+    r2 = sum((A[k] - cen[k]) ** 2 for k in range(3))
+    q2 = sum((E[k] - cen[k]) ** 2 for k in range(3))
+    return sgn(r2 - q2)
+
+
+def exact_tri_centre(a, b, c):
+    a, b, c = map(fr3, (a, b, c))
+    u = [b[k] - a[k] for k in range(3)]
+    w = [c[k] - a[k] for k in range(3)]
+    uu = sum(x * x for x in u); ww = sum(x * x for x in w); uw = sum(x * y for x, y in zip(u, w))
+    s, t = solve([[2 * uu, 2 * uw], [2 * uw, 2 * ww]], [uu, ww])
+    return [a[k] + s * u[k] + t * w[k] for k in range(3)]
+
+
+def exact_face_encroach(a, b, c, v):
+    """-1 when v is strictly inside the equatorial ball (the sign convention
+    of the oracle's facedot), +1 outside, 0 on the sphere."""
+    cen = exact_tri_centre(a, b, c)
+    A, V = fr3(a), fr3(v)
+    return sgn(sum((V[k] - cen[k]) ** 2 for k in range(3)) - sum((A[k] - cen[k]) ** 2 for k in range(3)))
+
+
+def exact_seg_encroach(a, b, v):
+    A, B, V = map(fr3, (a, b, v))
+    m = [(A[k] + B[k]) / 2 for k in range(3)]
+    half2 = sum((B[k] - A[k]) ** 2 for k in range(3)) / 4
+    return sgn(sum((V[k] - m[k]) ** 2 for k in range(3)) - half2)
+
+
+def lattice_points(rng, n, mode):
+    if mode == "uniform":
+        return rng.random((n, 3))
+    if mode == "grid":      # many exact degeneracies (coplanar, cospherical)
+        return rng.integers(0, 4, size=(n, 3)) / 4.0
+    if mode == "nudged":    # grid points moved by one lattice step
+        g = rng.integers(0, 4, size=(n, 3)) / 4.0
+        return g + rng.integers(-1, 2, size=(n, 3)) * 2.0 ** -53 * (g > 0)
+    raise ValueError(mode)
+
+
+MODES = ["uniform", "grid", "nudged"]
+
+
+# -------------------------------------------------------------- predicates
+@pytest.mark.parametrize("mode", MODES)
+def test_orient3d_exact(mode):
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        p = lattice_points(rng, 4, mode)
+        assert oracle.orient3d(*p) == exact_orient3d(*p)
+
+
+def test_orient3d_far_points():
+    rng = np.random.default_rng(12)
+    for _ in range(100):
+        p = rng.random((4, 3))
+        p[3] = qi.snap(p[3] * 1e12 - 5e11)
+        assert oracle.orient3d(*p) == exact_orient3d(*p)
+
+
+def test_orient3d_unit_tet_is_positive():
+    assert oracle.orient3d([0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]) == 1
+    assert oracle.orient3d([0, 0, 0], [0, 1, 0], [1, 0, 0], [0, 0, 1]) == -1
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_insphere_exact(mode):
+    rng = np.random.default_rng(13)
+    n = 0
+    while n < 200:
+        p = lattice_points(rng, 5, mode)
+        o = exact_orient3d(*p[:4])
+        if o == 0:
+            continue
+        if o < 0:
+            p[[0, 1]] = p[[1, 0]]
+        assert oracle.insphere(*p) == exact_insphere(*p)
+        n += 1
+
+
+def test_insphere_cube_corners_cospherical():
+    c = qi.corners()
+    # every corner lies on the sphere through any four non-coplanar corners
+    for tet in ([0, 1, 2, 4], [1, 2, 4, 7], [0, 3, 5, 6]):
+        t = c[tet]
+        if oracle.orient3d(*t) < 0:
+            t = t[[1, 0, 2, 3]]
+        for q in range(8):
+            if q not in tet:
+                assert oracle.insphere(*t, c[q]) == 0
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_orient2d_exact(mode):
+    rng = np.random.default_rng(14)
+    for _ in range(300):
+        p = lattice_points(rng, 3, mode)
+        ax = int(rng.integers(0, 3))
+        i, j = (ax + 1) % 3, (ax + 2) % 3
+        a, b, c = map(fr3, p)
+        want = sgn(det_gauss([[b[i] - a[i], b[j] - a[j]], [c[i] - a[i], c[j] - a[j]]]))
+        assert oracle.orient2d(ax, *p) == want
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_seg_encroach_exact(mode):
+    rng = np.random.default_rng(15)
+    for _ in range(300):
+        p = lattice_points(rng, 3, mode)
+        assert oracle.segdot(*p) == exact_seg_encroach(*p)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_face_encroach_exact(mode):
+    rng = np.random.default_rng(16)
+    n = 0
+    while n < 200:
+        p = lattice_points(rng, 4, mode)
+        a, b, c = map(fr3, p[:3])
+        u = [b[k] - a[k] for k in range(3)]; w = [c[k] - a[k] for k in range(3)]
+        if u[1] * w[2] - u[2] * w[1] == 0 and u[2] * w[0] - u[0] * w[2] == 0 and u[0] * w[1] - u[1] * w[0] == 0:
+            continue                      # collinear triangle: no circle
+        assert oracle.facedot(*p) == exact_face_encroach(*p)
+        n += 1
+
+
+def test_encroach_closed_forms():
+    a, b = [0, 0, 0], [1, 0, 0]
+    assert oracle.segdot(a, b, [0.5, 0.4, 0]) < 0       # inside the diametral ball
+    assert oracle.segdot(a, b, [0.5, 0.5, 0]) == 0      # on the sphere
+    tri = ([0, 0, 0], [1, 0, 0], [0, 1, 0])
+    assert oracle.facedot(*tri, [1, 1, 0]) == 0         # fourth square corner: cocircular
+    assert oracle.facedot(*tri, [0.5, 0.5, 0.5]) < 0    # |v-c|^2 = 1/4 < R^2 = 1/2
+    assert oracle.facedot(*tri, [0.5, 0.5, 1.0]) > 0    # |v-c|^2 = 1 > 1/2
+
+
+# ----------------------------------------------------------- constructions
+def test_tet_circumcentre_closed_form():
+    p, r2 = oracle.tet_cc([0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1])
+    assert list(p) == [0.5, 0.5, 0.5] and r2 == 0.75
+
+
+def test_tri_circumcentre_closed_form():
+    assert list(oracle.tri_cc([0, 0, 0], [1, 0, 0], [0, 1, 0])) == [0.5, 0.5, 0.0]
+
+
+def test_axis_plane_constructions_stay_on_plane():
+    rng = np.random.default_rng(17)
+    for _ in range(200):
+        p = rng.random((3, 3))
+        p[:, 2] = 1.0
+        assert oracle.tri_cc(*p)[2] == 1.0
+        assert oracle.midpoint(p[0], p[1])[2] == 1.0
+
+
+def test_radius_edge_closed_forms():
+    unit = ([0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1])     # ratio sqrt(3)/2 ~ 0.866
+    assert not oracle.is_bad(*unit, 0.87) and oracle.is_bad(*unit, 0.86)
+    reg = ([0, 0, 0], [1, 1, 0], [1, 0, 1], [0, 1, 1])      # regular: sqrt(6)/4 ~ 0.612
+    assert not oracle.is_bad(*reg, 0.613) and oracle.is_bad(*reg, 0.612)
+    needle = ([0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, qi.snap(1e-3)])
+    assert oracle.is_bad(*needle, 2.0)
+    sliver = ([0, 0, 0], [1, 0, 0], [1, 1, 2.0 ** -20], [0, 1, 0])  # flat square: ratio -> sqrt(2)/2
+    assert not oracle.is_bad(*sliver, 0.75)
+
+
+def test_circumcentres_match_exact_rationals():
+    rng = np.random.default_rng(18)
+    for _ in range(100):
+        p = rng.random((4, 3))
+        c, _ = oracle.tet_cc(*p)
+        ex = exact_sphere_centre(*p)
+        for k in range(3):
+            assert abs(Fr(float(c[k])) - ex[k]) <= Fr(1, 10 ** 9) * (1 + abs(ex[k]))
+        t = oracle.tri_cc(*p[:3])
+        ex = exact_tri_centre(*p[:3])
+        for k in range(3):
+            assert abs(Fr(float(t[k])) - ex[k]) <= Fr(1, 10 ** 9) * (1 + abs(ex[k]))
+
+
+def test_midpoint_rounding():
+    rng = np.random.default_rng(19)
+    for _ in range(200):
+        a, b = rng.random((2, 3))
+        m = oracle.midpoint(a, b)
+        for k in range(3):
+            assert abs(Fr(float(m[k])) - (Fr(float(a[k])) + Fr(float(b[k]))) / 2) <= Fr(1, 2 ** 54)
+            assert (Fr(float(m[k])) * 2 ** 53).denominator == 1     # on the lattice
+
+
+def test_priority_key_is_splitmix64():
+    # first output of SplitMix64 from state 0 (published reference value)
+    assert oracle.key(0, [0]) == 0xE220A8397B1DCDAF
+
+
+# ------------------------------------------------------------ the round rule
+def struct_ok(c):
+    keys = ("neg_orient", "face_overuse", "hull_not_subface", "sf_missing", "ss_missing", "chain_broken")
+    return all(c[k] == 0 for k in keys) and c["euler"] == 1 and abs(c["volume"] - 1.0) < 1e-9
+
+
+def test_config1_refinement_is_delaunay_and_conforming():
+    w = qi.config(1)
+    r = oracle.refine(w)
+    assert r.status == 0                                   # no candidates left
+    c = oracle.check(r.xyz, r.tets, r.sf, r.ss, r.ss_seg, w.B)
+    assert struct_ok(c) and c["nonlocal_delaunay"] == 0
+    assert oracle.check_global(r.xyz, r.tets) == 0
+    a0 = oracle.facet_areas(w.xyz, w.ftri, w.ftri_facet)
+    a1 = oracle.facet_areas(r.xyz, r.sf, r.sf_facet)
+    assert set(a0) == set(a1) and max(abs(a0[k] - a1[k]) for k in a0) < 1e-12
+    # every remaining bad tet was exempted (the exemption counters bound them)
+    assert c["bad_tets"] <= int(r.rstats[:, 6:14].sum())
+    # Steiner points on the hull stay exactly on their cube face
+    hull = r.sf[r.sf_facet < 6]
+    for f, axis_side in zip(hull, r.sf_facet[r.sf_facet < 6]):
+        assert np.all(r.xyz[f, axis_side // 2] == float(axis_side % 2))
+
+
+@pytest.mark.parametrize("n,seed,B", [(60, 1, 1.2), (150, 2, 1.6), (300, 3, 2.0)])
+def test_hull_only_delaunay_after_every_round(n, seed, B):
+    w = qi.uniform_cube(n, seed=seed, B=B)
+    full = oracle.refine(w)
+    for m in sorted(set(np.linspace(1, full.rounds, 6).astype(int))):
+        r = oracle.refine(w, max_rounds=int(m))
+        c = oracle.check(r.xyz, r.tets, r.sf, r.ss, r.ss_seg, B)
+        assert struct_ok(c) and c["nonlocal_delaunay"] == 0
+        assert oracle.check_global(r.xyz, r.tets) == 0
+
+
+def test_sequential_special_case_is_delaunay():
+    """One insertion per round is textbook sequential Delaunay refinement:
+    the mesh stays the Delaunay tetrahedralisation of its vertices."""
+    w = qi.uniform_cube(80, seed=5, B=1.5)
+    r = oracle.refine(w, max_kept=1)
+    assert r.status == 0 and np.all(r.rstats[:, 5] <= 1)
+    assert oracle.check_global(r.xyz, r.tets) == 0
+    c = oracle.check(r.xyz, r.tets, r.sf, r.ss, r.ss_seg, w.B)
+    assert struct_ok(c)
+
+
+@pytest.mark.parametrize("n,seed", [(120, 7), (250, 8)])
+def test_surface_refinement_conforms(n, seed):
+    w = qi.uniform_cube(n, seed=seed, B=1.5, spheres=(0.3,))
+    assert len(w.ftri) > 12
+    r = oracle.refine(w)
+    assert r.status == 0
+    c = oracle.check(r.xyz, r.tets, r.sf, r.ss, r.ss_seg, w.B)
+    assert struct_ok(c)
+    a0 = oracle.facet_areas(w.xyz, w.ftri, w.ftri_facet)
+    a1 = oracle.facet_areas(r.xyz, r.sf, r.sf_facet)
+    assert set(a0) == set(a1)
+    assert max(abs(a0[k] - a1[k]) / max(a0[k], 1e-300) for k in a0) < 1e-9
+    # every segment is still a chain of subsegments between its endpoints
+    assert c["chain_broken"] == 0 and set(r.ss_seg.tolist()) == set(range(len(w.seg)))
+
+
+def canon(r):
+    t = np.sort(r.tets, axis=1)
+    t = t[np.lexsort(t.T[::-1])]
+    return t, r.xyz
+
+
+def test_canonical_under_input_permutation():
+    """No decision depends on slot order: shuffling the tets and rotating
+    each tet's vertices (even permutations) leaves the output unchanged."""
+    w = qi.uniform_cube(150, seed=9, B=1.4, spheres=(0.3,))
+    r1 = oracle.refine(w)
+    rng = np.random.default_rng(0)
+    perm = rng.permutation(len(w.tets))
+    even = np.array([[0, 1, 2, 3], [1, 2, 0, 3], [2, 0, 1, 3], [1, 0, 3, 2], [0, 2, 3, 1],
+                     [2, 3, 0, 1], [3, 2, 1, 0], [0, 3, 1, 2]])
+    rot = even[rng.integers(0, len(even), size=len(w.tets))]
+    w2 = qi.Workload(w.name, w.xyz, np.take_along_axis(w.tets[perm], rot, axis=1), w.adj,
+                     w.ftri, w.ftri_facet, w.seg, w.B)
+    r2 = oracle.refine(w2)
+    t1, x1 = canon(r1)
+    t2, x2 = canon(r2)
+    assert np.array_equal(t1, t2) and np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+    assert np.array_equal(r1.rstats, r2.rstats)
+
+
+def test_deterministic_rerun():
+    w = qi.uniform_cube(100, seed=4, B=1.5, spheres=(0.3,))
+    a, b = oracle.refine(w), oracle.refine(w)
+    assert np.array_equal(canon(a)[0], canon(b)[0]) and np.array_equal(a.rstats, b.rstats)
