@@ -1,0 +1,127 @@
+/*
+ * qm.h -- C-ABI of libqm: round-based constrained Delaunay refinement on one
+ * AMD MI355X (gfx950).
+ *
+ * Problem (paper, Section 1): given a piecewise linear complex G = (P, E, F),
+ * a constrained Delaunay tetrahedralisation (CDT) T conforming to G and a
+ * bound B, add Steiner points so that the result is again a CDT conforming to
+ * G whose tetrahedra mostly have radius-edge ratio at most B.  Method (paper,
+ * Section 2): subsegments, then subfaces, then bad tetrahedra are split in
+ * rounds; each round computes splitting points, grows their Delaunay regions,
+ * keeps a set of points with disjoint regions (priority blasting) and inserts
+ * them concurrently.
+ *
+ * All entry points return 0 on success or a negative QM_E* code; the message
+ * of the last failure on the calling thread is qm_last_error().  No C++
+ * exception crosses this boundary.
+ *
+ * Coordinates: FP64, row-major [n][3], every value a multiple of 2^-53 inside
+ * the closed unit cube [0,1]^3 (the coordinate lattice; the library rounds
+ * every splitting point onto it, which keeps all predicates exact).  Ids are
+ * int32, 0-based.
+ */
+#ifndef QM_H
+#define QM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QM_OK 0
+#define QM_EINVAL (-1)        /* bad ids, off-lattice or out-of-cube coordinates, B <= 0 */
+#define QM_ENONCONFORM (-2)   /* a subface or subsegment is not a face or edge of the mesh,
+                                 a tet is not positively oriented, or faces do not match */
+#define QM_ENOMEM (-3)        /* device or host allocation failed */
+#define QM_EROUNDS (-4)       /* round guard reached (the result is still returned) */
+#define QM_EDEVICE (-5)       /* HIP runtime error */
+#define QM_EINTERNAL (-6)     /* a kernel found an impossible state (bug) */
+#define QM_ECAPACITY (-7)     /* a cavity exceeded the largest supported region size */
+
+/* The PLC G = (P, E, F): polygons are given as triangles carrying a polygon
+   (facet) id.  Borrowed for the duration of the call. */
+typedef struct qm_plc {
+    int32_t nv;              /* |P|; P are the first nv vertices of the mesh */
+    int32_t nseg;            /* |E| */
+    const int32_t* seg;      /* [nseg][2] */
+    int32_t nftri;           /* triangles of the polygons of F */
+    const int32_t* ftri;     /* [nftri][3] */
+    const int32_t* ftri_facet;   /* [nftri] polygon id, 0-based, dense */
+} qm_plc;
+
+/* A mesh: vertices, tetrahedra, subfaces and subsegments (paper, Section 1
+   definitions).  As input it is the CDT T; borrowed, never written. */
+typedef struct qm_mesh {
+    int32_t nv;
+    const double* xyz;       /* [nv][3] */
+    int32_t nt;
+    const int32_t* tet;      /* [nt][4], each positively oriented:
+                                det[b-a; c-a; d-a] > 0 */
+    int32_t nsf;
+    const int32_t* sf;       /* [nsf][3] subfaces (faces of T lying on polygons) */
+    const int32_t* sf_facet; /* [nsf] polygon id of each subface */
+    int32_t nss;
+    const int32_t* ss;       /* [nss][2] subsegments (edges of T lying on segments) */
+    const int32_t* ss_seg;   /* [nss] segment id of each subsegment */
+} qm_mesh;
+
+#define QM_INPUT_DEVICE 1u   /* mesh/PLC arrays are device pointers (same device) */
+
+typedef struct qm_options {
+    double B;                /* radius-edge bound (> 0) */
+    double hmin_factor;      /* h_min = hmin_factor * shortest input edge (0.5 typical) */
+    int32_t max_rounds;      /* round guard; QM_EROUNDS when reached */
+    int32_t max_kept;        /* > 0: insert at most this many points per round */
+    uint32_t flags;          /* QM_INPUT_DEVICE */
+} qm_options;
+
+/* per-round record (16 int32): class (0 subsegment, 1 subface, 2 tet),
+   candidates, accepted, rejected, exempted, inserted, exempted by reason
+   (non-finite point, walk cap, encroached exempt element, h_min, region
+   subface without region tets, invisible boundary face, invisible 2D
+   boundary edge, unclosed cavity boundary), vertices after, tets after */
+#define QM_ROUND_FIELDS 16
+
+typedef struct qm_stats {
+    int32_t rounds;
+    int32_t status;          /* 0 converged, 1 round guard reached */
+    int64_t inserted[3];     /* Steiner points by class */
+    int64_t candidates;      /* candidate evaluations over all rounds */
+    int64_t mis_passes;      /* marking passes of the disjoint-set selection */
+    int64_t nv_out, nt_out;  /* output sizes */
+    double seconds_setup;    /* device-side setup from the input arrays */
+    double seconds_refine;   /* round loop (device resident) */
+    double seconds_total;    /* whole call incl. transfers */
+} qm_stats;
+
+typedef struct qm_result qm_result;
+
+/* Refine one instance.  `hip_stream` is a hipStream_t (NULL: default stream).
+   On success *out owns the output until qm_result_free. */
+int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream,
+              qm_result** out);
+
+/* Host view of a result: the output mesh (Steiner vertices appended after the
+   input vertices, numbered by round and priority) and the statistics.
+   Pointers stay valid until qm_result_free. */
+int qm_result_view(const qm_result* r, qm_mesh* view, qm_stats* stats);
+
+/* Copy at most `cap` rounds of per-round records (QM_ROUND_FIELDS each) into
+   buf; returns the number of rounds available. */
+int qm_result_rounds(const qm_result* r, int32_t* buf, int32_t cap);
+
+void qm_result_free(qm_result* r);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* qm_last_error(void);
+
+/* Library version string. */
+const char* qm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,208 @@
+"""Round-based constrained Delaunay refinement on the AMD MI355X (gfx950).
+
+Thin ctypes binding of ``libqm.so`` (C-ABI in ``include/qm.h``): argument
+marshalling only, every step of the refinement runs in the HIP kernels.
+PyTorch, when used, only supplies device memory and the HIP stream.
+
+    import paper_1903_03406_amd as qm
+    out = qm.refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B=2.0)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+_SO = os.path.join(_HERE, "libqm.so")
+_SRC = os.path.join(_HERE, "csrc", "qm_lib.hip")
+_lib = None
+
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+QM_INPUT_DEVICE = 1
+ROUND_FIELDS = 16
+ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
+               "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
+               "ex_face", "ex_edge2d", "ex_manifold", "nv_after", "nt_after")
+ERRORS = {-1: "QM_EINVAL", -2: "QM_ENONCONFORM", -3: "QM_ENOMEM", -4: "QM_EROUNDS",
+          -5: "QM_EDEVICE", -6: "QM_EINTERNAL", -7: "QM_ECAPACITY"}
+
+
+def build() -> str:
+    """Compile libqm.so for gfx950 (in-tree)."""
+    cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(_ROOT, "include"), "-o", _SO + ".tmp", _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Plc(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int32), ("nseg", ctypes.c_int32), ("seg", ctypes.c_void_p),
+                ("nftri", ctypes.c_int32), ("ftri", ctypes.c_void_p), ("ftri_facet", ctypes.c_void_p)]
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("nt", ctypes.c_int32),
+                ("tet", ctypes.c_void_p), ("nsf", ctypes.c_int32), ("sf", ctypes.c_void_p),
+                ("sf_facet", ctypes.c_void_p), ("nss", ctypes.c_int32), ("ss", ctypes.c_void_p),
+                ("ss_seg", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_double), ("hmin_factor", ctypes.c_double),
+                ("max_rounds", ctypes.c_int32), ("max_kept", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("inserted", ctypes.c_int64 * 3), ("candidates", ctypes.c_int64),
+                ("mis_passes", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
+                ("seconds_setup", ctypes.c_double), ("seconds_refine", ctypes.c_double),
+                ("seconds_total", ctypes.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError(f"{_SO} is not built: run paper_1903_03406_amd.build() "
+                               "(the refinement has no CPU fallback)")
+        lib = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        lib.qm_refine.restype = ctypes.c_int
+        lib.qm_refine.argtypes = [ctypes.POINTER(_Plc), ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts), P,
+                                  ctypes.POINTER(P)]
+        lib.qm_result_view.restype = ctypes.c_int
+        lib.qm_result_view.argtypes = [P, ctypes.POINTER(_Mesh), ctypes.POINTER(_Stats)]
+        lib.qm_result_rounds.restype = ctypes.c_int
+        lib.qm_result_rounds.argtypes = [P, P, ctypes.c_int32]
+        lib.qm_result_free.argtypes = [P]
+        lib.qm_last_error.restype = ctypes.c_char_p
+        lib.qm_version.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+EXPORTS = ("qm_refine", "qm_result_view", "qm_result_rounds", "qm_result_free", "qm_last_error",
+           "qm_version")
+
+
+class QmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+@dataclass
+class RefineResult:
+    xyz: np.ndarray
+    tets: np.ndarray
+    sf: np.ndarray
+    sf_facet: np.ndarray
+    ss: np.ndarray
+    ss_seg: np.ndarray
+    rstats: np.ndarray          # (rounds, 16), same fields as ROUND_NAMES
+    rounds: int
+    status: int                 # 0 converged, 1 round guard reached
+    inserted: tuple
+    candidates: int
+    mis_passes: int
+    seconds_setup: float
+    seconds_refine: float
+    seconds_total: float
+
+    @property
+    def steiner(self) -> int:
+        return int(sum(self.inserted))
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None, hmin_factor=0.5,
+           max_rounds=100000, max_kept=0, stream=None) -> RefineResult:
+    """Refine a CDT.  Arrays are numpy (host) or torch CUDA tensors (device);
+    ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle."""
+    lib = _load()
+    dev = False
+    keep = []
+
+    def ptr(a, dtype):
+        nonlocal dev
+        if a is None:
+            return None, 0
+        if hasattr(a, "is_cuda") and a.is_cuda:
+            dev = True
+            import torch
+            t = a.contiguous().to(dtype={np.float64: torch.float64, np.int32: torch.int32}[dtype])
+            keep.append(t)
+            return t.data_ptr(), t.shape[0]
+        h = _arr(a, dtype)
+        keep.append(h)
+        return h.ctypes.data, h.shape[0]
+
+    pxyz, nv = ptr(xyz, np.float64)
+    ptet, nt = ptr(tets, np.int32)
+    psf, nsf = ptr(sf, np.int32)
+    psff, _ = ptr(sf_facet, np.int32)
+    pss, nss = ptr(ss, np.int32)
+    pssg, _ = ptr(ss_seg, np.int32)
+    pft, nft = ptr(ftri, np.int32)
+    pftf, _ = ptr(ftri_facet, np.int32)
+    pseg, nseg = ptr(seg if seg is not None else np.zeros((0, 2), np.int32), np.int32)
+    plc = _Plc(nv, nseg, pseg, nft, pft, pftf)
+    mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
+    opts = _Opts(float(B), float(hmin_factor), int(max_rounds), int(max_kept),
+                 QM_INPUT_DEVICE if dev else 0)
+    if stream is None:
+        hs = None
+    elif hasattr(stream, "cuda_stream"):
+        hs = stream.cuda_stream
+    else:
+        hs = int(stream)
+    res = ctypes.c_void_p()
+    rc = lib.qm_refine(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), hs, ctypes.byref(res))
+    if rc not in (0, -4):
+        raise QmError(rc, lib.qm_last_error().decode())
+    try:
+        view, st = _Mesh(), _Stats()
+        lib.qm_result_view(res, ctypes.byref(view), ctypes.byref(st))
+
+        def grab(p, n, cols, dtype):
+            if n == 0:
+                return np.zeros((0, cols) if cols > 1 else (0,), dtype=dtype)
+            ctype = ctypes.c_double if dtype == np.float64 else ctypes.c_int32
+            buf = ctypes.cast(p, ctypes.POINTER(ctype * (n * cols))).contents
+            a = np.frombuffer(buf, dtype=dtype).copy()
+            return a.reshape(n, cols) if cols > 1 else a
+
+        nr = lib.qm_result_rounds(res, None, 0)
+        rs = np.zeros((max(nr, 0), ROUND_FIELDS), dtype=np.int32)
+        if nr:
+            lib.qm_result_rounds(res, rs.ctypes.data, nr)
+        return RefineResult(grab(view.xyz, view.nv, 3, np.float64), grab(view.tet, view.nt, 4, np.int32),
+                            grab(view.sf, view.nsf, 3, np.int32), grab(view.sf_facet, view.nsf, 1, np.int32),
+                            grab(view.ss, view.nss, 2, np.int32), grab(view.ss_seg, view.nss, 1, np.int32),
+                            rs, int(st.rounds), int(st.status), tuple(int(x) for x in st.inserted),
+                            int(st.candidates), int(st.mis_passes), float(st.seconds_setup),
+                            float(st.seconds_refine), float(st.seconds_total))
+    finally:
+        lib.qm_result_free(res)
+
+
+def refine_workload(w, **kw) -> RefineResult:
+    """Refine a workload object exposing the PLC and CDT arrays
+    (xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, seg, B)."""
+    return refine(w.xyz, w.tets, w.sf, w.sf_facet, w.ss, w.ss_seg, w.ftri, w.ftri_facet,
+                  kw.pop("B", w.B), seg=w.seg, **kw)
+
+
+def version() -> str:
+    return _load().qm_version().decode()

@@ -1,0 +1,224 @@
+// qm_insert.h -- flags, disjoint-set selection and concurrent insertion.
+#pragma once
+#include "qm_grow.h"
+
+namespace qm {
+
+// final status of each candidate: the walk's verdict if it decided, else the
+// region evaluation's
+QMD int final_status(const Cands& C, int i) { return C.st[i] != ST_PENDING ? C.st[i] : C.gst[i]; }
+
+// Rejected points queue their targets; exempted elements are marked.  Runs
+// before insertion, so a flagged element destroyed this round loses its
+// flags with it and new elements start clean.
+__global__ void k_apply_flags(Mesh M, int cls, Cands C, Pools PL) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n) return;
+    int st = C.st[i] != ST_PENDING ? C.st[i] : C.gst[i];
+    auto queue = [&](int2 e) {
+        if (e.x == 0) atomicOr(&M.SFL[e.y], SS_QUEUED);
+        else {
+            int t = e.y >> 2, f = e.y & 3;
+            atomicOr(&M.TI[t], 1u << (4 + f));
+            int nb = M.TA[4 * (size_t)t + f];
+            if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (4 + (nb & 3)));
+        }
+    };
+    if (st == ST_REJECT) {
+        if (C.st[i] == ST_REJECT) queue(C.qw[i]);
+        else for (int k = 0; k < C.q_n[i]; ++k) queue(PL.q[C.q_off[i] + k]);
+    } else if (st == ST_EXEMPT) {
+        int e = C.elem[i];
+        if (cls == CLS_SS) atomicOr(&M.SFL[e], SS_EXEMPT);
+        else if (cls == CLS_SF) {
+            int t = e >> 2, f = e & 3;
+            atomicOr(&M.TI[t], 1u << (8 + f));
+            int nb = M.TA[4 * (size_t)t + f];
+            if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (8 + (nb & 3)));
+        } else atomicOr(&M.TI[e], TI_EXEMPT);
+    }
+}
+
+// round statistics: [ncand, ok, rejected, exempt, exempt by reason 1..8]
+__global__ void k_round_stats(Cands C, int* stats) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n) return;
+    int st = final_status(C, i);
+    atomicAdd(&stats[0], 1);
+    if (st == ST_OK) atomicAdd(&stats[1], 1);
+    else if (st == ST_REJECT) atomicAdd(&stats[2], 1);
+    else if (st == ST_EXEMPT) {
+        atomicAdd(&stats[3], 1);
+        int r = C.st[i] != ST_PENDING ? C.reason[i] : C.greason[i];
+        atomicAdd(&stats[3 + r], 1);
+    } else atomicAdd(&stats[12], 1);     // unresolved (internal error)
+}
+
+// ------------------------------------------------------------- selection
+// Iterated local maxima with fixed priorities: in each pass every undecided
+// candidate marks its claim set with its priority (atomic max); a candidate
+// owning all its marks is kept, one touching a kept claim is dropped.  The
+// result is exactly the greedy maximal disjoint set in priority order.
+__global__ void k_mis_init(Cands C) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= C.n) return;
+    C.state[i] = final_status(C, i) == ST_OK ? 0 : 3;
+}
+QMD unsigned long long mis_val(unsigned pass, int c) {
+    return ((unsigned long long)pass << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)c);
+}
+__global__ void k_mis_mark(int ncl, const int* cl, const int* clc, const int* state,
+                           unsigned long long* mark, unsigned pass) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ncl) return;
+    int c = clc[e];
+    if (state[c] != 0) return;
+    atomicMax(&mark[cl[e]], mis_val(pass, c));
+}
+__global__ void k_mis_decide(Cands C, const int* cl, const unsigned long long* mark, const int* owner,
+                             unsigned pass, int* undecided) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C.n || C.state[c] != 0) return;
+    unsigned long long me = mis_val(pass, c);
+    bool mine = true;
+    for (int k = 0; k < C.cl_n[c]; ++k) {
+        int t = cl[C.cl_off[c] + k];
+        if (owner[t] >= 0) { C.state[c] = 2; return; }
+        if (mark[t] != me) mine = false;
+    }
+    if (mine) C.state[c] = 1;
+    else atomicAdd(undecided, 1);
+}
+__global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* state, int* owner) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ncl) return;
+    int c = clc[e];
+    if (state[c] == 1) owner[cl[e]] = c;
+}
+__global__ void k_mis_release(int ncl, const int* cl, const int* clc, const int* state, int* owner) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ncl) return;
+    if (state[clc[e]] == 1) owner[cl[e]] = -1;
+}
+
+// per-candidate values to scan: kept flag, new tet slots (f - k), new
+// subsegment slots
+__global__ void k_scan_vals(Cands C, int cls, int* vk, int* vt, int* vs) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C.n) return;
+    bool kept = C.state[c] == 1;
+    vk[c] = kept;
+    int d = kept ? C.bf_n[c] - C.reg_n[c] : 0;
+    vt[c] = d > 0 ? d : 0;
+    vs[c] = kept && cls == CLS_SS;
+}
+// optional cap on insertions per round: only the first `cap` kept survive
+__global__ void k_cap_kept(Cands C, const int* sk, int cap) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C.n) return;
+    if (C.state[c] == 1 && sk[c] >= cap) C.state[c] = 2;
+}
+__global__ void k_kept_list(Cands C, const int* sk, int* list) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C.n) return;
+    if (C.state[c] == 1) list[sk[c]] = c;
+}
+__global__ void k_totals(int n, const int* a, const int* av, const int* b, const int* bv, const int* d,
+                         const int* dv, int* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out[0] = n ? a[n - 1] + av[n - 1] : 0;
+        out[1] = n ? b[n - 1] + bv[n - 1] : 0;
+        out[2] = n ? d[n - 1] + dv[n - 1] : 0;
+    }
+}
+
+// ------------------------------------------------------------- insertion
+// One workgroup per kept point: the new tets join p to the boundary faces
+// (slots of the deleted region tets are reused first, then fresh slots);
+// faces through p are linked by matching boundary edges, the outer face to
+// the old neighbour (whose back link is patched), subfaces (p, e) are created
+// on 2D boundary edges, and a split subsegment becomes (a,p) + (p,b).
+__global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                               const int* kept, int nkept, const int* sk, const int* st_,
+                                               const int* ss_, int nv0, int nt0, int nss0, int* dead) {
+    for (int kk = blockIdx.x; kk < nkept; kk += gridDim.x) {
+        const int c = kept[kk];
+        const int lane = threadIdx.x;
+        const int pid = nv0 + sk[c];
+        const int nf = C.bf_n[c], nk = C.reg_n[c];
+        const int bf0 = C.bf_off[c], rg0 = C.reg_off[c], be0 = C.be_off[c], nbe = C.be_n[c];
+        const int tbase = nt0 + st_[c];
+        int sa = -1, sb = -1, s_old = -1, s_new = -1;
+        if (cls == CLS_SS) {
+            int4 tp = C.tup[c];
+            sa = tp.x; sb = tp.y; s_old = C.elem[c]; s_new = nss0 + ss_[c];
+        }
+        // phase A: read the face flags of the old boundary faces before any
+        // slot of this region is overwritten
+        for (int j = lane; j < nf; j += 64) {
+            int h = BP.r[3 * (size_t)(bf0 + j) + 2].y;
+            unsigned ti = M.TI[h >> 2];
+            int f = h & 3;
+            int fl = (int)(((ti >> (4 + f)) & 1u) | (((ti >> (8 + f)) & 1u) << 1));
+            BP.r[3 * (size_t)(bf0 + j) + 1].y = fl;
+        }
+        __syncthreads();
+        auto slot = [&](int j) { return j < nk ? PL.reg[rg0 + j] : tbase + (j - nk); };
+        // phase B: write the new tets
+        for (int j = lane; j < nf; j += 64) {
+            int4 r0 = BP.r[3 * (size_t)(bf0 + j)];
+            int4 r1 = BP.r[3 * (size_t)(bf0 + j) + 1];
+            int4 r2 = BP.r[3 * (size_t)(bf0 + j) + 2];
+            const int x = r0.x, y = r0.y, z = r0.z;
+            const int sj = slot(j);
+            // faces through p: opposite x holds edge (y,z), opposite y (x,z), opposite z (x,y)
+            const int ea[3] = {y, x, x}, eb[3] = {z, z, y};
+            int adj[3], fid[3];
+            for (int l = 0; l < 3; ++l) {
+                int u = ea[l], w = eb[l];
+                adj[l] = -1;
+                for (int m = 0; m < nf; ++m) {
+                    if (m == j) continue;
+                    int4 q0 = BP.r[3 * (size_t)(bf0 + m)];
+                    bool hu = q0.x == u || q0.y == u || q0.z == u;
+                    bool hw = q0.x == w || q0.y == w || q0.z == w;
+                    if (hu && hw) {
+                        int lm = (q0.x != u && q0.x != w) ? 0 : ((q0.y != u && q0.y != w) ? 1 : 2);
+                        adj[l] = (slot(m) << 2) | lm;
+                        break;
+                    }
+                }
+                fid[l] = -1;
+                int lo = u < w ? u : w, hi = u < w ? w : u;
+                for (int m = 0; m < nbe; ++m) {
+                    int4 e = PL.be[be0 + m];
+                    if (e.x == lo && e.y == hi) { fid[l] = e.z; break; }
+                }
+            }
+            *reinterpret_cast<int4*>(M.TV + 4 * (size_t)sj) = make_int4(x, y, z, pid);
+            *reinterpret_cast<int4*>(M.TA + 4 * (size_t)sj) = make_int4(adj[0], adj[1], adj[2], r0.w);
+            *reinterpret_cast<int4*>(M.TF + 4 * (size_t)sj) = make_int4(fid[0], fid[1], fid[2], r1.x);
+            // edges of (x,y,z,p): (0,1)=xy (0,2)=xz (0,3)=xp (1,2)=yz (1,3)=yp (2,3)=zp
+            auto sp = [&](int v) { return v == sa ? s_old : (v == sb ? s_new : -1); };
+            int* ts = M.TS + 6 * (size_t)sj;
+            ts[0] = r1.z; ts[1] = r2.x; ts[2] = sp(x); ts[3] = r1.w; ts[4] = sp(y); ts[5] = sp(z);
+            M.TI[sj] = TI_ALIVE | ((unsigned)(r1.y & 1) << 7) | ((unsigned)((r1.y >> 1) & 1) << 11);
+            if (r0.w >= 0) M.TA[4 * (size_t)(r0.w >> 2) + (r0.w & 3)] = (sj << 2) | 3;
+            for (int e = 0; e < 6; ++e) if (ts[e] >= 0) M.STET[ts[e]] = sj;
+        }
+        for (int j = nf + lane; j < nk; j += 64) M.TI[PL.reg[rg0 + j]] = 0u;   // unused region slots
+        if (lane == 0 && nk > nf) atomicAdd(dead, nk - nf);
+        if (lane == 0) {
+            double4 p = C.p[c];
+            M.X[pid] = make_double4(p.x, p.y, p.z, 0.0);
+            if (cls == CLS_SS) {
+                int seg = M.SSEG[s_old];
+                M.SV[s_old] = make_int2(sa, pid); M.SFL[s_old] = 0u;
+                M.SV[s_new] = make_int2(sb, pid); M.SFL[s_new] = 0u; M.SSEG[s_new] = seg;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace qm

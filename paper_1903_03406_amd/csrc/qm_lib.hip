@@ -1,0 +1,556 @@
+// qm_lib.hip -- host driver of the round loop and the C-ABI (include/qm.h).
+//
+// One call = upload (or adopt device arrays) -> device setup -> rounds until
+// no candidate is left -> compact and download.  Everything between setup
+// and download runs on the GPU; the host only reads a few counters per round
+// (class choice, overflow, selection passes, totals) to size launches and
+// buffers.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "qm.h"
+#include "qm_insert.h"
+#include "qm_round.h"
+#include "qm_setup.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct QmError : std::runtime_error {
+    int code;
+    QmError(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCK(x)                                                                              \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess)                                                                 \
+            throw QmError(e_ == hipErrorOutOfMemory ? QM_ENOMEM : QM_EDEVICE,                 \
+                          std::string(#x) + ": " + hipGetErrorString(e_));                   \
+    } while (0)
+
+inline int nblk(long n, int b = 256) { return (int)std::max(1L, (n + b - 1) / b); }
+
+// growable device buffer (contents kept on growth when asked)
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t cap = 0;
+    void ensure(size_t n, hipStream_t s, bool keep, int fill_byte = -1) {
+        if (n <= cap) return;
+        size_t nc = std::max(n, cap + cap / 2 + 1024);
+        T* q = nullptr;
+        HIPCK(hipMallocAsync((void**)&q, nc * sizeof(T), s));
+        if (fill_byte >= 0) HIPCK(hipMemsetAsync(q, fill_byte, nc * sizeof(T), s));
+        if (keep && p && cap) HIPCK(hipMemcpyAsync(q, p, cap * sizeof(T), hipMemcpyDeviceToDevice, s));
+        if (p) HIPCK(hipFreeAsync(p, s));
+        p = q;
+        cap = nc;
+    }
+    void release(hipStream_t s) {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+template <class T>
+T read1(const T* dptr, hipStream_t s) {
+    T v;
+    HIPCK(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    return v;
+}
+
+}  // namespace
+
+struct qm_result {
+    std::vector<double> xyz;
+    std::vector<int32_t> tets, sf, sff, ss, ssg;
+    std::vector<int32_t> rounds;   // QM_ROUND_FIELDS per round
+    qm_stats stats;
+};
+
+namespace qm {
+
+__global__ void k_iota(int n, int* o) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = i;
+}
+__global__ void k_fill(int n, int* o, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = v;
+}
+__global__ void k_overflow_list(Cands C, int* list, int* n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C.n && C.st[i] == ST_PENDING && C.gst[i] == ST_OVERFLOW) list[atomicAdd(n, 1)] = i;
+}
+
+// LDS tiles of the fast grow path (one 64-lane workgroup per candidate)
+constexpr int G_MAXRT = 256, G_HCAP = 1024, G_RFHCAP = 128, G_MAXRF = 48, G_MAXBE = 96, G_QHCAP = 128,
+              G_MAXQ = 64, G_MAXBF = 384;
+// global-slab tiles of the overflow path
+constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, B_MAXBE = 4096,
+              B_QHCAP = 8192, B_MAXQ = 4096, B_MAXBF = 32768;
+
+struct Engine {
+    hipStream_t s;
+    Mesh M{};
+    DBuf<double4> X;
+    DBuf<int> TV, TA, TF, TS;
+    DBuf<unsigned> TI;
+    DBuf<int2> SV;
+    DBuf<int> SSEG, STET, FAX;
+    DBuf<unsigned> SFL;
+    DBuf<unsigned long long> mark;
+    DBuf<int> owner;
+    // candidates
+    DBuf<int> cand_out;   // classification output (one slot per element)
+    DBuf<int> c_elem0, c_st0, c_reason0, order0, order1;
+    DBuf<unsigned long long> c_key0, skey;
+    DBuf<int4> c_tup0;
+    DBuf<double4> c_p0;
+    DBuf<int> c_elem, c_st, c_reason, c_seed, gst, greason, reg_off, reg_n, bf_off, bf_n, be_off, be_n,
+        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist;
+    DBuf<unsigned long long> c_key;
+    DBuf<int4> c_tup;
+    DBuf<double4> c_p;
+    DBuf<int2> c_qw;
+    // pools
+    DBuf<int> p_reg, p_bf, p_cl, p_clc;
+    DBuf<int4> p_be, p_bfr;
+    DBuf<int2> p_q;
+    DBuf<int> ctr;     // pool counters [0..5], ncand [8], undecided [9], totals [10..12], err [13],
+                       // dead [14], stats [16..31], olist count [32]
+    DBuf<char> tmp;    // hipcub scratch
+    DBuf<char> slab;   // overflow grow tiles
+    Cands C{};
+    Pools PL{};
+    BfPool BP{};
+    unsigned pass = 1;
+    int64_t dead = 0;
+
+    explicit Engine(hipStream_t st) : s(st) {}
+    ~Engine() {
+        DBuf<char>* bufs_c[] = {&tmp, &slab};
+        for (auto* b : bufs_c) b->release(s);
+        X.release(s); TV.release(s); TA.release(s); TF.release(s); TS.release(s); TI.release(s);
+        SV.release(s); SSEG.release(s); STET.release(s); FAX.release(s); SFL.release(s);
+        mark.release(s); owner.release(s);
+        for (auto* b : {&cand_out, &c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
+                        &c_seed, &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off,
+                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &p_reg,
+                        &p_bf, &p_cl, &p_clc, &ctr})
+            b->release(s);
+        c_key0.release(s); skey.release(s); c_key.release(s);
+        c_tup0.release(s); c_tup.release(s); c_p0.release(s); c_p.release(s); c_qw.release(s);
+        p_be.release(s); p_bfr.release(s); p_q.release(s);
+        (void)hipStreamSynchronize(s);
+    }
+
+    void bind() {
+        M.X = X.p; M.TV = TV.p; M.TA = TA.p; M.TF = TF.p; M.TS = TS.p; M.TI = TI.p;
+        M.SV = SV.p; M.SSEG = SSEG.p; M.SFL = SFL.p; M.STET = STET.p; M.FAX = FAX.p;
+    }
+    void ensure_mesh(int nv, int nt, int nss) {
+        X.ensure(nv, s, true);
+        TV.ensure(4 * (size_t)nt, s, true);
+        TA.ensure(4 * (size_t)nt, s, true);
+        TF.ensure(4 * (size_t)nt, s, true, 0xFF);
+        TS.ensure(6 * (size_t)nt, s, true, 0xFF);
+        TI.ensure(nt, s, true, 0);
+        mark.ensure(nt, s, true, 0);
+        owner.ensure(nt, s, true, 0xFF);
+        SV.ensure(std::max(nss, 1), s, true);
+        SSEG.ensure(std::max(nss, 1), s, true);
+        SFL.ensure(std::max(nss, 1), s, true, 0);
+        STET.ensure(std::max(nss, 1), s, true);
+        bind();
+    }
+    void ensure_cands(int n) {
+        size_t m = std::max(n, 1);
+        for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
+                        &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
+                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist})
+            b->ensure(m, s, false);
+        c_key0.ensure(m, s, false); skey.ensure(m, s, false); c_key.ensure(m, s, false);
+        c_tup0.ensure(m, s, false); c_tup.ensure(m, s, false);
+        c_p0.ensure(m, s, false); c_p.ensure(m, s, false); c_qw.ensure(m, s, false);
+        C.n = n;
+        C.elem = c_elem.p; C.key = c_key.p; C.tup = c_tup.p; C.p = c_p.p; C.st = c_st.p; C.reason = c_reason.p;
+        C.seed = c_seed.p; C.qw = c_qw.p; C.gst = gst.p; C.greason = greason.p;
+        C.reg_off = reg_off.p; C.reg_n = reg_n.p; C.bf_off = bf_off.p; C.bf_n = bf_n.p;
+        C.be_off = be_off.p; C.be_n = be_n.p; C.cl_off = cl_off.p; C.cl_n = cl_n.p;
+        C.q_off = q_off.p; C.q_n = q_n.p; C.state = state.p;
+    }
+    void ensure_pools(size_t reg, size_t bf, size_t be, size_t cl, size_t q, bool keep) {
+        p_reg.ensure(reg, s, keep); p_bf.ensure(bf, s, keep); p_bfr.ensure(3 * bf, s, keep);
+        p_be.ensure(be, s, keep); p_cl.ensure(cl, s, keep); p_clc.ensure(cl, s, keep); p_q.ensure(q, s, keep);
+        PL.reg = p_reg.p; PL.bf = p_bf.p; PL.be = p_be.p; PL.cl = p_cl.p; PL.clc = p_clc.p; PL.q = p_q.p;
+        PL.cap_reg = (int)p_reg.cap; PL.cap_bf = (int)p_bf.cap; PL.cap_be = (int)p_be.cap;
+        PL.cap_cl = (int)p_cl.cap; PL.cap_q = (int)p_q.cap; PL.ctr = ctr.p;
+        BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / 3);
+    }
+    void* scratch(size_t bytes) {
+        tmp.ensure(bytes, s, false);
+        return tmp.p;
+    }
+    template <class K, class V>
+    void sort_desc(const K* kin, K* kout, const V* vin, V* vout, int n) {
+        size_t bytes = 0;
+        HIPCK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, kin, kout, vin, vout, n, 0,
+                                                           (int)(8 * sizeof(K)), s));
+        void* t = scratch(bytes);
+        HIPCK(hipcub::DeviceRadixSort::SortPairsDescending(t, bytes, kin, kout, vin, vout, n, 0,
+                                                           (int)(8 * sizeof(K)), s));
+    }
+    template <class K, class V>
+    void sort_asc(const K* kin, K* kout, const V* vin, V* vout, int n) {
+        size_t bytes = 0;
+        HIPCK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, n, 0, (int)(8 * sizeof(K)), s));
+        void* t = scratch(bytes);
+        HIPCK(hipcub::DeviceRadixSort::SortPairs(t, bytes, kin, kout, vin, vout, n, 0, (int)(8 * sizeof(K)), s));
+    }
+    void exscan(const int* in, int* out, int n) {
+        size_t bytes = 0;
+        HIPCK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n, s));
+        void* t = scratch(bytes);
+        HIPCK(hipcub::DeviceScan::ExclusiveSum(t, bytes, in, out, n, s));
+    }
+};
+
+}  // namespace qm
+
+using namespace qm;
+
+static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
+                      qm_result** out) {
+    auto T0 = std::chrono::steady_clock::now();
+    if (!plc || !in || !opt || !out) throw QmError(QM_EINVAL, "null argument");
+    if (!(opt->B > 0.0) || !(opt->hmin_factor >= 0.0) || opt->max_rounds < 0)
+        throw QmError(QM_EINVAL, "B must be > 0, hmin_factor >= 0, max_rounds >= 0");
+    if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
+        throw QmError(QM_EINVAL, "bad counts");
+    if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
+    const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
+    Engine E(s);
+    const int nv = in->nv, nt = in->nt, nsf = in->nsf, nss = in->nss, nftri = plc->nftri;
+    int nfacet = 0;
+    // staging of the input arrays on the device
+    auto stage = [&](const void* p, size_t bytes, DBuf<char>& buf) -> const void* {
+        if (dev || bytes == 0) return p;
+        buf.ensure(bytes, s, false);
+        HIPCK(hipMemcpyAsync(buf.p, p, bytes, hipMemcpyHostToDevice, s));
+        return buf.p;
+    };
+    DBuf<char> b_xyz, b_tet, b_sf, b_sff, b_ss, b_ssg, b_ft, b_ftf;
+    const double* d_xyz = (const double*)stage(in->xyz, sizeof(double) * 3 * nv, b_xyz);
+    const int* d_tet = (const int*)stage(in->tet, sizeof(int) * 4 * (size_t)nt, b_tet);
+    const int* d_sf = (const int*)stage(in->sf, sizeof(int) * 3 * (size_t)nsf, b_sf);
+    const int* d_sff = (const int*)stage(in->sf_facet, sizeof(int) * (size_t)nsf, b_sff);
+    const int* d_ss = (const int*)stage(in->ss, sizeof(int) * 2 * (size_t)nss, b_ss);
+    const int* d_ssg = (const int*)stage(in->ss_seg, sizeof(int) * (size_t)nss, b_ssg);
+    const int* d_ft = (const int*)stage(plc->ftri, sizeof(int) * 3 * (size_t)nftri, b_ft);
+    const int* d_ftf = (const int*)stage(plc->ftri_facet, sizeof(int) * (size_t)nftri, b_ftf);
+    // number of facets = 1 + max facet id over PLC triangles and subfaces
+    {
+        std::vector<int> h(std::max(nftri, nsf));
+        auto maxid = [&](const int* user, int n) {
+            if (n == 0) return -1;
+            if (dev) {
+                HIPCK(hipMemcpyAsync(h.data(), user, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+                HIPCK(hipStreamSynchronize(s));
+            } else std::memcpy(h.data(), user, sizeof(int) * n);
+            return *std::max_element(h.begin(), h.begin() + n);
+        };
+        nfacet = std::max(maxid(plc->ftri_facet, nftri), maxid(in->sf_facet, nsf)) + 1;
+    }
+    E.ctr.ensure(64, s, false, 0);
+    E.ensure_mesh(nv, nt, std::max(nss, 1));
+    E.FAX.ensure(std::max(nfacet, 1), s, false);
+    E.bind();
+    E.M.nv = nv; E.M.nt = nt; E.M.nss = nss;
+    int* err = E.ctr.p + 13;
+    auto T1 = std::chrono::steady_clock::now();
+    hipEvent_t e0, e1, e2;
+    HIPCK(hipEventCreate(&e0)); HIPCK(hipEventCreate(&e1)); HIPCK(hipEventCreate(&e2));
+    HIPCK(hipEventRecord(e0, s));
+    // ---- device setup
+    k_setup_verts<<<nblk(nv), 256, 0, s>>>(nv, d_xyz, E.X.p, err);
+    k_setup_tets<<<nblk(nt), 256, 0, s>>>(nt, nv, d_tet, E.M, err);
+    {
+        DBuf<unsigned long long> k0, k1;
+        DBuf<int> v0, v1;
+        size_t n4 = 4 * (size_t)nt, n6 = 6 * (size_t)nt;
+        k0.ensure(n6, s, false); k1.ensure(n6, s, false); v0.ensure(n6, s, false); v1.ensure(n6, s, false);
+        k_face_keys<<<nblk(n4), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
+        E.sort_asc(k0.p, k1.p, v0.p, v1.p, (int)n4);
+        k_face_match<<<nblk(n4), 256, 0, s>>>((int)n4, k1.p, v1.p, E.TA.p, err);
+        if (nsf) k_mark_subfaces<<<nblk(nsf), 256, 0, s>>>(nsf, nv, nfacet, d_sf, d_sff, k1.p, v1.p, (int)n4, E.TF.p, err);
+        k_edge_keys<<<nblk(n6), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
+        E.sort_asc(k0.p, k1.p, v0.p, v1.p, (int)n6);
+        if (nss) k_mark_subsegs<<<nblk(nss), 256, 0, s>>>(nss, nv, d_ss, d_ssg, k1.p, v1.p, (int)n6, E.M, err);
+        DBuf<int> first;
+        first.ensure(std::max(nfacet, 1), s, false);
+        k_fill<<<nblk(nfacet), 256, 0, s>>>(nfacet, first.p, 0x7fffffff);   // "no triangle yet"
+        if (nftri) k_facet_first<<<nblk(nftri), 256, 0, s>>>(nftri, d_ftf, nfacet, first.p, err);
+        k_facet_axis<<<nblk(nfacet), 256, 0, s>>>(nfacet, first.p, d_ft, E.X.p, nv, E.FAX.p, err);
+        unsigned long long* dmin = (unsigned long long*)(E.ctr.p + 40);
+        HIPCK(hipMemsetAsync(dmin, 0x7F, sizeof(unsigned long long), s));
+        k_min_edge<<<nblk(nt), 256, 0, s>>>(nt, E.M, dmin);
+        HIPCK(hipStreamSynchronize(s));
+        k0.release(s); k1.release(s); v0.release(s); v1.release(s); first.release(s);
+        int e = read1(err, s);
+        if (e & 1) throw QmError(QM_EINVAL, "ids out of range or coordinates off the 2^-53 lattice / outside [0,1]");
+        if (e & 2) throw QmError(QM_ENONCONFORM, "a tet is not positively oriented");
+        if (e & 4) throw QmError(QM_ENONCONFORM, "a face is shared by more than two tets");
+        if (e & 8) throw QmError(QM_ENONCONFORM, "a subface is not a face of the mesh");
+        if (e & 16) throw QmError(QM_ENONCONFORM, "a subsegment is not an edge of the mesh");
+        unsigned long long bits = read1(dmin, s);
+        double l2;
+        std::memcpy(&l2, &bits, sizeof l2);
+        E.M.hmin2 = (opt->hmin_factor * opt->hmin_factor) * l2;
+        E.M.B2 = opt->B * opt->B;
+    }
+    HIPCK(hipEventRecord(e1, s));
+    // ---- rounds
+    qm_result* R = new qm_result();
+    std::memset(&R->stats, 0, sizeof R->stats);
+    int* ncand_d = E.ctr.p + 8;
+    int* undec_d = E.ctr.p + 9;
+    int* tot_d = E.ctr.p + 10;
+    int* dead_d = E.ctr.p + 14;
+    int* stats_d = E.ctr.p + 16;
+    int* olist_n = E.ctr.p + 32;
+    int round = 0, status = 0;
+    GrowTiles BT{};
+    BT.maxrt = B_MAXRT; BT.hcap = B_HCAP; BT.rfhcap = B_RFHCAP; BT.maxrf = B_MAXRF; BT.maxbe = B_MAXBE;
+    BT.qhcap = B_QHCAP; BT.maxq = B_MAXQ; BT.maxbf = B_MAXBF; BT.maxcx = B_MAXBF;
+    const size_t slab_block = grow_slab_bytes(BT);
+    for (;; ++round) {
+        if (round >= opt->max_rounds) { status = 1; break; }
+        int cls = CLS_NONE, ncand = 0;
+        // step 1: classify, in the paper's order
+        for (int c = CLS_SS; c <= CLS_TET; ++c) {
+            int cap = c == CLS_SS ? E.M.nss : (c == CLS_SF ? 4 * E.M.nt : E.M.nt);
+            if (cap == 0) continue;
+            E.cand_out.ensure(cap, s, false);
+            HIPCK(hipMemsetAsync(ncand_d, 0, sizeof(int), s));
+            if (c == CLS_SS) k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
+            else if (c == CLS_SF) k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
+            else k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
+            ncand = read1(ncand_d, s);
+            if (ncand > 0) { cls = c; break; }
+        }
+        if (cls == CLS_NONE) break;
+        E.ensure_cands(ncand);
+        // step 2: splitting points and priorities, then priority order
+        HIPCK(hipMemcpyAsync(E.c_elem0.p, E.cand_out.p, sizeof(int) * ncand, hipMemcpyDeviceToDevice, s));
+        k_split<<<nblk(ncand), 256, 0, s>>>(E.M, cls, ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
+                                          E.c_st0.p, E.c_reason0.p);
+        k_iota<<<nblk(ncand), 256, 0, s>>>(ncand, E.order0.p);
+        E.sort_desc(E.c_key0.p, E.skey.p, E.order0.p, E.order1.p, ncand);
+        k_fix_ties<<<nblk(ncand), 256, 0, s>>>(ncand, E.skey.p, E.order1.p, E.c_tup0.p);
+        k_permute<<<nblk(ncand), 256, 0, s>>>(ncand, E.order1.p, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
+                                            E.c_st0.p, E.c_reason0.p, E.C);
+        // step 3: locate
+        if (cls != CLS_SS) k_locate<<<nblk(ncand, 64), 64, 0, s>>>(E.M, cls, E.C);
+        // steps 4-5: grow and validate
+        HIPCK(hipMemsetAsync(E.ctr.p, 0, 8 * sizeof(int), s));
+        E.ensure_pools((size_t)ncand * 24 + 4096, (size_t)ncand * 48 + 4096, (size_t)ncand * 4 + 4096,
+                       (size_t)ncand * 56 + 4096, (size_t)ncand * 2 + 4096, false);
+        {
+            int grid = std::min(ncand, 16384);
+            k_grow_lds<G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF>
+                <<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP);
+        }
+        for (int attempt = 0;; ++attempt) {
+            HIPCK(hipMemsetAsync(olist_n, 0, sizeof(int), s));
+            k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, olist_n);
+            int nover = read1(olist_n, s);
+            if (nover == 0) break;
+            if (attempt >= 4) throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size");
+            int full = read1(E.ctr.p + 5, s);
+            if (full) {
+                int used[5];
+                HIPCK(hipMemcpyAsync(used, E.ctr.p, sizeof used, hipMemcpyDeviceToHost, s));
+                HIPCK(hipStreamSynchronize(s));
+                E.ensure_pools(2 * (size_t)used[0] + (size_t)nover * B_MAXRT, 2 * (size_t)used[1] + (size_t)nover * B_MAXBF,
+                               2 * (size_t)used[2] + (size_t)nover * B_MAXBE, 2 * (size_t)used[3] + (size_t)nover * 2 * B_MAXRT,
+                               2 * (size_t)used[4] + (size_t)nover * B_MAXQ, true);
+                HIPCK(hipMemsetAsync(E.ctr.p + 5, 0, sizeof(int), s));
+            }
+            // sort the overflow list so the slab path visits candidates in order
+            int grid = std::min(nover, 64);
+            E.slab.ensure(slab_block * grid, s, false);
+            k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, E.olist.p, nover, BT, E.slab.p, slab_block);
+        }
+        // flags of rejected / exempted candidates
+        k_apply_flags<<<nblk(ncand), 256, 0, s>>>(E.M, cls, E.C, E.PL);
+        HIPCK(hipMemsetAsync(stats_d, 0, 16 * sizeof(int), s));
+        k_round_stats<<<nblk(ncand), 256, 0, s>>>(E.C, stats_d);
+        // step 6: maximal set of disjoint claim sets, greedy by priority
+        k_mis_init<<<nblk(ncand), 256, 0, s>>>(E.C);
+        int ncl = read1(E.ctr.p + 3, s);
+        int passes = 0;
+        if (ncl > 0) {
+            for (;;) {
+                ++passes;
+                unsigned ps = E.pass++;
+                HIPCK(hipMemsetAsync(undec_d, 0, sizeof(int), s));
+                k_mis_mark<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps);
+                k_mis_decide<<<nblk(ncand), 256, 0, s>>>(E.C, E.p_cl.p, E.mark.p, E.owner.p, ps, undec_d);
+                k_mis_commit<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p);
+                if (read1(undec_d, s) == 0) break;
+            }
+        }
+        // step 7: ids, slots and insertion
+        k_scan_vals<<<nblk(ncand), 256, 0, s>>>(E.C, cls, E.vk.p, E.vt.p, E.vs.p);
+        E.exscan(E.vk.p, E.sk.p, ncand);
+        if (opt->max_kept > 0) {
+            k_cap_kept<<<nblk(ncand), 256, 0, s>>>(E.C, E.sk.p, opt->max_kept);
+            k_scan_vals<<<nblk(ncand), 256, 0, s>>>(E.C, cls, E.vk.p, E.vt.p, E.vs.p);
+            E.exscan(E.vk.p, E.sk.p, ncand);
+        }
+        E.exscan(E.vt.p, E.st_.p, ncand);
+        E.exscan(E.vs.p, E.ss_.p, ncand);
+        k_totals<<<1, 1, 0, s>>>(ncand, E.sk.p, E.vk.p, E.st_.p, E.vt.p, E.ss_.p, E.vs.p, tot_d);
+        int tot[3];
+        HIPCK(hipMemcpyAsync(tot, tot_d, sizeof tot, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        const int nkept = tot[0], newt = tot[1], newss = tot[2];
+        if (nkept > 0) {
+            E.ensure_mesh(E.M.nv + nkept, E.M.nt + newt, E.M.nss + newss);
+            k_kept_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.sk.p, E.kept.p);
+            int grid = std::min(nkept, 16384);
+            k_insert<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, E.kept.p, nkept, E.sk.p, E.st_.p, E.ss_.p,
+                                         E.M.nv, E.M.nt, E.M.nss, dead_d);
+            k_mis_release<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p);
+            E.M.nv += nkept; E.M.nt += newt; E.M.nss += newss;
+        }
+        // dead slots: regions larger than their new tets
+        int st[16];
+        HIPCK(hipMemcpyAsync(st, stats_d, sizeof st, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        if (st[12]) throw QmError(QM_EINTERNAL, "candidate left unresolved");
+        int rec[QM_ROUND_FIELDS] = {cls, st[0], st[1], st[2], st[3], nkept};
+        for (int r = 1; r < EX_NREASON; ++r) rec[5 + r] = st[3 + r];
+        rec[14] = E.M.nv;
+        E.dead = read1(dead_d, s);
+        rec[15] = E.M.nt - (int)E.dead;
+        R->rounds.insert(R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
+        R->stats.inserted[cls] += nkept;
+        R->stats.candidates += ncand;
+        R->stats.mis_passes += passes;
+    }
+    HIPCK(hipEventRecord(e2, s));
+    int gerr = 0;
+    HIPCK(hipMemcpyFromSymbolAsync(&gerr, HIP_SYMBOL(g_geom_error), sizeof(int), 0, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (gerr) throw QmError(QM_EINTERNAL, "exact predicate precondition failed (code " + std::to_string(gerr) + ")");
+    // ---- output
+    {
+        int ntot = E.M.nt;
+        DBuf<int> tf, ts, ff, fs;
+        tf.ensure(ntot, s, false); ts.ensure(ntot, s, false);
+        ff.ensure(4 * (size_t)ntot, s, false); fs.ensure(4 * (size_t)ntot, s, false);
+        k_out_flags<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ff.p);
+        E.exscan(tf.p, ts.p, ntot);
+        E.exscan(ff.p, fs.p, 4 * ntot);
+        int a = read1(ts.p + ntot - 1, s) + read1(tf.p + ntot - 1, s);
+        int b = read1(fs.p + 4 * ntot - 1, s) + read1(ff.p + 4 * ntot - 1, s);
+        DBuf<int> ot, osf, osff;
+        DBuf<double> ox;
+        ot.ensure(4 * (size_t)std::max(a, 1), s, false);
+        osf.ensure(3 * (size_t)std::max(b, 1), s, false);
+        osff.ensure(std::max(b, 1), s, false);
+        ox.ensure(3 * (size_t)E.M.nv, s, false);
+        k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, ot.p);
+        k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, osf.p, osff.p);
+        k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, ox.p);
+        R->xyz.resize(3 * (size_t)E.M.nv);
+        R->tets.resize(4 * (size_t)a);
+        R->sf.resize(3 * (size_t)b);
+        R->sff.resize(b);
+        R->ss.resize(2 * (size_t)E.M.nss);
+        R->ssg.resize(E.M.nss);
+        HIPCK(hipMemcpyAsync(R->xyz.data(), ox.p, sizeof(double) * R->xyz.size(), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(R->tets.data(), ot.p, sizeof(int) * R->tets.size(), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(R->sf.data(), osf.p, sizeof(int) * R->sf.size(), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(R->sff.data(), osff.p, sizeof(int) * R->sff.size(), hipMemcpyDeviceToHost, s));
+        if (E.M.nss) {
+            HIPCK(hipMemcpyAsync(R->ss.data(), E.SV.p, sizeof(int) * R->ss.size(), hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(R->ssg.data(), E.SSEG.p, sizeof(int) * R->ssg.size(), hipMemcpyDeviceToHost, s));
+        }
+        HIPCK(hipStreamSynchronize(s));
+        tf.release(s); ts.release(s); ff.release(s); fs.release(s); ot.release(s); osf.release(s);
+        osff.release(s); ox.release(s);
+        R->stats.nt_out = a;
+    }
+    float ms_setup = 0, ms_ref = 0;
+    HIPCK(hipEventElapsedTime(&ms_setup, e0, e1));
+    HIPCK(hipEventElapsedTime(&ms_ref, e1, e2));
+    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
+    R->stats.rounds = round;
+    R->stats.status = status;
+    R->stats.nv_out = E.M.nv;
+    R->stats.seconds_setup = ms_setup * 1e-3;
+    R->stats.seconds_refine = ms_ref * 1e-3;
+    R->stats.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - T0).count();
+    (void)T1;
+    *out = R;
+    return status == 1 ? QM_EROUNDS : QM_OK;
+}
+
+extern "C" {
+
+int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream, qm_result** out) {
+    g_err.clear();
+    try {
+        return run_refine(plc, in, opt, (hipStream_t)hip_stream, out);
+    } catch (const QmError& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return QM_EINTERNAL;
+    } catch (...) {
+        g_err = "unknown failure";
+        return QM_EINTERNAL;
+    }
+}
+
+int qm_result_view(const qm_result* r, qm_mesh* v, qm_stats* st) {
+    if (!r) { g_err = "null result"; return QM_EINVAL; }
+    if (v) {
+        v->nv = (int32_t)(r->xyz.size() / 3); v->xyz = r->xyz.data();
+        v->nt = (int32_t)(r->tets.size() / 4); v->tet = r->tets.data();
+        v->nsf = (int32_t)r->sff.size(); v->sf = r->sf.data(); v->sf_facet = r->sff.data();
+        v->nss = (int32_t)r->ssg.size(); v->ss = r->ss.data(); v->ss_seg = r->ssg.data();
+    }
+    if (st) *st = r->stats;
+    return QM_OK;
+}
+
+int qm_result_rounds(const qm_result* r, int32_t* buf, int32_t cap) {
+    if (!r) { g_err = "null result"; return QM_EINVAL; }
+    int n = (int)(r->rounds.size() / QM_ROUND_FIELDS);
+    if (buf) std::memcpy(buf, r->rounds.data(), sizeof(int32_t) * QM_ROUND_FIELDS * (size_t)std::min(n, (int)cap));
+    return n;
+}
+
+void qm_result_free(qm_result* r) { delete r; }
+
+const char* qm_last_error(void) { return g_err.c_str(); }
+
+const char* qm_version(void) { return "qm 0.1 (gfx950)"; }
+
+}  // extern "C"

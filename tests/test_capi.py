@@ -1,0 +1,42 @@
+"""The C-ABI library loads and exports every entry point include/qm.h
+declares (no compute call: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1903_03406_amd as qm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "qm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    assert {"qm_refine", "qm_result_view", "qm_result_rounds", "qm_result_free", "qm_last_error"} <= set(names)
+    assert set(names) == set(qm.EXPORTS)
+
+
+@pytest.mark.skipif(not os.path.exists(qm._SO), reason="libqm.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(qm._SO)
+    for name in declared():
+        assert hasattr(lib, name), name
+    lib.qm_version.restype = ctypes.c_char_p
+    assert b"gfx950" in lib.qm_version()
+    lib.qm_last_error.restype = ctypes.c_char_p
+    assert lib.qm_last_error() == b""
+
+
+def test_binding_has_no_cpu_path(monkeypatch, tmp_path):
+    """Without the built library the binding fails loudly (no fallback)."""
+    monkeypatch.setattr(qm, "_SO", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(qm, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        qm.refine([[0, 0, 0]] * 8, [[0, 1, 2, 3]], [], [], [], [], [], [], B=2.0)
