@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Benchmark of the refinement loop on one MI355X.
+
+A step is one complete refinement (every round of the hot path) of the
+workload, with the input CDT already resident in HBM when timing starts.
+Prints one JSON line:
+
+  value        Steiner points inserted per second (whole call, wall clock)
+  tets_per_s   output tetrahedra per second
+  roofline     the dominant kernel family's algorithmic bytes / its event-timed
+               device time against the 8 TB/s HBM peak
+  cpu_baseline the oracle timed on a bounded sample of the same workload
+
+Default workload: corners + 900 000 points from 8 Gaussians + 100 000
+uniform points, three nested sphere surfaces, B = 1.4.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def grow_bytes(p):
+    """Algorithmic bytes of the grow/validate kernel: each tested tet costs its
+    vertex ids (16 B) and one new vertex (32 B: it is reached across a face
+    whose three vertices are already loaded); each region tet also its
+    neighbour, facet and subsegment words (56 B) and its region and claim
+    entries (8 B); each boundary face its record (52 B); each extra claim 8 B."""
+    return (48 * p["tested"] + 64 * p["region"] + 52 * p["bfaces"]
+            + 8 * max(p["claims"] - p["region"], 0))
+
+
+def classify_bytes(p):
+    """Tet classification scans: vertex ids + info word per tet (20 B) and
+    each vertex's coordinates once (32 B)."""
+    return 20 * p["scan_tets"] + 32 * p["scan_verts"]
+
+
+def make_workload(name):
+    import qm_inputs as qi
+    if name == "cfg3":
+        return qi.config(3)
+    if name == "cfg2":
+        return qi.config(2)
+    if name == "cfg1":
+        return qi.config(1)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, target_s):
+    """Oracle (as it stands) on the first R rounds of the workload, R doubled
+    until the oracle's own round loop runs for at least target_s seconds."""
+    import oracle
+    r, res = 1, None
+    while True:
+        res = oracle.refine(w, max_rounds=r)
+        if res.seconds >= target_s or res.status == 0 or r >= 4096:
+            break
+        r *= 2
+    steiner = len(res.xyz) - len(w.xyz)
+    return {"value": steiner / res.seconds if res.seconds > 0 else 0.0, "unit": "Steiner pts/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"first {res.rounds} rounds of the same workload ({steiner} Steiner points, "
+                      f"{res.seconds:.1f} s of oracle round loop, setup excluded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the refinement of one instance runs on a single "
+              "MI355X (no multi-GPU path in this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1903_03406_amd as qm
+
+    t0 = time.time()
+    w = make_workload(args.workload)
+    print(f"[bench] workload {w.name}: {len(w.xyz)} vertices, {len(w.tets)} tets, "
+          f"{len(w.ftri)} PLC triangles, input built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    names = ("xyz", "tets", "sf", "sf_facet", "ss", "ss_seg", "ftri", "ftri_facet")
+    d = {k: torch.from_numpy(np.ascontiguousarray(getattr(w, k))).to(dev) for k in names}
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step(profile=False):
+        return qm.refine(d["xyz"], d["tets"], d["sf"], d["sf_facet"], d["ss"], d["ss_seg"], d["ftri"],
+                         d["ftri_facet"], w.B, stream=stream, profile=profile)
+
+    for i in range(args.warmup):
+        r = step()
+        print(f"[bench] warmup {i}: {r.rounds} rounds, {r.steiner} Steiner, {len(r.tets)} tets, "
+              f"{r.seconds_total:.2f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        results.append(step(profile=True))
+        print(f"[bench] step {i}: {results[-1].seconds_total:.2f}s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    r = results[-1]
+    sec = (t2 - t1) / args.steps
+    steiner = r.steiner
+    prof = r.profile
+    fam = max(("grow_validate", "classify"), key=lambda k: prof["ms"][k])
+    nbytes = grow_bytes(prof) if fam == "grow_validate" else classify_bytes(prof)
+    kms = prof["ms"][fam]
+    achieved = nbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
+    dominant = max(prof["ms"], key=lambda k: prof["ms"][k])
+    out = {
+        "metric": "Steiner pts/sec (1M-pt PLC refinement)",
+        "value": steiner / sec,
+        "unit": "Steiner pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "input_vertices": int(len(w.xyz)), "input_tets": int(len(w.tets)),
+                   "plc_triangles": int(len(w.ftri)), "segments": int(len(w.seg)), "B": w.B,
+                   "parallelism": "single instance, one GPU"},
+        "tets_per_s": len(r.tets) / sec,
+        "output": {"vertices": int(len(r.xyz)), "tets": int(len(r.tets)), "steiner": steiner,
+                   "rounds": r.rounds, "device_refine_s": r.seconds_refine, "device_setup_s": r.seconds_setup},
+        "profile_ms": {k: round(v, 3) for k, v in prof["ms"].items()},
+        "roofline": {"kernel": "k_grow_lds" if fam == "grow_validate" else "k_classify_tet",
+                     "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "launches": prof["launches"][fam], "kernel_ms": kms,
+                     "algorithmic_bytes": nbytes, "dominant_family": dominant},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

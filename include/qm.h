@@ -68,6 +68,8 @@ typedef struct qm_mesh {
 } qm_mesh;
 
 #define QM_INPUT_DEVICE 1u   /* mesh/PLC arrays are device pointers (same device) */
+#define QM_PROFILE 2u        /* time each kernel family with HIP events on the call's
+                                stream and count the region work (qm_stats.prof_*) */
 
 typedef struct qm_options {
     double B;                /* radius-edge bound (> 0) */
@@ -94,6 +96,16 @@ typedef struct qm_stats {
     double seconds_setup;    /* device-side setup from the input arrays */
     double seconds_refine;   /* round loop (device resident) */
     double seconds_total;    /* whole call incl. transfers */
+    /* QM_PROFILE only: device milliseconds and launches per kernel family
+       0 classify, 1 split+order, 2 locate, 3 grow+validate, 4 flags+stats,
+       5 selection, 6 scans, 7 insert */
+    double prof_ms[8];
+    int64_t prof_launches[8];
+    /* QM_PROFILE only: region work of the grow kernel: tets tested, region
+       tets, boundary faces, claimed tets (accepted candidates) */
+    int64_t prof_tested, prof_region, prof_bfaces, prof_claims;
+    /* QM_PROFILE only: tets and vertices scanned by the tet classification */
+    int64_t prof_scan_tets, prof_scan_verts;
 } qm_stats;
 
 typedef struct qm_result qm_result;
@@ -111,6 +123,13 @@ int qm_result_view(const qm_result* r, qm_mesh* view, qm_stats* stats);
 /* Copy at most `cap` rounds of per-round records (QM_ROUND_FIELDS each) into
    buf; returns the number of rounds available. */
 int qm_result_rounds(const qm_result* r, int32_t* buf, int32_t cap);
+
+/* Verdicts of the last round's candidates in priority order, 9 int32 each:
+   sorted vertex ids (4, -1 padded), status (0 accepted, 1 rejected,
+   2 exempted), exemption reason, inserted flag, region tets and boundary
+   faces (accepted candidates).  Copies at most `cap`; returns the count.
+   For inspecting one round of a run (max_rounds) against a reference. */
+int qm_result_last_round(const qm_result* r, int32_t* buf, int32_t cap);
 
 void qm_result_free(qm_result* r);
 

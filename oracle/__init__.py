@@ -78,6 +78,7 @@ class OracleResult:
     rounds: int
     status: int               # 0 done, 1 round guard reached
     seconds: float
+    last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
 
 
 def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0) -> OracleResult:
@@ -104,6 +105,12 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0) -> OracleR
                        float(lib.qmo_result_seconds(res)))
     lib.qmo_result_copy(res, _ptr(out.xyz), _ptr(out.tets), _ptr(out.sf), _ptr(out.sf_facet),
                         _ptr(out.ss), _ptr(out.ss_seg), _ptr(out.rstats))
+    lib.qmo_result_lastc.restype = ctypes.c_int
+    lib.qmo_result_lastc.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    nl = lib.qmo_result_lastc(res, None)
+    out.last_cands = np.zeros((nl, 9), dtype=np.int32)
+    if nl:
+        lib.qmo_result_lastc(res, _ptr(out.last_cands))
     lib.qmo_result_free(res)
     return out
 

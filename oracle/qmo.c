@@ -737,6 +737,7 @@ static int insert_point(Mesh* M, Cand* c, int pid) {
    exempt by reason [1..8] in slots 6..13, vertices after, tets after */
 
 typedef struct qmo_result {
+    int* lastc; int nlastc;       /* last round: 9 ints per candidate */
     int nv, nt, nsf, nss, rounds, status;
     double* xyz; int* tets; int* sf; int* sf_facet; int* ss; int* ss_seg;
     int* rstats; int nrstats;
@@ -887,6 +888,16 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
         rs[14] = M->nv;
         int live = 0; for (int t = 0; t < M->nt; ++t) live += M->T[t].alive;
         rs[15] = live;
+        free(R->lastc);
+        R->lastc = (int*)malloc(sizeof(int) * 9 * (size_t)(L.n ? L.n : 1));
+        R->nlastc = L.n;
+        for (int i = 0; i < L.n; ++i) {
+            Cand* c = &L.c[i];
+            int* o = R->lastc + 9 * i;
+            for (int k = 0; k < 4; ++k) o[k] = k < c->ntup ? c->tup[k] : -1;
+            o[4] = c->status; o[5] = c->status == ST_EXEMPT ? c->reason : 0; o[6] = c->kept;
+            o[7] = c->status == ST_OK ? c->RT.n : 0; o[8] = c->status == ST_OK ? c->bface.n : 0;
+        }
         for (int i = 0; i < L.n; ++i) cand_free(&L.c[i]);
         L.n = 0;
         round++;
@@ -934,8 +945,13 @@ void qmo_result_copy(const qmo_result* R, double* xyz, int* tets, int* sf, int* 
     memcpy(ss_seg, R->ss_seg, sizeof(int) * (size_t)R->nss);
     memcpy(rstats, R->rstats, sizeof(int) * QMO_NSTAT * (size_t)R->nrstats);
 }
+int qmo_result_lastc(const qmo_result* R, int* buf) {
+    if (buf) memcpy(buf, R->lastc, sizeof(int) * 9 * (size_t)R->nlastc);
+    return R->nlastc;
+}
 void qmo_result_free(qmo_result* R) {
     if (!R) return;
+    free(R->lastc);
     free(R->xyz); free(R->tets); free(R->sf); free(R->sf_facet); free(R->ss); free(R->ss_seg); free(R->rstats);
     free(R);
 }

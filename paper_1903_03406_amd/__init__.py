@@ -26,6 +26,9 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 QM_INPUT_DEVICE = 1
+QM_PROFILE = 2
+PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
+                 "scans", "insert")
 ROUND_FIELDS = 16
 ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
@@ -64,7 +67,11 @@ class _Stats(ctypes.Structure):
                 ("inserted", ctypes.c_int64 * 3), ("candidates", ctypes.c_int64),
                 ("mis_passes", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
                 ("seconds_setup", ctypes.c_double), ("seconds_refine", ctypes.c_double),
-                ("seconds_total", ctypes.c_double)]
+                ("seconds_total", ctypes.c_double), ("prof_ms", ctypes.c_double * 8),
+                ("prof_launches", ctypes.c_int64 * 8), ("prof_tested", ctypes.c_int64),
+                ("prof_region", ctypes.c_int64), ("prof_bfaces", ctypes.c_int64),
+                ("prof_claims", ctypes.c_int64), ("prof_scan_tets", ctypes.c_int64),
+                ("prof_scan_verts", ctypes.c_int64)]
 
 
 def _load():
@@ -89,8 +96,8 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_result_view", "qm_result_rounds", "qm_result_free", "qm_last_error",
-           "qm_version")
+EXPORTS = ("qm_refine", "qm_result_view", "qm_result_rounds", "qm_result_last_round", "qm_result_free",
+           "qm_last_error", "qm_version")
 
 
 class QmError(RuntimeError):
@@ -116,6 +123,8 @@ class RefineResult:
     seconds_setup: float
     seconds_refine: float
     seconds_total: float
+    profile: dict = None        # QM_PROFILE: per-family ms/launches and region counters
+    last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
 
     @property
     def steiner(self) -> int:
@@ -127,7 +136,7 @@ def _arr(a, dtype):
 
 
 def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None, hmin_factor=0.5,
-           max_rounds=100000, max_kept=0, stream=None) -> RefineResult:
+           max_rounds=100000, max_kept=0, stream=None, profile=False) -> RefineResult:
     """Refine a CDT.  Arrays are numpy (host) or torch CUDA tensors (device);
     ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle."""
     lib = _load()
@@ -160,13 +169,14 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
     plc = _Plc(nv, nseg, pseg, nft, pft, pftf)
     mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
     opts = _Opts(float(B), float(hmin_factor), int(max_rounds), int(max_kept),
-                 QM_INPUT_DEVICE if dev else 0)
+                 (QM_INPUT_DEVICE if dev else 0) | (QM_PROFILE if profile else 0))
     if stream is None:
         hs = None
     elif hasattr(stream, "cuda_stream"):
         hs = stream.cuda_stream
     else:
         hs = int(stream)
+    P_ = ctypes.c_void_p
     res = ctypes.c_void_p()
     rc = lib.qm_refine(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), hs, ctypes.byref(res))
     if rc not in (0, -4):
@@ -183,6 +193,12 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
             a = np.frombuffer(buf, dtype=dtype).copy()
             return a.reshape(n, cols) if cols > 1 else a
 
+        lib.qm_result_last_round.restype = ctypes.c_int
+        lib.qm_result_last_round.argtypes = [P_, P_, ctypes.c_int32]
+        nl = lib.qm_result_last_round(res, None, 0)
+        last = np.zeros((max(nl, 0), 9), dtype=np.int32)
+        if nl:
+            lib.qm_result_last_round(res, last.ctypes.data, nl)
         nr = lib.qm_result_rounds(res, None, 0)
         rs = np.zeros((max(nr, 0), ROUND_FIELDS), dtype=np.int32)
         if nr:
@@ -192,7 +208,13 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
                             grab(view.ss, view.nss, 2, np.int32), grab(view.ss_seg, view.nss, 1, np.int32),
                             rs, int(st.rounds), int(st.status), tuple(int(x) for x in st.inserted),
                             int(st.candidates), int(st.mis_passes), float(st.seconds_setup),
-                            float(st.seconds_refine), float(st.seconds_total))
+                            float(st.seconds_refine), float(st.seconds_total),
+                            ({"ms": dict(zip(PROF_FAMILIES, list(st.prof_ms))),
+                              "launches": dict(zip(PROF_FAMILIES, [int(x) for x in st.prof_launches])),
+                              "tested": int(st.prof_tested), "region": int(st.prof_region),
+                              "bfaces": int(st.prof_bfaces), "claims": int(st.prof_claims),
+                              "scan_tets": int(st.prof_scan_tets), "scan_verts": int(st.prof_scan_verts)}
+                             if profile else None), last)
     finally:
         lib.qm_result_free(res)
 

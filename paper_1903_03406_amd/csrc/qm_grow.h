@@ -25,7 +25,7 @@ struct GrowTiles {
 // boundary-face record written for an accepted candidate (three int4 per face)
 //   r0 = (x, y, z, old neighbour)   r1 = (facet id, face flags, ss(x,y), ss(y,z))
 //   r2 = (ss(z,x), old tet<<2|face, 0, 0)
-struct BfPool { int4* r; int cap; };
+struct BfPool { int4* r; int cap; unsigned long long* prof; };   // prof: tested, region, bfaces, claims
 
 struct GrowShared {
     int nrt, nrf, nbf, nbe, nq, ncx, hcount;
@@ -200,8 +200,10 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     if (cls != CLS_TET) {
         int head = 0;
         while (true) {
-            int end = S.nrf;
-            if (head >= end || S.over) break;
+            const int end = S.nrf;
+            const bool stop = head >= end || S.over;
+            __syncthreads();              // every lane has read the level bounds
+            if (stop) break;
             int items = (end - head) * 3;
             for (int k = lane; k < items; k += 64) {
                 int h = W.rf[head + k / 3];
@@ -222,7 +224,6 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             }
             __syncthreads();
             head = end;
-            __syncthreads();
         }
         // tets on region subfaces are seeds too
         int nrf = S.nrf < W.maxrf ? S.nrf : W.maxrf;
@@ -240,8 +241,10 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     {
         int head = 0;
         while (true) {
-            int end = S.nrt;
-            if (head >= end || S.over) break;
+            const int end = S.nrt;
+            const bool stop = head >= end || S.over;
+            __syncthreads();              // every lane has read the level bounds
+            if (stop) break;
             int items = (end - head) * 4;
             for (int k = lane; k < items; k += 64) {
                 int t = W.rt[head + (k >> 2)], f = k & 3;
@@ -249,6 +252,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 if (nb < 0) continue;
                 if (M.TF[4 * (size_t)t + f] >= 0 && !in_rf(t, f)) continue;
                 int n = nb >> 2;
+                if (n >= M.nt) { atomicOr(&g_geom_error, 64); continue; }
                 unsigned key = (unsigned)n + 1u;
                 if (hget(W.H, W.hcap, key) != 0u) continue;
                 int4 v = ld4(M.TV, n);
@@ -269,7 +273,6 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             }
             __syncthreads();
             head = end;
-            __syncthreads();
         }
     }
     if (S.over) {
@@ -277,6 +280,10 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         return;
     }
     const int nrt = S.nrt, nrf = S.nrf;
+    if (lane == 0 && BP.prof) {
+        atomicAdd(&BP.prof[0], (unsigned long long)S.hcount);
+        atomicAdd(&BP.prof[1], (unsigned long long)nrt);
+    }
     auto in_rt = [&](int t) { return hget(W.H, W.hcap, (unsigned)t + 1u) == HS_IN; };
     auto fail = [&](int reason) { S.fail = 1; S.reason = reason; };   // one reason per phase
 
@@ -484,12 +491,24 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     if (S.over) { if (lane == 0) C.gst[cid] = ST_OVERFLOW; return; }
     const int ncx = S.ncx;
     if (lane == 0) {
+        // region, face and edge pools are only read through this candidate's
+        // offsets; the claim pool is scanned whole by the selection, so a
+        // claim range is reserved all-or-nothing and only when it will be filled
         int br = atomicAdd(&PL.ctr[0], nrt);
         int bb = atomicAdd(&PL.ctr[1], nbf);
         int be = atomicAdd(&PL.ctr[2], nbe);
-        int bc = atomicAdd(&PL.ctr[3], nrt + ncx);
         bool full = br + nrt > PL.cap_reg || bb + nbf > PL.cap_bf || bb + nbf > BP.cap ||
-                    be + nbe > PL.cap_be || bc + nrt + ncx > PL.cap_cl;
+                    be + nbe > PL.cap_be;
+        int bc = -1;
+        if (!full) {
+            int cur = atomicAdd(&PL.ctr[3], 0);
+            while (true) {
+                if (cur + nrt + ncx > PL.cap_cl) { full = true; break; }
+                int prev = atomicCAS(&PL.ctr[3], cur, cur + nrt + ncx);
+                if (prev == cur) { bc = cur; break; }
+                cur = prev;
+            }
+        }
         if (full) { atomicOr(&PL.ctr[5], 1); C.gst[cid] = ST_OVERFLOW; S.base_reg = -1; }
         else {
             S.base_reg = br; S.base_bf = bb; S.base_be = be; S.base_cl = bc;
@@ -502,6 +521,10 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     __syncthreads();
     if (S.base_reg < 0) return;
+    if (lane == 0 && BP.prof) {
+        atomicAdd(&BP.prof[2], (unsigned long long)nbf);
+        atomicAdd(&BP.prof[3], (unsigned long long)(nrt + ncx));
+    }
     for (int k = lane; k < nrt; k += 64) {
         PL.reg[S.base_reg + k] = W.rt[k];
         PL.cl[S.base_cl + k] = W.rt[k]; PL.clc[S.base_cl + k] = cid;

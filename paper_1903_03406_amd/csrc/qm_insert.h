@@ -72,6 +72,7 @@ __global__ void k_mis_mark(int ncl, const int* cl, const int* clc, const int* st
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ncl) return;
     int c = clc[e];
+    if (c < 0) { atomicOr(&g_geom_error, 128); return; }
     if (state[c] != 0) return;
     atomicMax(&mark[cl[e]], mis_val(pass, c));
 }
@@ -93,12 +94,15 @@ __global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* 
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ncl) return;
     int c = clc[e];
+    if (c < 0) return;
     if (state[c] == 1) owner[cl[e]] = c;
 }
-__global__ void k_mis_release(int ncl, const int* cl, const int* clc, const int* state, int* owner) {
+// clear every ownership of this round (kept candidates, and kept ones that
+// a per-round cap demoted afterwards)
+__global__ void k_mis_release(int ncl, const int* cl, const int* clc, int* owner) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ncl) return;
-    if (state[clc[e]] == 1) owner[cl[e]] = -1;
+    if (owner[cl[e]] == clc[e]) owner[cl[e]] = -1;
 }
 
 // per-candidate values to scan: kept flag, new tet slots (f - k), new

@@ -118,6 +118,7 @@ __device__ bool ring(const Mesh& M, int t0, int a, int b, F&& visit) {
             int nb = M.TA[4 * (size_t)t + lu];
             if (nb < 0) break;                       // hull: go the other way
             int tn = nb >> 2;
+            if (tn >= M.nt) { atomicOr(&g_geom_error, 64); return false; }
             if (tn == t0) { closed = true; break; }
             int apex = M.TV[4 * (size_t)tn + (nb & 3)];
             if (visit(tn, w, apex)) return true;

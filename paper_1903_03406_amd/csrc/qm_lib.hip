@@ -76,6 +76,7 @@ struct qm_result {
     std::vector<double> xyz;
     std::vector<int32_t> tets, sf, sff, ss, ssg;
     std::vector<int32_t> rounds;   // QM_ROUND_FIELDS per round
+    std::vector<int32_t> last;     // last round's candidates, 9 per candidate
     qm_stats stats;
 };
 
@@ -137,6 +138,37 @@ struct Engine {
     BfPool BP{};
     unsigned pass = 1;
     int64_t dead = 0;
+    // kernel-family timing with events on the call's stream (QM_PROFILE)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_cat;
+    int ev_used = 0;
+    double prof_ms[8] = {0};
+    int64_t prof_n[8] = {0};
+    DBuf<unsigned long long> pctr;
+    void pbegin() {
+        if (!prof) return;
+        if (ev_used + 2 > (int)ev.size()) {
+            for (int i = 0; i < 64; ++i) { hipEvent_t e; HIPCK(hipEventCreate(&e)); ev.push_back(e); }
+            ev_cat.resize(ev.size());
+        }
+        HIPCK(hipEventRecord(ev[ev_used], s));
+    }
+    void pend(int cat) {
+        if (!prof) return;
+        HIPCK(hipEventRecord(ev[ev_used + 1], s));
+        ev_cat[ev_used] = cat;
+        ev_used += 2;
+        prof_n[cat]++;
+    }
+    void pflush() {          // after a stream synchronisation
+        for (int i = 0; i < ev_used; i += 2) {
+            float ms = 0;
+            HIPCK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+            prof_ms[ev_cat[i]] += ms;
+        }
+        ev_used = 0;
+    }
 
     explicit Engine(hipStream_t st) : s(st) {}
     ~Engine() {
@@ -152,8 +184,9 @@ struct Engine {
             b->release(s);
         c_key0.release(s); skey.release(s); c_key.release(s);
         c_tup0.release(s); c_tup.release(s); c_p0.release(s); c_p.release(s); c_qw.release(s);
-        p_be.release(s); p_bfr.release(s); p_q.release(s);
+        p_be.release(s); p_bfr.release(s); p_q.release(s); pctr.release(s);
         (void)hipStreamSynchronize(s);
+        for (auto e : ev) (void)hipEventDestroy(e);
     }
 
     void bind() {
@@ -197,7 +230,7 @@ struct Engine {
         PL.reg = p_reg.p; PL.bf = p_bf.p; PL.be = p_be.p; PL.cl = p_cl.p; PL.clc = p_clc.p; PL.q = p_q.p;
         PL.cap_reg = (int)p_reg.cap; PL.cap_bf = (int)p_bf.cap; PL.cap_be = (int)p_be.cap;
         PL.cap_cl = (int)p_cl.cap; PL.cap_q = (int)p_q.cap; PL.ctr = ctr.p;
-        BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / 3);
+        BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / 3); BP.prof = prof ? pctr.p : nullptr;
     }
     void* scratch(size_t bytes) {
         tmp.ensure(bytes, s, false);
@@ -242,6 +275,9 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
     Engine E(s);
+    E.prof = (opt->flags & QM_PROFILE) != 0;
+    if (E.prof) { E.pctr.ensure(8, s, false, 0); }
+    int64_t scan_tets = 0, scan_verts = 0;
     const int nv = in->nv, nt = in->nt, nsf = in->nsf, nss = in->nss, nftri = plc->nftri;
     int nfacet = 0;
     // staging of the input arrays on the device
@@ -344,9 +380,11 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             if (cap == 0) continue;
             E.cand_out.ensure(cap, s, false);
             HIPCK(hipMemsetAsync(ncand_d, 0, sizeof(int), s));
+            E.pbegin();
             if (c == CLS_SS) k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
             else if (c == CLS_SF) k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
-            else k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
+            else { k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d); scan_tets += E.M.nt; scan_verts += E.M.nv; }
+            E.pend(0);
             ncand = read1(ncand_d, s);
             if (ncand > 0) { cls = c; break; }
         }
@@ -354,6 +392,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.ensure_cands(ncand);
         // step 2: splitting points and priorities, then priority order
         HIPCK(hipMemcpyAsync(E.c_elem0.p, E.cand_out.p, sizeof(int) * ncand, hipMemcpyDeviceToDevice, s));
+        E.pbegin();
         k_split<<<nblk(ncand), 256, 0, s>>>(E.M, cls, ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
                                           E.c_st0.p, E.c_reason0.p);
         k_iota<<<nblk(ncand), 256, 0, s>>>(ncand, E.order0.p);
@@ -361,16 +400,19 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         k_fix_ties<<<nblk(ncand), 256, 0, s>>>(ncand, E.skey.p, E.order1.p, E.c_tup0.p);
         k_permute<<<nblk(ncand), 256, 0, s>>>(ncand, E.order1.p, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
                                             E.c_st0.p, E.c_reason0.p, E.C);
+        E.pend(1);
         // step 3: locate
-        if (cls != CLS_SS) k_locate<<<nblk(ncand, 64), 64, 0, s>>>(E.M, cls, E.C);
+        if (cls != CLS_SS) { E.pbegin(); k_locate<<<nblk(ncand, 64), 64, 0, s>>>(E.M, cls, E.C); E.pend(2); }
         // steps 4-5: grow and validate
         HIPCK(hipMemsetAsync(E.ctr.p, 0, 8 * sizeof(int), s));
         E.ensure_pools((size_t)ncand * 24 + 4096, (size_t)ncand * 48 + 4096, (size_t)ncand * 4 + 4096,
                        (size_t)ncand * 56 + 4096, (size_t)ncand * 2 + 4096, false);
         {
             int grid = std::min(ncand, 16384);
+            E.pbegin();
             k_grow_lds<G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF>
                 <<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP);
+            E.pend(3);
         }
         for (int attempt = 0;; ++attempt) {
             HIPCK(hipMemsetAsync(olist_n, 0, sizeof(int), s));
@@ -391,12 +433,16 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             // sort the overflow list so the slab path visits candidates in order
             int grid = std::min(nover, 64);
             E.slab.ensure(slab_block * grid, s, false);
+            E.pbegin();
             k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, E.olist.p, nover, BT, E.slab.p, slab_block);
+            E.pend(3);
         }
         // flags of rejected / exempted candidates
-        k_apply_flags<<<nblk(ncand), 256, 0, s>>>(E.M, cls, E.C, E.PL);
         HIPCK(hipMemsetAsync(stats_d, 0, 16 * sizeof(int), s));
+        E.pbegin();
+        k_apply_flags<<<nblk(ncand), 256, 0, s>>>(E.M, cls, E.C, E.PL);
         k_round_stats<<<nblk(ncand), 256, 0, s>>>(E.C, stats_d);
+        E.pend(4);
         // step 6: maximal set of disjoint claim sets, greedy by priority
         k_mis_init<<<nblk(ncand), 256, 0, s>>>(E.C);
         int ncl = read1(E.ctr.p + 3, s);
@@ -406,13 +452,16 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 ++passes;
                 unsigned ps = E.pass++;
                 HIPCK(hipMemsetAsync(undec_d, 0, sizeof(int), s));
+                E.pbegin();
                 k_mis_mark<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps);
                 k_mis_decide<<<nblk(ncand), 256, 0, s>>>(E.C, E.p_cl.p, E.mark.p, E.owner.p, ps, undec_d);
                 k_mis_commit<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p);
+                E.pend(5);
                 if (read1(undec_d, s) == 0) break;
             }
         }
         // step 7: ids, slots and insertion
+        E.pbegin();
         k_scan_vals<<<nblk(ncand), 256, 0, s>>>(E.C, cls, E.vk.p, E.vt.p, E.vs.p);
         E.exscan(E.vk.p, E.sk.p, ncand);
         if (opt->max_kept > 0) {
@@ -423,6 +472,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.exscan(E.vt.p, E.st_.p, ncand);
         E.exscan(E.vs.p, E.ss_.p, ncand);
         k_totals<<<1, 1, 0, s>>>(ncand, E.sk.p, E.vk.p, E.st_.p, E.vt.p, E.ss_.p, E.vs.p, tot_d);
+        E.pend(6);
         int tot[3];
         HIPCK(hipMemcpyAsync(tot, tot_d, sizeof tot, hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
@@ -431,10 +481,34 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             E.ensure_mesh(E.M.nv + nkept, E.M.nt + newt, E.M.nss + newss);
             k_kept_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.sk.p, E.kept.p);
             int grid = std::min(nkept, 16384);
+            E.pbegin();
             k_insert<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, E.kept.p, nkept, E.sk.p, E.st_.p, E.ss_.p,
                                          E.M.nv, E.M.nt, E.M.nss, dead_d);
-            k_mis_release<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p);
+            E.pend(7);
             E.M.nv += nkept; E.M.nt += newt; E.M.nss += newss;
+        }
+        if (ncl > 0) k_mis_release<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.owner.p);
+        // verdicts of this round's candidates (kept for the last round)
+        {
+            std::vector<int4> tup(ncand);
+            std::vector<int> st0(ncand), gs(ncand), rs0(ncand), grs(ncand), stt(ncand), rn(ncand), bn(ncand);
+            HIPCK(hipMemcpyAsync(tup.data(), E.c_tup.p, sizeof(int4) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(st0.data(), E.c_st.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(gs.data(), E.gst.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(rs0.data(), E.c_reason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(grs.data(), E.greason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(stt.data(), E.state.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(rn.data(), E.reg_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(bn.data(), E.bf_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            R->last.assign(9 * (size_t)ncand, 0);
+            for (int i = 0; i < ncand; ++i) {
+                int* o = R->last.data() + 9 * (size_t)i;
+                int fs = st0[i] != ST_PENDING ? st0[i] : gs[i];
+                o[0] = tup[i].x; o[1] = tup[i].y; o[2] = tup[i].z; o[3] = tup[i].w;
+                o[4] = fs; o[5] = fs == ST_EXEMPT ? (st0[i] != ST_PENDING ? rs0[i] : grs[i]) : 0;
+                o[6] = stt[i] == 1; o[7] = fs == ST_OK ? rn[i] : 0; o[8] = fs == ST_OK ? bn[i] : 0;
+            }
         }
         // dead slots: regions larger than their new tets
         int st[16];
@@ -450,8 +524,11 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         R->stats.inserted[cls] += nkept;
         R->stats.candidates += ncand;
         R->stats.mis_passes += passes;
+        if (E.prof) E.pflush();
     }
     HIPCK(hipEventRecord(e2, s));
+    HIPCK(hipStreamSynchronize(s));
+    if (E.prof) E.pflush();
     int gerr = 0;
     HIPCK(hipMemcpyFromSymbolAsync(&gerr, HIP_SYMBOL(g_geom_error), sizeof(int), 0, hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
@@ -499,6 +576,14 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     HIPCK(hipEventElapsedTime(&ms_setup, e0, e1));
     HIPCK(hipEventElapsedTime(&ms_ref, e1, e2));
     (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
+    if (E.prof) {
+        for (int i = 0; i < 8; ++i) { R->stats.prof_ms[i] = E.prof_ms[i]; R->stats.prof_launches[i] = E.prof_n[i]; }
+        unsigned long long pc[4];
+        HIPCK(hipMemcpy(pc, E.pctr.p, sizeof pc, hipMemcpyDeviceToHost));
+        R->stats.prof_tested = (int64_t)pc[0]; R->stats.prof_region = (int64_t)pc[1];
+        R->stats.prof_bfaces = (int64_t)pc[2]; R->stats.prof_claims = (int64_t)pc[3];
+        R->stats.prof_scan_tets = scan_tets; R->stats.prof_scan_verts = scan_verts;
+    }
     R->stats.rounds = round;
     R->stats.status = status;
     R->stats.nv_out = E.M.nv;
@@ -544,6 +629,13 @@ int qm_result_rounds(const qm_result* r, int32_t* buf, int32_t cap) {
     if (!r) { g_err = "null result"; return QM_EINVAL; }
     int n = (int)(r->rounds.size() / QM_ROUND_FIELDS);
     if (buf) std::memcpy(buf, r->rounds.data(), sizeof(int32_t) * QM_ROUND_FIELDS * (size_t)std::min(n, (int)cap));
+    return n;
+}
+
+int qm_result_last_round(const qm_result* r, int32_t* buf, int32_t cap) {
+    if (!r) { g_err = "null result"; return QM_EINVAL; }
+    int n = (int)(r->last.size() / 9);
+    if (buf) std::memcpy(buf, r->last.data(), sizeof(int32_t) * 9 * (size_t)std::min(n, (int)cap));
     return n;
 }
 
