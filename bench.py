@@ -100,7 +100,7 @@ def main():
 
     def step(profile=False):
         return qm.refine(d["xyz"], d["tets"], d["sf"], d["sf_facet"], d["ss"], d["ss_seg"], d["ftri"],
-                         d["ftri_facet"], w.B, stream=stream, profile=profile)
+                         d["ftri_facet"], w.B, stream=stream, profile=profile, verbose=True)
 
     for i in range(args.warmup):
         r = step()

@@ -70,13 +70,14 @@ typedef struct qm_mesh {
 #define QM_INPUT_DEVICE 1u   /* mesh/PLC arrays are device pointers (same device) */
 #define QM_PROFILE 2u        /* time each kernel family with HIP events on the call's
                                 stream and count the region work (qm_stats.prof_*) */
+#define QM_VERBOSE 4u        /* progress line on stderr every few seconds of rounds */
 
 typedef struct qm_options {
     double B;                /* radius-edge bound (> 0) */
     double hmin_factor;      /* h_min = hmin_factor * shortest input edge (0.5 typical) */
     int32_t max_rounds;      /* round guard; QM_EROUNDS when reached */
     int32_t max_kept;        /* > 0: insert at most this many points per round */
-    uint32_t flags;          /* QM_INPUT_DEVICE */
+    uint32_t flags;          /* QM_INPUT_DEVICE | QM_PROFILE | QM_VERBOSE */
 } qm_options;
 
 /* per-round record (16 int32): class (0 subsegment, 1 subface, 2 tet),

@@ -27,6 +27,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 QM_INPUT_DEVICE = 1
 QM_PROFILE = 2
+QM_VERBOSE = 4
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
                  "scans", "insert")
 ROUND_FIELDS = 16
@@ -80,6 +81,10 @@ def _load():
         if not os.path.exists(_SO):
             raise RuntimeError(f"{_SO} is not built: run paper_1903_03406_amd.build() "
                                "(the refinement has no CPU fallback)")
+        try:                       # share torch's HIP runtime when torch is present:
+            import torch  # noqa: F401  (one runtime per process)
+        except ImportError:
+            pass
         lib = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         lib.qm_refine.restype = ctypes.c_int
@@ -136,7 +141,7 @@ def _arr(a, dtype):
 
 
 def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None, hmin_factor=0.5,
-           max_rounds=100000, max_kept=0, stream=None, profile=False) -> RefineResult:
+           max_rounds=100000, max_kept=0, stream=None, profile=False, verbose=False) -> RefineResult:
     """Refine a CDT.  Arrays are numpy (host) or torch CUDA tensors (device);
     ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle."""
     lib = _load()
@@ -169,7 +174,8 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
     plc = _Plc(nv, nseg, pseg, nft, pft, pftf)
     mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
     opts = _Opts(float(B), float(hmin_factor), int(max_rounds), int(max_kept),
-                 (QM_INPUT_DEVICE if dev else 0) | (QM_PROFILE if profile else 0))
+                 (QM_INPUT_DEVICE if dev else 0) | (QM_PROFILE if profile else 0)
+                 | (QM_VERBOSE if verbose else 0))
     if stream is None:
         hs = None
     elif hasattr(stream, "cuda_stream"):

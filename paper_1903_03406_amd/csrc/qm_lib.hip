@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -371,6 +372,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     BT.maxrt = B_MAXRT; BT.hcap = B_HCAP; BT.rfhcap = B_RFHCAP; BT.maxrf = B_MAXRF; BT.maxbe = B_MAXBE;
     BT.qhcap = B_QHCAP; BT.maxq = B_MAXQ; BT.maxbf = B_MAXBF; BT.maxcx = B_MAXBF;
     const size_t slab_block = grow_slab_bytes(BT);
+    const bool verbose = (opt->flags & QM_VERBOSE) != 0;
+    auto last_note = std::chrono::steady_clock::now();
     for (;; ++round) {
         if (round >= opt->max_rounds) { status = 1; break; }
         int cls = CLS_NONE, ncand = 0;
@@ -522,6 +525,11 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         rec[15] = E.M.nt - (int)E.dead;
         R->rounds.insert(R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
         R->stats.inserted[cls] += nkept;
+        if (verbose && std::chrono::steady_clock::now() - last_note > std::chrono::seconds(5)) {
+            last_note = std::chrono::steady_clock::now();
+            fprintf(stderr, "qm: round %d class %d candidates %d inserted %d vertices %d tets %d\n", round, cls,
+                    ncand, nkept, E.M.nv, rec[15]);
+        }
         R->stats.candidates += ncand;
         R->stats.mis_passes += passes;
         if (E.prof) E.pflush();

@@ -140,7 +140,10 @@ def test_invalid_inputs_fail_cleanly():
     flipped = w.tets.copy(); flipped[0, [0, 1]] = flipped[0, [1, 0]]
     with pytest.raises(qm.QmError, match="ENONCONFORM"):
         qm.refine(w.xyz, flipped, w.sf, w.sf_facet, w.ss, w.ss_seg, w.ftri, w.ftri_facet, 2.0)
-    sf = w.sf.copy(); sf[0] = [8, 9, 10]          # not a face of the mesh
+    faces = {tuple(sorted(t[i] for i in f)) for t in w.tets.tolist() for f in qi.FACE.tolist()}
+    nonface = next((a, b, c) for a in range(8, 40) for b in range(a + 1, 40) for c in range(b + 1, 40)
+                   if (a, b, c) not in faces)
+    sf = w.sf.copy(); sf[0] = nonface             # not a face of the mesh
     with pytest.raises(qm.QmError, match="ENONCONFORM"):
         qm.refine(w.xyz, w.tets, sf, w.sf_facet, w.ss, w.ss_seg, w.ftri, w.ftri_facet, 2.0)
     with pytest.raises(qm.QmError, match="EINVAL"):
