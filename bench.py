@@ -60,6 +60,7 @@ def cpu_baseline(w, target_s):
     r, res = 1, None
     while True:
         res = oracle.refine(w, max_rounds=r)
+        print(f"[bench] cpu baseline: {res.rounds} rounds in {res.seconds:.1f}s", file=sys.stderr, flush=True)
         if res.seconds >= target_s or res.status == 0 or r >= 4096:
             break
         r *= 2
@@ -78,6 +79,8 @@ def main():
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--dump-rounds", default=None,
+                    help="write the last step's per-round records and per-round kernel-family ms (JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the refinement of one instance runs on a single "
@@ -143,12 +146,17 @@ def main():
         "output": {"vertices": int(len(r.xyz)), "tets": int(len(r.tets)), "steiner": steiner,
                    "rounds": r.rounds, "device_refine_s": r.seconds_refine, "device_setup_s": r.seconds_setup},
         "profile_ms": {k: round(v, 3) for k, v in prof["ms"].items()},
+        "overflow_candidates": prof.get("overflow", 0), "poolfull_candidates": prof.get("poolfull", 0),
         "roofline": {"kernel": "k_grow_lds" if fam == "grow_validate" else "k_classify_tet",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "launches": prof["launches"][fam], "kernel_ms": kms,
                      "algorithmic_bytes": nbytes, "dominant_family": dominant},
     }
+    if args.dump_rounds:
+        with open(args.dump_rounds, "w") as f:
+            json.dump({"fields": list(qm.ROUND_NAMES), "rounds": r.rstats.tolist(),
+                       "families": list(qm.PROF_FAMILIES), "round_ms": prof["round_ms"].tolist()}, f)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

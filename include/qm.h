@@ -86,6 +86,7 @@ typedef struct qm_options {
    subface without region tets, invisible boundary face, invisible 2D
    boundary edge, unclosed cavity boundary), vertices after, tets after */
 #define QM_ROUND_FIELDS 16
+#define QM_PROF_FAMILIES 9
 
 typedef struct qm_stats {
     int32_t rounds;
@@ -98,15 +99,20 @@ typedef struct qm_stats {
     double seconds_refine;   /* round loop (device resident) */
     double seconds_total;    /* whole call incl. transfers */
     /* QM_PROFILE only: device milliseconds and launches per kernel family
-       0 classify, 1 split+order, 2 locate, 3 grow+validate, 4 flags+stats,
-       5 selection, 6 scans, 7 insert */
-    double prof_ms[8];
-    int64_t prof_launches[8];
-    /* QM_PROFILE only: region work of the grow kernel: tets tested, region
-       tets, boundary faces, claimed tets (accepted candidates) */
+       0 classify, 1 split+order, 2 locate, 3 grow+validate (LDS tiles),
+       4 flags+stats, 5 selection, 6 scans, 7 insert, 8 grow+validate re-run
+       of the regions that outgrew the LDS tiles (global-memory tiles) */
+    double prof_ms[QM_PROF_FAMILIES];
+    int64_t prof_launches[QM_PROF_FAMILIES];
+    /* QM_PROFILE only: region work of the grow kernel with LDS tiles (family
+       3): tets tested, region tets, boundary faces, claimed tets (accepted
+       candidates) */
     int64_t prof_tested, prof_region, prof_bfaces, prof_claims;
     /* QM_PROFILE only: tets and vertices scanned by the tet classification */
     int64_t prof_scan_tets, prof_scan_verts;
+    /* QM_PROFILE only: candidates evaluated again with global-memory tiles
+       (region over the LDS tiles), and again after a result pool grew */
+    int64_t prof_overflow, prof_poolfull;
 } qm_stats;
 
 typedef struct qm_result qm_result;
@@ -131,6 +137,11 @@ int qm_result_rounds(const qm_result* r, int32_t* buf, int32_t cap);
    faces (accepted candidates).  Copies at most `cap`; returns the count.
    For inspecting one round of a run (max_rounds) against a reference. */
 int qm_result_last_round(const qm_result* r, int32_t* buf, int32_t cap);
+
+/* QM_PROFILE only: device milliseconds of each kernel family (as in
+   qm_stats.prof_ms, QM_PROF_FAMILIES doubles) for each round.  Copies at most
+   `cap` rounds; returns the number of rounds recorded (0 without QM_PROFILE). */
+int qm_result_round_profile(const qm_result* r, double* buf, int32_t cap);
 
 void qm_result_free(qm_result* r);
 

@@ -29,7 +29,7 @@ QM_INPUT_DEVICE = 1
 QM_PROFILE = 2
 QM_VERBOSE = 4
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
-                 "scans", "insert")
+                 "scans", "insert", "grow_overflow")
 ROUND_FIELDS = 16
 ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
@@ -68,11 +68,12 @@ class _Stats(ctypes.Structure):
                 ("inserted", ctypes.c_int64 * 3), ("candidates", ctypes.c_int64),
                 ("mis_passes", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
                 ("seconds_setup", ctypes.c_double), ("seconds_refine", ctypes.c_double),
-                ("seconds_total", ctypes.c_double), ("prof_ms", ctypes.c_double * 8),
-                ("prof_launches", ctypes.c_int64 * 8), ("prof_tested", ctypes.c_int64),
+                ("seconds_total", ctypes.c_double), ("prof_ms", ctypes.c_double * 9),
+                ("prof_launches", ctypes.c_int64 * 9), ("prof_tested", ctypes.c_int64),
                 ("prof_region", ctypes.c_int64), ("prof_bfaces", ctypes.c_int64),
                 ("prof_claims", ctypes.c_int64), ("prof_scan_tets", ctypes.c_int64),
-                ("prof_scan_verts", ctypes.c_int64)]
+                ("prof_scan_verts", ctypes.c_int64), ("prof_overflow", ctypes.c_int64),
+                ("prof_poolfull", ctypes.c_int64)]
 
 
 def _load():
@@ -101,8 +102,8 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_result_view", "qm_result_rounds", "qm_result_last_round", "qm_result_free",
-           "qm_last_error", "qm_version")
+EXPORTS = ("qm_refine", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
+           "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version")
 
 
 class QmError(RuntimeError):
@@ -205,6 +206,14 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
         last = np.zeros((max(nl, 0), 9), dtype=np.int32)
         if nl:
             lib.qm_result_last_round(res, last.ctypes.data, nl)
+        round_ms = None
+        if profile:
+            lib.qm_result_round_profile.restype = ctypes.c_int
+            lib.qm_result_round_profile.argtypes = [P_, P_, ctypes.c_int32]
+            npr = lib.qm_result_round_profile(res, None, 0)
+            round_ms = np.zeros((max(npr, 0), len(PROF_FAMILIES)), dtype=np.float64)
+            if npr:
+                lib.qm_result_round_profile(res, round_ms.ctypes.data, npr)
         nr = lib.qm_result_rounds(res, None, 0)
         rs = np.zeros((max(nr, 0), ROUND_FIELDS), dtype=np.int32)
         if nr:
@@ -219,7 +228,9 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
                               "launches": dict(zip(PROF_FAMILIES, [int(x) for x in st.prof_launches])),
                               "tested": int(st.prof_tested), "region": int(st.prof_region),
                               "bfaces": int(st.prof_bfaces), "claims": int(st.prof_claims),
-                              "scan_tets": int(st.prof_scan_tets), "scan_verts": int(st.prof_scan_verts)}
+                              "scan_tets": int(st.prof_scan_tets), "scan_verts": int(st.prof_scan_verts),
+                              "overflow": int(st.prof_overflow), "poolfull": int(st.prof_poolfull),
+                              "round_ms": round_ms}
                              if profile else None), last)
     finally:
         lib.qm_result_free(res)

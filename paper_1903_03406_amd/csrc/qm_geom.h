@@ -2,19 +2,18 @@
 //
 // Exact predicates: each is an FP64 evaluation with a semi-static error bound
 // (error <= c * eps * permanent, Shewchuk 1997, "Adaptive precision
-// floating-point arithmetic and fast robust geometric predicates", Sec. 4),
-// and, when the sign is not certain, an exact evaluation in floating-point
-// expansion arithmetic (same paper, Sec. 2: TWO-SUM, TWO-PRODUCT via FMA,
-// FAST-EXPANSION-SUM and SCALE-EXPANSION with zero elimination).
+// floating-point arithmetic and fast robust geometric predicates", Sec. 4);
+// when the sign is not certain it is computed exactly.
 //
-// Buffer sizes of the exact paths.  All coordinates are multiples of 2^-53.
-// A zero-eliminated nonoverlapping expansion whose value is a multiple of
-// 2^L and below 2^H in magnitude has at most H - L + 1 components (the
-// components occupy disjoint bit ranges inside [L, H]).  For points of the
-// unit cube a degree-d form has L = -53 d and H <= 7, which bounds every
-// intermediate of insphere (d = 5) by 273 and of the equatorial-ball test
-// (d = 6) by 326 components.  orient3d and orient2d accept any finite point
-// (the walks may aim outside the cube) and use the classical length bounds.
+// Every vertex of the mesh is a point of the unit cube on the 2^-53 lattice,
+// so the predicates of the region growth, validation and classification
+// (orient3d, orient2d, insphere, segment and face encroachment) evaluate
+// their polynomial in fixed-width integers held in registers (no scratch
+// memory).  Only the tet walk of the locate step can aim at a point outside
+// the cube; its orientation tests (orient3d_any, orient2d_any) fall back to
+// floating-point expansion arithmetic (same paper, Sec. 2: TWO-SUM,
+// TWO-PRODUCT via FMA, FAST-EXPANSION-SUM and SCALE-EXPANSION with zero
+// elimination).
 //
 // Constructions (midpoint, circumcentres, radius-edge test) use one fixed
 // FP64 operation order with no contraction (-ffp-contract=off) and IEEE
@@ -126,9 +125,13 @@ __device__ inline int exp_mul(int an, const double* a, int bn, const double* b, 
     return n;
 }
 
-// -------------------------------------------------------------- orient3d
+// --------------------------------------------- predicates on any finite point
+// The tet walk of the locate step may aim at a splitting point outside the
+// unit cube (a circumcentre far from its tet), so its orientation tests take
+// arbitrary finite coordinates: exact fallback in expansion arithmetic.
+
 // sign of det[b-a; c-a; d-a]
-QMN int orient3d_exact(const double* a, const double* b, const double* c, const double* d) {
+QMN int orient3d_any_exact(const double* a, const double* b, const double* c, const double* d) {
     double u[3][2], v[3][2], w[3][2];
     int un[3], vn[3], wn[3];
     for (int k = 0; k < 3; ++k) {
@@ -152,23 +155,31 @@ QMN int orient3d_exact(const double* a, const double* b, const double* c, const 
     return exp_sign(an, acc);
 }
 
-QMD int orient3d(const double* a, const double* b, const double* c, const double* d) {
+// FP64 value of det[b-a; c-a; d-a] and its permanent (error scale)
+QMD void orient3d_fp(const double* a, const double* b, const double* c, const double* d, double& det,
+                     double& per) {
     double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
     double v0 = c[0] - a[0], v1 = c[1] - a[1], v2 = c[2] - a[2];
     double w0 = d[0] - a[0], w1 = d[1] - a[1], w2 = d[2] - a[2];
     double m0a = v1 * w2, m0b = v2 * w1, m1a = v2 * w0, m1b = v0 * w2, m2a = v0 * w1, m2b = v1 * w0;
-    double det = u0 * (m0a - m0b) + u1 * (m1a - m1b) + u2 * (m2a - m2b);
-    double per = fabs(u0) * (fabs(m0a) + fabs(m0b)) + fabs(u1) * (fabs(m1a) + fabs(m1b))
-               + fabs(u2) * (fabs(m2a) + fabs(m2b));
-    double bound = (7.0 + 56.0 * kEps) * kEps * per;
+    det = u0 * (m0a - m0b) + u1 * (m1a - m1b) + u2 * (m2a - m2b);
+    per = fabs(u0) * (fabs(m0a) + fabs(m0b)) + fabs(u1) * (fabs(m1a) + fabs(m1b))
+        + fabs(u2) * (fabs(m2a) + fabs(m2b));
+}
+constexpr double kO3 = (7.0 + 56.0 * kEps) * kEps;
+constexpr double kO2 = (3.0 + 16.0 * kEps) * kEps;
+
+QMD int orient3d_any(const double* a, const double* b, const double* c, const double* d) {
+    double det, per;
+    orient3d_fp(a, b, c, d, det, per);
+    double bound = kO3 * per;
     if (det > bound) return 1;
     if (-det > bound) return -1;
-    return orient3d_exact(a, b, c, d);
+    return orient3d_any_exact(a, b, c, d);
 }
 
-// -------------------------------------------------------------- orient2d
 // 2D orientation after dropping coordinate `ax` (kept: ax+1, ax+2 mod 3)
-QMN int orient2d_exact(int ax, const double* a, const double* b, const double* c) {
+QMN int orient2d_any_exact(int ax, const double* a, const double* b, const double* c) {
     int i = (ax + 1) % 3, j = (ax + 2) % 3;
     double ux[2], uy[2], vx[2], vy[2];
     int uxn = exp_diff(b[i], a[i], ux), uyn = exp_diff(b[j], a[j], uy);
@@ -181,83 +192,192 @@ QMN int orient2d_exact(int ax, const double* a, const double* b, const double* c
     return exp_sign(n, out);
 }
 
-QMD int orient2d(int ax, const double* a, const double* b, const double* c) {
+QMD void orient2d_fp(int ax, const double* a, const double* b, const double* c, double& det, double& per) {
     int i = (ax + 1) % 3, j = (ax + 2) % 3;
     double ux = b[i] - a[i], uy = b[j] - a[j], vx = c[i] - a[i], vy = c[j] - a[j];
     double l = ux * vy, r = uy * vx;
-    double det = l - r;
-    double bound = (3.0 + 16.0 * kEps) * kEps * (fabs(l) + fabs(r));
+    det = l - r;
+    per = fabs(l) + fabs(r);
+}
+
+QMD int orient2d_any(int ax, const double* a, const double* b, const double* c) {
+    double det, per;
+    orient2d_fp(ax, a, b, c, det, per);
+    double bound = kO2 * per;
+    if (det > bound) return 1;
+    if (-det > bound) return -1;
+    return orient2d_any_exact(ax, a, b, c);
+}
+
+// ------------------------------------------------------- lattice integers
+// A point of the unit cube on the 2^-53 lattice is k * 2^-53 with integer
+// 0 <= k <= 2^53, so each predicate below is an integer polynomial in the
+// k's.  When the FP64 filter cannot decide, the polynomial is evaluated
+// exactly in fixed-width two's-complement integers (32-bit limbs, little
+// endian, every loop unrolled so the limbs stay in registers).  Widths: a
+// form of degree d in coordinate differences (|dk| <= 2^53) with at most m
+// terms needs 53 d + log2(m) + 1 bits:
+//   orient2d  d = 2   -> 128 bits      segdot   d = 2  -> 128 bits
+//   orient3d  d = 3   -> 192 bits      insphere d = 5  -> 288 bits
+//   facedot   d = 6   -> 352 bits
+template <int N> struct Z { uint32_t w[N]; };
+
+// k = x * 2^53 (exact for lattice points of the cube); off-lattice or
+// out-of-cube input is a broken precondition and raises the error flag
+QMD int64_t lat(double x) {
+    double k = x * kLat;
+    if (!(k >= 0.0 && k <= kLat) || k != rint(k)) atomicOr(&g_geom_error, 256);
+    return (int64_t)k;
+}
+template <int N> QMD Z<N> zfrom(int64_t v) {
+    Z<N> r;
+    const uint32_t s = v < 0 ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r.w[i] = i == 0 ? (uint32_t)v : (i == 1 ? (uint32_t)((uint64_t)v >> 32) : s);
+    return r;
+}
+template <int M, int N> QMD Z<M> zext(const Z<N>& a) {   // sign-extend (M >= N)
+    Z<M> r;
+    const uint32_t s = (int32_t)a.w[N - 1] < 0 ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int i = 0; i < M; ++i) r.w[i] = i < N ? a.w[i] : s;
+    return r;
+}
+template <int N> QMD Z<N> zadd(const Z<N>& a, const Z<N>& b) {
+    Z<N> r;
+    uint64_t c = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        uint64_t s = (uint64_t)a.w[i] + b.w[i] + c;
+        r.w[i] = (uint32_t)s;
+        c = s >> 32;
+    }
+    return r;
+}
+template <int N> QMD Z<N> zsub(const Z<N>& a, const Z<N>& b) {
+    Z<N> r;
+    uint64_t br = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        uint64_t s = (uint64_t)a.w[i] - b.w[i] - br;
+        r.w[i] = (uint32_t)s;
+        br = s >> 63;
+    }
+    return r;
+}
+// -a when neg, else a (two's complement: flip every bit, add one)
+template <int N> QMD Z<N> zcneg(const Z<N>& a, bool neg) {
+    Z<N> r;
+    const uint32_t m = neg ? 0xFFFFFFFFu : 0u;
+    uint64_t c = neg ? 1u : 0u;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        uint64_t s = (uint64_t)(a.w[i] ^ m) + c;
+        r.w[i] = (uint32_t)s;
+        c = s >> 32;
+    }
+    return r;
+}
+// a * b into R limbs (R large enough for the true product): schoolbook on
+// the magnitudes, then the sign
+template <int R, int A, int B> QMD Z<R> zmul(const Z<A>& a, const Z<B>& b) {
+    const bool na = (int32_t)a.w[A - 1] < 0, nb = (int32_t)b.w[B - 1] < 0;
+    const Z<A> x = zcneg(a, na);
+    const Z<B> y = zcneg(b, nb);
+    Z<R> r;
+#pragma unroll
+    for (int i = 0; i < R; ++i) r.w[i] = 0u;
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+        uint64_t c = 0;
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+            if (i + j < R) {
+                uint64_t t = (uint64_t)x.w[i] * y.w[j] + r.w[i + j] + c;
+                r.w[i + j] = (uint32_t)t;
+                c = t >> 32;
+            }
+        }
+        if (i + B < R) r.w[i + B] = (uint32_t)c;
+    }
+    return zcneg(r, na != nb);
+}
+template <int N> QMD int zsign(const Z<N>& a) {
+    if ((int32_t)a.w[N - 1] < 0) return -1;
+    uint32_t o = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) o |= a.w[i];
+    return o != 0u ? 1 : 0;
+}
+// difference of two lattice coordinates as a 2-limb integer
+QMD Z<2> zd(double x, double y) { return zfrom<2>(lat(x) - lat(y)); }
+// p*s - q*r for 2-limb operands (|.| <= 2^53): 109 bits
+QMD Z<4> zdet2(const Z<2>& p, const Z<2>& q, const Z<2>& r, const Z<2>& s) {
+    return zsub(zmul<4>(p, s), zmul<4>(q, r));
+}
+// dot product of two difference vectors: < 3 * 2^106
+QMD Z<4> zdot(const Z<2>* x, const Z<2>* y) {
+    return zadd(zadd(zmul<4>(x[0], y[0]), zmul<4>(x[1], y[1])), zmul<4>(x[2], y[2]));
+}
+// det[u; v; w] of difference vectors: < 2^165
+QMD Z<6> zdet3(const Z<2>* u, const Z<2>* v, const Z<2>* w) {
+    Z<6> r = zmul<6>(u[0], zdet2(v[1], v[2], w[1], w[2]));
+    r = zadd(r, zmul<6>(u[1], zdet2(v[2], v[0], w[2], w[0])));
+    return zadd(r, zmul<6>(u[2], zdet2(v[0], v[1], w[0], w[1])));
+}
+
+// ------------------------------------- predicates on lattice points of the cube
+// orient3d: sign of det[b-a; c-a; d-a]
+QMN int orient3d_exact(const double* a, const double* b, const double* c, const double* d) {
+    Z<2> u[3], v[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { u[k] = zd(b[k], a[k]); v[k] = zd(c[k], a[k]); w[k] = zd(d[k], a[k]); }
+    return zsign(zdet3(u, v, w));
+}
+QMD int orient3d(const double* a, const double* b, const double* c, const double* d) {
+    double det, per;
+    orient3d_fp(a, b, c, d, det, per);
+    double bound = kO3 * per;
+    if (det > bound) return 1;
+    if (-det > bound) return -1;
+    return orient3d_exact(a, b, c, d);
+}
+
+// orient2d in the plane of the coordinates other than `ax`
+QMN int orient2d_exact(int ax, const double* a, const double* b, const double* c) {
+    int i = (ax + 1) % 3, j = (ax + 2) % 3;
+    return zsign(zdet2(zd(b[i], a[i]), zd(b[j], a[j]), zd(c[i], a[i]), zd(c[j], a[j])));
+}
+QMD int orient2d(int ax, const double* a, const double* b, const double* c) {
+    double det, per;
+    orient2d_fp(ax, a, b, c, det, per);
+    double bound = kO2 * per;
     if (det > bound) return 1;
     if (-det > bound) return -1;
     return orient2d_exact(ax, a, b, c);
 }
 
-// exact differences of two points of the unit cube (lattice): one component
-QMD double ediff(double x, double y) {
-    double h, l;
-    two_diff(x, y, h, l);
-    if (l != 0.0) atomicOr(&g_geom_error, 2);
-    return h;
-}
-
-// -------------------------------------------------------------- insphere
-// > 0 iff e is strictly inside the circumsphere of positively oriented abcd;
-// value = -det[[a-e, |a-e|^2], ..., [d-e, |d-e|^2]]
+// insphere: > 0 iff e is strictly inside the circumsphere of positively
+// oriented abcd.  With rows r_i = (x_i - e, |x_i - e|^2) the value is
+// -det[r_a; r_b; r_c; r_d], expanded along the lifted column.
 QMN int insphere_exact(const double* a, const double* b, const double* c, const double* d,
                        const double* e) {
     const double* r[4] = {a, b, c, d};
-    double m[4][3];
+    Z<2> m[4][3];
+#pragma unroll
     for (int i = 0; i < 4; ++i)
-        for (int k = 0; k < 3; ++k) m[i][k] = ediff(r[i][k], e[k]);
-    constexpr int CAP = 288;
-    double acc[CAP], tmp[CAP], term[CAP], s[64];
-    int an = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) m[i][k] = zd(r[i][k], e[k]);
+    Z<9> acc = zfrom<9>(0);
+#pragma unroll
     for (int i = 0; i < 4; ++i) {
-        // lift of row i: x^2 + y^2 + z^2 (<= 6 components)
-        double lift[6], sq[2], l2[6];
-        int ln = 0;
-        for (int k = 0; k < 3; ++k) {
-            double x, y;
-            two_prod(m[i][k], m[i][k], x, y);
-            int qn = 0;
-            if (y != 0.0) sq[qn++] = y;
-            if (x != 0.0) sq[qn++] = x;
-            int nn = exp_sum(ln, lift, qn, sq, l2);
-            exp_copy(nn, l2, lift);
-            ln = nn;
-        }
-        // 3x3 minor of the other rows (<= 24 components)
-        int rr[3], q = 0;
-        for (int s2 = 0; s2 < 4; ++s2) if (s2 != i) rr[q++] = s2;
-        double mn[24], mt[24], p[4], t8[8];
-        int mnn = 0;
-        for (int k = 0; k < 3; ++k) {
-            int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-            double x1, y1, x2, y2;
-            two_prod(m[rr[1]][k1], m[rr[2]][k2], x1, y1);
-            two_prod(m[rr[1]][k2], m[rr[2]][k1], x2, y2);
-            double e1[2], e2[2];
-            int n1 = 0, n2 = 0;
-            if (y1 != 0.0) e1[n1++] = y1;
-            if (x1 != 0.0) e1[n1++] = x1;
-            if (y2 != 0.0) e2[n2++] = -y2;
-            if (x2 != 0.0) e2[n2++] = -x2;
-            int pn = exp_sum(n1, e1, n2, e2, p);
-            int tn = exp_scale(pn, p, m[rr[0]][k], t8);
-            int nn = exp_sum(mnn, mn, tn, t8, mt);
-            exp_copy(nn, mt, mn);
-            mnn = nn;
-        }
-        int tn = exp_mul(mnn, mn, ln, lift, term, s, tmp, CAP);
-        if ((i + 3) & 1) exp_neg(tn, term);
-        int nn = exp_sum(an, acc, tn, term, tmp);
-        if (nn > CAP) { atomicOr(&g_geom_error, 4); nn = CAP; }
-        exp_copy(nn, tmp, acc);
-        an = nn;
+        const int r0 = i == 0 ? 1 : 0, r1 = i <= 1 ? 2 : 1, r2 = i <= 2 ? 3 : 2;
+        Z<4> lift = zdot(m[i], m[i]);
+        Z<9> t = zmul<9>(lift, zdet3(m[r0], m[r1], m[r2]));
+        acc = (i & 1) ? zadd(acc, t) : zsub(acc, t);
     }
-    return -exp_sign(an, acc);
+    return -zsign(acc);
 }
-
 QMD int insphere(const double* a, const double* b, const double* c, const double* d, const double* e) {
     const double* r[4] = {a, b, c, d};
     double m[4][4], pm[4][4];
@@ -289,23 +409,13 @@ QMD int insphere(const double* a, const double* b, const double* c, const double
     return insphere_exact(a, b, c, d, e);
 }
 
-// ------------------------------------------------------ segment encroach
-// sign of (v-a).(v-b); negative iff v strictly inside the diametral ball
+// segment encroachment: sign of (v-a).(v-b); negative iff v is strictly
+// inside the diametral ball of ab
 QMN int segdot_exact(const double* a, const double* b, const double* v) {
-    double acc[8], tmp[8];
-    int an = 0;
-    for (int k = 0; k < 3; ++k) {
-        double x, y;
-        two_prod(ediff(v[k], a[k]), ediff(v[k], b[k]), x, y);
-        double e[2];
-        int n = 0;
-        if (y != 0.0) e[n++] = y;
-        if (x != 0.0) e[n++] = x;
-        int nn = exp_sum(an, acc, n, e, tmp);
-        exp_copy(nn, tmp, acc);
-        an = nn;
-    }
-    return exp_sign(an, acc);
+    Z<2> x[3], y[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { x[k] = zd(v[k], a[k]); y[k] = zd(v[k], b[k]); }
+    return zsign(zdot(x, y));
 }
 QMD int segdot(const double* a, const double* b, const double* v) {
     double val = 0.0, per = 0.0;
@@ -321,61 +431,23 @@ QMD int segdot(const double* a, const double* b, const double* v) {
     return segdot_exact(a, b, v);
 }
 
-// ----------------------------------------------------- face (equatorial) encroach
-// sign of F = |n|^2|q|^2 - (q.u)|w|^2(|u|^2 - u.w) - (q.w)|u|^2(|w|^2 - u.w),
-// u = b-a, w = c-a, q = v-a: F < 0 iff v strictly inside the ball whose
-// great circle is the circumcircle of abc.
-QMD int dot_exp(const double* x, const double* y, double* out) {   // <= 6 components
-    double tmp[6];
-    int n = 0;
-    for (int k = 0; k < 3; ++k) {
-        double h, l;
-        two_prod(x[k], y[k], h, l);
-        double e[2];
-        int m = 0;
-        if (l != 0.0) e[m++] = l;
-        if (h != 0.0) e[m++] = h;
-        int nn = exp_sum(n, out, m, e, tmp);
-        exp_copy(nn, tmp, out);
-        n = nn;
-    }
-    return n;
-}
+// face (equatorial ball) encroachment: sign of
+//   F = |u x w|^2 |q|^2 - (q.u)|w|^2(|u|^2 - u.w) - (q.w)|u|^2(|w|^2 - u.w),
+// u = b-a, w = c-a, q = v-a, with |u x w|^2 = |u|^2|w|^2 - (u.w)^2;
+// F < 0 iff v is strictly inside the ball whose great circle is the
+// circumcircle of abc
 QMN int facedot_exact(const double* a, const double* b, const double* c, const double* v) {
-    double u[3], w[3], q[3];
-    for (int k = 0; k < 3; ++k) { u[k] = ediff(b[k], a[k]); w[k] = ediff(c[k], a[k]); q[k] = ediff(v[k], a[k]); }
-    double uu[6], ww[6], uw[6], qu[6], qw[6], qq[6], nuwv[6];
-    int nuu = dot_exp(u, u, uu), nww = dot_exp(w, w, ww), nuw = dot_exp(u, w, uw);
-    int nqu = dot_exp(q, u, qu), nqw = dot_exp(q, w, qw), nqq = dot_exp(q, q, qq);
-    exp_copy(nuw, uw, nuwv);
-    exp_neg(nuw, nuwv);
-    constexpr int CAP = 336;   // span bound of a degree-6 form (see header)
-    double s[CAP], tmp[CAP], R[CAP], T[CAP], X1[80], X2[80], S[12];
-    // T0 = (uu ww - uw uw) qq
-    int n1 = exp_mul(nuu, uu, nww, ww, X1, s, tmp, 80);
-    int n2 = exp_mul(nuw, uw, nuw, uw, X2, s, tmp, 80);
-    exp_neg(n2, X2);
-    int nt = exp_sum(n1, X1, n2, X2, T);
-    int nr = exp_mul(nt, T, nqq, qq, R, s, tmp, CAP);
-    // - (q.u) ww (uu - uw)
-    int ns = exp_sum(nuu, uu, nuw, nuwv, S);
-    n1 = exp_mul(nqu, qu, nww, ww, X1, s, tmp, 80);
-    nt = exp_mul(n1, X1, ns, S, T, s, tmp, CAP);
-    exp_neg(nt, T);
-    int m = exp_sum(nr, R, nt, T, tmp);
-    if (m > CAP) { atomicOr(&g_geom_error, 8); m = CAP; }
-    exp_copy(m, tmp, R);
-    nr = m;
-    // - (q.w) uu (ww - uw)
-    ns = exp_sum(nww, ww, nuw, nuwv, S);
-    n1 = exp_mul(nqw, qw, nuu, uu, X1, s, tmp, 80);
-    nt = exp_mul(n1, X1, ns, S, T, s, tmp, CAP);
-    exp_neg(nt, T);
-    m = exp_sum(nr, R, nt, T, tmp);
-    if (m > CAP) { atomicOr(&g_geom_error, 8); m = CAP; }
-    return exp_sign(m, tmp);
+    Z<2> u[3], w[3], q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { u[k] = zd(b[k], a[k]); w[k] = zd(c[k], a[k]); q[k] = zd(v[k], a[k]); }
+    const Z<4> uu = zdot(u, u), ww = zdot(w, w), uw = zdot(u, w);
+    const Z<4> qu = zdot(q, u), qw = zdot(q, w), qq = zdot(q, q);
+    Z<7> n2 = zsub(zmul<7>(uu, ww), zmul<7>(uw, uw));
+    Z<11> F = zmul<11>(n2, qq);
+    F = zsub(F, zmul<11>(zmul<7>(qu, ww), zsub(uu, uw)));
+    F = zsub(F, zmul<11>(zmul<7>(qw, uu), zsub(ww, uw)));
+    return zsign(F);
 }
-
 QMD int facedot(const double* a, const double* b, const double* c, const double* v) {
     double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
     double w0 = c[0] - a[0], w1 = c[1] - a[1], w2 = c[2] - a[2];
@@ -393,6 +465,7 @@ QMD int facedot(const double* a, const double* b, const double* c, const double*
     if (-val > bound) return -1;
     return facedot_exact(a, b, c, v);
 }
+
 
 // --------------------------------------------------------- constructions
 QMD double snap(double x) { return rint(x * kLat) * kInvLat; }

@@ -15,23 +15,56 @@
 namespace qm {
 
 constexpr unsigned KEYMASK = 0x1FFFFFFFu;
+// which tile a region outgrew (GrowShared::over, reported for the largest tiles)
+enum { OV_RT = 1, OV_HASH = 2, OV_RF = 4, OV_Q = 8, OV_BF = 16, OV_BE = 32, OV_CX = 64, OV_EDGE = 128 };
 enum { HS_IN = 1u, HS_OUT = 2u, HS_CLAIM = 3u };
 
+// Tiles of one candidate's evaluation.  cx holds CXW ints per boundary face
+// (x, y, z, old tet<<2|face, then for the edges opposite x, y and z the
+// partner face sharing that edge as m<<2|slot, -1 when none) followed by
+// maxcx extra claims.  EK/EV: edge table (global-memory tiles only, ehcap
+// entries; ehcap 0 selects the pairwise scans bounded by the LDS tiles).
+constexpr int CXW = 7;
 struct GrowTiles {
     int* rt; unsigned* H; unsigned* RFH; int* rf; int4* be; unsigned long long* QH; int2* q; int* cx;
-    int maxrt, hcap, rfhcap, maxrf, maxbe, qhcap, maxq, maxbf, maxcx;   // cx: 4*maxbf + maxcx ints
+    int maxrt, hcap, rfhcap, maxrf, maxbe, qhcap, maxq, maxbf, maxcx;
+    int big;              // 1: the largest (global-memory) tiles, nothing to fall back to
+    unsigned long long* EK; int4* EV; int ehcap;
 };
 
-// boundary-face record written for an accepted candidate (three int4 per face)
+// boundary-face record written for an accepted candidate (BFR int4 per face)
 //   r0 = (x, y, z, old neighbour)   r1 = (facet id, face flags, ss(x,y), ss(y,z))
 //   r2 = (ss(z,x), old tet<<2|face, 0, 0)
+//   r3 = (partner across edge yz, across xz, across xy, 0) as m<<2|slot, m the
+//        partner's index among the candidate's faces, -1 on the hull
+constexpr int BFR = 4;
 struct BfPool { int4* r; int cap; unsigned long long* prof; };   // prof: tested, region, bfaces, claims
 
 struct GrowShared {
     int nrt, nrf, nbf, nbe, nq, ncx, hcount;
     int over, fail, reason;
     int base_reg, base_bf, base_be, base_cl, base_q;
+    unsigned long long prof[4];   // region counters of this workgroup (flushed at exit)
 };
+
+QMD void prof_begin(GrowShared& S) {
+    if (threadIdx.x == 0) S.prof[0] = S.prof[1] = S.prof[2] = S.prof[3] = 0ull;
+}
+QMD void prof_flush(const GrowShared& S, const BfPool& BP) {
+    if (threadIdx.x == 0 && BP.prof)
+        for (int i = 0; i < 4; ++i)
+            if (S.prof[i]) atomicAdd(&BP.prof[i], S.prof[i]);
+}
+
+// End of a validation phase: wait for every lane's writes, take the verdict
+// flags, and wait again so that no lane starts the next phase (which may
+// set the flags) before all have read them.  True: stop (over or failed).
+QMD bool phase_end(const GrowShared& S) {
+    __syncthreads();
+    const bool stop = S.over != 0 || S.fail != 0;
+    __syncthreads();
+    return stop;
+}
 
 QMD unsigned hmix(unsigned k) { return k * 2654435761u; }
 
@@ -122,6 +155,49 @@ QMD int qput(unsigned long long* H, int cap, unsigned long long key) {
     return -1;
 }
 
+// edge table of the global-memory tiles: key (lo<<32 | hi) with bit 63 set,
+// value (faces holding the edge, first and second face-edge code, 2D
+// boundary edges with this key + 0x10000 if one of them is one-sided)
+QMD unsigned long long ekey(int x, int y) {
+    unsigned lo = (unsigned)(x < y ? x : y), hi = (unsigned)(x < y ? y : x);
+    return ((unsigned long long)lo << 32) | hi | (1ull << 63);
+}
+QMD unsigned ehash(unsigned long long k, int cap) {
+    return (unsigned)((k * 0x9E3779B97F4A7C15ull) >> 40) & (unsigned)(cap - 1);
+}
+QMD int eput(unsigned long long* EK, int cap, unsigned long long key) {   // slot of key (inserted)
+    unsigned h = ehash(key, cap);
+    for (int probe = 0; probe < cap; ++probe) {
+        unsigned long long cur = EK[h];
+        if (cur == 0ull) {
+            unsigned long long prev = atomicCAS(&EK[h], 0ull, key);
+            if (prev == 0ull) return (int)h;
+            cur = prev;
+        }
+        if (cur == key) return (int)h;
+        h = (h + 1) & (unsigned)(cap - 1);
+    }
+    return -1;
+}
+QMD int eget(const unsigned long long* EK, int cap, unsigned long long key) {   // slot or -1
+    unsigned h = ehash(key, cap);
+    for (int probe = 0; probe < cap; ++probe) {
+        unsigned long long cur = EK[h];
+        if (cur == 0ull) return -1;
+        if (cur == key) return (int)h;
+        h = (h + 1) & (unsigned)(cap - 1);
+    }
+    return -1;
+}
+// table size for n keys (power of two, at least 2n), cleared by all lanes
+QMD int eclear(const GrowTiles& W, int n) {
+    int cap = 64;
+    while (cap < 2 * n) cap <<= 1;
+    if (cap > W.ehcap) cap = W.ehcap;
+    for (int i = threadIdx.x; i < cap; i += 64) { W.EK[i] = 0ull; W.EV[i] = make_int4(0, -1, -1, 0); }
+    return cap;
+}
+
 QMD double wave_min(double v) {
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
     return v;
@@ -135,6 +211,13 @@ QMD void sub_edge(int4 v, int f, int e, int& x, int& y, int& z) {
     if (e == 0) { x = g0; y = g1; z = g2; }
     else if (e == 1) { x = g0; y = g2; z = g1; }
     else { x = g1; y = g2; z = g0; }
+}
+
+// a region over the tiles: evaluate again with larger tiles, or (largest
+// tiles) report which tile was too small in the counter word PL.ctr[35]
+QMD void over_status(const Cands& C, const Pools& PL, const GrowTiles& W, int cid, int over) {
+    if (W.big) { C.gst[cid] = ST_TOOBIG; atomicOr(&PL.ctr[35], over); }
+    else C.gst[cid] = ST_OVERFLOW;
 }
 
 // Evaluate candidate `cid` (steps: seeds, grow R_F, grow R_T, validate,
@@ -157,20 +240,20 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     auto add_rt = [&](int t) {
         unsigned os;
         int r = hput(W.H, W.hcap, (unsigned)t + 1u, HS_IN, &os);
-        if (r < 0) { S.over = 1; return; }
+        if (r < 0) { S.over |= OV_HASH; return; }
         if (r == 1) {
             int c = atomicAdd(&S.hcount, 1);
-            if (4 * c > 3 * W.hcap) S.over = 1;
+            if (4 * c > 3 * W.hcap) S.over |= OV_HASH;
             int idx = atomicAdd(&S.nrt, 1);
-            if (idx < W.maxrt) W.rt[idx] = t; else S.over = 1;
+            if (idx < W.maxrt) W.rt[idx] = t; else S.over |= OV_RT;
         }
     };
     auto add_rf = [&](int h) {
         int r = sput(W.RFH, W.rfhcap, (unsigned)face_ckey(M, h >> 2, h & 3) + 1u);
-        if (r < 0) { S.over = 1; return; }
+        if (r < 0) { S.over |= OV_RF; return; }
         if (r == 1) {
             int idx = atomicAdd(&S.nrf, 1);
-            if (idx < W.maxrf && 2 * idx < W.rfhcap) W.rf[idx] = h; else S.over = 1;
+            if (idx < W.maxrf && 2 * idx < W.rfhcap) W.rf[idx] = h; else S.over |= OV_RF;
         }
     };
     auto in_rf = [&](int t, int f) { return shas(W.RFH, W.rfhcap, (unsigned)face_ckey(M, t, f) + 1u); };
@@ -238,11 +321,13 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
 
     // ---- R_T: tets whose circumsphere strictly holds p, connected to the
     // seeds across faces that are not subfaces (or are region subfaces)
+    bool over_rt = false;
     {
         int head = 0;
         while (true) {
             const int end = S.nrt;
-            const bool stop = head >= end || S.over;
+            over_rt = S.over != 0;
+            const bool stop = head >= end || over_rt;
             __syncthreads();              // every lane has read the level bounds
             if (stop) break;
             int items = (end - head) * 4;
@@ -261,13 +346,13 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 bool inside = insphere(A, B, Cc, D, P) > 0;
                 unsigned os;
                 int r = hput(W.H, W.hcap, key, inside ? HS_IN : HS_OUT, &os);
-                if (r < 0) { S.over = 1; continue; }
+                if (r < 0) { S.over |= OV_HASH; continue; }
                 if (r == 1) {
                     int c = atomicAdd(&S.hcount, 1);
-                    if (4 * c > 3 * W.hcap) S.over = 1;
+                    if (4 * c > 3 * W.hcap) S.over |= OV_HASH;
                     if (inside) {
                         int idx = atomicAdd(&S.nrt, 1);
-                        if (idx < W.maxrt) W.rt[idx] = n; else S.over = 1;
+                        if (idx < W.maxrt) W.rt[idx] = n; else S.over |= OV_RT;
                     }
                 }
             }
@@ -275,15 +360,12 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             head = end;
         }
     }
-    if (S.over) {
-        if (lane == 0) C.gst[cid] = ST_OVERFLOW;
+    if (over_rt) {                        // read before the last level barrier
+        if (lane == 0) over_status(C, PL, W, cid, S.over);
         return;
     }
     const int nrt = S.nrt, nrf = S.nrf;
-    if (lane == 0 && BP.prof) {
-        atomicAdd(&BP.prof[0], (unsigned long long)S.hcount);
-        atomicAdd(&BP.prof[1], (unsigned long long)nrt);
-    }
+    if (lane == 0) { S.prof[0] += S.hcount; S.prof[1] += nrt; }
     auto in_rt = [&](int t) { return hget(W.H, W.hcap, (unsigned)t + 1u) == HS_IN; };
     auto fail = [&](int reason) { S.fail = 1; S.reason = reason; };   // one reason per phase
 
@@ -301,8 +383,8 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 xyz(M, at4(v, c_EV[j][0]), A); xyz(M, at4(v, c_EV[j][1]), B);
                 if (segdot(A, B, P) < 0) {
                     int r = qput(W.QH, W.qhcap, ((unsigned long long)s << 1) + 1ull);
-                    if (r == 1) { int idx = atomicAdd(&S.nq, 1); if (idx < W.maxq) W.q[idx] = make_int2(0, s); else S.over = 1; }
-                    if (r < 0) S.over = 1;
+                    if (r == 1) { int idx = atomicAdd(&S.nq, 1); if (idx < W.maxq) W.q[idx] = make_int2(0, s); else S.over |= OV_Q; }
+                    if (r < 0) S.over |= OV_Q;
                 }
             } else {
                 int f = j - 6;
@@ -312,17 +394,20 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 if (facedot(A, B, Cc, P) < 0) {
                     int ck = face_ckey(M, t, f);
                     int r = qput(W.QH, W.qhcap, ((unsigned long long)ck << 1) + 2ull);
-                    if (r == 1) { int idx = atomicAdd(&S.nq, 1); if (idx < W.maxq) W.q[idx] = make_int2(1, ck); else S.over = 1; }
-                    if (r < 0) S.over = 1;
+                    if (r == 1) { int idx = atomicAdd(&S.nq, 1); if (idx < W.maxq) W.q[idx] = make_int2(1, ck); else S.over |= OV_Q; }
+                    if (r < 0) S.over |= OV_Q;
                 }
             }
         }
         __syncthreads();
-        if (S.over) {
-            if (lane == 0) C.gst[cid] = ST_OVERFLOW;
+        const bool over_q = S.over != 0;
+        const int nq = S.nq;
+        __syncthreads();                  // flags read before any lane goes on
+        if (over_q) {
+            if (lane == 0) over_status(C, PL, W, cid, S.over);
             return;
         }
-        if (S.nq > 0) {
+        if (nq > 0) {
             // rejected: queue the targets, unless all of them are exempt
             __shared__ int any_live;
             if (lane == 0) any_live = 0;
@@ -337,7 +422,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             if (lane == 0) {
                 if (any_live) {
                     int base = atomicAdd(&PL.ctr[4], S.nq);
-                    if (base + S.nq > PL.cap_q) { atomicOr(&PL.ctr[5], 1); C.gst[cid] = ST_OVERFLOW; S.base_q = -1; }
+                    if (base + S.nq > PL.cap_q) { atomicOr(&PL.ctr[5], 1); C.gst[cid] = ST_POOLFULL; S.base_q = -1; }
                     else { C.gst[cid] = ST_REJECT; C.greason[cid] = EX_NONE; C.q_off[cid] = base; C.q_n[cid] = S.nq; S.base_q = base; }
                 } else {
                     C.gst[cid] = ST_EXEMPT; C.greason[cid] = EX_ENC_EXEMPT; S.base_q = -1;
@@ -378,8 +463,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         int nb = M.TA[4 * (size_t)(h >> 2) + (h & 3)];
         if (!in_rt(h >> 2) || (nb >= 0 && !in_rt(nb >> 2))) fail(EX_RFTET);
     }
-    __syncthreads();
-    if (S.fail) {
+    if (phase_end(S)) {
         if (lane == 0) { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
         return;
     }
@@ -401,12 +485,17 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         int idx = atomicAdd(&S.nbf, 1);
         if (idx < W.maxbf) {
             // stage the face record in the claim scratch (x, y, z, neighbour)
-            W.cx[4 * idx] = x; W.cx[4 * idx + 1] = y; W.cx[4 * idx + 2] = z; W.cx[4 * idx + 3] = (t << 2) | f;
-        } else S.over = 1;
+            int* r = W.cx + CXW * idx;
+            r[0] = x; r[1] = y; r[2] = z; r[3] = (t << 2) | f;
+        } else S.over |= OV_BF;
     }
-    __syncthreads();
-    if (S.over) { if (lane == 0) C.gst[cid] = ST_OVERFLOW; return; }
-    if (S.fail) { if (lane == 0) { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; } return; }
+    if (phase_end(S)) {
+        if (lane == 0) {
+            if (S.over) over_status(C, PL, W, cid, S.over);
+            else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
+        }
+        return;
+    }
     const int nbf = S.nbf;
 
     // ---- (e) 2D boundary edges of R_F must see p strictly inside, in the
@@ -433,84 +522,158 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             if (op == 0 || op != oz) { fail(EX_EDGE2D); continue; }
             int one = M.TA[4 * (size_t)t + f] < 0 ? 1 : 0;
             int idx = atomicAdd(&S.nbe, 1);
-            if (idx < W.maxbe) W.be[idx] = make_int4(x, y, F, one); else S.over = 1;
+            if (idx < W.maxbe) W.be[idx] = make_int4(x, y, F, one); else S.over |= OV_BE;
         }
-        __syncthreads();
-        if (S.over) { if (lane == 0) C.gst[cid] = ST_OVERFLOW; return; }
+        if (phase_end(S)) {
+            if (lane == 0) {
+                if (S.over) over_status(C, PL, W, cid, S.over);
+                else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
+            }
+            return;
+        }
         const int nbe = S.nbe;
-        for (int i = lane; i < nbe; i += 64)                  // one new subface per edge
-            for (int j = i + 1; j < nbe; ++j)
-                if (W.be[i].x == W.be[j].x && W.be[i].y == W.be[j].y) fail(EX_EDGE2D);
-        __syncthreads();
-        if (S.fail) { if (lane == 0) { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; } return; }
+        // one new subface per edge: no two 2D boundary edges alike
+        if (W.ehcap) {
+            const int ecap = eclear(W, 3 * nbf + nbe);
+            __syncthreads();
+            for (int i = lane; i < nbe; i += 64) {
+                int4 e = W.be[i];
+                int sl = eput(W.EK, ecap, ekey(e.x, e.y));
+                if (sl < 0) { S.over |= OV_EDGE; continue; }
+                atomicAdd(&W.EV[sl].w, 1 + (e.w ? 0x10000 : 0));
+            }
+            __syncthreads();
+            for (int i = lane; i < nbe; i += 64) {
+                int4 e = W.be[i];
+                int sl = eget(W.EK, ecap, ekey(e.x, e.y));
+                if (sl >= 0 && (W.EV[sl].w & 0xFFFF) > 1) fail(EX_EDGE2D);
+            }
+        } else {
+            for (int i = lane; i < nbe; i += 64)
+                for (int j = i + 1; j < nbe; ++j)
+                    if (W.be[i].x == W.be[j].x && W.be[i].y == W.be[j].y) fail(EX_EDGE2D);
+        }
+        if (phase_end(S)) {
+            if (lane == 0) {
+                if (S.over) over_status(C, PL, W, cid, S.over);
+                else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
+            }
+            return;
+        }
+    } else if (W.ehcap) {
+        eclear(W, 3 * nbf);
     }
     const int nbe = S.nbe;
 
     // ---- (f) the boundary closes up around p: each edge of a boundary face
     // lies on two boundary faces (one for a 2D boundary edge of a one-sided
-    // region subface); every 2D boundary edge lies on as many
-    for (int k = lane; k < nbf * 3 + nbe; k += 64) {
-        int x, y;
-        if (k < nbf * 3) {
-            int i = k / 3, j = k % 3;
-            x = W.cx[4 * i + j]; y = W.cx[4 * i + (j + 1) % 3];
-        } else {
-            int4 e = W.be[k - nbf * 3];
-            x = e.x; y = e.y;
+    // region subface); every 2D boundary edge lies on as many.  The face
+    // sharing each edge is recorded: it is the neighbour of the new tet.
+    // Edge of face i opposite its slot l: l = 0 (y,z), 1 (x,z), 2 (x,y).
+    if (W.ehcap) {
+        int ecap = 64;
+        while (ecap < 2 * (3 * nbf + nbe)) ecap <<= 1;
+        if (ecap > W.ehcap) ecap = W.ehcap;
+        __syncthreads();                  // table cleared (and 2D boundary edges in)
+        for (int k = lane; k < 3 * nbf; k += 64) {
+            const int i = k / 3, l = k % 3;
+            const int* r = W.cx + CXW * i;
+            int sl = eput(W.EK, ecap, ekey(l == 0 ? r[1] : r[0], l == 2 ? r[1] : r[2]));
+            if (sl < 0) { S.over |= OV_EDGE; continue; }
+            atomicAdd(&W.EV[sl].x, 1);
+            const int fe = (i << 2) | l;
+            if (atomicCAS(&W.EV[sl].y, -1, fe) != -1) atomicCAS(&W.EV[sl].z, -1, fe);
         }
-        int lo = x < y ? x : y, hi = x < y ? y : x;
-        int cnt = 0;
-        for (int i = 0; i < nbf; ++i) {
-            int a = W.cx[4 * i], b = W.cx[4 * i + 1], c = W.cx[4 * i + 2];
-            bool hx = a == x || b == x || c == x, hy = a == y || b == y || c == y;
-            cnt += hx && hy;
+        __syncthreads();
+        for (int k = lane; k < 3 * nbf + nbe; k += 64) {
+            unsigned long long key;
+            if (k < 3 * nbf) {
+                const int* r = W.cx + CXW * (k / 3);
+                const int l = k % 3;
+                key = ekey(l == 0 ? r[1] : r[0], l == 2 ? r[1] : r[2]);
+            } else {
+                int4 e = W.be[k - 3 * nbf];
+                key = ekey(e.x, e.y);
+            }
+            int sl = eget(W.EK, ecap, key);
+            int4 ev = sl >= 0 ? W.EV[sl] : make_int4(0, -1, -1, 0);
+            int want = (ev.w & 0x10000) ? 1 : 2;
+            if (ev.x != want) { fail(EX_MANIFOLD); continue; }
+            if (k < 3 * nbf) {
+                const int fe = ((k / 3) << 2) | (k % 3);
+                W.cx[CXW * (k / 3) + 4 + k % 3] = want == 1 ? -1 : (ev.y == fe ? ev.z : ev.y);
+            }
         }
-        int want = 2;
-        for (int i = 0; i < nbe; ++i) {
-            int4 e = W.be[i];
-            if (e.x == lo && e.y == hi && e.w) want = 1;
+    } else {
+        for (int k = lane; k < 3 * nbf + nbe; k += 64) {
+            int u, w, i = -1, l = 0;
+            if (k < 3 * nbf) {
+                i = k / 3; l = k % 3;
+                const int* r = W.cx + CXW * i;
+                u = l == 0 ? r[1] : r[0];
+                w = l == 2 ? r[1] : r[2];
+            } else {
+                int4 e = W.be[k - 3 * nbf];
+                u = e.x; w = e.y;
+            }
+            int cnt = 0, partner = -1;
+            for (int m = 0; m < nbf; ++m) {
+                const int* q = W.cx + CXW * m;
+                bool hu = q[0] == u || q[1] == u || q[2] == u, hw = q[0] == w || q[1] == w || q[2] == w;
+                if (hu && hw) {
+                    ++cnt;
+                    if (m != i) partner = (m << 2) | ((q[0] != u && q[0] != w) ? 0 : ((q[1] != u && q[1] != w) ? 1 : 2));
+                }
+            }
+            const int lo = u < w ? u : w, hi = u < w ? w : u;
+            int want = 2;
+            for (int j = 0; j < nbe; ++j) {
+                int4 e = W.be[j];
+                if (e.x == lo && e.y == hi && e.w) want = 1;
+            }
+            if (cnt != want) { fail(EX_MANIFOLD); continue; }
+            if (i >= 0) W.cx[CXW * i + 4 + l] = want == 1 ? -1 : partner;
         }
-        if (cnt != want) fail(EX_MANIFOLD);
     }
-    __syncthreads();
-    if (S.fail) { if (lane == 0) { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; } return; }
+    if (phase_end(S)) {
+        if (lane == 0) {
+            if (S.over) over_status(C, PL, W, cid, S.over);
+            else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
+        }
+        return;
+    }
 
     // ---- accepted: claim set = region tets + tets across boundary faces
-    int* cext = W.cx + 4 * W.maxbf;              // extra claims after the face records
+    int* cext = W.cx + CXW * W.maxbf;            // extra claims after the face records
     for (int i = lane; i < nbf; i += 64) {
-        int h = W.cx[4 * i + 3];
+        int h = W.cx[CXW * i + 3];
         int nb = M.TA[4 * (size_t)(h >> 2) + (h & 3)];
         if (nb < 0) continue;
         int r = hclaim(W.H, W.hcap, (unsigned)(nb >> 2) + 1u);
         if (r == 1) {
             int idx = atomicAdd(&S.ncx, 1);
-            if (idx < W.maxcx) cext[idx] = nb >> 2; else S.over = 1;
-        } else if (r < 0) S.over = 1;
+            if (idx < W.maxcx) cext[idx] = nb >> 2; else S.over |= OV_CX;
+        } else if (r < 0) S.over |= OV_HASH;
     }
-    __syncthreads();
-    if (S.over) { if (lane == 0) C.gst[cid] = ST_OVERFLOW; return; }
+    if (phase_end(S)) {
+        if (lane == 0) over_status(C, PL, W, cid, S.over);
+        return;
+    }
     const int ncx = S.ncx;
     if (lane == 0) {
         // region, face and edge pools are only read through this candidate's
         // offsets; the claim pool is scanned whole by the selection, so a
-        // claim range is reserved all-or-nothing and only when it will be filled
+        // reserved claim range that will not be filled is marked void (-1)
         int br = atomicAdd(&PL.ctr[0], nrt);
         int bb = atomicAdd(&PL.ctr[1], nbf);
         int be = atomicAdd(&PL.ctr[2], nbe);
+        int bc = atomicAdd(&PL.ctr[3], nrt + ncx);
         bool full = br + nrt > PL.cap_reg || bb + nbf > PL.cap_bf || bb + nbf > BP.cap ||
-                    be + nbe > PL.cap_be;
-        int bc = -1;
-        if (!full) {
-            int cur = atomicAdd(&PL.ctr[3], 0);
-            while (true) {
-                if (cur + nrt + ncx > PL.cap_cl) { full = true; break; }
-                int prev = atomicCAS(&PL.ctr[3], cur, cur + nrt + ncx);
-                if (prev == cur) { bc = cur; break; }
-                cur = prev;
-            }
-        }
-        if (full) { atomicOr(&PL.ctr[5], 1); C.gst[cid] = ST_OVERFLOW; S.base_reg = -1; }
-        else {
+                    be + nbe > PL.cap_be || bc + nrt + ncx > PL.cap_cl;
+        if (full) {
+            atomicOr(&PL.ctr[5], 1); C.gst[cid] = ST_POOLFULL; S.base_reg = -1;
+            S.base_cl = bc;
+        } else {
             S.base_reg = br; S.base_bf = bb; S.base_be = be; S.base_cl = bc;
             C.reg_off[cid] = br; C.reg_n[cid] = nrt;
             C.bf_off[cid] = bb; C.bf_n[cid] = nbf;
@@ -520,11 +683,12 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
     }
     __syncthreads();
-    if (S.base_reg < 0) return;
-    if (lane == 0 && BP.prof) {
-        atomicAdd(&BP.prof[2], (unsigned long long)nbf);
-        atomicAdd(&BP.prof[3], (unsigned long long)(nrt + ncx));
+    if (S.base_reg < 0) {
+        const int end = S.base_cl + nrt + ncx < PL.cap_cl ? S.base_cl + nrt + ncx : PL.cap_cl;
+        for (int k = S.base_cl + lane; k < end; k += 64) PL.clc[k] = -1;
+        return;
     }
+    if (lane == 0) { S.prof[2] += nbf; S.prof[3] += nrt + ncx; }
     for (int k = lane; k < nrt; k += 64) {
         PL.reg[S.base_reg + k] = W.rt[k];
         PL.cl[S.base_cl + k] = W.rt[k]; PL.clc[S.base_cl + k] = cid;
@@ -532,7 +696,8 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     for (int k = lane; k < ncx; k += 64) { PL.cl[S.base_cl + nrt + k] = cext[k]; PL.clc[S.base_cl + nrt + k] = cid; }
     for (int k = lane; k < nbe; k += 64) PL.be[S.base_be + k] = W.be[k];
     for (int i = lane; i < nbf; i += 64) {
-        int x = W.cx[4 * i], y = W.cx[4 * i + 1], z = W.cx[4 * i + 2], h = W.cx[4 * i + 3];
+        const int* rc = W.cx + CXW * i;
+        int x = rc[0], y = rc[1], z = rc[2], h = rc[3];
         int t = h >> 2, f = h & 3;
         int4 v = ld4(M.TV, t);
         int lx = local_of(v, x), ly = local_of(v, y), lz = local_of(v, z);
@@ -540,15 +705,15 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         int4 r0 = make_int4(x, y, z, M.TA[4 * (size_t)t + f]);
         int4 r1 = make_int4(M.TF[4 * (size_t)t + f], 0, ts[c_EIDX[lx][ly]], ts[c_EIDX[ly][lz]]);
         int4 r2 = make_int4(ts[c_EIDX[lz][lx]], h, 0, 0);
-        BP.r[3 * (size_t)(S.base_bf + i)] = r0;
-        BP.r[3 * (size_t)(S.base_bf + i) + 1] = r1;
-        BP.r[3 * (size_t)(S.base_bf + i) + 2] = r2;
+        int4* out = BP.r + BFR * (size_t)(S.base_bf + i);
+        out[0] = r0; out[1] = r1; out[2] = r2; out[3] = make_int4(rc[4], rc[5], rc[6], 0);
         PL.bf[S.base_bf + i] = h;
     }
 }
 
 template <int MAXRT, int HCAP, int RFHCAP, int MAXRF, int MAXBE, int QHCAP, int MAXQ, int MAXBF>
-__global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP) {
+__global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                                 const int* list, int nlist) {
     __shared__ int rt[MAXRT];
     __shared__ unsigned H[HCAP];
     __shared__ unsigned RFH[RFHCAP];
@@ -556,10 +721,15 @@ __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools
     __shared__ int4 be[MAXBE];
     __shared__ unsigned long long QH[QHCAP];
     __shared__ int2 q[MAXQ];
-    __shared__ int cx[4 * MAXBF + MAXBF];
+    __shared__ int cx[CXW * MAXBF + MAXBF];
     __shared__ GrowShared S;
-    GrowTiles W{rt, H, RFH, rf, be, QH, q, cx, MAXRT, HCAP, RFHCAP, MAXRF, MAXBE, QHCAP, MAXQ, MAXBF, MAXBF};
-    for (int cid = blockIdx.x; cid < C.n; cid += gridDim.x) {
+    GrowTiles W{rt, H, RFH, rf, be, QH, q, cx, MAXRT, HCAP, RFHCAP, MAXRF, MAXBE, QHCAP, MAXQ, MAXBF, MAXBF, 0,
+                nullptr, nullptr, 0};
+    prof_begin(S);
+    // all candidates in priority order, or the re-run list (pool-full ones)
+    const int n = list ? nlist : C.n;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int cid = list ? list[i] : i;
         if (C.st[cid] != ST_PENDING) {
             if (threadIdx.x == 0) { C.gst[cid] = C.st[cid]; C.greason[cid] = C.reason[cid]; }
             continue;
@@ -567,6 +737,7 @@ __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools
         grow_one(M, cls, C, PL, BP, cid, W, S);
         __syncthreads();
     }
+    prof_flush(S, BP);
 }
 
 // re-run of the candidates that overflowed the LDS tiles (or a pool), with
@@ -586,18 +757,23 @@ __global__ __launch_bounds__(64) void k_grow_global(Mesh M, int cls, Cands C, Po
     W.be = (int4*)carve(sizeof(int4) * T.maxbe);
     W.QH = (unsigned long long*)carve(sizeof(unsigned long long) * T.qhcap);
     W.q = (int2*)carve(sizeof(int2) * T.maxq);
-    W.cx = (int*)carve(sizeof(int) * (4 * T.maxbf + T.maxcx));
+    W.cx = (int*)carve(sizeof(int) * (CXW * T.maxbf + T.maxcx));
+    W.EK = (unsigned long long*)carve(sizeof(unsigned long long) * T.ehcap);
+    W.EV = (int4*)carve(sizeof(int4) * T.ehcap);
+    prof_begin(S);
     for (int i = blockIdx.x; i < nlist; i += gridDim.x) {
         grow_one(M, cls, C, PL, BP, list[i], W, S);
         __syncthreads();
     }
+    prof_flush(S, BP);
 }
 
 inline size_t grow_slab_bytes(const GrowTiles& T) {
     auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
     return r(sizeof(int) * T.maxrt) + r(sizeof(unsigned) * T.hcap) + r(sizeof(unsigned) * T.rfhcap) +
            r(sizeof(int) * T.maxrf) + r(sizeof(int4) * T.maxbe) + r(sizeof(unsigned long long) * T.qhcap) +
-           r(sizeof(int2) * T.maxq) + r(sizeof(int) * (4 * T.maxbf + T.maxcx));
+           r(sizeof(int2) * T.maxq) + r(sizeof(int) * (CXW * T.maxbf + T.maxcx)) +
+           r(sizeof(unsigned long long) * T.ehcap) + r(sizeof(int4) * T.ehcap);
 }
 
 }  // namespace qm

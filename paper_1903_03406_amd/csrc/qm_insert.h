@@ -72,7 +72,7 @@ __global__ void k_mis_mark(int ncl, const int* cl, const int* clc, const int* st
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= ncl) return;
     int c = clc[e];
-    if (c < 0) { atomicOr(&g_geom_error, 128); return; }
+    if (c < 0) return;                 // void range (reservation that did not fit)
     if (state[c] != 0) return;
     atomicMax(&mark[cl[e]], mis_val(pass, c));
 }
@@ -101,7 +101,7 @@ __global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* 
 // a per-round cap demoted afterwards)
 __global__ void k_mis_release(int ncl, const int* cl, const int* clc, int* owner) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ncl) return;
+    if (e >= ncl || clc[e] < 0) return;
     if (owner[cl[e]] == clc[e]) owner[cl[e]] = -1;
 }
 
@@ -160,40 +160,31 @@ __global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools P
         // phase A: read the face flags of the old boundary faces before any
         // slot of this region is overwritten
         for (int j = lane; j < nf; j += 64) {
-            int h = BP.r[3 * (size_t)(bf0 + j) + 2].y;
+            int4* rec = BP.r + BFR * (size_t)(bf0 + j);
+            int h = rec[2].y;
             unsigned ti = M.TI[h >> 2];
             int f = h & 3;
-            int fl = (int)(((ti >> (4 + f)) & 1u) | (((ti >> (8 + f)) & 1u) << 1));
-            BP.r[3 * (size_t)(bf0 + j) + 1].y = fl;
+            rec[1].y = (int)(((ti >> (4 + f)) & 1u) | (((ti >> (8 + f)) & 1u) << 1));
         }
         __syncthreads();
         auto slot = [&](int j) { return j < nk ? PL.reg[rg0 + j] : tbase + (j - nk); };
         // phase B: write the new tets
         for (int j = lane; j < nf; j += 64) {
-            int4 r0 = BP.r[3 * (size_t)(bf0 + j)];
-            int4 r1 = BP.r[3 * (size_t)(bf0 + j) + 1];
-            int4 r2 = BP.r[3 * (size_t)(bf0 + j) + 2];
+            const int4* rec = BP.r + BFR * (size_t)(bf0 + j);
+            const int4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
             const int x = r0.x, y = r0.y, z = r0.z;
             const int sj = slot(j);
-            // faces through p: opposite x holds edge (y,z), opposite y (x,z), opposite z (x,y)
+            // faces through p: opposite x holds edge (y,z), opposite y (x,z),
+            // opposite z (x,y); the neighbour across each is the new tet of the
+            // boundary face sharing that edge (recorded by the validation)
             const int ea[3] = {y, x, x}, eb[3] = {z, z, y};
+            const int pr[3] = {r3.x, r3.y, r3.z};
             int adj[3], fid[3];
             for (int l = 0; l < 3; ++l) {
-                int u = ea[l], w = eb[l];
-                adj[l] = -1;
-                for (int m = 0; m < nf; ++m) {
-                    if (m == j) continue;
-                    int4 q0 = BP.r[3 * (size_t)(bf0 + m)];
-                    bool hu = q0.x == u || q0.y == u || q0.z == u;
-                    bool hw = q0.x == w || q0.y == w || q0.z == w;
-                    if (hu && hw) {
-                        int lm = (q0.x != u && q0.x != w) ? 0 : ((q0.y != u && q0.y != w) ? 1 : 2);
-                        adj[l] = (slot(m) << 2) | lm;
-                        break;
-                    }
-                }
+                adj[l] = pr[l] < 0 ? -1 : ((slot(pr[l] >> 2) << 2) | (pr[l] & 3));
                 fid[l] = -1;
-                int lo = u < w ? u : w, hi = u < w ? w : u;
+                const int u = ea[l], w = eb[l];
+                const int lo = u < w ? u : w, hi = u < w ? w : u;
                 for (int m = 0; m < nbe; ++m) {
                     int4 e = PL.be[be0 + m];
                     if (e.x == lo && e.y == hi) { fid[l] = e.z; break; }

@@ -78,6 +78,7 @@ struct qm_result {
     std::vector<int32_t> tets, sf, sff, ss, ssg;
     std::vector<int32_t> rounds;   // QM_ROUND_FIELDS per round
     std::vector<int32_t> last;     // last round's candidates, 9 per candidate
+    std::vector<double> round_ms;  // QM_PROFILE: QM_PROF_FAMILIES device ms per round
     qm_stats stats;
 };
 
@@ -91,17 +92,24 @@ __global__ void k_fill(int n, int* o, int v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = v;
 }
-__global__ void k_overflow_list(Cands C, int* list, int* n) {
+// candidates to evaluate again: regions over the LDS or global-memory tiles
+// (list a, count n[0]) and candidates whose results did not fit a pool (list
+// b, count n[1]); n[2] counts the regions over the global-memory tiles
+__global__ void k_overflow_list(Cands C, int* la, int* lb, int* n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < C.n && C.st[i] == ST_PENDING && C.gst[i] == ST_OVERFLOW) list[atomicAdd(n, 1)] = i;
+    if (i >= C.n || C.st[i] != ST_PENDING) return;
+    if (C.gst[i] == ST_OVERFLOW || C.gst[i] == ST_TOOBIG) la[atomicAdd(&n[0], 1)] = i;
+    else if (C.gst[i] == ST_POOLFULL) lb[atomicAdd(&n[1], 1)] = i;
+    if (C.gst[i] == ST_TOOBIG) atomicAdd(&n[2], 1);
 }
 
 // LDS tiles of the fast grow path (one 64-lane workgroup per candidate)
 constexpr int G_MAXRT = 256, G_HCAP = 1024, G_RFHCAP = 128, G_MAXRF = 48, G_MAXBE = 96, G_QHCAP = 128,
-              G_MAXQ = 64, G_MAXBF = 384;
+              G_MAXQ = 64, G_MAXBF = 256;
 // global-slab tiles of the overflow path
 constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, B_MAXBE = 4096,
               B_QHCAP = 8192, B_MAXQ = 4096, B_MAXBF = 32768;
+constexpr int B_MAXSCALE = 64;     // largest scale of the global tiles (1M region tets)
 
 struct Engine {
     hipStream_t s;
@@ -121,7 +129,7 @@ struct Engine {
     DBuf<int4> c_tup0;
     DBuf<double4> c_p0;
     DBuf<int> c_elem, c_st, c_reason, c_seed, gst, greason, reg_off, reg_n, bf_off, bf_n, be_off, be_n,
-        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist;
+        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, plist;
     DBuf<unsigned long long> c_key;
     DBuf<int4> c_tup;
     DBuf<double4> c_p;
@@ -131,7 +139,7 @@ struct Engine {
     DBuf<int4> p_be, p_bfr;
     DBuf<int2> p_q;
     DBuf<int> ctr;     // pool counters [0..5], ncand [8], undecided [9], totals [10..12], err [13],
-                       // dead [14], stats [16..31], olist count [32]
+                       // dead [14], stats [16..31], re-run list counts [32..34]
     DBuf<char> tmp;    // hipcub scratch
     DBuf<char> slab;   // overflow grow tiles
     Cands C{};
@@ -144,8 +152,9 @@ struct Engine {
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_cat;
     int ev_used = 0;
-    double prof_ms[8] = {0};
-    int64_t prof_n[8] = {0};
+    double prof_ms[QM_PROF_FAMILIES] = {0};
+    int64_t prof_n[QM_PROF_FAMILIES] = {0};
+    int64_t prof_over = 0, prof_full = 0;
     DBuf<unsigned long long> pctr;
     void pbegin() {
         if (!prof) return;
@@ -162,11 +171,12 @@ struct Engine {
         ev_used += 2;
         prof_n[cat]++;
     }
-    void pflush() {          // after a stream synchronisation
+    void pflush(double* round_ms = nullptr) {   // after a stream synchronisation
         for (int i = 0; i < ev_used; i += 2) {
             float ms = 0;
             HIPCK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
             prof_ms[ev_cat[i]] += ms;
+            if (round_ms) round_ms[ev_cat[i]] += ms;
         }
         ev_used = 0;
     }
@@ -180,7 +190,7 @@ struct Engine {
         mark.release(s); owner.release(s);
         for (auto* b : {&cand_out, &c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
                         &c_seed, &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off,
-                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &p_reg,
+                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &p_reg,
                         &p_bf, &p_cl, &p_clc, &ctr})
             b->release(s);
         c_key0.release(s); skey.release(s); c_key.release(s);
@@ -213,7 +223,7 @@ struct Engine {
         size_t m = std::max(n, 1);
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
                         &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
-                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist})
+                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist})
             b->ensure(m, s, false);
         c_key0.ensure(m, s, false); skey.ensure(m, s, false); c_key.ensure(m, s, false);
         c_tup0.ensure(m, s, false); c_tup.ensure(m, s, false);
@@ -226,12 +236,28 @@ struct Engine {
         C.q_off = q_off.p; C.q_n = q_n.p; C.state = state.p;
     }
     void ensure_pools(size_t reg, size_t bf, size_t be, size_t cl, size_t q, bool keep) {
-        p_reg.ensure(reg, s, keep); p_bf.ensure(bf, s, keep); p_bfr.ensure(3 * bf, s, keep);
-        p_be.ensure(be, s, keep); p_cl.ensure(cl, s, keep); p_clc.ensure(cl, s, keep); p_q.ensure(q, s, keep);
+        p_reg.ensure(reg, s, keep); p_bf.ensure(bf, s, keep); p_bfr.ensure(BFR * bf, s, keep);
+        p_be.ensure(be, s, keep); p_cl.ensure(cl, s, keep); p_q.ensure(q, s, keep);
+        p_clc.ensure(cl, s, keep, 0xFF);   // new claim entries start void
         PL.reg = p_reg.p; PL.bf = p_bf.p; PL.be = p_be.p; PL.cl = p_cl.p; PL.clc = p_clc.p; PL.q = p_q.p;
         PL.cap_reg = (int)p_reg.cap; PL.cap_bf = (int)p_bf.cap; PL.cap_be = (int)p_be.cap;
         PL.cap_cl = (int)p_cl.cap; PL.cap_q = (int)p_q.cap; PL.ctr = ctr.p;
-        BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / 3); BP.prof = prof ? pctr.p : nullptr;
+        BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / BFR); BP.prof = prof ? pctr.p : nullptr;
+    }
+    // pool entries per candidate seen in the last round (region tets,
+    // boundary faces, 2D boundary edges, claims, queue entries); the next
+    // round reserves 1.5x that plus slack
+    // pool entries per candidate (region tets, boundary faces, 2D boundary
+    // edges, claims, queue entries) used by the last round of each class
+    // (counters include ranges of re-run candidates); the next round of the
+    // class reserves 1.25x that plus slack
+    double pool_rate[3][5] = {{24, 48, 8, 56, 4}, {24, 48, 8, 56, 4}, {24, 48, 8, 56, 4}};
+    size_t pool_need(int k, int ncand, int cls) const {
+        return (size_t)(pool_rate[cls][k] * 1.25 * ncand) + 4096;
+    }
+    void pool_seen(const int* used, int ncand, int cls) {
+        if (ncand <= 0) return;
+        for (int k = 0; k < 5; ++k) pool_rate[cls][k] = (double)used[k] / ncand;
     }
     void* scratch(size_t bytes) {
         tmp.ensure(bytes, s, false);
@@ -367,13 +393,28 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     int* dead_d = E.ctr.p + 14;
     int* stats_d = E.ctr.p + 16;
     int* olist_n = E.ctr.p + 32;
-    int round = 0, status = 0;
-    GrowTiles BT{};
-    BT.maxrt = B_MAXRT; BT.hcap = B_HCAP; BT.rfhcap = B_RFHCAP; BT.maxrf = B_MAXRF; BT.maxbe = B_MAXBE;
-    BT.qhcap = B_QHCAP; BT.maxq = B_MAXQ; BT.maxbf = B_MAXBF; BT.maxcx = B_MAXBF;
-    const size_t slab_block = grow_slab_bytes(BT);
+    int round = 0, status = 0, last_ncand = 0;
+    // global-memory tiles: scale 1 first; a region over them (cavities can
+    // grow with the number of vertices a point sees, e.g. next to a dense
+    // cluster) makes the round retry those candidates at 4x the scale
+    int tile_scale = 1;
+    auto big_tiles = [&](int k) {
+        GrowTiles T{};
+        T.maxrt = B_MAXRT * k; T.hcap = B_HCAP * k; T.rfhcap = B_RFHCAP * k; T.maxrf = B_MAXRF * k;
+        T.maxbe = B_MAXBE * k; T.qhcap = B_QHCAP * k; T.maxq = B_MAXQ * k; T.maxbf = B_MAXBF * k;
+        T.maxcx = B_MAXBF * k; T.big = 1;
+        T.ehcap = 1;
+        while (T.ehcap < 2 * (3 * T.maxbf + T.maxbe)) T.ehcap <<= 1;
+        return T;
+    };
     const bool verbose = (opt->flags & QM_VERBOSE) != 0;
     auto last_note = std::chrono::steady_clock::now();
+    // progress inside a long round (verbose): at most one line per 10 s
+    auto note = [&](const char* phase, int round_, int cls_, int n_) {
+        if (!verbose || std::chrono::steady_clock::now() - last_note < std::chrono::seconds(10)) return;
+        last_note = std::chrono::steady_clock::now();
+        fprintf(stderr, "qm: round %d class %d %s (%d)\n", round_, cls_, phase, n_);
+    };
     for (;; ++round) {
         if (round >= opt->max_rounds) { status = 1; break; }
         int cls = CLS_NONE, ncand = 0;
@@ -406,39 +447,63 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.pend(1);
         // step 3: locate
         if (cls != CLS_SS) { E.pbegin(); k_locate<<<nblk(ncand, 64), 64, 0, s>>>(E.M, cls, E.C); E.pend(2); }
-        // steps 4-5: grow and validate
+        // steps 4-5: grow and validate.  Pools are sized from the previous
+        // round's use per candidate; candidates whose results did not fit are
+        // evaluated again after the pools grow, and regions over the LDS tiles
+        // are evaluated again with global-memory tiles.
         HIPCK(hipMemsetAsync(E.ctr.p, 0, 8 * sizeof(int), s));
-        E.ensure_pools((size_t)ncand * 24 + 4096, (size_t)ncand * 48 + 4096, (size_t)ncand * 4 + 4096,
-                       (size_t)ncand * 56 + 4096, (size_t)ncand * 2 + 4096, false);
+        HIPCK(hipMemsetAsync(E.ctr.p + 35, 0, sizeof(int), s));
+        E.ensure_pools(E.pool_need(0, ncand, cls), E.pool_need(1, ncand, cls), E.pool_need(2, ncand, cls),
+                       E.pool_need(3, ncand, cls), E.pool_need(4, ncand, cls), false);
         {
             int grid = std::min(ncand, 16384);
             E.pbegin();
             k_grow_lds<G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF>
-                <<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP);
+                <<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, nullptr, 0);
             E.pend(3);
         }
         for (int attempt = 0;; ++attempt) {
-            HIPCK(hipMemsetAsync(olist_n, 0, sizeof(int), s));
-            k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, olist_n);
-            int nover = read1(olist_n, s);
-            if (nover == 0) break;
-            if (attempt >= 4) throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size");
-            int full = read1(E.ctr.p + 5, s);
-            if (full) {
-                int used[5];
-                HIPCK(hipMemcpyAsync(used, E.ctr.p, sizeof used, hipMemcpyDeviceToHost, s));
-                HIPCK(hipStreamSynchronize(s));
-                E.ensure_pools(2 * (size_t)used[0] + (size_t)nover * B_MAXRT, 2 * (size_t)used[1] + (size_t)nover * B_MAXBF,
-                               2 * (size_t)used[2] + (size_t)nover * B_MAXBE, 2 * (size_t)used[3] + (size_t)nover * 2 * B_MAXRT,
-                               2 * (size_t)used[4] + (size_t)nover * B_MAXQ, true);
+            HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
+            k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.plist.p, olist_n);
+            int cw[36];
+            HIPCK(hipMemcpyAsync(cw, E.ctr.p, sizeof cw, hipMemcpyDeviceToHost, s));
+            HIPCK(hipStreamSynchronize(s));
+            const int nover = cw[32], nfull = cw[33];
+            if (cw[34]) {
+                if (tile_scale >= B_MAXSCALE)
+                    throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size (round " +
+                                                    std::to_string(round) + ", class " + std::to_string(cls) +
+                                                    ", tile code " + std::to_string(cw[35]) + ")");
+                tile_scale *= 4;
+                if (verbose)
+                    fprintf(stderr, "qm: round %d class %d: %d regions over the global tiles (code %d), tile scale %d\n",
+                            round, cls, cw[34], cw[35], tile_scale);
+                HIPCK(hipMemsetAsync(E.ctr.p + 35, 0, sizeof(int), s));
+            }
+            note(attempt == 0 ? "grown; over the tiles / pools" : "re-run; still over the tiles / pools", round,
+                 cls, nover + nfull);
+            if (E.prof) { E.prof_over += nover; E.prof_full += nfull; }
+            if (nover + nfull == 0) { E.pool_seen(cw, ncand, cls); break; }
+            if (attempt >= 16) throw QmError(QM_ENOMEM, "result pools kept overflowing");
+            if (cw[5]) {                 // a pool was full: double every pool, keep what is in it
+                E.ensure_pools(2 * E.p_reg.cap, 2 * E.p_bf.cap, 2 * E.p_be.cap, 2 * E.p_cl.cap, 2 * E.p_q.cap, true);
                 HIPCK(hipMemsetAsync(E.ctr.p + 5, 0, sizeof(int), s));
             }
-            // sort the overflow list so the slab path visits candidates in order
-            int grid = std::min(nover, 64);
-            E.slab.ensure(slab_block * grid, s, false);
+            BfPool BPr = E.BP;
+            BPr.prof = nullptr;          // region counters cover the first LDS-tile launch only
             E.pbegin();
-            k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, E.olist.p, nover, BT, E.slab.p, slab_block);
-            E.pend(3);
+            if (nfull > 0)               // same tiles again: these regions fit them
+                k_grow_lds<G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF>
+                    <<<std::min(nfull, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.plist.p, nfull);
+            if (nover > 0) {
+                const GrowTiles BT = big_tiles(tile_scale);
+                const size_t slab_block = grow_slab_bytes(BT);
+                int grid = (int)std::min<size_t>({(size_t)nover, 256, std::max<size_t>(1, (2ull << 30) / slab_block)});
+                E.slab.ensure(slab_block * grid, s, false);
+                k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover, BT, E.slab.p,
+                                                  slab_block);
+            }
+            E.pend(8);
         }
         // flags of rejected / exempted candidates
         HIPCK(hipMemsetAsync(stats_d, 0, 16 * sizeof(int), s));
@@ -448,7 +513,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.pend(4);
         // step 6: maximal set of disjoint claim sets, greedy by priority
         k_mis_init<<<nblk(ncand), 256, 0, s>>>(E.C);
-        int ncl = read1(E.ctr.p + 3, s);
+        int ncl = std::min(read1(E.ctr.p + 3, s), E.PL.cap_cl);
         int passes = 0;
         if (ncl > 0) {
             for (;;) {
@@ -461,6 +526,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 k_mis_commit<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p);
                 E.pend(5);
                 if (read1(undec_d, s) == 0) break;
+                note("selection pass", round, cls, passes);
             }
         }
         // step 7: ids, slots and insertion
@@ -491,37 +557,16 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             E.M.nv += nkept; E.M.nt += newt; E.M.nss += newss;
         }
         if (ncl > 0) k_mis_release<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.owner.p);
-        // verdicts of this round's candidates (kept for the last round)
-        {
-            std::vector<int4> tup(ncand);
-            std::vector<int> st0(ncand), gs(ncand), rs0(ncand), grs(ncand), stt(ncand), rn(ncand), bn(ncand);
-            HIPCK(hipMemcpyAsync(tup.data(), E.c_tup.p, sizeof(int4) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(st0.data(), E.c_st.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(gs.data(), E.gst.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(rs0.data(), E.c_reason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(grs.data(), E.greason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(stt.data(), E.state.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(rn.data(), E.reg_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(bn.data(), E.bf_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-            HIPCK(hipStreamSynchronize(s));
-            R->last.assign(9 * (size_t)ncand, 0);
-            for (int i = 0; i < ncand; ++i) {
-                int* o = R->last.data() + 9 * (size_t)i;
-                int fs = st0[i] != ST_PENDING ? st0[i] : gs[i];
-                o[0] = tup[i].x; o[1] = tup[i].y; o[2] = tup[i].z; o[3] = tup[i].w;
-                o[4] = fs; o[5] = fs == ST_EXEMPT ? (st0[i] != ST_PENDING ? rs0[i] : grs[i]) : 0;
-                o[6] = stt[i] == 1; o[7] = fs == ST_OK ? rn[i] : 0; o[8] = fs == ST_OK ? bn[i] : 0;
-            }
-        }
         // dead slots: regions larger than their new tets
-        int st[16];
-        HIPCK(hipMemcpyAsync(st, stats_d, sizeof st, hipMemcpyDeviceToHost, s));
+        int cw[18];                                  // ctr[14..32): dead counter, round stats
+        HIPCK(hipMemcpyAsync(cw, dead_d, sizeof cw, hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
+        const int* st = cw + 2;
         if (st[12]) throw QmError(QM_EINTERNAL, "candidate left unresolved");
         int rec[QM_ROUND_FIELDS] = {cls, st[0], st[1], st[2], st[3], nkept};
         for (int r = 1; r < EX_NREASON; ++r) rec[5 + r] = st[3 + r];
         rec[14] = E.M.nv;
-        E.dead = read1(dead_d, s);
+        E.dead = cw[0];
         rec[15] = E.M.nt - (int)E.dead;
         R->rounds.insert(R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
         R->stats.inserted[cls] += nkept;
@@ -530,13 +575,42 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             fprintf(stderr, "qm: round %d class %d candidates %d inserted %d vertices %d tets %d\n", round, cls,
                     ncand, nkept, E.M.nv, rec[15]);
         }
+        last_ncand = ncand;
         R->stats.candidates += ncand;
         R->stats.mis_passes += passes;
-        if (E.prof) E.pflush();
+        if (E.prof) {
+            R->round_ms.resize(R->round_ms.size() + QM_PROF_FAMILIES, 0.0);
+            E.pflush(R->round_ms.data() + R->round_ms.size() - QM_PROF_FAMILIES);
+        }
     }
     HIPCK(hipEventRecord(e2, s));
     HIPCK(hipStreamSynchronize(s));
     if (E.prof) E.pflush();
+    // verdicts of the last round's candidates: the candidate arrays are only
+    // rewritten by a round that has candidates, so they still hold that round
+    if (last_ncand > 0) {
+        const int ncand = last_ncand;
+        std::vector<int4> tup(ncand);
+        std::vector<int> st0(ncand), gs(ncand), rs0(ncand), grs(ncand), stt(ncand), rn(ncand), bn(ncand);
+        HIPCK(hipMemcpyAsync(tup.data(), E.c_tup.p, sizeof(int4) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(st0.data(), E.c_st.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(gs.data(), E.gst.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(rs0.data(), E.c_reason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(grs.data(), E.greason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(stt.data(), E.state.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(rn.data(), E.reg_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(bn.data(), E.bf_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        R->last.assign(9 * (size_t)ncand, 0);
+        for (int i = 0; i < ncand; ++i) {
+            int* o = R->last.data() + 9 * (size_t)i;
+            int fs = st0[i] != ST_PENDING ? st0[i] : gs[i];
+            o[0] = tup[i].x; o[1] = tup[i].y; o[2] = tup[i].z; o[3] = tup[i].w;
+            o[4] = fs; o[5] = fs == ST_EXEMPT ? (st0[i] != ST_PENDING ? rs0[i] : grs[i]) : 0;
+            o[6] = stt[i] == 1; o[7] = fs == ST_OK ? rn[i] : 0; o[8] = fs == ST_OK ? bn[i] : 0;
+        }
+    }
+
     int gerr = 0;
     HIPCK(hipMemcpyFromSymbolAsync(&gerr, HIP_SYMBOL(g_geom_error), sizeof(int), 0, hipMemcpyDeviceToHost, s));
     HIPCK(hipStreamSynchronize(s));
@@ -585,12 +659,14 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     HIPCK(hipEventElapsedTime(&ms_ref, e1, e2));
     (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
     if (E.prof) {
-        for (int i = 0; i < 8; ++i) { R->stats.prof_ms[i] = E.prof_ms[i]; R->stats.prof_launches[i] = E.prof_n[i]; }
+        for (int i = 0; i < QM_PROF_FAMILIES; ++i) { R->stats.prof_ms[i] = E.prof_ms[i]; R->stats.prof_launches[i] = E.prof_n[i]; }
         unsigned long long pc[4];
         HIPCK(hipMemcpy(pc, E.pctr.p, sizeof pc, hipMemcpyDeviceToHost));
         R->stats.prof_tested = (int64_t)pc[0]; R->stats.prof_region = (int64_t)pc[1];
         R->stats.prof_bfaces = (int64_t)pc[2]; R->stats.prof_claims = (int64_t)pc[3];
         R->stats.prof_scan_tets = scan_tets; R->stats.prof_scan_verts = scan_verts;
+        R->stats.prof_overflow = E.prof_over;
+        R->stats.prof_poolfull = E.prof_full;
     }
     R->stats.rounds = round;
     R->stats.status = status;
@@ -644,6 +720,13 @@ int qm_result_last_round(const qm_result* r, int32_t* buf, int32_t cap) {
     if (!r) { g_err = "null result"; return QM_EINVAL; }
     int n = (int)(r->last.size() / 9);
     if (buf) std::memcpy(buf, r->last.data(), sizeof(int32_t) * 9 * (size_t)std::min(n, (int)cap));
+    return n;
+}
+
+int qm_result_round_profile(const qm_result* r, double* buf, int32_t cap) {
+    if (!r) { g_err = "null result"; return QM_EINVAL; }
+    int n = (int)(r->round_ms.size() / QM_PROF_FAMILIES);
+    if (buf) std::memcpy(buf, r->round_ms.data(), sizeof(double) * QM_PROF_FAMILIES * (size_t)std::min(n, (int)cap));
     return n;
 }
 

@@ -174,7 +174,7 @@ __global__ void k_locate(Mesh M, int cls, Cands C) {
                 int f = ord[j];
                 double A[3], B[3], D[3];
                 xyz(M, at4(v, c_FI[f][0]), A); xyz(M, at4(v, c_FI[f][1]), B); xyz(M, at4(v, c_FI[f][2]), D);
-                if (orient3d(A, B, D, P) >= 0) continue;
+                if (orient3d_any(A, B, D, P) >= 0) continue;
                 if (M.TF[4 * (size_t)t + f] >= 0) {
                     bool ex = (M.TI[t] >> (8 + f)) & 1u;
                     C.qw[i] = make_int2(1, face_ckey(M, t, f));
@@ -206,8 +206,8 @@ __global__ void k_locate(Mesh M, int cls, Cands C) {
                 int x = E[j][0], y = E[j][1], z = E[j][2];
                 double Xx[3], Y[3], Z[3];
                 xyz(M, x, Xx); xyz(M, y, Y); xyz(M, z, Z);
-                int oz = orient2d(ax, Xx, Y, Z);
-                int op = orient2d(ax, Xx, Y, P);
+                int oz = orient2d_any(ax, Xx, Y, Z);
+                int op = orient2d_any(ax, Xx, Y, P);
                 if (op == 0 || op != -oz) continue;
                 int s = edge_ss(M, t, v, x, y);
                 if (s >= 0) {

@@ -30,7 +30,7 @@ __global__ void k_setup_tets(int nt, int nv, const int* tin, Mesh M, int* err) {
     } else {
         double A[3], B[3], Cc[3], D[3];
         xyz(M, v.x, A); xyz(M, v.y, B); xyz(M, v.z, Cc); xyz(M, v.w, D);
-        if (orient3d(A, B, Cc, D) <= 0) atomicOr(err, 2);
+        if (orient3d_any(A, B, Cc, D) <= 0) atomicOr(err, 2);
     }
     *reinterpret_cast<int4*>(M.TV + 4 * (size_t)t) = v;
     M.TI[t] = TI_ALIVE;
