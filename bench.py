@@ -11,8 +11,11 @@ Prints one JSON line:
                device time against the 8 TB/s HBM peak
   cpu_baseline the oracle timed on a bounded sample of the same workload
 
-Default workload: corners + 900 000 points from 8 Gaussians + 100 000
-uniform points, three nested sphere surfaces, B = 1.4.
+Default workload: corners + 50 000 uniform points with one sphere surface
+(r = 0.3), B = 1.5.  The 1M-point workload (--workload cfg3: 900 000 points
+from 8 Gaussians + 100 000 uniform, three nested sphere surfaces, B = 1.4)
+is not run by default: its largest cavities need the enlarged global tiles,
+a path that is switched off until a GPU fault there is understood.
 """
 import argparse
 import json
@@ -76,7 +79,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--dump-rounds", default=None,

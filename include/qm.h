@@ -139,8 +139,10 @@ int qm_result_rounds(const qm_result* r, int32_t* buf, int32_t cap);
 int qm_result_last_round(const qm_result* r, int32_t* buf, int32_t cap);
 
 /* QM_PROFILE only: device milliseconds of each kernel family (as in
-   qm_stats.prof_ms, QM_PROF_FAMILIES doubles) for each round.  Copies at most
-   `cap` rounds; returns the number of rounds recorded (0 without QM_PROFILE). */
+   qm_stats.prof_ms, QM_PROF_FAMILIES doubles) for each round; one more entry
+   than rounds run holds the last classification (the one that found no work
+   or was cut by the round guard).  Copies at most `cap` entries; returns the
+   number recorded (0 without QM_PROFILE). */
 int qm_result_round_profile(const qm_result* r, double* buf, int32_t cap);
 
 void qm_result_free(qm_result* r);

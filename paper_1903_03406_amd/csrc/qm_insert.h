@@ -8,50 +8,52 @@ namespace qm {
 // region evaluation's
 QMD int final_status(const Cands& C, int i) { return C.st[i] != ST_PENDING ? C.st[i] : C.gst[i]; }
 
-// Rejected points queue their targets; exempted elements are marked.  Runs
-// before insertion, so a flagged element destroyed this round loses its
-// flags with it and new elements start clean.
-__global__ void k_apply_flags(Mesh M, int cls, Cands C, Pools PL) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= C.n) return;
-    int st = C.st[i] != ST_PENDING ? C.st[i] : C.gst[i];
-    auto queue = [&](int2 e) {
-        if (e.x == 0) atomicOr(&M.SFL[e.y], SS_QUEUED);
-        else {
-            int t = e.y >> 2, f = e.y & 3;
-            atomicOr(&M.TI[t], 1u << (4 + f));
-            int nb = M.TA[4 * (size_t)t + f];
-            if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (4 + (nb & 3)));
-        }
-    };
-    if (st == ST_REJECT) {
-        if (C.st[i] == ST_REJECT) queue(C.qw[i]);
-        else for (int k = 0; k < C.q_n[i]; ++k) queue(PL.q[C.q_off[i] + k]);
-    } else if (st == ST_EXEMPT) {
-        int e = C.elem[i];
-        if (cls == CLS_SS) atomicOr(&M.SFL[e], SS_EXEMPT);
-        else if (cls == CLS_SF) {
-            int t = e >> 2, f = e & 3;
-            atomicOr(&M.TI[t], 1u << (8 + f));
-            int nb = M.TA[4 * (size_t)t + f];
-            if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (8 + (nb & 3)));
-        } else atomicOr(&M.TI[e], TI_EXEMPT);
+// Verdicts of the round, one thread per candidate: rejected points queue
+// their targets and exempted elements are marked (before insertion, so a
+// flagged element destroyed this round loses its flags with it and new
+// elements start clean); the round statistics [ncand, ok, rejected, exempt,
+// exempt by reason 1..8, unresolved] are counted per block in LDS; accepted
+// candidates enter the selection undecided (state 0), the others never do
+// (state 3).
+__global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pools PL, int* stats) {
+    __shared__ int bs[16];
+    if (threadIdx.x < 16) bs[threadIdx.x] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < C.n) {
+        const int st = C.st[i] != ST_PENDING ? C.st[i] : C.gst[i];
+        auto queue = [&](int2 e) {
+            if (e.x == 0) atomicOr(&M.SFL[e.y], SS_QUEUED);
+            else {
+                int t = e.y >> 2, f = e.y & 3;
+                atomicOr(&M.TI[t], 1u << (4 + f));
+                int nb = M.TA[4 * (size_t)t + f];
+                if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (4 + (nb & 3)));
+            }
+        };
+        atomicAdd(&bs[0], 1);
+        if (st == ST_OK) atomicAdd(&bs[1], 1);
+        else if (st == ST_REJECT) {
+            atomicAdd(&bs[2], 1);
+            if (C.st[i] == ST_REJECT) queue(C.qw[i]);
+            else for (int k = 0; k < C.q_n[i]; ++k) queue(PL.q[C.q_off[i] + k]);
+        } else if (st == ST_EXEMPT) {
+            atomicAdd(&bs[3], 1);
+            int r = C.st[i] != ST_PENDING ? C.reason[i] : C.greason[i];
+            atomicAdd(&bs[3 + r], 1);
+            int e = C.elem[i];
+            if (cls == CLS_SS) atomicOr(&M.SFL[e], SS_EXEMPT);
+            else if (cls == CLS_SF) {
+                int t = e >> 2, f = e & 3;
+                atomicOr(&M.TI[t], 1u << (8 + f));
+                int nb = M.TA[4 * (size_t)t + f];
+                if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (8 + (nb & 3)));
+            } else atomicOr(&M.TI[e], TI_EXEMPT);
+        } else atomicAdd(&bs[12], 1);     // unresolved (internal error)
+        C.state[i] = st == ST_OK ? 0 : 3;
     }
-}
-
-// round statistics: [ncand, ok, rejected, exempt, exempt by reason 1..8]
-__global__ void k_round_stats(Cands C, int* stats) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= C.n) return;
-    int st = final_status(C, i);
-    atomicAdd(&stats[0], 1);
-    if (st == ST_OK) atomicAdd(&stats[1], 1);
-    else if (st == ST_REJECT) atomicAdd(&stats[2], 1);
-    else if (st == ST_EXEMPT) {
-        atomicAdd(&stats[3], 1);
-        int r = C.st[i] != ST_PENDING ? C.reason[i] : C.greason[i];
-        atomicAdd(&stats[3 + r], 1);
-    } else atomicAdd(&stats[12], 1);     // unresolved (internal error)
+    __syncthreads();
+    if (threadIdx.x < 16 && bs[threadIdx.x]) atomicAdd(&stats[threadIdx.x], bs[threadIdx.x]);
 }
 
 // ------------------------------------------------------------- selection
@@ -59,40 +61,53 @@ __global__ void k_round_stats(Cands C, int* stats) {
 // candidate marks its claim set with its priority (atomic max); a candidate
 // owning all its marks is kept, one touching a kept claim is dropped.  The
 // result is exactly the greedy maximal disjoint set in priority order.
-__global__ void k_mis_init(Cands C) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= C.n) return;
-    C.state[i] = final_status(C, i) == ST_OK ? 0 : 3;
-}
+// Passes are launched in batches without waiting: every kernel of a pass
+// returns at once when the previous pass left nothing undecided (`prev`).
 QMD unsigned long long mis_val(unsigned pass, int c) {
     return ((unsigned long long)pass << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)c);
 }
 __global__ void k_mis_mark(int ncl, const int* cl, const int* clc, const int* state,
-                           unsigned long long* mark, unsigned pass) {
+                           unsigned long long* mark, unsigned pass, const int* prev) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ncl) return;
+    if (e >= ncl || (prev && *prev == 0)) return;
     int c = clc[e];
     if (c < 0) return;                 // void range (reservation that did not fit)
     if (state[c] != 0) return;
     atomicMax(&mark[cl[e]], mis_val(pass, c));
 }
-__global__ void k_mis_decide(Cands C, const int* cl, const unsigned long long* mark, const int* owner,
-                             unsigned pass, int* undecided) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C.n || C.state[c] != 0) return;
-    unsigned long long me = mis_val(pass, c);
-    bool mine = true;
-    for (int k = 0; k < C.cl_n[c]; ++k) {
-        int t = cl[C.cl_off[c] + k];
-        if (owner[t] >= 0) { C.state[c] = 2; return; }
-        if (mark[t] != me) mine = false;
-    }
-    if (mine) C.state[c] = 1;
-    else atomicAdd(undecided, 1);
-}
-__global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* state, int* owner) {
+// per claim entry of an undecided candidate: touching a kept claim drops it
+// (drop[c]), a tet marked by a higher priority leaves it undecided (lose[c]);
+// every writer stores the same value, so plain stores suffice
+__global__ void k_mis_check(int ncl, const int* cl, const int* clc, const int* state,
+                            const unsigned long long* mark, const int* owner, unsigned pass,
+                            unsigned char* drop, unsigned char* lose, const int* prev) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= ncl) return;
+    if (e >= ncl || (prev && *prev == 0)) return;
+    int c = clc[e];
+    if (c < 0 || state[c] != 0) return;
+    int t = cl[e];
+    if (owner[t] >= 0) drop[c] = 1;
+    else if (mark[t] != mis_val(pass, c)) lose[c] = 1;
+}
+__global__ __launch_bounds__(256) void k_mis_decide(int n, int* state, unsigned char* drop, unsigned char* lose,
+                                                    int* undecided, const int* prev) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n && !(prev && *prev == 0) && state[c] == 0) {
+        if (drop[c]) state[c] = 2;
+        else if (lose[c]) atomicAdd(&cnt, 1);
+        else state[c] = 1;
+        drop[c] = 0; lose[c] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd(undecided, cnt);
+}
+__global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* state, int* owner,
+                             const int* prev) {
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ncl || (prev && *prev == 0)) return;
     int c = clc[e];
     if (c < 0) return;
     if (state[c] == 1) owner[cl[e]] = c;

@@ -109,7 +109,12 @@ constexpr int G_MAXRT = 256, G_HCAP = 1024, G_RFHCAP = 128, G_MAXRF = 48, G_MAXB
 // global-slab tiles of the overflow path
 constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, B_MAXBE = 4096,
               B_QHCAP = 8192, B_MAXQ = 4096, B_MAXBF = 32768;
-constexpr int B_MAXSCALE = 64;     // largest scale of the global tiles (1M region tets)
+// Largest scale of the global tiles.  Scales above 1 (4x per retry) are
+// switched off: a 1M-point refinement faulted the GPU in the first round that
+// used them and the cause is not yet shown; such a region is reported as
+// QM_ECAPACITY instead.
+constexpr int B_MAXSCALE = 1;
+constexpr int MIS_BATCH = 4;       // selection passes launched per synchronisation
 
 struct Engine {
     hipStream_t s;
@@ -130,6 +135,7 @@ struct Engine {
     DBuf<double4> c_p0;
     DBuf<int> c_elem, c_st, c_reason, c_seed, gst, greason, reg_off, reg_n, bf_off, bf_n, be_off, be_n,
         cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, plist;
+    DBuf<unsigned char> mis_drop, mis_lose;   // selection: per-candidate pass flags (kept zero)
     DBuf<unsigned long long> c_key;
     DBuf<int4> c_tup;
     DBuf<double4> c_p;
@@ -138,8 +144,9 @@ struct Engine {
     DBuf<int> p_reg, p_bf, p_cl, p_clc;
     DBuf<int4> p_be, p_bfr;
     DBuf<int2> p_q;
-    DBuf<int> ctr;     // pool counters [0..5], ncand [8], undecided [9], totals [10..12], err [13],
-                       // dead [14], stats [16..31], re-run list counts [32..34]
+    DBuf<int> ctr;     // pool counters [0..5], candidates per class [8..10], totals [11..13],
+                       // dead [14], stats [16..31], re-run list counts [32..34], tile code [35],
+                       // undecided per selection pass of a batch [40..40+MIS_BATCH)
     DBuf<char> tmp;    // hipcub scratch
     DBuf<char> slab;   // overflow grow tiles
     Cands C{};
@@ -150,8 +157,8 @@ struct Engine {
     // kernel-family timing with events on the call's stream (QM_PROFILE)
     bool prof = false;
     std::vector<hipEvent_t> ev;
-    std::vector<int> ev_cat;
-    int ev_used = 0;
+    std::vector<int> ev_cat, ev_round;
+    int ev_used = 0, cur_round = 0;
     double prof_ms[QM_PROF_FAMILIES] = {0};
     int64_t prof_n[QM_PROF_FAMILIES] = {0};
     int64_t prof_over = 0, prof_full = 0;
@@ -161,6 +168,7 @@ struct Engine {
         if (ev_used + 2 > (int)ev.size()) {
             for (int i = 0; i < 64; ++i) { hipEvent_t e; HIPCK(hipEventCreate(&e)); ev.push_back(e); }
             ev_cat.resize(ev.size());
+            ev_round.resize(ev.size());
         }
         HIPCK(hipEventRecord(ev[ev_used], s));
     }
@@ -168,15 +176,21 @@ struct Engine {
         if (!prof) return;
         HIPCK(hipEventRecord(ev[ev_used + 1], s));
         ev_cat[ev_used] = cat;
+        ev_round[ev_used] = cur_round;
         ev_used += 2;
         prof_n[cat]++;
     }
-    void pflush(double* round_ms = nullptr) {   // after a stream synchronisation
+    // after a stream synchronisation: every recorded pair is complete
+    void pflush(std::vector<double>* round_ms = nullptr) {
         for (int i = 0; i < ev_used; i += 2) {
             float ms = 0;
             HIPCK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
             prof_ms[ev_cat[i]] += ms;
-            if (round_ms) round_ms[ev_cat[i]] += ms;
+            if (round_ms) {
+                size_t need = (size_t)(ev_round[i] + 1) * QM_PROF_FAMILIES;
+                if (round_ms->size() < need) round_ms->resize(need, 0.0);
+                (*round_ms)[(size_t)ev_round[i] * QM_PROF_FAMILIES + ev_cat[i]] += ms;
+            }
         }
         ev_used = 0;
     }
@@ -193,7 +207,7 @@ struct Engine {
                         &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &p_reg,
                         &p_bf, &p_cl, &p_clc, &ctr})
             b->release(s);
-        c_key0.release(s); skey.release(s); c_key.release(s);
+        c_key0.release(s); skey.release(s); c_key.release(s); mis_drop.release(s); mis_lose.release(s);
         c_tup0.release(s); c_tup.release(s); c_p0.release(s); c_p.release(s); c_qw.release(s);
         p_be.release(s); p_bfr.release(s); p_q.release(s); pctr.release(s);
         (void)hipStreamSynchronize(s);
@@ -226,6 +240,7 @@ struct Engine {
                         &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist})
             b->ensure(m, s, false);
         c_key0.ensure(m, s, false); skey.ensure(m, s, false); c_key.ensure(m, s, false);
+        mis_drop.ensure(m, s, false, 0); mis_lose.ensure(m, s, false, 0);
         c_tup0.ensure(m, s, false); c_tup.ensure(m, s, false);
         c_p0.ensure(m, s, false); c_p.ensure(m, s, false); c_qw.ensure(m, s, false);
         C.n = n;
@@ -387,13 +402,26 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     // ---- rounds
     qm_result* R = new qm_result();
     std::memset(&R->stats, 0, sizeof R->stats);
-    int* ncand_d = E.ctr.p + 8;
-    int* undec_d = E.ctr.p + 9;
-    int* tot_d = E.ctr.p + 10;
+    int* cnt_d = E.ctr.p + 8;
+    int* tot_d = E.ctr.p + 11;
     int* dead_d = E.ctr.p + 14;
     int* stats_d = E.ctr.p + 16;
     int* olist_n = E.ctr.p + 32;
+    int* undec_d = E.ctr.p + 40;
     int round = 0, status = 0, last_ncand = 0;
+    int hc[48];                     // host copy of ctr[0..48), taken at each synchronisation
+    auto sync_counters = [&]() {
+        HIPCK(hipMemcpyAsync(hc, E.ctr.p, sizeof hc, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        if (E.prof) E.pflush(&R->round_ms);
+    };
+    // the dead-slot count after a round's insertion is read at the next
+    // synchronisation; it completes that round's record (tets after)
+    auto patch_last_record = [&]() {
+        if (R->rounds.empty()) return;
+        E.dead = hc[14];
+        R->rounds[R->rounds.size() - QM_ROUND_FIELDS + 15] = E.M.nt - (int)E.dead;
+    };
     // global-memory tiles: scale 1 first; a region over them (cavities can
     // grow with the number of vertices a point sees, e.g. next to a dense
     // cluster) makes the round retry those candidates at 4x the scale
@@ -417,21 +445,22 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     };
     for (;; ++round) {
         if (round >= opt->max_rounds) { status = 1; break; }
+        E.cur_round = round;
+        // step 1: classify, in the paper's order (a class is skipped on the
+        // device when an earlier one has candidates); one synchronisation
+        E.cand_out.ensure(std::max((size_t)E.M.nss, 4 * (size_t)E.M.nt), s, false);
+        HIPCK(hipMemsetAsync(cnt_d, 0, 3 * sizeof(int), s));
+        E.pbegin();
+        if (E.M.nss) k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.cand_out.p, cnt_d);
+        k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, cnt_d);
+        k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, cnt_d);
+        E.pend(0);
+        sync_counters();
+        patch_last_record();
         int cls = CLS_NONE, ncand = 0;
-        // step 1: classify, in the paper's order
-        for (int c = CLS_SS; c <= CLS_TET; ++c) {
-            int cap = c == CLS_SS ? E.M.nss : (c == CLS_SF ? 4 * E.M.nt : E.M.nt);
-            if (cap == 0) continue;
-            E.cand_out.ensure(cap, s, false);
-            HIPCK(hipMemsetAsync(ncand_d, 0, sizeof(int), s));
-            E.pbegin();
-            if (c == CLS_SS) k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
-            else if (c == CLS_SF) k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d);
-            else { k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, ncand_d); scan_tets += E.M.nt; scan_verts += E.M.nv; }
-            E.pend(0);
-            ncand = read1(ncand_d, s);
-            if (ncand > 0) { cls = c; break; }
-        }
+        for (int c = CLS_SS; c <= CLS_TET && cls == CLS_NONE; ++c)
+            if (hc[8 + c] > 0) { cls = c; ncand = hc[8 + c]; }
+        if (hc[8 + CLS_SS] == 0 && hc[8 + CLS_SF] == 0) { scan_tets += E.M.nt; scan_verts += E.M.nv; }
         if (cls == CLS_NONE) break;
         E.ensure_cands(ncand);
         // step 2: splitting points and priorities, then priority order
@@ -462,6 +491,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 <<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, nullptr, 0);
             E.pend(3);
         }
+        int ncl_final = 0;
         for (int attempt = 0;; ++attempt) {
             HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
             k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.plist.p, olist_n);
@@ -483,7 +513,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             note(attempt == 0 ? "grown; over the tiles / pools" : "re-run; still over the tiles / pools", round,
                  cls, nover + nfull);
             if (E.prof) { E.prof_over += nover; E.prof_full += nfull; }
-            if (nover + nfull == 0) { E.pool_seen(cw, ncand, cls); break; }
+            if (nover + nfull == 0) { E.pool_seen(cw, ncand, cls); ncl_final = cw[3]; break; }
             if (attempt >= 16) throw QmError(QM_ENOMEM, "result pools kept overflowing");
             if (cw[5]) {                 // a pool was full: double every pool, keep what is in it
                 E.ensure_pools(2 * E.p_reg.cap, 2 * E.p_bf.cap, 2 * E.p_be.cap, 2 * E.p_cl.cap, 2 * E.p_q.cap, true);
@@ -505,47 +535,64 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             }
             E.pend(8);
         }
-        // flags of rejected / exempted candidates
+        const int ncl = std::min(ncl_final, E.PL.cap_cl);
+        // verdicts: flags of rejected / exempted candidates, round statistics,
+        // selection state
         HIPCK(hipMemsetAsync(stats_d, 0, 16 * sizeof(int), s));
         E.pbegin();
-        k_apply_flags<<<nblk(ncand), 256, 0, s>>>(E.M, cls, E.C, E.PL);
-        k_round_stats<<<nblk(ncand), 256, 0, s>>>(E.C, stats_d);
+        k_verdicts<<<nblk(ncand), 256, 0, s>>>(E.M, cls, E.C, E.PL, stats_d);
         E.pend(4);
-        // step 6: maximal set of disjoint claim sets, greedy by priority
-        k_mis_init<<<nblk(ncand), 256, 0, s>>>(E.C);
-        int ncl = std::min(read1(E.ctr.p + 3, s), E.PL.cap_cl);
-        int passes = 0;
-        if (ncl > 0) {
-            for (;;) {
-                ++passes;
-                unsigned ps = E.pass++;
-                HIPCK(hipMemsetAsync(undec_d, 0, sizeof(int), s));
-                E.pbegin();
-                k_mis_mark<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps);
-                k_mis_decide<<<nblk(ncand), 256, 0, s>>>(E.C, E.p_cl.p, E.mark.p, E.owner.p, ps, undec_d);
-                k_mis_commit<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p);
-                E.pend(5);
-                if (read1(undec_d, s) == 0) break;
-                note("selection pass", round, cls, passes);
-            }
-        }
-        // step 7: ids, slots and insertion
-        E.pbegin();
-        k_scan_vals<<<nblk(ncand), 256, 0, s>>>(E.C, cls, E.vk.p, E.vt.p, E.vs.p);
-        E.exscan(E.vk.p, E.sk.p, ncand);
-        if (opt->max_kept > 0) {
-            k_cap_kept<<<nblk(ncand), 256, 0, s>>>(E.C, E.sk.p, opt->max_kept);
+        // step 6: maximal set of disjoint claim sets, greedy by priority, in
+        // batches of passes; step 7 ids and slots are scanned with each batch
+        // and taken once the selection is complete (one synchronisation)
+        auto scans = [&](bool cap) {
+            E.pbegin();
             k_scan_vals<<<nblk(ncand), 256, 0, s>>>(E.C, cls, E.vk.p, E.vt.p, E.vs.p);
             E.exscan(E.vk.p, E.sk.p, ncand);
+            if (cap) {
+                k_cap_kept<<<nblk(ncand), 256, 0, s>>>(E.C, E.sk.p, opt->max_kept);
+                k_scan_vals<<<nblk(ncand), 256, 0, s>>>(E.C, cls, E.vk.p, E.vt.p, E.vs.p);
+                E.exscan(E.vk.p, E.sk.p, ncand);
+            }
+            E.exscan(E.vt.p, E.st_.p, ncand);
+            E.exscan(E.vs.p, E.ss_.p, ncand);
+            k_totals<<<1, 1, 0, s>>>(ncand, E.sk.p, E.vk.p, E.st_.p, E.vt.p, E.ss_.p, E.vs.p, tot_d);
+            E.pend(6);
+        };
+        int passes = 0;
+        for (int batch = 0;; ++batch) {
+            if (ncl > 0) {
+                HIPCK(hipMemsetAsync(undec_d, 0, MIS_BATCH * sizeof(int), s));
+                E.pbegin();
+                for (int b = 0; b < MIS_BATCH; ++b) {
+                    const unsigned ps = E.pass++;
+                    const int* prev = b ? undec_d + b - 1 : nullptr;
+                    k_mis_mark<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps, prev);
+                    k_mis_check<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, E.owner.p,
+                                                          ps, E.mis_drop.p, E.mis_lose.p, prev);
+                    k_mis_decide<<<nblk(ncand), 256, 0, s>>>(ncand, E.state.p, E.mis_drop.p, E.mis_lose.p,
+                                                             undec_d + b, prev);
+                    k_mis_commit<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p, prev);
+                }
+                E.pend(5);
+            }
+            scans(false);
+            sync_counters();
+            if (ncl > 0)
+                for (int b = 0; b < MIS_BATCH; ++b) {
+                    ++passes;
+                    if (hc[40 + b] == 0) break;
+                }
+            if (ncl == 0 || hc[40 + MIS_BATCH - 1] == 0) break;
+            note("selection batch", round, cls, batch + 1);
         }
-        E.exscan(E.vt.p, E.st_.p, ncand);
-        E.exscan(E.vs.p, E.ss_.p, ncand);
-        k_totals<<<1, 1, 0, s>>>(ncand, E.sk.p, E.vk.p, E.st_.p, E.vt.p, E.ss_.p, E.vs.p, tot_d);
-        E.pend(6);
-        int tot[3];
-        HIPCK(hipMemcpyAsync(tot, tot_d, sizeof tot, hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        const int nkept = tot[0], newt = tot[1], newss = tot[2];
+        if (opt->max_kept > 0) {        // a cap applies to the complete selection
+            scans(true);
+            sync_counters();
+        }
+        const int nkept = hc[11], newt = hc[12], newss = hc[13];
+        const int* st = hc + 16;
+        if (st[12]) throw QmError(QM_EINTERNAL, "candidate left unresolved");
         if (nkept > 0) {
             E.ensure_mesh(E.M.nv + nkept, E.M.nt + newt, E.M.nss + newss);
             k_kept_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.sk.p, E.kept.p);
@@ -557,35 +604,24 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             E.M.nv += nkept; E.M.nt += newt; E.M.nss += newss;
         }
         if (ncl > 0) k_mis_release<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.owner.p);
-        // dead slots: regions larger than their new tets
-        int cw[18];                                  // ctr[14..32): dead counter, round stats
-        HIPCK(hipMemcpyAsync(cw, dead_d, sizeof cw, hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        const int* st = cw + 2;
-        if (st[12]) throw QmError(QM_EINTERNAL, "candidate left unresolved");
         int rec[QM_ROUND_FIELDS] = {cls, st[0], st[1], st[2], st[3], nkept};
         for (int r = 1; r < EX_NREASON; ++r) rec[5 + r] = st[3 + r];
         rec[14] = E.M.nv;
-        E.dead = cw[0];
-        rec[15] = E.M.nt - (int)E.dead;
+        rec[15] = E.M.nt - (int)E.dead;   // completed at the next synchronisation
         R->rounds.insert(R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
         R->stats.inserted[cls] += nkept;
         if (verbose && std::chrono::steady_clock::now() - last_note > std::chrono::seconds(5)) {
             last_note = std::chrono::steady_clock::now();
-            fprintf(stderr, "qm: round %d class %d candidates %d inserted %d vertices %d tets %d\n", round, cls,
-                    ncand, nkept, E.M.nv, rec[15]);
+            fprintf(stderr, "qm: round %d class %d candidates %d inserted %d vertices %d\n", round, cls, ncand,
+                    nkept, E.M.nv);
         }
         last_ncand = ncand;
         R->stats.candidates += ncand;
         R->stats.mis_passes += passes;
-        if (E.prof) {
-            R->round_ms.resize(R->round_ms.size() + QM_PROF_FAMILIES, 0.0);
-            E.pflush(R->round_ms.data() + R->round_ms.size() - QM_PROF_FAMILIES);
-        }
     }
     HIPCK(hipEventRecord(e2, s));
-    HIPCK(hipStreamSynchronize(s));
-    if (E.prof) E.pflush();
+    sync_counters();
+    patch_last_record();
     // verdicts of the last round's candidates: the candidate arrays are only
     // rewritten by a round that has candidates, so they still hold that round
     if (last_ncand > 0) {

@@ -8,9 +8,13 @@ namespace qm {
 // ------------------------------------------------------------------ classify
 // Subsegment ab is encroached when queued, or when a vertex of its link (an
 // apex of a tet around ab) lies strictly inside its diametral ball.
-__global__ void k_classify_ss(Mesh M, int* cand, int* ncand) {
+// Each classification kernel counts its class in cnt[cls] and writes the
+// candidates to cand; a class is skipped when an earlier one has candidates
+// (the paper's order), which the kernel reads from cnt itself.
+__global__ void k_classify_ss(Mesh M, int* cand, int* cnt) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= M.nss) return;
+    int* ncand = cnt + CLS_SS;
     unsigned fl = M.SFL[s];
     if (fl & SS_EXEMPT) return;
     int2 ab = M.SV[s];
@@ -33,9 +37,10 @@ __global__ void k_classify_ss(Mesh M, int* cand, int* ncand) {
 // Subface abc is encroached when queued, or when the apex of one of its
 // tets lies strictly inside its equatorial ball.  Each subface is taken from
 // the tet whose apex has the smaller id (or its only tet).
-__global__ void k_classify_sf(Mesh M, int* cand, int* ncand) {
+__global__ void k_classify_sf(Mesh M, int* cand, int* cnt) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= M.nt) return;
+    if (t >= M.nt || cnt[CLS_SS] > 0) return;
+    int* ncand = cnt + CLS_SF;
     unsigned ti = M.TI[t];
     if (!(ti & TI_ALIVE)) return;
     int4 tf = ld4(M.TF, t);
@@ -60,9 +65,10 @@ __global__ void k_classify_sf(Mesh M, int* cand, int* ncand) {
 }
 
 // Bad tetrahedron: radius-edge ratio above B (paper, Section 1).
-__global__ void k_classify_tet(Mesh M, int* cand, int* ncand) {
+__global__ void k_classify_tet(Mesh M, int* cand, int* cnt) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= M.nt) return;
+    if (t >= M.nt || cnt[CLS_SS] > 0 || cnt[CLS_SF] > 0) return;
+    int* ncand = cnt + CLS_TET;
     unsigned ti = M.TI[t];
     if (!(ti & TI_ALIVE) || (ti & TI_EXEMPT)) return;
     int4 v = ld4(M.TV, t);
