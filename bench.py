@@ -27,6 +27,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_grow_lds_uniform50k_traffic.md")
+
+
+def kernel_source_sha256():
+    """Digest of the HIP sources: measured traffic is only valid for the
+    kernels it was measured on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1903_03406_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, launches):
+    """HBM bytes of k_grow_lds per launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration),
+    or None when the summary is for other sources or another workload."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_SUMMARY):
+        if "=" in line and line.strip().startswith("qm."):
+            k, v = line.strip().split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("qm.source_sha256") != kernel_source_sha256() or kv.get("qm.workload") != workload:
+        return None
+    fetch = float(kv["qm.fetch_kib_total"]) * float(kv["qm.fetch_scale"])
+    write = float(kv["qm.write_kib_total"]) * float(kv["qm.write_scale"])
+    return (fetch + write) * 1024.0 / float(kv["qm.launches"])
 
 
 def grow_bytes(p):
@@ -152,7 +183,9 @@ def main():
         "overflow_candidates": prof.get("overflow", 0), "poolfull_candidates": prof.get("poolfull", 0),
         "roofline": {"kernel": "k_grow_lds" if fam == "grow_validate" else "k_classify_tet",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic(w.name, prof["launches"][fam]) if fam == "grow_validate"
+                                 else None),
                      "launches": prof["launches"][fam], "kernel_ms": kms,
                      "algorithmic_bytes": nbytes, "dominant_family": dominant},
     }

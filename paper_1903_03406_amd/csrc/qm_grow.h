@@ -28,7 +28,7 @@ constexpr int CXW = 7;
 struct GrowTiles {
     int* rt; unsigned* H; unsigned* RFH; int* rf; int4* be; unsigned long long* QH; int2* q; int* cx;
     int maxrt, hcap, rfhcap, maxrf, maxbe, qhcap, maxq, maxbf, maxcx;
-    int big;              // 1: the largest (global-memory) tiles, nothing to fall back to
+    int tier;             // 0 small LDS tiles, 1 medium LDS tiles, 2 global-memory tiles (the largest)
     unsigned long long* EK; int4* EV; int ehcap;
 };
 
@@ -213,11 +213,18 @@ QMD void sub_edge(int4 v, int f, int e, int& x, int& y, int& z) {
     else { x = g1; y = g2; z = g0; }
 }
 
-// a region over the tiles: evaluate again with larger tiles, or (largest
-// tiles) report which tile was too small in the counter word PL.ctr[35]
+// a region over the tiles: evaluate again with the next tier's tiles, or
+// (largest tiles) report which tile was too small in the counter word
+// PL.ctr[35]
 QMD void over_status(const Cands& C, const Pools& PL, const GrowTiles& W, int cid, int over) {
-    if (W.big) { C.gst[cid] = ST_TOOBIG; atomicOr(&PL.ctr[35], over); }
-    else C.gst[cid] = ST_OVERFLOW;
+    if (W.tier == 2) { C.gst[cid] = ST_TOOBIG; atomicOr(&PL.ctr[35], over); }
+    else C.gst[cid] = W.tier == 0 ? ST_OVERFLOW : ST_OVERFLOW2;
+}
+
+// results that did not fit a pool: evaluate again, after the pools grow, in
+// the same tier's tiles (the region is known to fit them)
+QMD int poolfull_status(const GrowTiles& W) {
+    return W.tier == 0 ? ST_POOLFULL : (W.tier == 1 ? ST_OVERFLOW : ST_OVERFLOW2);
 }
 
 // Evaluate candidate `cid` (steps: seeds, grow R_F, grow R_T, validate,
@@ -422,7 +429,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             if (lane == 0) {
                 if (any_live) {
                     int base = atomicAdd(&PL.ctr[4], S.nq);
-                    if (base + S.nq > PL.cap_q) { atomicOr(&PL.ctr[5], 1); C.gst[cid] = ST_POOLFULL; S.base_q = -1; }
+                    if (base + S.nq > PL.cap_q) { atomicOr(&PL.ctr[5], 1); C.gst[cid] = poolfull_status(W); S.base_q = -1; }
                     else { C.gst[cid] = ST_REJECT; C.greason[cid] = EX_NONE; C.q_off[cid] = base; C.q_n[cid] = S.nq; S.base_q = base; }
                 } else {
                     C.gst[cid] = ST_EXEMPT; C.greason[cid] = EX_ENC_EXEMPT; S.base_q = -1;
@@ -671,7 +678,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         bool full = br + nrt > PL.cap_reg || bb + nbf > PL.cap_bf || bb + nbf > BP.cap ||
                     be + nbe > PL.cap_be || bc + nrt + ncx > PL.cap_cl;
         if (full) {
-            atomicOr(&PL.ctr[5], 1); C.gst[cid] = ST_POOLFULL; S.base_reg = -1;
+            atomicOr(&PL.ctr[5], 1); C.gst[cid] = poolfull_status(W); S.base_reg = -1;
             S.base_cl = bc;
         } else {
             S.base_reg = br; S.base_bf = bb; S.base_be = be; S.base_cl = bc;
@@ -711,9 +718,12 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
 }
 
-template <int MAXRT, int HCAP, int RFHCAP, int MAXRF, int MAXBE, int QHCAP, int MAXQ, int MAXBF>
+// LDS tiles; TIER 1 (medium) also takes an edge table of EHCAP entries per
+// workgroup from the global slab `eslab` (EHCAP 0: pairwise scans)
+template <int TIER, int MAXRT, int HCAP, int RFHCAP, int MAXRF, int MAXBE, int QHCAP, int MAXQ, int MAXBF,
+          int EHCAP>
 __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
-                                                 const int* list, int nlist) {
+                                                 const int* list, int nlist, char* eslab) {
     __shared__ int rt[MAXRT];
     __shared__ unsigned H[HCAP];
     __shared__ unsigned RFH[RFHCAP];
@@ -723,8 +733,14 @@ __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools
     __shared__ int2 q[MAXQ];
     __shared__ int cx[CXW * MAXBF + MAXBF];
     __shared__ GrowShared S;
-    GrowTiles W{rt, H, RFH, rf, be, QH, q, cx, MAXRT, HCAP, RFHCAP, MAXRF, MAXBE, QHCAP, MAXQ, MAXBF, MAXBF, 0,
+    GrowTiles W{rt, H, RFH, rf, be, QH, q, cx, MAXRT, HCAP, RFHCAP, MAXRF, MAXBE, QHCAP, MAXQ, MAXBF, MAXBF, TIER,
                 nullptr, nullptr, 0};
+    if (EHCAP > 0) {
+        char* base = eslab + (size_t)blockIdx.x * EHCAP * (sizeof(unsigned long long) + sizeof(int4));
+        W.EK = (unsigned long long*)base;
+        W.EV = (int4*)(base + (size_t)EHCAP * sizeof(unsigned long long));
+        W.ehcap = EHCAP;
+    }
     prof_begin(S);
     // all candidates in priority order, or the re-run list (pool-full ones)
     const int n = list ? nlist : C.n;

@@ -92,20 +92,30 @@ __global__ void k_fill(int n, int* o, int v) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = v;
 }
-// candidates to evaluate again: regions over the LDS or global-memory tiles
-// (list a, count n[0]) and candidates whose results did not fit a pool (list
-// b, count n[1]); n[2] counts the regions over the global-memory tiles
-__global__ void k_overflow_list(Cands C, int* la, int* lb, int* n) {
+// candidates to evaluate again: regions over the small LDS tiles (list a,
+// count n[0]), candidates whose results did not fit a pool (list b, n[1]),
+// regions over the medium LDS tiles or the global-memory tiles (list c,
+// n[4]); n[2] counts the regions over the global-memory tiles
+__global__ void k_overflow_list(Cands C, int* la, int* lb, int* lc, int* n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= C.n || C.st[i] != ST_PENDING) return;
-    if (C.gst[i] == ST_OVERFLOW || C.gst[i] == ST_TOOBIG) la[atomicAdd(&n[0], 1)] = i;
-    else if (C.gst[i] == ST_POOLFULL) lb[atomicAdd(&n[1], 1)] = i;
-    if (C.gst[i] == ST_TOOBIG) atomicAdd(&n[2], 1);
+    const int g = C.gst[i];
+    if (g == ST_OVERFLOW) la[atomicAdd(&n[0], 1)] = i;
+    else if (g == ST_POOLFULL) lb[atomicAdd(&n[1], 1)] = i;
+    else if (g == ST_OVERFLOW2 || g == ST_TOOBIG) lc[atomicAdd(&n[4], 1)] = i;
+    if (g == ST_TOOBIG) atomicAdd(&n[2], 1);
 }
 
 // LDS tiles of the fast grow path (one 64-lane workgroup per candidate)
-constexpr int G_MAXRT = 256, G_HCAP = 1024, G_RFHCAP = 128, G_MAXRF = 48, G_MAXBE = 96, G_QHCAP = 128,
-              G_MAXQ = 64, G_MAXBF = 256;
+// (about 12 KB: 12 workgroups per CU, the register limit of this kernel)
+constexpr int G_MAXRT = 192, G_HCAP = 512, G_RFHCAP = 128, G_MAXRF = 48, G_MAXBE = 64, G_QHCAP = 128,
+              G_MAXQ = 64, G_MAXBF = 192;
+#define QM_TILES_SMALL 0, G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF, 0
+// medium LDS tiles (about 64 KB: two workgroups per CU) for the regions over
+// the small ones; their edge table (M_EHCAP entries) lives in global memory
+constexpr int M_MAXRT = 1024, M_HCAP = 4096, M_RFHCAP = 512, M_MAXRF = 256, M_MAXBE = 384, M_QHCAP = 256,
+              M_MAXQ = 128, M_MAXBF = 1024, M_EHCAP = 8192;
+#define QM_TILES_MEDIUM 1, M_MAXRT, M_HCAP, M_RFHCAP, M_MAXRF, M_MAXBE, M_QHCAP, M_MAXQ, M_MAXBF, M_EHCAP
 // global-slab tiles of the overflow path
 constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, B_MAXBE = 4096,
               B_QHCAP = 8192, B_MAXQ = 4096, B_MAXBF = 32768;
@@ -134,7 +144,7 @@ struct Engine {
     DBuf<int4> c_tup0;
     DBuf<double4> c_p0;
     DBuf<int> c_elem, c_st, c_reason, c_seed, gst, greason, reg_off, reg_n, bf_off, bf_n, be_off, be_n,
-        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, plist;
+        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, plist, glist;
     DBuf<unsigned char> mis_drop, mis_lose;   // selection: per-candidate pass flags (kept zero)
     DBuf<unsigned long long> c_key;
     DBuf<int4> c_tup;
@@ -145,10 +155,11 @@ struct Engine {
     DBuf<int4> p_be, p_bfr;
     DBuf<int2> p_q;
     DBuf<int> ctr;     // pool counters [0..5], candidates per class [8..10], totals [11..13],
-                       // dead [14], stats [16..31], re-run list counts [32..34], tile code [35],
+                       // dead [14], stats [16..31], re-run list counts [32..34] and [36], tile code [35],
                        // undecided per selection pass of a batch [40..40+MIS_BATCH)
     DBuf<char> tmp;    // hipcub scratch
     DBuf<char> slab;   // overflow grow tiles
+    DBuf<char> eslab;  // edge tables of the medium LDS tier
     Cands C{};
     Pools PL{};
     BfPool BP{};
@@ -197,14 +208,14 @@ struct Engine {
 
     explicit Engine(hipStream_t st) : s(st) {}
     ~Engine() {
-        DBuf<char>* bufs_c[] = {&tmp, &slab};
+        DBuf<char>* bufs_c[] = {&tmp, &slab, &eslab};
         for (auto* b : bufs_c) b->release(s);
         X.release(s); TV.release(s); TA.release(s); TF.release(s); TS.release(s); TI.release(s);
         SV.release(s); SSEG.release(s); STET.release(s); FAX.release(s); SFL.release(s);
         mark.release(s); owner.release(s);
         for (auto* b : {&cand_out, &c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
                         &c_seed, &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off,
-                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &p_reg,
+                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &glist, &p_reg,
                         &p_bf, &p_cl, &p_clc, &ctr})
             b->release(s);
         c_key0.release(s); skey.release(s); c_key.release(s); mis_drop.release(s); mis_lose.release(s);
@@ -237,7 +248,7 @@ struct Engine {
         size_t m = std::max(n, 1);
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
                         &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
-                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist})
+                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &glist})
             b->ensure(m, s, false);
         c_key0.ensure(m, s, false); skey.ensure(m, s, false); c_key.ensure(m, s, false);
         mis_drop.ensure(m, s, false, 0); mis_lose.ensure(m, s, false, 0);
@@ -430,7 +441,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         GrowTiles T{};
         T.maxrt = B_MAXRT * k; T.hcap = B_HCAP * k; T.rfhcap = B_RFHCAP * k; T.maxrf = B_MAXRF * k;
         T.maxbe = B_MAXBE * k; T.qhcap = B_QHCAP * k; T.maxq = B_MAXQ * k; T.maxbf = B_MAXBF * k;
-        T.maxcx = B_MAXBF * k; T.big = 1;
+        T.maxcx = B_MAXBF * k; T.tier = 2;
         T.ehcap = 1;
         while (T.ehcap < 2 * (3 * T.maxbf + T.maxbe)) T.ehcap <<= 1;
         return T;
@@ -487,18 +498,18 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         {
             int grid = std::min(ncand, 16384);
             E.pbegin();
-            k_grow_lds<G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF>
-                <<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, nullptr, 0);
+            k_grow_lds<QM_TILES_SMALL><<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, nullptr, 0, nullptr);
             E.pend(3);
         }
         int ncl_final = 0;
         for (int attempt = 0;; ++attempt) {
             HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
-            k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.plist.p, olist_n);
-            int cw[36];
+            HIPCK(hipMemsetAsync(olist_n + 4, 0, sizeof(int), s));
+            k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.plist.p, E.glist.p, olist_n);
+            int cw[37];
             HIPCK(hipMemcpyAsync(cw, E.ctr.p, sizeof cw, hipMemcpyDeviceToHost, s));
             HIPCK(hipStreamSynchronize(s));
-            const int nover = cw[32], nfull = cw[33];
+            const int nover = cw[32], nfull = cw[33], nbig = cw[36];
             if (cw[34]) {
                 if (tile_scale >= B_MAXSCALE)
                     throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size (round " +
@@ -511,10 +522,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 HIPCK(hipMemsetAsync(E.ctr.p + 35, 0, sizeof(int), s));
             }
             note(attempt == 0 ? "grown; over the tiles / pools" : "re-run; still over the tiles / pools", round,
-                 cls, nover + nfull);
-            if (E.prof) { E.prof_over += nover; E.prof_full += nfull; }
-            if (nover + nfull == 0) { E.pool_seen(cw, ncand, cls); ncl_final = cw[3]; break; }
-            if (attempt >= 16) throw QmError(QM_ENOMEM, "result pools kept overflowing");
+                 cls, nover + nfull + nbig);
+            if (E.prof) { E.prof_over += nover + nbig; E.prof_full += nfull; }
+            if (nover + nfull + nbig == 0) { E.pool_seen(cw, ncand, cls); ncl_final = cw[3]; break; }
+            if (attempt >= 64) throw QmError(QM_ENOMEM, "result pools kept overflowing");
             if (cw[5]) {                 // a pool was full: double every pool, keep what is in it
                 E.ensure_pools(2 * E.p_reg.cap, 2 * E.p_bf.cap, 2 * E.p_be.cap, 2 * E.p_cl.cap, 2 * E.p_q.cap, true);
                 HIPCK(hipMemsetAsync(E.ctr.p + 5, 0, sizeof(int), s));
@@ -522,15 +533,21 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             BfPool BPr = E.BP;
             BPr.prof = nullptr;          // region counters cover the first LDS-tile launch only
             E.pbegin();
-            if (nfull > 0)               // same tiles again: these regions fit them
-                k_grow_lds<G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF>
-                    <<<std::min(nfull, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.plist.p, nfull);
-            if (nover > 0) {
+            if (nfull > 0)               // small tiles again (a region over them moves on)
+                k_grow_lds<QM_TILES_SMALL><<<std::min(nfull, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr,
+                                                                                E.plist.p, nfull, nullptr);
+            if (nover > 0) {             // medium LDS tiles
+                const int grid = std::min(nover, 1024);
+                E.eslab.ensure((size_t)grid * M_EHCAP * (sizeof(unsigned long long) + sizeof(int4)), s, false);
+                k_grow_lds<QM_TILES_MEDIUM><<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover,
+                                                                E.eslab.p);
+            }
+            if (nbig > 0) {              // global-memory tiles
                 const GrowTiles BT = big_tiles(tile_scale);
                 const size_t slab_block = grow_slab_bytes(BT);
-                int grid = (int)std::min<size_t>({(size_t)nover, 256, std::max<size_t>(1, (2ull << 30) / slab_block)});
+                int grid = (int)std::min<size_t>({(size_t)nbig, 256, std::max<size_t>(1, (2ull << 30) / slab_block)});
                 E.slab.ensure(slab_block * grid, s, false);
-                k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover, BT, E.slab.p,
+                k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
                                                   slab_block);
             }
             E.pend(8);
