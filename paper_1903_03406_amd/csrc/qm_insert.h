@@ -131,6 +131,47 @@ __global__ void k_scan_vals(Cands C, int cls, int* vk, int* vt, int* vs) {
     vt[c] = d > 0 ? d : 0;
     vs[c] = kept && cls == CLS_SS;
 }
+// the three per-candidate values (kept, new tets, new subsegments)
+QMD int3 scan_vals(const Cands& C, int cls, int c) {
+    bool kept = C.state[c] == 1;
+    int d = kept ? C.bf_n[c] - C.reg_n[c] : 0;
+    return make_int3(kept ? 1 : 0, d > 0 ? d : 0, kept && cls == CLS_SS ? 1 : 0);
+}
+// Exclusive scans of the three values and their totals in one workgroup
+// (rounds with few candidates: one launch instead of a device-wide scan per
+// value).  sk/st/ss as from k_scan_vals + exclusive sums; tot = k_totals.
+__global__ __launch_bounds__(1024) void k_scan_small(Cands C, int cls, int n, int* sk, int* st, int* ss,
+                                                     int* tot) {
+    __shared__ int3 wsum[16];
+    __shared__ int3 carry;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = make_int3(0, 0, 0);
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int c = base + threadIdx.x;
+        int3 v = c < n ? scan_vals(C, cls, c) : make_int3(0, 0, 0);
+        int3 x = v;                                   // inclusive scan within the wave
+        for (int off = 1; off < 64; off <<= 1) {
+            int a = __shfl_up(x.x, off, 64), b = __shfl_up(x.y, off, 64), d = __shfl_up(x.z, off, 64);
+            if (lane >= off) { x.x += a; x.y += b; x.z += d; }
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int3 pre = carry;                             // waves before this one, chunks before this one
+        for (int w = 0; w < wid; ++w) { pre.x += wsum[w].x; pre.y += wsum[w].y; pre.z += wsum[w].z; }
+        if (c < n) {
+            sk[c] = pre.x + x.x - v.x;
+            st[c] = pre.y + x.y - v.y;
+            ss[c] = pre.z + x.z - v.z;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < 16; ++w) { carry.x += wsum[w].x; carry.y += wsum[w].y; carry.z += wsum[w].z; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { tot[0] = carry.x; tot[1] = carry.y; tot[2] = carry.z; }
+}
+
 // optional cap on insertions per round: only the first `cap` kept survive
 __global__ void k_cap_kept(Cands C, const int* sk, int cap) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;

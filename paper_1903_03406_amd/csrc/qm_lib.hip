@@ -84,6 +84,13 @@ struct qm_result {
 
 namespace qm {
 
+// round start: zero the round's counters (all of ctr[0..48) except the
+// totals and the running dead-slot count, ctr[11..15))
+__global__ void k_round_reset(int* ctr) {
+    int i = threadIdx.x;
+    if (i < 48 && (i < 11 || i >= 15)) ctr[i] = 0;
+}
+
 __global__ void k_iota(int n, int* o) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = i;
@@ -125,6 +132,7 @@ constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, 
 // QM_ECAPACITY instead.
 constexpr int B_MAXSCALE = 1;
 constexpr int MIS_BATCH = 4;       // selection passes launched per synchronisation
+constexpr int SCAN_SMALL = 32768;  // up to this many candidates, one workgroup scans
 
 struct Engine {
     hipStream_t s;
@@ -138,7 +146,6 @@ struct Engine {
     DBuf<unsigned long long> mark;
     DBuf<int> owner;
     // candidates
-    DBuf<int> cand_out;   // classification output (one slot per element)
     DBuf<int> c_elem0, c_st0, c_reason0, order0, order1;
     DBuf<unsigned long long> c_key0, skey;
     DBuf<int4> c_tup0;
@@ -213,7 +220,7 @@ struct Engine {
         X.release(s); TV.release(s); TA.release(s); TF.release(s); TS.release(s); TI.release(s);
         SV.release(s); SSEG.release(s); STET.release(s); FAX.release(s); SFL.release(s);
         mark.release(s); owner.release(s);
-        for (auto* b : {&cand_out, &c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
+        for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
                         &c_seed, &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off,
                         &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &glist, &p_reg,
                         &p_bf, &p_cl, &p_clc, &ctr})
@@ -459,12 +466,14 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.cur_round = round;
         // step 1: classify, in the paper's order (a class is skipped on the
         // device when an earlier one has candidates); one synchronisation
-        E.cand_out.ensure(std::max((size_t)E.M.nss, 4 * (size_t)E.M.nt), s, false);
-        HIPCK(hipMemsetAsync(cnt_d, 0, 3 * sizeof(int), s));
+        // candidates go straight to the first candidate array, sized for the
+        // largest class (so the later sizing never moves it)
+        E.c_elem0.ensure(std::max((size_t)E.M.nss, 4 * (size_t)E.M.nt), s, false);
+        k_round_reset<<<1, 64, 0, s>>>(E.ctr.p);
         E.pbegin();
-        if (E.M.nss) k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.cand_out.p, cnt_d);
-        k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, cnt_d);
-        k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.cand_out.p, cnt_d);
+        if (E.M.nss) k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
+        k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
+        k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
         E.pend(0);
         sync_counters();
         patch_last_record();
@@ -475,7 +484,6 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         if (cls == CLS_NONE) break;
         E.ensure_cands(ncand);
         // step 2: splitting points and priorities, then priority order
-        HIPCK(hipMemcpyAsync(E.c_elem0.p, E.cand_out.p, sizeof(int) * ncand, hipMemcpyDeviceToDevice, s));
         E.pbegin();
         k_split<<<nblk(ncand), 256, 0, s>>>(E.M, cls, ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
                                           E.c_st0.p, E.c_reason0.p);
@@ -491,8 +499,6 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         // round's use per candidate; candidates whose results did not fit are
         // evaluated again after the pools grow, and regions over the LDS tiles
         // are evaluated again with global-memory tiles.
-        HIPCK(hipMemsetAsync(E.ctr.p, 0, 8 * sizeof(int), s));
-        HIPCK(hipMemsetAsync(E.ctr.p + 35, 0, sizeof(int), s));
         E.ensure_pools(E.pool_need(0, ncand, cls), E.pool_need(1, ncand, cls), E.pool_need(2, ncand, cls),
                        E.pool_need(3, ncand, cls), E.pool_need(4, ncand, cls), false);
         {
@@ -503,8 +509,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         }
         int ncl_final = 0;
         for (int attempt = 0;; ++attempt) {
-            HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
-            HIPCK(hipMemsetAsync(olist_n + 4, 0, sizeof(int), s));
+            if (attempt > 0) {           // the round reset zeroed them for the first attempt
+                HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
+                HIPCK(hipMemsetAsync(olist_n + 4, 0, sizeof(int), s));
+            }
             k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.plist.p, E.glist.p, olist_n);
             int cw[37];
             HIPCK(hipMemcpyAsync(cw, E.ctr.p, sizeof cw, hipMemcpyDeviceToHost, s));
@@ -555,7 +563,6 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         const int ncl = std::min(ncl_final, E.PL.cap_cl);
         // verdicts: flags of rejected / exempted candidates, round statistics,
         // selection state
-        HIPCK(hipMemsetAsync(stats_d, 0, 16 * sizeof(int), s));
         E.pbegin();
         k_verdicts<<<nblk(ncand), 256, 0, s>>>(E.M, cls, E.C, E.PL, stats_d);
         E.pend(4);
@@ -564,6 +571,11 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         // and taken once the selection is complete (one synchronisation)
         auto scans = [&](bool cap) {
             E.pbegin();
+            if (!cap && ncand <= SCAN_SMALL) {
+                k_scan_small<<<1, 1024, 0, s>>>(E.C, cls, ncand, E.sk.p, E.st_.p, E.ss_.p, tot_d);
+                E.pend(6);
+                return;
+            }
             k_scan_vals<<<nblk(ncand), 256, 0, s>>>(E.C, cls, E.vk.p, E.vt.p, E.vs.p);
             E.exscan(E.vk.p, E.sk.p, ncand);
             if (cap) {
@@ -579,7 +591,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         int passes = 0;
         for (int batch = 0;; ++batch) {
             if (ncl > 0) {
-                HIPCK(hipMemsetAsync(undec_d, 0, MIS_BATCH * sizeof(int), s));
+                if (batch > 0) HIPCK(hipMemsetAsync(undec_d, 0, MIS_BATCH * sizeof(int), s));
                 E.pbegin();
                 for (int b = 0; b < MIS_BATCH; ++b) {
                     const unsigned ps = E.pass++;
