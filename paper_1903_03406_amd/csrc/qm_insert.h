@@ -112,6 +112,51 @@ __global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* 
     if (c < 0) return;
     if (state[c] == 1) owner[cl[e]] = c;
 }
+// All passes of a small round in one workgroup (phases separated by block
+// barriers): one launch instead of four per pass.  *npass receives the
+// passes run, or -1 when max_pass passes did not finish.
+__global__ __launch_bounds__(1024) void k_mis_small(int ncl, const int* cl, const int* clc, int n, int* state,
+                                                    unsigned long long* mark, int* owner, unsigned char* drop,
+                                                    unsigned char* lose, unsigned pass0, int max_pass, int* npass) {
+    __shared__ int undecided;
+    for (int k = 0; k < max_pass; ++k) {
+        const unsigned pass = pass0 + (unsigned)k;
+        for (int e = threadIdx.x; e < ncl; e += blockDim.x) {          // mark
+            int c = clc[e];
+            if (c >= 0 && state[c] == 0) atomicMax(&mark[cl[e]], mis_val(pass, c));
+        }
+        if (threadIdx.x == 0) undecided = 0;
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncl; e += blockDim.x) {          // check
+            int c = clc[e];
+            if (c < 0 || state[c] != 0) continue;
+            int t = cl[e];
+            if (owner[t] >= 0) drop[c] = 1;
+            else if (mark[t] != mis_val(pass, c)) lose[c] = 1;
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {            // decide
+            if (state[c] != 0) continue;
+            if (drop[c]) state[c] = 2;
+            else if (lose[c]) atomicAdd(&undecided, 1);
+            else state[c] = 1;
+            drop[c] = 0; lose[c] = 0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < ncl; e += blockDim.x) {          // commit
+            int c = clc[e];
+            if (c >= 0 && state[c] == 1) owner[cl[e]] = c;
+        }
+        __syncthreads();
+        if (undecided == 0) {
+            if (threadIdx.x == 0) *npass = k + 1;
+            return;
+        }
+        __syncthreads();                     // all have read `undecided` before the next reset
+    }
+    if (threadIdx.x == 0) *npass = -1;
+}
+
 // clear every ownership of this round (kept candidates, and kept ones that
 // a per-round cap demoted afterwards)
 __global__ void k_mis_release(int ncl, const int* cl, const int* clc, int* owner) {

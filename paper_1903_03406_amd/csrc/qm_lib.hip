@@ -133,6 +133,8 @@ constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, 
 constexpr int B_MAXSCALE = 1;
 constexpr int MIS_BATCH = 4;       // selection passes launched per synchronisation
 constexpr int SCAN_SMALL = 32768;  // up to this many candidates, one workgroup scans
+constexpr int MIS_SMALL = 65536;   // up to this many claims and candidates, one workgroup selects
+constexpr int MIS_SMALL_PASSES = 1 << 16;
 
 struct Engine {
     hipStream_t s;
@@ -163,6 +165,7 @@ struct Engine {
     DBuf<int2> p_q;
     DBuf<int> ctr;     // pool counters [0..5], candidates per class [8..10], totals [11..13],
                        // dead [14], stats [16..31], re-run list counts [32..34] and [36], tile code [35],
+                       // passes of a one-workgroup selection [38],
                        // undecided per selection pass of a batch [40..40+MIS_BATCH)
     DBuf<char> tmp;    // hipcub scratch
     DBuf<char> slab;   // overflow grow tiles
@@ -426,6 +429,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     int* stats_d = E.ctr.p + 16;
     int* olist_n = E.ctr.p + 32;
     int* undec_d = E.ctr.p + 40;
+    int* npass_d = E.ctr.p + 38;
     int round = 0, status = 0, last_ncand = 0;
     int hc[48];                     // host copy of ctr[0..48), taken at each synchronisation
     auto sync_counters = [&]() {
@@ -589,8 +593,15 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             E.pend(6);
         };
         int passes = 0;
+        const bool small_sel = ncl > 0 && ncl <= MIS_SMALL && ncand <= MIS_SMALL;
+        if (small_sel) {
+            E.pbegin();
+            k_mis_small<<<1, 1024, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, ncand, E.state.p, E.mark.p, E.owner.p,
+                                           E.mis_drop.p, E.mis_lose.p, E.pass, MIS_SMALL_PASSES, npass_d);
+            E.pend(5);
+        }
         for (int batch = 0;; ++batch) {
-            if (ncl > 0) {
+            if (ncl > 0 && !small_sel) {
                 if (batch > 0) HIPCK(hipMemsetAsync(undec_d, 0, MIS_BATCH * sizeof(int), s));
                 E.pbegin();
                 for (int b = 0; b < MIS_BATCH; ++b) {
@@ -607,6 +618,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             }
             scans(false);
             sync_counters();
+            if (small_sel) {
+                if (hc[38] < 0) throw QmError(QM_EINTERNAL, "selection did not finish");
+                passes = hc[38];
+                E.pass += (unsigned)passes;      // marks of later passes must compare higher
+                break;
+            }
             if (ncl > 0)
                 for (int b = 0; b < MIS_BATCH; ++b) {
                     ++passes;
