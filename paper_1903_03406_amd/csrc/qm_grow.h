@@ -221,11 +221,9 @@ QMD void over_status(const Cands& C, const Pools& PL, const GrowTiles& W, int ci
     else C.gst[cid] = W.tier == 0 ? ST_OVERFLOW : ST_OVERFLOW2;
 }
 
-// results that did not fit a pool: evaluate again, after the pools grow, in
-// the same tier's tiles (the region is known to fit them)
-QMD int poolfull_status(const GrowTiles& W) {
-    return W.tier == 0 ? ST_POOLFULL : (W.tier == 1 ? ST_OVERFLOW : ST_OVERFLOW2);
-}
+// results that did not fit a pool: the whole pass is evaluated again with
+// larger pools
+QMD int poolfull_status(const GrowTiles&) { return ST_POOLFULL; }
 
 // Evaluate candidate `cid` (steps: seeds, grow R_F, grow R_T, validate,
 // write results).  All 64 lanes of the workgroup call this together.

@@ -100,17 +100,22 @@ __global__ void k_fill(int n, int* o, int v) {
     if (i < n) o[i] = v;
 }
 // candidates to evaluate again: regions over the small LDS tiles (list a,
-// count n[0]), candidates whose results did not fit a pool (list b, n[1]),
-// regions over the medium LDS tiles or the global-memory tiles (list c,
-// n[4]); n[2] counts the regions over the global-memory tiles
-__global__ void k_overflow_list(Cands C, int* la, int* lb, int* lc, int* n) {
+// count n[0]) and regions over the medium LDS tiles or the global-memory
+// tiles (list c, n[4]); n[1] counts candidates whose results did not fit a
+// pool, n[2] the regions over the global-memory tiles
+__global__ void k_overflow_list(Cands C, int* la, int* lc, int* n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= C.n || C.st[i] != ST_PENDING) return;
     const int g = C.gst[i];
     if (g == ST_OVERFLOW) la[atomicAdd(&n[0], 1)] = i;
-    else if (g == ST_POOLFULL) lb[atomicAdd(&n[1], 1)] = i;
+    else if (g == ST_POOLFULL) atomicAdd(&n[1], 1);
     else if (g == ST_OVERFLOW2 || g == ST_TOOBIG) lc[atomicAdd(&n[4], 1)] = i;
     if (g == ST_TOOBIG) atomicAdd(&n[2], 1);
+}
+// a pass over again: zero the pool counters and the full flag
+__global__ void k_round_reset_pools(int* ctr) {
+    int i = threadIdx.x;
+    if (i < 8) ctr[i] = 0;
 }
 
 // LDS tiles of the fast grow path (one 64-lane workgroup per candidate)
@@ -153,7 +158,7 @@ struct Engine {
     DBuf<int4> c_tup0;
     DBuf<double4> c_p0;
     DBuf<int> c_elem, c_st, c_reason, c_seed, gst, greason, reg_off, reg_n, bf_off, bf_n, be_off, be_n,
-        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, plist, glist;
+        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, glist;
     DBuf<unsigned char> mis_drop, mis_lose;   // selection: per-candidate pass flags (kept zero)
     DBuf<unsigned long long> c_key;
     DBuf<int4> c_tup;
@@ -225,7 +230,7 @@ struct Engine {
         mark.release(s); owner.release(s);
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
                         &c_seed, &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off,
-                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &glist, &p_reg,
+                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &p_reg,
                         &p_bf, &p_cl, &p_clc, &ctr})
             b->release(s);
         c_key0.release(s); skey.release(s); c_key.release(s); mis_drop.release(s); mis_lose.release(s);
@@ -258,7 +263,7 @@ struct Engine {
         size_t m = std::max(n, 1);
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
                         &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
-                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &plist, &glist})
+                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist})
             b->ensure(m, s, false);
         c_key0.ensure(m, s, false); skey.ensure(m, s, false); c_key.ensure(m, s, false);
         mis_drop.ensure(m, s, false, 0); mis_lose.ensure(m, s, false, 0);
@@ -271,14 +276,24 @@ struct Engine {
         C.be_off = be_off.p; C.be_n = be_n.p; C.cl_off = cl_off.p; C.cl_n = cl_n.p;
         C.q_off = q_off.p; C.q_n = q_n.p; C.state = state.p;
     }
+    bool verbose = false;
     void ensure_pools(size_t reg, size_t bf, size_t be, size_t cl, size_t q, bool keep) {
+        // pool offsets and counters are int32: refuse sizes they cannot index
+        const size_t lim = (size_t)1 << 30;
+        if (reg > lim || bf > lim || be > lim || cl > lim || q > lim)
+            throw QmError(QM_ENOMEM, "a round's result pools exceed 2^30 entries");
+        const size_t before = p_reg.cap + p_bf.cap + p_bfr.cap + p_be.cap + p_cl.cap + p_q.cap;
         p_reg.ensure(reg, s, keep); p_bf.ensure(bf, s, keep); p_bfr.ensure(BFR * bf, s, keep);
         p_be.ensure(be, s, keep); p_cl.ensure(cl, s, keep); p_q.ensure(q, s, keep);
-        p_clc.ensure(cl, s, keep, 0xFF);   // new claim entries start void
+        p_clc.ensure(cl, s, keep);
         PL.reg = p_reg.p; PL.bf = p_bf.p; PL.be = p_be.p; PL.cl = p_cl.p; PL.clc = p_clc.p; PL.q = p_q.p;
         PL.cap_reg = (int)p_reg.cap; PL.cap_bf = (int)p_bf.cap; PL.cap_be = (int)p_be.cap;
         PL.cap_cl = (int)p_cl.cap; PL.cap_q = (int)p_q.cap; PL.ctr = ctr.p;
         BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / BFR); BP.prof = prof ? pctr.p : nullptr;
+        if (verbose && p_reg.cap + p_bf.cap + p_bfr.cap + p_be.cap + p_cl.cap + p_q.cap != before)
+            fprintf(stderr, "qm: pools %s: region %zu, faces %zu (%.2f GB of records), edges %zu, claims %zu, "
+                    "queue %zu entries\n", keep ? "doubled" : "grown", p_reg.cap, p_bf.cap,
+                    p_bfr.cap * sizeof(int4) / 1e9, p_be.cap, p_cl.cap, p_q.cap);
     }
     // pool entries per candidate seen in the last round (region tets,
     // boundary faces, 2D boundary edges, claims, queue entries); the next
@@ -294,6 +309,11 @@ struct Engine {
     void pool_seen(const int* used, int ncand, int cls) {
         if (ncand <= 0) return;
         for (int k = 0; k < 5; ++k) pool_rate[cls][k] = (double)used[k] / ncand;
+    }
+    BfPool BPnoprof() const {   // region counters cover the first small-tile launch only
+        BfPool b = BP;
+        b.prof = nullptr;
+        return b;
     }
     void* scratch(size_t bytes) {
         tmp.ensure(bytes, s, false);
@@ -458,6 +478,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         return T;
     };
     const bool verbose = (opt->flags & QM_VERBOSE) != 0;
+    E.verbose = verbose;
     auto last_note = std::chrono::steady_clock::now();
     // progress inside a long round (verbose): at most one line per 10 s
     auto note = [&](const char* phase, int round_, int cls_, int n_) {
@@ -505,64 +526,70 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         // are evaluated again with global-memory tiles.
         E.ensure_pools(E.pool_need(0, ncand, cls), E.pool_need(1, ncand, cls), E.pool_need(2, ncand, cls),
                        E.pool_need(3, ncand, cls), E.pool_need(4, ncand, cls), false);
-        {
-            int grid = std::min(ncand, 16384);
-            E.pbegin();
-            k_grow_lds<QM_TILES_SMALL><<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, E.BP, nullptr, 0, nullptr);
-            E.pend(3);
-        }
+        // A pass evaluates every candidate once: small LDS tiles, then the
+        // regions over them with medium LDS tiles, then global-memory tiles.
+        // When a result pool was full the pass is repeated whole with fresh
+        // pools sized for everything it reserved (no pool is ever copied).
         int ncl_final = 0;
-        for (int attempt = 0;; ++attempt) {
-            if (attempt > 0) {           // the round reset zeroed them for the first attempt
-                HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
-                HIPCK(hipMemsetAsync(olist_n + 4, 0, sizeof(int), s));
-            }
-            k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.plist.p, E.glist.p, olist_n);
-            int cw[37];
-            HIPCK(hipMemcpyAsync(cw, E.ctr.p, sizeof cw, hipMemcpyDeviceToHost, s));
-            HIPCK(hipStreamSynchronize(s));
-            const int nover = cw[32], nfull = cw[33], nbig = cw[36];
-            if (cw[34]) {
-                if (tile_scale >= B_MAXSCALE)
-                    throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size (round " +
-                                                    std::to_string(round) + ", class " + std::to_string(cls) +
-                                                    ", tile code " + std::to_string(cw[35]) + ")");
-                tile_scale *= 4;
-                if (verbose)
-                    fprintf(stderr, "qm: round %d class %d: %d regions over the global tiles (code %d), tile scale %d\n",
-                            round, cls, cw[34], cw[35], tile_scale);
-                HIPCK(hipMemsetAsync(E.ctr.p + 35, 0, sizeof(int), s));
-            }
-            note(attempt == 0 ? "grown; over the tiles / pools" : "re-run; still over the tiles / pools", round,
-                 cls, nover + nfull + nbig);
-            if (E.prof) { E.prof_over += nover + nbig; E.prof_full += nfull; }
-            if (nover + nfull + nbig == 0) { E.pool_seen(cw, ncand, cls); ncl_final = cw[3]; break; }
-            if (attempt >= 64) throw QmError(QM_ENOMEM, "result pools kept overflowing");
-            if (cw[5]) {                 // a pool was full: double every pool, keep what is in it
-                E.ensure_pools(2 * E.p_reg.cap, 2 * E.p_bf.cap, 2 * E.p_be.cap, 2 * E.p_cl.cap, 2 * E.p_q.cap, true);
-                HIPCK(hipMemsetAsync(E.ctr.p + 5, 0, sizeof(int), s));
-            }
-            BfPool BPr = E.BP;
-            BPr.prof = nullptr;          // region counters cover the first LDS-tile launch only
+        for (int pass = 0;; ++pass) {
+            if (pass > 0) k_round_reset_pools<<<1, 64, 0, s>>>(E.ctr.p);
             E.pbegin();
-            if (nfull > 0)               // small tiles again (a region over them moves on)
-                k_grow_lds<QM_TILES_SMALL><<<std::min(nfull, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr,
-                                                                                E.plist.p, nfull, nullptr);
-            if (nover > 0) {             // medium LDS tiles
-                const int grid = std::min(nover, 1024);
-                E.eslab.ensure((size_t)grid * M_EHCAP * (sizeof(unsigned long long) + sizeof(int4)), s, false);
-                k_grow_lds<QM_TILES_MEDIUM><<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover,
-                                                                E.eslab.p);
+            k_grow_lds<QM_TILES_SMALL><<<std::min(ncand, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL,
+                                                                             pass == 0 ? E.BP : E.BPnoprof(),
+                                                                             nullptr, 0, nullptr);
+            E.pend(pass == 0 ? 3 : 8);
+            int cw[37];
+            for (int attempt = 0;; ++attempt) {
+                if (attempt > 0 || pass > 0) {
+                    HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
+                    HIPCK(hipMemsetAsync(olist_n + 4, 0, sizeof(int), s));
+                }
+                k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.glist.p, olist_n);
+                HIPCK(hipMemcpyAsync(cw, E.ctr.p, sizeof cw, hipMemcpyDeviceToHost, s));
+                HIPCK(hipStreamSynchronize(s));
+                const int nover = cw[32], nbig = cw[36];
+                if (cw[34]) {
+                    if (tile_scale >= B_MAXSCALE)
+                        throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size (round " +
+                                                        std::to_string(round) + ", class " + std::to_string(cls) +
+                                                        ", tile code " + std::to_string(cw[35]) + ")");
+                    tile_scale *= 4;
+                    if (verbose)
+                        fprintf(stderr, "qm: round %d class %d: %d regions over the global tiles (code %d), "
+                                "tile scale %d\n", round, cls, cw[34], cw[35], tile_scale);
+                    HIPCK(hipMemsetAsync(E.ctr.p + 35, 0, sizeof(int), s));
+                }
+                note("grown; regions over the tiles", round, cls, nover + nbig);
+                if (E.prof) E.prof_over += nover + nbig;
+                if (nover + nbig == 0) break;
+                if (attempt >= 64) throw QmError(QM_EINTERNAL, "regions kept outgrowing the tiles");
+                const BfPool BPr = E.BPnoprof();
+                E.pbegin();
+                if (nover > 0) {             // medium LDS tiles
+                    const int grid = std::min(nover, 1024);
+                    E.eslab.ensure((size_t)grid * M_EHCAP * (sizeof(unsigned long long) + sizeof(int4)), s, false);
+                    k_grow_lds<QM_TILES_MEDIUM><<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover,
+                                                                    E.eslab.p);
+                }
+                if (nbig > 0) {              // global-memory tiles
+                    const GrowTiles BT = big_tiles(tile_scale);
+                    const size_t slab_block = grow_slab_bytes(BT);
+                    int grid = (int)std::min<size_t>({(size_t)nbig, 256,
+                                                      std::max<size_t>(1, (2ull << 30) / slab_block)});
+                    E.slab.ensure(slab_block * grid, s, false);
+                    k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
+                                                      slab_block);
+                }
+                E.pend(8);
             }
-            if (nbig > 0) {              // global-memory tiles
-                const GrowTiles BT = big_tiles(tile_scale);
-                const size_t slab_block = grow_slab_bytes(BT);
-                int grid = (int)std::min<size_t>({(size_t)nbig, 256, std::max<size_t>(1, (2ull << 30) / slab_block)});
-                E.slab.ensure(slab_block * grid, s, false);
-                k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
-                                                  slab_block);
-            }
-            E.pend(8);
+            if (!cw[5]) { E.pool_seen(cw, ncand, cls); ncl_final = cw[3]; break; }
+            // a pool was full: the counters hold everything this pass reserved
+            if (E.prof) E.prof_full += cw[33];
+            if (pass >= 8) throw QmError(QM_ENOMEM, "result pools kept overflowing");
+            auto need = [](int used, size_t cap) { return std::max(cap, (size_t)used + (size_t)used / 8 + 4096); };
+            E.ensure_pools(need(cw[0], E.p_reg.cap), need(cw[1], E.p_bf.cap), need(cw[2], E.p_be.cap),
+                           need(cw[3], E.p_cl.cap), need(cw[4], E.p_q.cap), false);
+            note("result pools grown; evaluating the round again", round, cls, pass + 1);
         }
         const int ncl = std::min(ncl_final, E.PL.cap_cl);
         // verdicts: flags of rejected / exempted candidates, round statistics,
