@@ -105,6 +105,42 @@ def cpu_baseline(w, target_s):
                       f"{res.seconds:.1f} s of oracle round loop, setup excluded)"}
 
 
+def bench_batch(args, qm):
+    """Batched workload (config 4 instances 0..N-1, uniform points + a rotated
+    ellipsoid surface, B = 2.0): the whole set refined by qm_refine_batch on
+    --streams streams, against the same set refined one instance at a time.
+    Host arrays in, host results out in both forms."""
+    import numpy as np
+    import qm_inputs as qi
+    t0 = time.time()
+    ws = [qi.config(4, i) for i in range(args.batch)]
+    npts = [len(w.xyz) - 8 for w in ws]
+    print(f"[bench] {len(ws)} instances, {sum(npts)} points (min {min(npts)}, max {max(npts)}), "
+          f"built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    qm.refine_batch(ws[:min(4, len(ws))], nstreams=args.streams)          # warm-up
+    t1 = time.perf_counter()
+    lat = []
+    for w in ws:
+        a = time.perf_counter()
+        qm.refine_workload(w)
+        lat.append(time.perf_counter() - a)
+    t2 = time.perf_counter()
+    res = qm.refine_batch(ws, nstreams=args.streams)
+    t3 = time.perf_counter()
+    steiner = sum(r.steiner for r in res)
+    seq, bat = t2 - t1, t3 - t2
+    out = {
+        "metric": "batched jobs/sec (config 4 instances)", "value": len(ws) / bat, "unit": "jobs/s",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"cfg4_instances_0_{len(ws) - 1}", "instances": len(ws), "points": int(sum(npts)),
+                   "streams": args.streams},
+        "one_at_a_time_jobs_per_s": len(ws) / seq, "speedup": seq / bat,
+        "steiner_per_s_batched": steiner / bat,
+        "latency_one_at_a_time_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +149,10 @@ def main():
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="instead of the single-instance line: the first N instances of the batched "
+                         "workload (config 4), batched jobs/s against one-at-a-time jobs/s")
+    ap.add_argument("--streams", type=int, default=8, help="streams of the batched run")
     ap.add_argument("--dump-rounds", default=None,
                     help="write the last step's per-round records and per-round kernel-family ms (JSON)")
     args = ap.parse_args()
@@ -125,6 +165,8 @@ def main():
     import torch
     import paper_1903_03406_amd as qm
 
+    if args.batch > 0:
+        return bench_batch(args, qm)
     t0 = time.time()
     w = make_workload(args.workload)
     print(f"[bench] workload {w.name}: {len(w.xyz)} vertices, {len(w.tets)} tets, "

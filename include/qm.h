@@ -122,6 +122,17 @@ typedef struct qm_result qm_result;
 int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream,
               qm_result** out);
 
+/* Refine n independent instances (each as qm_refine: the round loop of
+   paper, Section 2, on its own mesh).  plcs, meshes and opts are arrays of n;
+   the instances run concurrently on `nstreams` HIP streams of the calling
+   thread's current device (default priority), each taken in index order by a
+   worker thread.  outs[i] receives instance i's result (free each with
+   qm_result_free) and codes[i] its return code.  Returns 0 when every
+   instance returned 0 or QM_EROUNDS, else the code of the first instance that
+   failed (qm_last_error names it).  Inputs are borrowed for the call. */
+int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                    int32_t nstreams, qm_result** outs, int32_t* codes);
+
 /* Host view of a result: the output mesh (Steiner vertices appended after the
    input vertices, numbered by round and priority) and the statistics.
    Pointers stay valid until qm_result_free. */

@@ -102,7 +102,7 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
+EXPORTS = ("qm_refine", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version")
 
 
@@ -183,11 +183,16 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
         hs = stream.cuda_stream
     else:
         hs = int(stream)
-    P_ = ctypes.c_void_p
     res = ctypes.c_void_p()
     rc = lib.qm_refine(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), hs, ctypes.byref(res))
     if rc not in (0, -4):
         raise QmError(rc, lib.qm_last_error().decode())
+    return _take_result(lib, res, profile)
+
+
+def _take_result(lib, res, profile) -> RefineResult:
+    """Copy a qm_result into numpy arrays and free it."""
+    P_ = ctypes.c_void_p
     try:
         view, st = _Mesh(), _Stats()
         lib.qm_result_view(res, ctypes.byref(view), ctypes.byref(st))
@@ -234,6 +239,49 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
                              if profile else None), last)
     finally:
         lib.qm_result_free(res)
+
+
+def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, max_kept=0,
+                 profile=False) -> list:
+    """Refine independent instances concurrently (qm_refine_batch): each
+    workload exposes the PLC and CDT arrays and B (host arrays)."""
+    lib = _load()
+    n = len(workloads)
+    plcs, meshes, opts, keep = (_Plc * n)(), (_Mesh * n)(), (_Opts * n)(), []
+    for i, w in enumerate(workloads):
+        def h(a, dtype):
+            a = _arr(a, dtype)
+            keep.append(a)
+            return a.ctypes.data, a.shape[0]
+        pxyz, nv = h(w.xyz, np.float64)
+        ptet, nt = h(w.tets, np.int32)
+        psf, nsf = h(w.sf, np.int32)
+        psff, _ = h(w.sf_facet, np.int32)
+        pss, nss = h(w.ss, np.int32)
+        pssg, _ = h(w.ss_seg, np.int32)
+        pft, nft = h(w.ftri, np.int32)
+        pftf, _ = h(w.ftri_facet, np.int32)
+        pseg, nseg = h(w.seg if w.seg is not None else np.zeros((0, 2), np.int32), np.int32)
+        plcs[i] = _Plc(nv, nseg, pseg, nft, pft, pftf)
+        meshes[i] = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
+        opts[i] = _Opts(float(w.B), float(hmin_factor), int(max_rounds), int(max_kept),
+                        QM_PROFILE if profile else 0)
+    outs = (ctypes.c_void_p * max(n, 1))()
+    codes = (ctypes.c_int32 * max(n, 1))()
+    lib.qm_refine_batch.restype = ctypes.c_int
+    lib.qm_refine_batch.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    rc = lib.qm_refine_batch(n, ctypes.addressof(plcs), ctypes.addressof(meshes), ctypes.addressof(opts),
+                             int(nstreams), ctypes.addressof(outs), ctypes.addressof(codes))
+    results = []
+    for i in range(n):
+        if outs[i]:
+            results.append(_take_result(lib, ctypes.c_void_p(outs[i]), profile))
+        else:
+            results.append(None)
+    if rc not in (0, -4):
+        raise QmError(rc, lib.qm_last_error().decode())
+    return results
 
 
 def refine_workload(w, **kw) -> RefineResult:

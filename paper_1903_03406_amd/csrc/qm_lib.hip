@@ -15,6 +15,8 @@
 #include <stdexcept>
 #include <string>
 #include <vector>
+#include <thread>
+#include <atomic>
 
 #include "qm.h"
 #include "qm_insert.h"
@@ -804,6 +806,43 @@ int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void*
         g_err = "unknown failure";
         return QM_EINTERNAL;
     }
+}
+
+// Instances of a batch run concurrently: worker threads, each with its own
+// stream on the caller's device, take the instances in index order.
+int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                    int32_t nstreams, qm_result** outs, int32_t* codes) {
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!plcs || !meshes || !opts || !outs || !codes)) || nstreams < 1) {
+        g_err = "bad batch arguments";
+        return QM_EINVAL;
+    }
+    for (int i = 0; i < n; ++i) { outs[i] = nullptr; codes[i] = QM_EINTERNAL; }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { g_err = "no HIP device"; return QM_EDEVICE; }
+    std::atomic<int> next{0};
+    std::vector<std::string> msgs(n);
+    auto work = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+        for (int i = next++; i < n; i = next++) {
+            codes[i] = qm_refine(&plcs[i], &meshes[i], &opts[i], st, &outs[i]);
+            if (codes[i] != QM_OK && codes[i] != QM_EROUNDS) msgs[i] = qm_last_error();
+        }
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    };
+    std::vector<std::thread> th;
+    const int nw = std::min<int>(nstreams, std::max(n, 1));
+    for (int w = 0; w < nw; ++w) th.emplace_back(work);
+    for (auto& t : th) t.join();
+    for (int i = 0; i < n; ++i)
+        if (codes[i] != QM_OK && codes[i] != QM_EROUNDS) {
+            g_err = "instance " + std::to_string(i) + ": " + (msgs[i].empty() ? "not run" : msgs[i]);
+            return codes[i];
+        }
+    return QM_OK;
 }
 
 int qm_result_view(const qm_result* r, qm_mesh* v, qm_stats* st) {
