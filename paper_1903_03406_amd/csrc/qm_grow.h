@@ -216,9 +216,14 @@ QMD void sub_edge(int4 v, int f, int e, int& x, int& y, int& z) {
 // a region over the tiles: evaluate again with the next tier's tiles, or
 // (largest tiles) report which tile was too small in the counter word
 // PL.ctr[35]
-QMD void over_status(const Cands& C, const Pools& PL, const GrowTiles& W, int cid, int over) {
-    if (W.tier == 2) { C.gst[cid] = ST_TOOBIG; atomicOr(&PL.ctr[35], over); }
-    else C.gst[cid] = W.tier == 0 ? ST_OVERFLOW : ST_OVERFLOW2;
+QMD void over_status(const Cands& C, const Pools& PL, const GrowTiles& W, int cid, int over,
+                     const GrowShared& S) {
+    if (W.tier == 2) {
+        C.gst[cid] = ST_TOOBIG;
+        atomicOr(&PL.ctr[35], over);
+        atomicMax(&PL.ctr[44], S.nrt);       // largest region and tested count reached
+        atomicMax(&PL.ctr[45], S.hcount);
+    } else C.gst[cid] = W.tier == 0 ? ST_OVERFLOW : ST_OVERFLOW2;
 }
 
 // results that did not fit a pool: the whole pass is evaluated again with
@@ -366,7 +371,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
     }
     if (over_rt) {                        // read before the last level barrier
-        if (lane == 0) over_status(C, PL, W, cid, S.over);
+        if (lane == 0) over_status(C, PL, W, cid, S.over, S);
         return;
     }
     const int nrt = S.nrt, nrf = S.nrf;
@@ -409,7 +414,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         const int nq = S.nq;
         __syncthreads();                  // flags read before any lane goes on
         if (over_q) {
-            if (lane == 0) over_status(C, PL, W, cid, S.over);
+            if (lane == 0) over_status(C, PL, W, cid, S.over, S);
             return;
         }
         if (nq > 0) {
@@ -496,7 +501,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     if (phase_end(S)) {
         if (lane == 0) {
-            if (S.over) over_status(C, PL, W, cid, S.over);
+            if (S.over) over_status(C, PL, W, cid, S.over, S);
             else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
         }
         return;
@@ -531,7 +536,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
         if (phase_end(S)) {
             if (lane == 0) {
-                if (S.over) over_status(C, PL, W, cid, S.over);
+                if (S.over) over_status(C, PL, W, cid, S.over, S);
                 else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
             }
             return;
@@ -560,7 +565,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
         if (phase_end(S)) {
             if (lane == 0) {
-                if (S.over) over_status(C, PL, W, cid, S.over);
+                if (S.over) over_status(C, PL, W, cid, S.over, S);
                 else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
             }
             return;
@@ -642,7 +647,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     if (phase_end(S)) {
         if (lane == 0) {
-            if (S.over) over_status(C, PL, W, cid, S.over);
+            if (S.over) over_status(C, PL, W, cid, S.over, S);
             else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
         }
         return;
@@ -661,7 +666,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         } else if (r < 0) S.over |= OV_HASH;
     }
     if (phase_end(S)) {
-        if (lane == 0) over_status(C, PL, W, cid, S.over);
+        if (lane == 0) over_status(C, PL, W, cid, S.over, S);
         return;
     }
     const int ncx = S.ncx;

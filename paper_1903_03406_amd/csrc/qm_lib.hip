@@ -540,7 +540,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                                                                              pass == 0 ? E.BP : E.BPnoprof(),
                                                                              nullptr, 0, nullptr);
             E.pend(pass == 0 ? 3 : 8);
-            int cw[37];
+            int cw[46];
             for (int attempt = 0;; ++attempt) {
                 if (attempt > 0 || pass > 0) {
                     HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
@@ -554,7 +554,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                     if (tile_scale >= B_MAXSCALE)
                         throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size (round " +
                                                         std::to_string(round) + ", class " + std::to_string(cls) +
-                                                        ", tile code " + std::to_string(cw[35]) + ")");
+                                                        ", " + std::to_string(cw[34]) + " regions, tile code " +
+                                                        std::to_string(cw[35]) + ", reached " +
+                                                        std::to_string(cw[44]) + " region tets, " +
+                                                        std::to_string(cw[45]) + " tested)");
                     tile_scale *= 4;
                     if (verbose)
                         fprintf(stderr, "qm: round %d class %d: %d regions over the global tiles (code %d), "
