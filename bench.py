@@ -223,6 +223,9 @@ def main():
                    "rounds": r.rounds, "device_refine_s": r.seconds_refine, "device_setup_s": r.seconds_setup},
         "profile_ms": {k: round(v, 3) for k, v in prof["ms"].items()},
         "overflow_candidates": prof.get("overflow", 0), "poolfull_candidates": prof.get("poolfull", 0),
+        "grow_phase_frac": (lambda c: {n: round(x / max(sum(c), 1), 4) for n, x in zip(
+            ("setup_seeds", "facet_region", "tet_region", "encroach", "radius_rftets", "bfaces",
+             "edges_closure", "claims_results"), c)})(prof.get("grow_cycles", [0] * 8)),
         "roofline": {"kernel": "k_grow_lds" if fam == "grow_validate" else "k_classify_tet",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -113,6 +113,12 @@ typedef struct qm_stats {
     /* QM_PROFILE only: candidates evaluated again with global-memory tiles
        (region over the LDS tiles), and again after a result pool grew */
     int64_t prof_overflow, prof_poolfull;
+    /* QM_PROFILE only: shader-clock cycles of the small-tile grow kernel's
+       phases summed over its workgroups: 0 set-up and seeds, 1 facet region,
+       2 tet region, 3 encroachment, 4 insertion radius and facet-region tets,
+       5 boundary faces, 6 2D boundary edges and closure, 7 claims and
+       results (phases a candidate leaves early are not counted) */
+    int64_t prof_grow_cycles[8];
 } qm_stats;
 
 typedef struct qm_result qm_result;

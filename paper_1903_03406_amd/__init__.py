@@ -73,7 +73,7 @@ class _Stats(ctypes.Structure):
                 ("prof_region", ctypes.c_int64), ("prof_bfaces", ctypes.c_int64),
                 ("prof_claims", ctypes.c_int64), ("prof_scan_tets", ctypes.c_int64),
                 ("prof_scan_verts", ctypes.c_int64), ("prof_overflow", ctypes.c_int64),
-                ("prof_poolfull", ctypes.c_int64)]
+                ("prof_poolfull", ctypes.c_int64), ("prof_grow_cycles", ctypes.c_int64 * 8)]
 
 
 def _load():
@@ -235,6 +235,7 @@ def _take_result(lib, res, profile) -> RefineResult:
                               "bfaces": int(st.prof_bfaces), "claims": int(st.prof_claims),
                               "scan_tets": int(st.prof_scan_tets), "scan_verts": int(st.prof_scan_verts),
                               "overflow": int(st.prof_overflow), "poolfull": int(st.prof_poolfull),
+                              "grow_cycles": [int(x) for x in st.prof_grow_cycles],
                               "round_ms": round_ms}
                              if profile else None), last)
     finally:

@@ -19,10 +19,10 @@ constexpr unsigned KEYMASK = 0x1FFFFFFFu;
 enum { OV_RT = 1, OV_HASH = 2, OV_RF = 4, OV_Q = 8, OV_BF = 16, OV_BE = 32, OV_CX = 64, OV_EDGE = 128 };
 enum { HS_IN = 1u, HS_OUT = 2u, HS_CLAIM = 3u };
 
-// Tiles of one candidate's evaluation.  cx holds CXW ints per boundary face
-// (x, y, z, old tet<<2|face, then for the edges opposite x, y and z the
-// partner face sharing that edge as m<<2|slot, -1 when none) followed by
-// maxcx extra claims.  EK/EV: edge table (global-memory tiles only, ehcap
+// Tiles of one candidate's evaluation.  cx (16-byte aligned) holds maxbf
+// face records int4 (x, y, z, old tet<<2|face), then 3 ints per face: for the
+// edges opposite x, y and z the partner face sharing that edge as m<<2|slot,
+// -1 when none; then maxcx extra claims (CXW ints per face in all).  EK/EV: edge table (global-memory tiles only, ehcap
 // entries; ehcap 0 selects the pairwise scans bounded by the LDS tiles).
 constexpr int CXW = 7;
 struct GrowTiles {
@@ -40,20 +40,35 @@ struct GrowTiles {
 constexpr int BFR = 4;
 struct BfPool { int4* r; int cap; unsigned long long* prof; };   // prof: tested, region, bfaces, claims
 
+// phases timed by ptick: 0 set-up and seeds, 1 R_F, 2 R_T, 3 encroachment,
+// 4 insertion radius and R_F tets, 5 boundary faces, 6 2D edges and closure,
+// 7 claims and results
+constexpr int GROW_PHASES = 8;
 struct GrowShared {
     int nrt, nrf, nbf, nbe, nq, ncx, hcount;
     int over, fail, reason;
     int base_reg, base_bf, base_be, base_cl, base_q;
-    unsigned long long prof[4];   // region counters of this workgroup (flushed at exit)
+    unsigned long long prof[4 + GROW_PHASES];   // region counters and phase clocks of this workgroup
+    unsigned long long tlast;                   // (flushed at exit)
 };
 
 QMD void prof_begin(GrowShared& S) {
-    if (threadIdx.x == 0) S.prof[0] = S.prof[1] = S.prof[2] = S.prof[3] = 0ull;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < 4 + GROW_PHASES; ++i) S.prof[i] = 0ull;
 }
 QMD void prof_flush(const GrowShared& S, const BfPool& BP) {
     if (threadIdx.x == 0 && BP.prof)
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4 + GROW_PHASES; ++i)
             if (S.prof[i]) atomicAdd(&BP.prof[i], S.prof[i]);
+}
+// shader clock at a phase boundary (profiling only): the cycles since the
+// last boundary go to phase `ph`
+QMD void ptick(GrowShared& S, const BfPool& BP, int ph) {
+    if (BP.prof && threadIdx.x == 0) {
+        unsigned long long t = clock64();
+        if (ph >= 0) S.prof[4 + ph] += t - S.tlast;
+        S.tlast = t;
+    }
 }
 
 // End of a validation phase: wait for every lane's writes, take the verdict
@@ -238,6 +253,9 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     const double4 pp = C.p[cid];
     const double P[3] = {pp.x, pp.y, pp.z};
     const int4 tup = C.tup[cid];
+    int4* const CF = reinterpret_cast<int4*>(W.cx);       // boundary-face records
+    int* const CP = W.cx + 4 * W.maxbf;                     // their edge partners
+    ptick(S, BP, -1);
     if (lane == 0) {
         S.nrt = S.nrf = S.nbf = S.nbe = S.nq = S.ncx = S.hcount = 0;
         S.over = S.fail = 0; S.reason = EX_NONE;
@@ -287,6 +305,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
     }
     __syncthreads();
+    ptick(S, BP, 0);
 
     // ---- R_F: subfaces of the seed facets connected across non-subsegment
     // edges whose equatorial ball strictly holds p (seeds always included)
@@ -329,6 +348,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         __syncthreads();
     }
 
+    ptick(S, BP, 1);
     // ---- R_T: tets whose circumsphere strictly holds p, connected to the
     // seeds across faces that are not subfaces (or are region subfaces)
     bool over_rt = false;
@@ -376,18 +396,25 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     const int nrt = S.nrt, nrf = S.nrf;
     if (lane == 0) { S.prof[0] += S.hcount; S.prof[1] += nrt; }
+    ptick(S, BP, 2);
     auto in_rt = [&](int t) { return hget(W.H, W.hcap, (unsigned)t + 1u) == HS_IN; };
     auto fail = [&](int reason) { S.fail = 1; S.reason = reason; };   // one reason per phase
 
     // ---- (a) encroachment: tet points reject on encroached subsegments and
     // subfaces of the region, subface points on subsegments (Shewchuk's rule)
     if (cls != CLS_SS) {
-        const int per = cls == CLS_TET ? 10 : 6;
-        for (int k = lane; k < nrt * per; k += 64) {
-            int t = W.rt[k / per], j = k % per;
-            int4 v = ld4(M.TV, t);
-            if (j < 6) {
-                int s = M.TS[6 * (size_t)t + j];
+        // one region tet per lane: its six edge words and (tet points) four
+        // face words are loaded together; most are not constraints
+        for (int k = lane; k < nrt; k += 64) {
+            const int t = W.rt[k];
+            const int* ts = M.TS + 6 * (size_t)t;
+            const int s6[6] = {ts[0], ts[1], ts[2], ts[3], ts[4], ts[5]};
+            const int4 tf = cls == CLS_TET ? ld4(M.TF, t) : make_int4(-1, -1, -1, -1);
+            // the AND of the words has its sign bit clear iff some word is >= 0
+            if ((s6[0] & s6[1] & s6[2] & s6[3] & s6[4] & s6[5] & tf.x & tf.y & tf.z & tf.w) < 0) continue;
+            const int4 v = ld4(M.TV, t);
+            for (int j = 0; j < 6; ++j) {
+                const int s = s6[j];
                 if (s < 0) continue;
                 double A[3], B[3];
                 xyz(M, at4(v, c_EV[j][0]), A); xyz(M, at4(v, c_EV[j][1]), B);
@@ -396,9 +423,9 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                     if (r == 1) { int idx = atomicAdd(&S.nq, 1); if (idx < W.maxq) W.q[idx] = make_int2(0, s); else S.over |= OV_Q; }
                     if (r < 0) S.over |= OV_Q;
                 }
-            } else {
-                int f = j - 6;
-                if (M.TF[4 * (size_t)t + f] < 0) continue;
+            }
+            for (int f = 0; f < 4; ++f) {
+                if (at4(tf, f) < 0) continue;
                 double A[3], B[3], Cc[3];
                 xyz(M, at4(v, c_FI[f][0]), A); xyz(M, at4(v, c_FI[f][1]), B); xyz(M, at4(v, c_FI[f][2]), Cc);
                 if (facedot(A, B, Cc, P) < 0) {
@@ -445,20 +472,22 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
     }
 
+    ptick(S, BP, 3);
     // ---- (b) insertion radius: nearest region vertex at least h_min away
     {
         double r2 = INFINITY;
-        for (int k = lane; k < nrt * 4 + nrf * 3; k += 64) {
-            int vid;
-            if (k < nrt * 4) vid = M.TV[4 * (size_t)W.rt[k >> 2] + (k & 3)];
-            else {
-                int j = k - nrt * 4, h = W.rf[j / 3];
-                vid = M.TV[4 * (size_t)(h >> 2) + c_FI[h & 3][j % 3]];
+        for (int k = lane; k < nrt + nrf * 3; k += 64) {
+            if (k < nrt) {                       // the four vertices of a region tet
+                const int4 v = ld4(M.TV, W.rt[k]);
+                double V0[3], V1[3], V2[3], V3[3];
+                xyz(M, v.x, V0); xyz(M, v.y, V1); xyz(M, v.z, V2); xyz(M, v.w, V3);
+                r2 = fmin(r2, fmin(fmin(d2(V0, P), d2(V1, P)), fmin(d2(V2, P), d2(V3, P))));
+            } else {                             // a vertex of a region subface
+                int j = k - nrt, h = W.rf[j / 3];
+                double V[3];
+                xyz(M, M.TV[4 * (size_t)(h >> 2) + c_FI[h & 3][j % 3]], V);
+                r2 = fmin(r2, d2(V, P));
             }
-            double V[3];
-            xyz(M, vid, V);
-            double d = d2(V, P);
-            if (d < r2) r2 = d;
         }
         r2 = wave_min(r2);
         if (r2 < M.hmin2) {
@@ -478,26 +507,28 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         return;
     }
 
+    ptick(S, BP, 4);
     // ---- (d) boundary faces (not region subfaces; other side hull, outside
     // the region, or a constraint) must see p strictly on their inner side
-    for (int k = lane; k < nrt * 4; k += 64) {
-        int t = W.rt[k >> 2], f = k & 3;
-        int fid = M.TF[4 * (size_t)t + f];
-        if (fid >= 0 && in_rf(t, f)) continue;
-        int nb = M.TA[4 * (size_t)t + f];
-        bool bnd = nb < 0 || !in_rt(nb >> 2) || fid >= 0;
-        if (!bnd) continue;
-        int4 v = ld4(M.TV, t);
-        int x = at4(v, c_FI[f][0]), y = at4(v, c_FI[f][1]), z = at4(v, c_FI[f][2]);
-        double A[3], B[3], Cc[3];
-        xyz(M, x, A); xyz(M, y, B); xyz(M, z, Cc);
-        if (orient3d(A, B, Cc, P) <= 0) { fail(EX_FACE); continue; }
-        int idx = atomicAdd(&S.nbf, 1);
-        if (idx < W.maxbf) {
-            // stage the face record in the claim scratch (x, y, z, neighbour)
-            int* r = W.cx + CXW * idx;
-            r[0] = x; r[1] = y; r[2] = z; r[3] = (t << 2) | f;
-        } else S.over |= OV_BF;
+    for (int k = lane; k < nrt; k += 64) {      // one region tet per lane, its four faces
+        const int t = W.rt[k];
+        const int4 tf = ld4(M.TF, t), ta = ld4(M.TA, t), v = ld4(M.TV, t);
+        for (int f = 0; f < 4; ++f) {
+            const int fid = at4(tf, f);
+            if (fid >= 0 && in_rf(t, f)) continue;
+            const int nb = at4(ta, f);
+            const bool bnd = nb < 0 || fid >= 0 || !in_rt(nb >> 2);
+            if (!bnd) continue;
+            const int x = at4(v, c_FI[f][0]), y = at4(v, c_FI[f][1]), z = at4(v, c_FI[f][2]);
+            double A[3], B[3], Cc[3];
+            xyz(M, x, A); xyz(M, y, B); xyz(M, z, Cc);
+            if (orient3d(A, B, Cc, P) <= 0) { fail(EX_FACE); continue; }
+            int idx = atomicAdd(&S.nbf, 1);
+            if (idx < W.maxbf) {
+                // stage the face record in the claim scratch (x, y, z, old tet<<2|face)
+                reinterpret_cast<int4*>(W.cx)[idx] = make_int4(x, y, z, (t << 2) | f);
+            } else S.over |= OV_BF;
+        }
     }
     if (phase_end(S)) {
         if (lane == 0) {
@@ -508,6 +539,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     const int nbf = S.nbf;
 
+    ptick(S, BP, 5);
     // ---- (e) 2D boundary edges of R_F must see p strictly inside, in the
     // facet's projection; the subsegment being split is excluded
     if (cls != CLS_TET) {
@@ -587,8 +619,8 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         __syncthreads();                  // table cleared (and 2D boundary edges in)
         for (int k = lane; k < 3 * nbf; k += 64) {
             const int i = k / 3, l = k % 3;
-            const int* r = W.cx + CXW * i;
-            int sl = eput(W.EK, ecap, ekey(l == 0 ? r[1] : r[0], l == 2 ? r[1] : r[2]));
+            const int4 r = CF[i];
+            int sl = eput(W.EK, ecap, ekey(l == 0 ? r.y : r.x, l == 2 ? r.y : r.z));
             if (sl < 0) { S.over |= OV_EDGE; continue; }
             atomicAdd(&W.EV[sl].x, 1);
             const int fe = (i << 2) | l;
@@ -598,9 +630,9 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         for (int k = lane; k < 3 * nbf + nbe; k += 64) {
             unsigned long long key;
             if (k < 3 * nbf) {
-                const int* r = W.cx + CXW * (k / 3);
+                const int4 r = CF[k / 3];
                 const int l = k % 3;
-                key = ekey(l == 0 ? r[1] : r[0], l == 2 ? r[1] : r[2]);
+                key = ekey(l == 0 ? r.y : r.x, l == 2 ? r.y : r.z);
             } else {
                 int4 e = W.be[k - 3 * nbf];
                 key = ekey(e.x, e.y);
@@ -611,7 +643,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             if (ev.x != want) { fail(EX_MANIFOLD); continue; }
             if (k < 3 * nbf) {
                 const int fe = ((k / 3) << 2) | (k % 3);
-                W.cx[CXW * (k / 3) + 4 + k % 3] = want == 1 ? -1 : (ev.y == fe ? ev.z : ev.y);
+                CP[3 * (k / 3) + k % 3] = want == 1 ? -1 : (ev.y == fe ? ev.z : ev.y);
             }
         }
     } else {
@@ -619,20 +651,20 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             int u, w, i = -1, l = 0;
             if (k < 3 * nbf) {
                 i = k / 3; l = k % 3;
-                const int* r = W.cx + CXW * i;
-                u = l == 0 ? r[1] : r[0];
-                w = l == 2 ? r[1] : r[2];
+                const int4 r = CF[i];
+                u = l == 0 ? r.y : r.x;
+                w = l == 2 ? r.y : r.z;
             } else {
                 int4 e = W.be[k - 3 * nbf];
                 u = e.x; w = e.y;
             }
             int cnt = 0, partner = -1;
             for (int m = 0; m < nbf; ++m) {
-                const int* q = W.cx + CXW * m;
-                bool hu = q[0] == u || q[1] == u || q[2] == u, hw = q[0] == w || q[1] == w || q[2] == w;
+                const int4 q = CF[m];
+                bool hu = q.x == u || q.y == u || q.z == u, hw = q.x == w || q.y == w || q.z == w;
                 if (hu && hw) {
                     ++cnt;
-                    if (m != i) partner = (m << 2) | ((q[0] != u && q[0] != w) ? 0 : ((q[1] != u && q[1] != w) ? 1 : 2));
+                    if (m != i) partner = (m << 2) | ((q.x != u && q.x != w) ? 0 : ((q.y != u && q.y != w) ? 1 : 2));
                 }
             }
             const int lo = u < w ? u : w, hi = u < w ? w : u;
@@ -642,7 +674,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 if (e.x == lo && e.y == hi && e.w) want = 1;
             }
             if (cnt != want) { fail(EX_MANIFOLD); continue; }
-            if (i >= 0) W.cx[CXW * i + 4 + l] = want == 1 ? -1 : partner;
+            if (i >= 0) CP[3 * i + l] = want == 1 ? -1 : partner;
         }
     }
     if (phase_end(S)) {
@@ -653,10 +685,11 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         return;
     }
 
+    ptick(S, BP, 6);
     // ---- accepted: claim set = region tets + tets across boundary faces
     int* cext = W.cx + CXW * W.maxbf;            // extra claims after the face records
     for (int i = lane; i < nbf; i += 64) {
-        int h = W.cx[CXW * i + 3];
+        int h = CF[i].w;
         int nb = M.TA[4 * (size_t)(h >> 2) + (h & 3)];
         if (nb < 0) continue;
         int r = hclaim(W.H, W.hcap, (unsigned)(nb >> 2) + 1u);
@@ -671,21 +704,20 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     const int ncx = S.ncx;
     if (lane == 0) {
-        // region, face and edge pools are only read through this candidate's
-        // offsets; the claim pool is scanned whole by the selection, so a
-        // reserved claim range that will not be filled is marked void (-1)
-        int br = atomicAdd(&PL.ctr[0], nrt);
+        // face and edge pools are only read through this candidate's offsets;
+        // the claim pool is scanned whole by the selection, so a reserved
+        // claim range that will not be filled is marked void (-1).  The claim
+        // range starts with the region tets, which is also the region list.
         int bb = atomicAdd(&PL.ctr[1], nbf);
-        int be = atomicAdd(&PL.ctr[2], nbe);
+        int be = nbe > 0 ? atomicAdd(&PL.ctr[2], nbe) : 0;
         int bc = atomicAdd(&PL.ctr[3], nrt + ncx);
-        bool full = br + nrt > PL.cap_reg || bb + nbf > PL.cap_bf || bb + nbf > BP.cap ||
-                    be + nbe > PL.cap_be || bc + nrt + ncx > PL.cap_cl;
+        bool full = bb + nbf > BP.cap || be + nbe > PL.cap_be || bc + nrt + ncx > PL.cap_cl;
         if (full) {
             atomicOr(&PL.ctr[5], 1); C.gst[cid] = poolfull_status(W); S.base_reg = -1;
             S.base_cl = bc;
         } else {
-            S.base_reg = br; S.base_bf = bb; S.base_be = be; S.base_cl = bc;
-            C.reg_off[cid] = br; C.reg_n[cid] = nrt;
+            S.base_reg = bc; S.base_bf = bb; S.base_be = be; S.base_cl = bc;
+            C.reg_off[cid] = bc; C.reg_n[cid] = nrt;
             C.bf_off[cid] = bb; C.bf_n[cid] = nbf;
             C.be_off[cid] = be; C.be_n[cid] = nbe;
             C.cl_off[cid] = bc; C.cl_n[cid] = nrt + ncx;
@@ -699,15 +731,13 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         return;
     }
     if (lane == 0) { S.prof[2] += nbf; S.prof[3] += nrt + ncx; }
-    for (int k = lane; k < nrt; k += 64) {
-        PL.reg[S.base_reg + k] = W.rt[k];
-        PL.cl[S.base_cl + k] = W.rt[k]; PL.clc[S.base_cl + k] = cid;
-    }
+    for (int k = lane; k < nrt; k += 64) { PL.cl[S.base_cl + k] = W.rt[k]; PL.clc[S.base_cl + k] = cid; }
     for (int k = lane; k < ncx; k += 64) { PL.cl[S.base_cl + nrt + k] = cext[k]; PL.clc[S.base_cl + nrt + k] = cid; }
     for (int k = lane; k < nbe; k += 64) PL.be[S.base_be + k] = W.be[k];
     for (int i = lane; i < nbf; i += 64) {
-        const int* rc = W.cx + CXW * i;
-        int x = rc[0], y = rc[1], z = rc[2], h = rc[3];
+        const int4 rc = CF[i];
+        const int* pc = CP + 3 * i;
+        int x = rc.x, y = rc.y, z = rc.z, h = rc.w;
         int t = h >> 2, f = h & 3;
         int4 v = ld4(M.TV, t);
         int lx = local_of(v, x), ly = local_of(v, y), lz = local_of(v, z);
@@ -716,9 +746,9 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         int4 r1 = make_int4(M.TF[4 * (size_t)t + f], 0, ts[c_EIDX[lx][ly]], ts[c_EIDX[ly][lz]]);
         int4 r2 = make_int4(ts[c_EIDX[lz][lx]], h, 0, 0);
         int4* out = BP.r + BFR * (size_t)(S.base_bf + i);
-        out[0] = r0; out[1] = r1; out[2] = r2; out[3] = make_int4(rc[4], rc[5], rc[6], 0);
-        PL.bf[S.base_bf + i] = h;
+        out[0] = r0; out[1] = r1; out[2] = r2; out[3] = make_int4(pc[0], pc[1], pc[2], 0);
     }
+    ptick(S, BP, 7);
 }
 
 // LDS tiles; TIER 1 (medium) also takes an edge table of EHCAP entries per
@@ -734,7 +764,8 @@ __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools
     __shared__ int4 be[MAXBE];
     __shared__ unsigned long long QH[QHCAP];
     __shared__ int2 q[MAXQ];
-    __shared__ int cx[CXW * MAXBF + MAXBF];
+    __shared__ int4 cx4[(CXW * MAXBF + MAXBF + 3) / 4];
+    int* cx = reinterpret_cast<int*>(cx4);
     __shared__ GrowShared S;
     GrowTiles W{rt, H, RFH, rf, be, QH, q, cx, MAXRT, HCAP, RFHCAP, MAXRF, MAXBE, QHCAP, MAXQ, MAXBF, MAXBF, TIER,
                 nullptr, nullptr, 0};

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools P
             rec[1].y = (int)(((ti >> (4 + f)) & 1u) | (((ti >> (8 + f)) & 1u) << 1));
         }
         __syncthreads();
-        auto slot = [&](int j) { return j < nk ? PL.reg[rg0 + j] : tbase + (j - nk); };
+        auto slot = [&](int j) { return j < nk ? PL.cl[rg0 + j] : tbase + (j - nk); };
         // phase B: write the new tets
         for (int j = lane; j < nf; j += 64) {
             const int4* rec = BP.r + BFR * (size_t)(bf0 + j);
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools P
             if (r0.w >= 0) M.TA[4 * (size_t)(r0.w >> 2) + (r0.w & 3)] = (sj << 2) | 3;
             for (int e = 0; e < 6; ++e) if (ts[e] >= 0) M.STET[ts[e]] = sj;
         }
-        for (int j = nf + lane; j < nk; j += 64) M.TI[PL.reg[rg0 + j]] = 0u;   // unused region slots
+        for (int j = nf + lane; j < nk; j += 64) M.TI[PL.cl[rg0 + j]] = 0u;   // unused region slots
         if (lane == 0 && nk > nf) atomicAdd(dead, nk - nf);
         if (lane == 0) {
             double4 p = C.p[c];

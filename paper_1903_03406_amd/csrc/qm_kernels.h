@@ -65,9 +65,9 @@ struct Cands {
 };
 
 struct Pools {
-    int* reg; int* bf; int4* be; int* cl; int* clc; int2* q;
-    int cap_reg, cap_bf, cap_be, cap_cl, cap_q;
-    int* ctr;             // [0] reg, [1] bf, [2] be, [3] cl, [4] q, [5] pool overflow
+    int4* be; int* cl; int* clc; int2* q;
+    int cap_be, cap_cl, cap_q;
+    int* ctr;             // [1] face records, [2] be, [3] cl, [4] q, [5] pool overflow
 };
 
 __constant__ int c_FI[4][3] = {{1, 3, 2}, {0, 2, 3}, {0, 3, 1}, {0, 1, 2}};

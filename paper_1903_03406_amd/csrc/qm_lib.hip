@@ -167,7 +167,7 @@ struct Engine {
     DBuf<double4> c_p;
     DBuf<int2> c_qw;
     // pools
-    DBuf<int> p_reg, p_bf, p_cl, p_clc;
+    DBuf<int> p_cl, p_clc;
     DBuf<int4> p_be, p_bfr;
     DBuf<int2> p_q;
     DBuf<int> ctr;     // pool counters [0..5], candidates per class [8..10], totals [11..13],
@@ -232,8 +232,8 @@ struct Engine {
         mark.release(s); owner.release(s);
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
                         &c_seed, &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off,
-                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &p_reg,
-                        &p_bf, &p_cl, &p_clc, &ctr})
+                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist,
+                        &p_cl, &p_clc, &ctr})
             b->release(s);
         c_key0.release(s); skey.release(s); c_key.release(s); mis_drop.release(s); mis_lose.release(s);
         c_tup0.release(s); c_tup.release(s); c_p0.release(s); c_p.release(s); c_qw.release(s);
@@ -279,23 +279,23 @@ struct Engine {
         C.q_off = q_off.p; C.q_n = q_n.p; C.state = state.p;
     }
     bool verbose = false;
-    void ensure_pools(size_t reg, size_t bf, size_t be, size_t cl, size_t q, bool keep) {
+    // pools: boundary-face records (bf entries), 2D boundary edges, claims
+    // (each candidate's range starts with its region tets), queue entries
+    void ensure_pools(size_t bf, size_t be, size_t cl, size_t q) {
         // pool offsets and counters are int32: refuse sizes they cannot index
         const size_t lim = (size_t)1 << 30;
-        if (reg > lim || bf > lim || be > lim || cl > lim || q > lim)
+        if (bf > lim || be > lim || cl > lim || q > lim)
             throw QmError(QM_ENOMEM, "a round's result pools exceed 2^30 entries");
-        const size_t before = p_reg.cap + p_bf.cap + p_bfr.cap + p_be.cap + p_cl.cap + p_q.cap;
-        p_reg.ensure(reg, s, keep); p_bf.ensure(bf, s, keep); p_bfr.ensure(BFR * bf, s, keep);
-        p_be.ensure(be, s, keep); p_cl.ensure(cl, s, keep); p_q.ensure(q, s, keep);
-        p_clc.ensure(cl, s, keep);
-        PL.reg = p_reg.p; PL.bf = p_bf.p; PL.be = p_be.p; PL.cl = p_cl.p; PL.clc = p_clc.p; PL.q = p_q.p;
-        PL.cap_reg = (int)p_reg.cap; PL.cap_bf = (int)p_bf.cap; PL.cap_be = (int)p_be.cap;
-        PL.cap_cl = (int)p_cl.cap; PL.cap_q = (int)p_q.cap; PL.ctr = ctr.p;
+        const size_t before = p_bfr.cap + p_be.cap + p_cl.cap + p_q.cap;
+        p_bfr.ensure(BFR * bf, s, false);
+        p_be.ensure(be, s, false); p_cl.ensure(cl, s, false); p_q.ensure(q, s, false);
+        p_clc.ensure(cl, s, false);
+        PL.be = p_be.p; PL.cl = p_cl.p; PL.clc = p_clc.p; PL.q = p_q.p;
+        PL.cap_be = (int)p_be.cap; PL.cap_cl = (int)p_cl.cap; PL.cap_q = (int)p_q.cap; PL.ctr = ctr.p;
         BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / BFR); BP.prof = prof ? pctr.p : nullptr;
-        if (verbose && p_reg.cap + p_bf.cap + p_bfr.cap + p_be.cap + p_cl.cap + p_q.cap != before)
-            fprintf(stderr, "qm: pools %s: region %zu, faces %zu (%.2f GB of records), edges %zu, claims %zu, "
-                    "queue %zu entries\n", keep ? "doubled" : "grown", p_reg.cap, p_bf.cap,
-                    p_bfr.cap * sizeof(int4) / 1e9, p_be.cap, p_cl.cap, p_q.cap);
+        if (verbose && p_bfr.cap + p_be.cap + p_cl.cap + p_q.cap != before)
+            fprintf(stderr, "qm: pools grown: faces %zu (%.2f GB of records), edges %zu, claims %zu, queue %zu "
+                    "entries\n", p_bfr.cap / BFR, p_bfr.cap * sizeof(int4) / 1e9, p_be.cap, p_cl.cap, p_q.cap);
     }
     // pool entries per candidate seen in the last round (region tets,
     // boundary faces, 2D boundary edges, claims, queue entries); the next
@@ -304,7 +304,7 @@ struct Engine {
     // edges, claims, queue entries) used by the last round of each class
     // (counters include ranges of re-run candidates); the next round of the
     // class reserves 1.25x that plus slack
-    double pool_rate[3][5] = {{24, 48, 8, 56, 4}, {24, 48, 8, 56, 4}, {24, 48, 8, 56, 4}};
+    double pool_rate[3][5] = {{0, 48, 8, 56, 4}, {0, 48, 8, 56, 4}, {0, 48, 8, 56, 4}};
     size_t pool_need(int k, int ncand, int cls) const {
         return (size_t)(pool_rate[cls][k] * 1.25 * ncand) + 4096;
     }
@@ -361,7 +361,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
     Engine E(s);
     E.prof = (opt->flags & QM_PROFILE) != 0;
-    if (E.prof) { E.pctr.ensure(8, s, false, 0); }
+    if (E.prof) { E.pctr.ensure(4 + GROW_PHASES, s, false, 0); }
     int64_t scan_tets = 0, scan_verts = 0;
     const int nv = in->nv, nt = in->nt, nsf = in->nsf, nss = in->nss, nftri = plc->nftri;
     int nfacet = 0;
@@ -526,8 +526,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         // round's use per candidate; candidates whose results did not fit are
         // evaluated again after the pools grow, and regions over the LDS tiles
         // are evaluated again with global-memory tiles.
-        E.ensure_pools(E.pool_need(0, ncand, cls), E.pool_need(1, ncand, cls), E.pool_need(2, ncand, cls),
-                       E.pool_need(3, ncand, cls), E.pool_need(4, ncand, cls), false);
+        E.ensure_pools(E.pool_need(1, ncand, cls), E.pool_need(2, ncand, cls), E.pool_need(3, ncand, cls),
+                       E.pool_need(4, ncand, cls));
         // A pass evaluates every candidate once: small LDS tiles, then the
         // regions over them with medium LDS tiles, then global-memory tiles.
         // When a result pool was full the pass is repeated whole with fresh
@@ -592,8 +592,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             if (E.prof) E.prof_full += cw[33];
             if (pass >= 8) throw QmError(QM_ENOMEM, "result pools kept overflowing");
             auto need = [](int used, size_t cap) { return std::max(cap, (size_t)used + (size_t)used / 8 + 4096); };
-            E.ensure_pools(need(cw[0], E.p_reg.cap), need(cw[1], E.p_bf.cap), need(cw[2], E.p_be.cap),
-                           need(cw[3], E.p_cl.cap), need(cw[4], E.p_q.cap), false);
+            E.ensure_pools(need(cw[1], E.p_bfr.cap / BFR), need(cw[2], E.p_be.cap), need(cw[3], E.p_cl.cap),
+                           need(cw[4], E.p_q.cap));
             note("result pools grown; evaluating the round again", round, cls, pass + 1);
         }
         const int ncl = std::min(ncl_final, E.PL.cap_cl);
@@ -774,8 +774,9 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
     if (E.prof) {
         for (int i = 0; i < QM_PROF_FAMILIES; ++i) { R->stats.prof_ms[i] = E.prof_ms[i]; R->stats.prof_launches[i] = E.prof_n[i]; }
-        unsigned long long pc[4];
+        unsigned long long pc[4 + GROW_PHASES];
         HIPCK(hipMemcpy(pc, E.pctr.p, sizeof pc, hipMemcpyDeviceToHost));
+        for (int i = 0; i < GROW_PHASES; ++i) R->stats.prof_grow_cycles[i] = (int64_t)pc[4 + i];
         R->stats.prof_tested = (int64_t)pc[0]; R->stats.prof_region = (int64_t)pc[1];
         R->stats.prof_bfaces = (int64_t)pc[2]; R->stats.prof_claims = (int64_t)pc[3];
         R->stats.prof_scan_tets = scan_tets; R->stats.prof_scan_verts = scan_verts;
