@@ -7,7 +7,8 @@ bytes, subfaces and subsegments with their facet / segment ids) and of the
 per-round records, plus the sizes.
 
     python tests/golden/make_golden.py cfg2            # full refinement
-    python tests/golden/make_golden.py cfg3 --rounds 12
+    python tests/golden/make_golden.py cfg3 --rounds 8
+    python tests/golden/make_golden.py cfg3 --rounds 1099   # about 3.4 h of oracle time
 """
 import argparse
 import hashlib

@@ -63,10 +63,13 @@ def cfg3():
     return qi.config(3)
 
 
-def test_config3_first_rounds_parity(cfg3):
-    gold = load("cfg3_rounds8.json")
+@pytest.mark.parametrize("name", ["cfg3_rounds8.json", "cfg3_rounds1099.json"])
+def test_config3_first_rounds_parity(cfg3, name):
+    """The first 8 rounds, and every round before the first bad-tet round
+    (1099 subsegment and subface rounds, 386 539 Steiner points)."""
+    gold = load(name)
     assert cfg3.sha256() == gold["input_sha256"]
-    compare(qm.refine_workload(cfg3, max_rounds=gold["max_rounds"]), gold, "config3 first rounds")
+    compare(qm.refine_workload(cfg3, max_rounds=gold["max_rounds"]), gold, f"config3 {gold['max_rounds']} rounds")
 
 
 @pytest.mark.skip(reason="the 1M-point refinement faulted the GPU in the round whose largest cavity "
