@@ -141,6 +141,71 @@ def bench_batch(args, qm):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args, qm):
+    """Served workload: Poisson arrivals of jobs from the served generator
+    (clustered or ellipsoid instances, log-uniform sizes, B in {1.4, 2.0}),
+    admitted by qm_server_* against a device-memory budget.  The job inputs
+    are generated before the timed region and reused round-robin; each rate
+    runs --serve-jobs arrivals.  Latency of a job: arrival to completion
+    (time waiting for admission included)."""
+    import numpy as np
+    import qm_inputs as qi
+    t0 = time.time()
+    pool = [qi.serve_job(i, max_points=args.serve_max_points) for i in range(args.serve_pool)]
+    npts = [len(w.xyz) - 8 for w in pool]
+    print(f"[bench] serve pool: {len(pool)} jobs, {min(npts)}..{max(npts)} points, "
+          f"built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    rng = np.random.Generator(np.random.PCG64(55))
+    per_rate = []
+    with qm.Server(budget, nworkers=args.streams) as srv:
+        for t in [srv.submit(w) for w in pool[:min(4, len(pool))]]:      # warm-up
+            srv.result(t)
+        for rate in rates:
+            arrive = np.cumsum(rng.exponential(1.0 / rate, size=args.serve_jobs))
+            jobs = [pool[k % len(pool)] for k in range(args.serve_jobs)]
+            lat, fails, steiner = [], 0, 0
+            pending = {}                       # ticket -> (job index, submit delay)
+            nxt = 0
+            start = time.perf_counter()
+            while nxt < len(jobs) or pending:
+                now = time.perf_counter() - start
+                while nxt < len(jobs) and arrive[nxt] <= now:
+                    tk = srv.submit(jobs[nxt])
+                    if tk is None:             # no room: retry after completions
+                        break
+                    pending[tk] = (nxt, time.perf_counter() - start - arrive[nxt])
+                    nxt += 1
+                for tk in list(pending):
+                    got = srv.poll(tk, wait_ms=0)
+                    if got is None:
+                        continue
+                    res, code, _, _, total = got
+                    k, delay = pending.pop(tk)
+                    lat.append(delay + total)
+                    if res is None or code not in (0, -4):
+                        fails += 1
+                    else:
+                        steiner += res.steiner
+                time.sleep(0.0005)
+            span = time.perf_counter() - start
+            per_rate.append({"rate_jobs_per_s": rate, "jobs": len(jobs), "failed": fails,
+                             "jobs_per_s": len(jobs) / span, "steiner_per_s": steiner / span,
+                             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99))})
+            print(f"[bench] rate {rate:g}/s: {per_rate[-1]}", file=sys.stderr, flush=True)
+        info = srv.info()
+    best = max(per_rate, key=lambda r: r["jobs_per_s"])
+    out = {
+        "metric": "served jobs/sec (Poisson arrivals)", "value": best["jobs_per_s"], "unit": "jobs/s",
+        "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"served_pool{len(pool)}_max{args.serve_max_points}", "workers": args.streams,
+                   "budget_gib": args.serve_budget_gib, "points": [int(min(npts)), int(max(npts))]},
+        "rates": per_rate, "server": info,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,7 +217,15 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single-instance line: the first N instances of the batched "
                          "workload (config 4), batched jobs/s against one-at-a-time jobs/s")
-    ap.add_argument("--streams", type=int, default=8, help="streams of the batched run")
+    ap.add_argument("--streams", type=int, default=8, help="streams (workers) of the batched or served run")
+    ap.add_argument("--serve", action="store_true",
+                    help="instead of the single-instance line: the served workload at --serve-rates")
+    ap.add_argument("--serve-rates", default="5,20,80", help="Poisson arrival rates (jobs/s)")
+    ap.add_argument("--serve-jobs", type=int, default=48, help="arrivals per rate")
+    ap.add_argument("--serve-pool", type=int, default=24, help="distinct pre-generated jobs")
+    ap.add_argument("--serve-max-points", type=int, default=50000,
+                    help="largest job (the served workload's full range ends at 500000)")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="device-memory budget of the server")
     ap.add_argument("--dump-rounds", default=None,
                     help="write the last step's per-round records and per-round kernel-family ms (JSON)")
     args = ap.parse_args()
@@ -165,6 +238,9 @@ def main():
     import torch
     import paper_1903_03406_amd as qm
 
+    if args.serve:
+        bench_serve(args, qm)
+        return
     if args.batch > 0:
         return bench_batch(args, qm)
     t0 = time.time()

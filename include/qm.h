@@ -39,6 +39,7 @@ extern "C" {
 #define QM_EDEVICE (-5)       /* HIP runtime error */
 #define QM_EINTERNAL (-6)     /* a kernel found an impossible state (bug) */
 #define QM_ECAPACITY (-7)     /* a cavity exceeded the largest supported region size */
+#define QM_EAGAIN (-8)        /* server: over the memory budget now, or the job is not done yet */
 
 /* The PLC G = (P, E, F): polygons are given as triangles carrying a polygon
    (facet) id.  Borrowed for the duration of the call. */
@@ -163,6 +164,60 @@ int qm_result_last_round(const qm_result* r, int32_t* buf, int32_t cap);
 int qm_result_round_profile(const qm_result* r, double* buf, int32_t cap);
 
 void qm_result_free(qm_result* r);
+
+/* ---- Served form: refinement jobs (each one qm_refine, the round loop of
+   paper, Section 2) arriving over time on one device -------------------- */
+
+typedef struct qm_server qm_server;
+
+typedef struct qm_server_stats {
+    size_t budget;           /* device-memory budget given at creation (bytes) */
+    size_t resident;         /* estimates of the admitted, unfinished jobs (bytes) */
+    int32_t queued;          /* admitted jobs not started */
+    int32_t running;         /* jobs being refined */
+    int64_t admitted, refused, completed;   /* since creation; refused = QM_EAGAIN */
+} qm_server_stats;
+
+/* Device bytes the library budgets for refining this instance: an upper
+   estimate from the input tet count and B (tighter bounds insert more
+   points), including over-allocation of growing buffers.  0 for bad
+   arguments. */
+size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options* opt);
+
+/* Create a server on the calling thread's current device with `nworkers`
+   (1..64) worker threads, each owning a HIP stream (non-blocking, default
+   priority) on which it runs one job at a time.  `hbm_budget_bytes` bounds
+   the summed estimates of admitted, unfinished jobs.  *out is freed with
+   qm_server_destroy. */
+int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out);
+
+/* Submit one job (host arrays only; QM_INPUT_DEVICE is rejected).  The
+   server copies the arrays, so they are borrowed for the call only.
+   `est_bytes` is the job's device-memory estimate (0: qm_estimate_bytes).
+   Returns 0 and a ticket when admitted; QM_EAGAIN when the estimate does not
+   fit in the budget minus the resident estimates (nothing is kept: retry
+   after jobs finish); QM_ENOMEM when it exceeds the whole budget.  Input
+   errors of the job itself are reported by qm_server_poll. */
+int qm_server_submit(qm_server* srv, const qm_plc* plc, const qm_mesh* in, const qm_options* opt,
+                     size_t est_bytes, uint64_t* ticket);
+
+/* Collect a job.  wait_ms: 0 returns at once, > 0 waits at most that long,
+   < 0 waits until the job is done.  Returns QM_EAGAIN while it is not done;
+   0 when done, with *out the result (or NULL if the job failed; free it with
+   qm_result_free), *code the job's qm_refine return code (its message is
+   then this thread's qm_last_error) and, if `seconds` is not NULL,
+   seconds[0] the time queued and seconds[1] the time from submission to
+   completion.  A ticket is collected once; unknown tickets give QM_EINVAL. */
+int qm_server_poll(qm_server* srv, uint64_t ticket, int32_t wait_ms, qm_result** out, int32_t* code,
+                   double* seconds);
+
+/* Counters of the server (a consistent snapshot). */
+int qm_server_info(qm_server* srv, qm_server_stats* info);
+
+/* Drop the jobs not yet started, wait for the running ones, free every
+   uncollected result and the server.  No other call on `srv` may run
+   concurrently with it or follow it. */
+void qm_server_destroy(qm_server* srv);
 
 /* Message of the last failure on this thread ("" if none). */
 const char* qm_last_error(void);

@@ -35,7 +35,7 @@ ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
                "ex_face", "ex_edge2d", "ex_manifold", "nv_after", "nt_after")
 ERRORS = {-1: "QM_EINVAL", -2: "QM_ENONCONFORM", -3: "QM_ENOMEM", -4: "QM_EROUNDS",
-          -5: "QM_EDEVICE", -6: "QM_EINTERNAL", -7: "QM_ECAPACITY"}
+          -5: "QM_EDEVICE", -6: "QM_EINTERNAL", -7: "QM_ECAPACITY", -8: "QM_EAGAIN"}
 
 
 def build() -> str:
@@ -103,7 +103,9 @@ def _load():
 
 
 EXPORTS = ("qm_refine", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
-           "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version")
+           "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
+           "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_poll", "qm_server_info",
+           "qm_server_destroy")
 
 
 class QmError(RuntimeError):
@@ -242,6 +244,26 @@ def _take_result(lib, res, profile) -> RefineResult:
         lib.qm_result_free(res)
 
 
+def _marshal(w, keep):
+    """qm_plc and qm_mesh views of a workload's host arrays (the arrays are
+    appended to `keep`, which must outlive the views)."""
+    def h(a, dtype):
+        a = _arr(a, dtype)
+        keep.append(a)
+        return a.ctypes.data, a.shape[0]
+    pxyz, nv = h(w.xyz, np.float64)
+    ptet, nt = h(w.tets, np.int32)
+    psf, nsf = h(w.sf, np.int32)
+    psff, _ = h(w.sf_facet, np.int32)
+    pss, nss = h(w.ss, np.int32)
+    pssg, _ = h(w.ss_seg, np.int32)
+    pft, nft = h(w.ftri, np.int32)
+    pftf, _ = h(w.ftri_facet, np.int32)
+    pseg, nseg = h(w.seg if w.seg is not None else np.zeros((0, 2), np.int32), np.int32)
+    return (_Plc(nv, nseg, pseg, nft, pft, pftf),
+            _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg))
+
+
 def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, max_kept=0,
                  profile=False) -> list:
     """Refine independent instances concurrently (qm_refine_batch): each
@@ -250,21 +272,7 @@ def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, m
     n = len(workloads)
     plcs, meshes, opts, keep = (_Plc * n)(), (_Mesh * n)(), (_Opts * n)(), []
     for i, w in enumerate(workloads):
-        def h(a, dtype):
-            a = _arr(a, dtype)
-            keep.append(a)
-            return a.ctypes.data, a.shape[0]
-        pxyz, nv = h(w.xyz, np.float64)
-        ptet, nt = h(w.tets, np.int32)
-        psf, nsf = h(w.sf, np.int32)
-        psff, _ = h(w.sf_facet, np.int32)
-        pss, nss = h(w.ss, np.int32)
-        pssg, _ = h(w.ss_seg, np.int32)
-        pft, nft = h(w.ftri, np.int32)
-        pftf, _ = h(w.ftri_facet, np.int32)
-        pseg, nseg = h(w.seg if w.seg is not None else np.zeros((0, 2), np.int32), np.int32)
-        plcs[i] = _Plc(nv, nseg, pseg, nft, pft, pftf)
-        meshes[i] = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
+        plcs[i], meshes[i] = _marshal(w, keep)
         opts[i] = _Opts(float(w.B), float(hmin_factor), int(max_rounds), int(max_kept),
                         QM_PROFILE if profile else 0)
     outs = (ctypes.c_void_p * max(n, 1))()
@@ -294,3 +302,107 @@ def refine_workload(w, **kw) -> RefineResult:
 
 def version() -> str:
     return _load().qm_version().decode()
+
+
+class _SrvStats(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_size_t), ("resident", ctypes.c_size_t), ("queued", ctypes.c_int32),
+                ("running", ctypes.c_int32), ("admitted", ctypes.c_int64), ("refused", ctypes.c_int64),
+                ("completed", ctypes.c_int64)]
+
+
+class Server:
+    """Served refinement (qm_server_*): jobs are admitted against a
+    device-memory budget and refined by `nworkers` worker threads, each with
+    its own HIP stream, on the current device."""
+
+    def __init__(self, hbm_budget_bytes: int, nworkers: int = 8):
+        lib = self._lib = _load()
+        P = ctypes.c_void_p
+        lib.qm_server_create.restype = ctypes.c_int
+        lib.qm_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(P)]
+        lib.qm_server_submit.restype = ctypes.c_int
+        lib.qm_server_submit.argtypes = [P, ctypes.POINTER(_Plc), ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts),
+                                         ctypes.c_size_t, ctypes.POINTER(ctypes.c_uint64)]
+        lib.qm_server_poll.restype = ctypes.c_int
+        lib.qm_server_poll.argtypes = [P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(P),
+                                       ctypes.POINTER(ctypes.c_int32), P]
+        lib.qm_server_info.restype = ctypes.c_int
+        lib.qm_server_info.argtypes = [P, ctypes.POINTER(_SrvStats)]
+        lib.qm_server_destroy.argtypes = [P]
+        lib.qm_estimate_bytes.restype = ctypes.c_size_t
+        lib.qm_estimate_bytes.argtypes = [ctypes.POINTER(_Plc), ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts)]
+        h = P()
+        rc = lib.qm_server_create(int(hbm_budget_bytes), int(nworkers), ctypes.byref(h))
+        if rc:
+            raise QmError(rc, lib.qm_last_error().decode())
+        self._h = h
+        self._profile = {}
+
+    @staticmethod
+    def _opts(w, hmin_factor, max_rounds, max_kept, profile):
+        return _Opts(float(w.B), float(hmin_factor), int(max_rounds), int(max_kept),
+                     QM_PROFILE if profile else 0)
+
+    def estimate_bytes(self, w, *, hmin_factor=0.5) -> int:
+        keep = []
+        plc, mesh = _marshal(w, keep)
+        opt = self._opts(w, hmin_factor, 1, 0, False)
+        return int(self._lib.qm_estimate_bytes(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opt)))
+
+    def submit(self, w, *, est_bytes=0, hmin_factor=0.5, max_rounds=100000, max_kept=0, profile=False):
+        """Ticket of the admitted job, or None when the budget has no room
+        now (QM_EAGAIN)."""
+        keep = []
+        plc, mesh = _marshal(w, keep)
+        opt = self._opts(w, hmin_factor, max_rounds, max_kept, profile)
+        t = ctypes.c_uint64()
+        rc = self._lib.qm_server_submit(self._h, ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opt),
+                                        int(est_bytes), ctypes.byref(t))
+        if rc == -8:
+            return None
+        if rc:
+            raise QmError(rc, self._lib.qm_last_error().decode())
+        self._profile[t.value] = profile
+        return t.value
+
+    def poll(self, ticket, wait_ms=0):
+        """None while the job runs; else (result or None, code, message,
+        seconds queued, seconds from submission to completion)."""
+        res, code = ctypes.c_void_p(), ctypes.c_int32()
+        sec = (ctypes.c_double * 2)()
+        rc = self._lib.qm_server_poll(self._h, int(ticket), int(wait_ms), ctypes.byref(res), ctypes.byref(code),
+                                      ctypes.addressof(sec))
+        if rc == -8:
+            return None
+        if rc:
+            raise QmError(rc, self._lib.qm_last_error().decode())
+        msg = self._lib.qm_last_error().decode()
+        prof = self._profile.pop(int(ticket), False)
+        out = _take_result(self._lib, res, prof) if res.value else None
+        return out, int(code.value), msg, float(sec[0]), float(sec[1])
+
+    def result(self, ticket):
+        """Wait for a job and return its RefineResult (QmError if it failed)."""
+        out, code, msg, _, _ = self.poll(ticket, wait_ms=-1)
+        if code not in (0, -4):
+            raise QmError(code, msg)
+        return out
+
+    def info(self) -> dict:
+        st = _SrvStats()
+        self._lib.qm_server_info(self._h, ctypes.byref(st))
+        return {k: int(getattr(st, k)) for k, _ in _SrvStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.qm_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        self.close()

@@ -889,3 +889,5 @@ const char* qm_last_error(void) { return g_err.c_str(); }
 const char* qm_version(void) { return "qm 0.1 (gfx950)"; }
 
 }  // extern "C"
+
+#include "qm_server.h"

@@ -1,0 +1,255 @@
+// qm_server.h -- served form of the refinement: a job queue admitted against
+// a device-memory budget, run by worker threads that each own a HIP stream.
+//
+// Host code only (no kernels).  A job is one qm_refine call (the round loop
+// of paper, Section 2) on the server's device; the server copies the job's
+// host arrays at submission, so the caller's buffers are free again when
+// qm_server_submit returns.  Admission: a job is taken when its byte
+// estimate fits in the budget minus the estimates of the jobs already
+// admitted and not finished; otherwise submission returns QM_EAGAIN and the
+// caller retries later.  Workers take admitted jobs first come, first served;
+// a finished job's estimate is released before its result is handed out.
+#pragma once
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+
+namespace {
+
+using srv_clock = std::chrono::steady_clock;
+
+struct SrvJob {
+    uint64_t ticket = 0;
+    size_t est = 0;
+    std::vector<double> xyz;
+    std::vector<int32_t> tet, sf, sff, ss, ssg, seg, ftri, ftrif;
+    qm_plc plc{};
+    qm_mesh mesh{};
+    qm_options opt{};
+    srv_clock::time_point t_sub;
+};
+
+struct SrvDone {
+    qm_result* res = nullptr;
+    int code = QM_EINTERNAL;
+    std::string msg;
+    double wait_s = 0, total_s = 0;
+};
+
+// copy n*cols elements of a borrowed host array; false when a non-empty
+// array has no pointer
+template <class T>
+bool srv_copy(std::vector<T>& dst, const T* src, long n, int cols) {
+    if (n < 0) return false;
+    if (n == 0) return true;
+    if (!src) return false;
+    dst.assign(src, src + n * (long)cols);
+    return true;
+}
+
+}  // namespace
+
+struct qm_server {
+    int dev = 0;
+    size_t budget = 0, resident = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::unique_ptr<SrvJob>> queue;
+    std::unordered_map<uint64_t, SrvDone> done;
+    std::unordered_map<uint64_t, int> live;   // admitted and not yet collected
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int running = 0;
+    int64_t admitted = 0, refused = 0, completed = 0;
+    std::vector<std::thread> workers;
+};
+
+namespace {
+
+void srv_worker(qm_server* S) {
+    hipStream_t st = nullptr;
+    bool ok = hipSetDevice(S->dev) == hipSuccess &&
+              hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    for (;;) {
+        std::unique_ptr<SrvJob> J;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+            if (S->stop) break;
+            J = std::move(S->queue.front());
+            S->queue.pop_front();
+            ++S->running;
+        }
+        const auto t_start = srv_clock::now();
+        SrvDone d;
+        if (ok) {
+            d.code = qm_refine(&J->plc, &J->mesh, &J->opt, st, &d.res);
+            if (d.code != QM_OK && d.code != QM_EROUNDS) d.msg = qm_last_error();
+        } else {
+            d.code = QM_EDEVICE;
+            d.msg = "server worker has no HIP stream";
+        }
+        const auto t_end = srv_clock::now();
+        d.wait_s = std::chrono::duration<double>(t_start - J->t_sub).count();
+        d.total_s = std::chrono::duration<double>(t_end - J->t_sub).count();
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->resident -= J->est;
+            --S->running;
+            ++S->completed;
+            S->done[J->ticket] = std::move(d);
+        }
+        S->cv_done.notify_all();
+    }
+    if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options* opt) {
+    if (!plc || !in || !opt || in->nt < 0 || in->nv < 0) return 0;
+    // Output tets per input tet: Steiner points grow the mesh a few times at
+    // moderate bounds and more at tight ones.  Per output tet the device holds
+    // the mesh arrays (vertices, adjacency, face and edge marks, 84 B), the
+    // per-candidate arrays and the grow pools of a round; 256 B covers them,
+    // and growable buffers over-allocate by up to half again.
+    const double grow = opt->B < 1.6 ? 8.0 : 4.0;
+    const double tets = (double)in->nt * grow + 4096.0;
+    return (size_t)(tets * 256.0 * 1.5) + ((size_t)64 << 20);
+}
+
+int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out) {
+    g_err.clear();
+    if (!out || nworkers < 1 || nworkers > 64 || hbm_budget_bytes == 0) {
+        g_err = "bad server arguments";
+        return QM_EINVAL;
+    }
+    *out = nullptr;
+    auto S = std::make_unique<qm_server>();
+    if (hipGetDevice(&S->dev) != hipSuccess) { g_err = "no HIP device"; return QM_EDEVICE; }
+    S->budget = hbm_budget_bytes;
+    try {
+        for (int i = 0; i < nworkers; ++i) S->workers.emplace_back(srv_worker, S.get());
+    } catch (const std::exception& e) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv_work.notify_all();
+        for (auto& t : S->workers) t.join();
+        g_err = e.what();
+        return QM_ENOMEM;
+    }
+    *out = S.release();
+    return QM_OK;
+}
+
+int qm_server_submit(qm_server* S, const qm_plc* plc, const qm_mesh* in, const qm_options* opt,
+                     size_t est_bytes, uint64_t* ticket) {
+    g_err.clear();
+    if (!S || !plc || !in || !opt || !ticket) { g_err = "null argument"; return QM_EINVAL; }
+    if (opt->flags & QM_INPUT_DEVICE) { g_err = "server jobs take host arrays"; return QM_EINVAL; }
+    const size_t est = est_bytes ? est_bytes : qm_estimate_bytes(plc, in, opt);
+    if (est > S->budget) {
+        g_err = "job estimate " + std::to_string(est) + " B exceeds the server budget";
+        return QM_ENOMEM;
+    }
+    auto J = std::make_unique<SrvJob>();
+    try {
+        if (!srv_copy(J->xyz, in->xyz, in->nv, 3) || !srv_copy(J->tet, in->tet, in->nt, 4) ||
+            !srv_copy(J->sf, in->sf, in->nsf, 3) || !srv_copy(J->sff, in->sf_facet, in->nsf, 1) ||
+            !srv_copy(J->ss, in->ss, in->nss, 2) || !srv_copy(J->ssg, in->ss_seg, in->nss, 1) ||
+            !srv_copy(J->seg, plc->seg, plc->nseg, 2) || !srv_copy(J->ftri, plc->ftri, plc->nftri, 3) ||
+            !srv_copy(J->ftrif, plc->ftri_facet, plc->nftri, 1)) {
+            g_err = "negative count or missing array";
+            return QM_EINVAL;
+        }
+    } catch (const std::bad_alloc&) {
+        g_err = "host copy of the job failed";
+        return QM_ENOMEM;
+    }
+    J->plc = qm_plc{plc->nv, plc->nseg, J->seg.data(), plc->nftri, J->ftri.data(), J->ftrif.data()};
+    J->mesh = qm_mesh{in->nv, J->xyz.data(), in->nt, J->tet.data(), in->nsf, J->sf.data(), J->sff.data(),
+                      in->nss, J->ss.data(), J->ssg.data()};
+    J->opt = *opt;
+    J->est = est;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->resident + est > S->budget) {
+            ++S->refused;
+            g_err = "over the server budget (resident " + std::to_string(S->resident) + " B)";
+            return QM_EAGAIN;
+        }
+        S->resident += est;
+        J->ticket = S->next_ticket++;
+        J->t_sub = srv_clock::now();
+        *ticket = J->ticket;
+        S->live[J->ticket] = 1;
+        ++S->admitted;
+        S->queue.push_back(std::move(J));
+    }
+    S->cv_work.notify_one();
+    return QM_OK;
+}
+
+int qm_server_poll(qm_server* S, uint64_t ticket, int32_t wait_ms, qm_result** out, int32_t* code,
+                   double* seconds) {
+    g_err.clear();
+    if (!S || !out || !code) { g_err = "null argument"; return QM_EINVAL; }
+    std::unique_lock<std::mutex> lk(S->mu);
+    if (!S->live.count(ticket)) { g_err = "unknown ticket"; return QM_EINVAL; }
+    auto ready = [&] { return S->done.count(ticket) > 0; };
+    if (!ready()) {
+        if (wait_ms < 0) S->cv_done.wait(lk, ready);
+        else if (wait_ms > 0) S->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), ready);
+    }
+    if (!ready()) return QM_EAGAIN;
+    auto it = S->done.find(ticket);
+    SrvDone d = std::move(it->second);
+    S->done.erase(it);
+    S->live.erase(ticket);
+    *out = d.res;
+    *code = d.code;
+    if (seconds) { seconds[0] = d.wait_s; seconds[1] = d.total_s; }
+    g_err = d.msg;
+    return QM_OK;
+}
+
+int qm_server_info(qm_server* S, qm_server_stats* info) {
+    g_err.clear();
+    if (!S || !info) { g_err = "null argument"; return QM_EINVAL; }
+    std::lock_guard<std::mutex> lk(S->mu);
+    info->budget = S->budget;
+    info->resident = S->resident;
+    info->queued = (int32_t)S->queue.size();
+    info->running = S->running;
+    info->admitted = S->admitted;
+    info->refused = S->refused;
+    info->completed = S->completed;
+    return QM_OK;
+}
+
+void qm_server_destroy(qm_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        for (auto& J : S->queue) S->resident -= J->est;
+        S->queue.clear();
+    }
+    S->cv_work.notify_all();
+    for (auto& t : S->workers) t.join();
+    for (auto& kv : S->done) qm_result_free(kv.second.res);
+    delete S;
+}
+
+}  // extern "C"

@@ -301,3 +301,26 @@ def config(k: int, instance: int = 0) -> Workload:
         return make_workload(f"cfg4_inst{instance}", pts, 2.0, [ellipsoid_inside(axes, rot)],
                              {"n": n, "instance": instance})
     raise ValueError(f"unknown workload {k}")
+
+
+def serve_job(i: int, max_points: int = 500000, seed: int = 5) -> Workload:
+    """Job i of the served workload: n log-uniform in [1 000, max_points];
+    half the jobs use the clustered generator of workload 3 (90% from 8
+    Gaussians, 10% uniform, three nested spheres), half the one of workload 4
+    (uniform, one rotated ellipsoid); B drawn from {1.4, 2.0}."""
+    ss = np.random.SeedSequence(seed).spawn(i + 1)[i]
+    rng = np.random.Generator(np.random.PCG64(ss))
+    n = int(np.floor(np.exp(rng.uniform(np.log(1000.0), np.log(float(max_points))))))
+    B = 1.4 if rng.uniform() < 0.5 else 2.0
+    if rng.uniform() < 0.5:
+        ng = (9 * n) // 10
+        pts = np.concatenate([gaussmix_interior(rng, ng), uniform_interior(rng, n - ng)])
+        fns = [sphere_inside(r) for r in (0.15, 0.30, 0.45)]
+        kind = "clustered"
+    else:
+        axes = rng.uniform(0.15, 0.40, size=3)
+        rot = quat_rotation(rng.standard_normal(4))
+        pts = uniform_interior(rng, n)
+        fns = [ellipsoid_inside(axes, rot)]
+        kind = "ellipsoid"
+    return make_workload(f"serve_job{i}_{kind}{n}", pts, B, fns, {"n": n, "job": i, "kind": kind})
