@@ -65,6 +65,18 @@ struct DBuf {
     }
 };
 
+// pinned host ints (hipHostMalloc), freed with the owner
+struct PinnedInts {
+    int* p = nullptr;
+    explicit PinnedInts(size_t n) {
+        if (hipHostMalloc((void**)&p, n * sizeof(int), hipHostMallocDefault) != hipSuccess || !p)
+            throw std::runtime_error("pinned host allocation failed");
+    }
+    ~PinnedInts() { if (p) (void)hipHostFree(p); }
+    PinnedInts(const PinnedInts&) = delete;
+    PinnedInts& operator=(const PinnedInts&) = delete;
+};
+
 template <class T>
 T read1(const T* dptr, hipStream_t s) {
     T v;
@@ -453,9 +465,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     int* undec_d = E.ctr.p + 40;
     int* npass_d = E.ctr.p + 38;
     int round = 0, status = 0, last_ncand = 0;
-    int hc[48];                     // host copy of ctr[0..48), taken at each synchronisation
+    // host copies of the counters live in pinned memory: the per-round
+    // read-backs are then direct copies, not staged through a bounce buffer
+    PinnedInts pin(48 + 46);
+    int* const hc = pin.p;          // ctr[0..48), taken at each synchronisation
     auto sync_counters = [&]() {
-        HIPCK(hipMemcpyAsync(hc, E.ctr.p, sizeof hc, hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(hc, E.ctr.p, 48 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
         if (E.prof) E.pflush(&R->round_ms);
     };
@@ -540,14 +555,14 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                                                                              pass == 0 ? E.BP : E.BPnoprof(),
                                                                              nullptr, 0, nullptr);
             E.pend(pass == 0 ? 3 : 8);
-            int cw[46];
+            int* const cw = pin.p + 48;  // ctr[0..46) after a grow pass
             for (int attempt = 0;; ++attempt) {
                 if (attempt > 0 || pass > 0) {
                     HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
                     HIPCK(hipMemsetAsync(olist_n + 4, 0, sizeof(int), s));
                 }
                 k_overflow_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.olist.p, E.glist.p, olist_n);
-                HIPCK(hipMemcpyAsync(cw, E.ctr.p, sizeof cw, hipMemcpyDeviceToHost, s));
+                HIPCK(hipMemcpyAsync(cw, E.ctr.p, 46 * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCK(hipStreamSynchronize(s));
                 const int nover = cw[32], nbig = cw[36];
                 if (cw[34]) {
