@@ -72,13 +72,17 @@ typedef struct qm_mesh {
 #define QM_PROFILE 2u        /* time each kernel family with HIP events on the call's
                                 stream and count the region work (qm_stats.prof_*) */
 #define QM_VERBOSE 4u        /* progress line on stderr every few seconds of rounds */
+#define QM_PROFILE_GROW 8u   /* time only the grow launches with small LDS tiles (family 3 of
+                                qm_stats.prof_ms and prof_launches; the rest stay 0) with HIP
+                                events on the call's stream; the kernels run as unprofiled.
+                                Ignored with QM_PROFILE */
 
 typedef struct qm_options {
     double B;                /* radius-edge bound (> 0) */
     double hmin_factor;      /* h_min = hmin_factor * shortest input edge (0.5 typical) */
     int32_t max_rounds;      /* round guard; QM_EROUNDS when reached */
     int32_t max_kept;        /* > 0: insert at most this many points per round */
-    uint32_t flags;          /* QM_INPUT_DEVICE | QM_PROFILE | QM_VERBOSE */
+    uint32_t flags;          /* QM_INPUT_DEVICE | QM_PROFILE | QM_VERBOSE | QM_PROFILE_GROW */
 } qm_options;
 
 /* per-round record (16 int32): class (0 subsegment, 1 subface, 2 tet),

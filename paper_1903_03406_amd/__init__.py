@@ -27,6 +27,7 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 QM_INPUT_DEVICE = 1
 QM_PROFILE = 2
+QM_PROFILE_GROW = 8   # time only the small-tile grow launches (family grow_validate)
 QM_VERBOSE = 4
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
                  "scans", "insert", "grow_overflow")
@@ -139,6 +140,14 @@ class RefineResult:
         return int(sum(self.inserted))
 
 
+def _prof_flag(profile):
+    """profile=True: every kernel family and the region counters (QM_PROFILE);
+    profile="grow": only the small-tile grow launches (QM_PROFILE_GROW)."""
+    if profile == "grow":
+        return QM_PROFILE_GROW
+    return QM_PROFILE if profile else 0
+
+
 def _arr(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
@@ -177,7 +186,7 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
     plc = _Plc(nv, nseg, pseg, nft, pft, pftf)
     mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
     opts = _Opts(float(B), float(hmin_factor), int(max_rounds), int(max_kept),
-                 (QM_INPUT_DEVICE if dev else 0) | (QM_PROFILE if profile else 0)
+                 (QM_INPUT_DEVICE if dev else 0) | (_prof_flag(profile))
                  | (QM_VERBOSE if verbose else 0))
     if stream is None:
         hs = None
@@ -274,7 +283,7 @@ def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, m
     for i, w in enumerate(workloads):
         plcs[i], meshes[i] = _marshal(w, keep)
         opts[i] = _Opts(float(w.B), float(hmin_factor), int(max_rounds), int(max_kept),
-                        QM_PROFILE if profile else 0)
+                        _prof_flag(profile))
     outs = (ctypes.c_void_p * max(n, 1))()
     codes = (ctypes.c_int32 * max(n, 1))()
     lib.qm_refine_batch.restype = ctypes.c_int
@@ -341,7 +350,7 @@ class Server:
     @staticmethod
     def _opts(w, hmin_factor, max_rounds, max_kept, profile):
         return _Opts(float(w.B), float(hmin_factor), int(max_rounds), int(max_kept),
-                     QM_PROFILE if profile else 0)
+                     _prof_flag(profile))
 
     def estimate_bytes(self, w, *, hmin_factor=0.5) -> int:
         keep = []

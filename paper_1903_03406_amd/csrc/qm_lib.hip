@@ -196,6 +196,7 @@ struct Engine {
     int64_t dead = 0;
     // kernel-family timing with events on the call's stream (QM_PROFILE)
     bool prof = false;
+    bool prof_grow = false;   // events around the first small-tile grow launch only
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_cat, ev_round;
     int ev_used = 0, cur_round = 0;
@@ -203,8 +204,9 @@ struct Engine {
     int64_t prof_n[QM_PROF_FAMILIES] = {0};
     int64_t prof_over = 0, prof_full = 0;
     DBuf<unsigned long long> pctr;
-    void pbegin() {
-        if (!prof) return;
+    bool timed(int cat) const { return prof || (prof_grow && cat == 3); }
+    void pbegin(int cat = -1) {
+        if (!timed(cat)) return;
         if (ev_used + 2 > (int)ev.size()) {
             for (int i = 0; i < 64; ++i) { hipEvent_t e; HIPCK(hipEventCreate(&e)); ev.push_back(e); }
             ev_cat.resize(ev.size());
@@ -213,7 +215,7 @@ struct Engine {
         HIPCK(hipEventRecord(ev[ev_used], s));
     }
     void pend(int cat) {
-        if (!prof) return;
+        if (!timed(cat)) return;
         HIPCK(hipEventRecord(ev[ev_used + 1], s));
         ev_cat[ev_used] = cat;
         ev_round[ev_used] = cur_round;
@@ -373,6 +375,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
     Engine E(s);
     E.prof = (opt->flags & QM_PROFILE) != 0;
+    E.prof_grow = !E.prof && (opt->flags & QM_PROFILE_GROW) != 0;
     if (E.prof) { E.pctr.ensure(4 + GROW_PHASES, s, false, 0); }
     int64_t scan_tets = 0, scan_verts = 0;
     const int nv = in->nv, nt = in->nt, nsf = in->nsf, nss = in->nss, nftri = plc->nftri;
@@ -473,6 +476,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         HIPCK(hipMemcpyAsync(hc, E.ctr.p, 48 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
         if (E.prof) E.pflush(&R->round_ms);
+        else if (E.prof_grow) E.pflush();
     };
     // the dead-slot count after a round's insertion is read at the next
     // synchronisation; it completes that round's record (tets after)
@@ -550,7 +554,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         int ncl_final = 0;
         for (int pass = 0;; ++pass) {
             if (pass > 0) k_round_reset_pools<<<1, 64, 0, s>>>(E.ctr.p);
-            E.pbegin();
+            E.pbegin(pass == 0 ? 3 : 8);
             k_grow_lds<QM_TILES_SMALL><<<std::min(ncand, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL,
                                                                              pass == 0 ? E.BP : E.BPnoprof(),
                                                                              nullptr, 0, nullptr);
@@ -787,6 +791,11 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     HIPCK(hipEventElapsedTime(&ms_setup, e0, e1));
     HIPCK(hipEventElapsedTime(&ms_ref, e1, e2));
     (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
+    if (E.prof_grow) {             // the stream is synchronised: every pair is complete
+        E.pflush();
+        R->stats.prof_ms[3] = E.prof_ms[3];
+        R->stats.prof_launches[3] = E.prof_n[3];
+    }
     if (E.prof) {
         for (int i = 0; i < QM_PROF_FAMILIES; ++i) { R->stats.prof_ms[i] = E.prof_ms[i]; R->stats.prof_launches[i] = E.prof_n[i]; }
         unsigned long long pc[4 + GROW_PHASES];
