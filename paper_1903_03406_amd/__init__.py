@@ -313,6 +313,18 @@ def version() -> str:
     return _load().qm_version().decode()
 
 
+def estimate_bytes(w, *, hmin_factor=0.5) -> int:
+    """Device bytes the server budgets for refining workload w
+    (qm_estimate_bytes; host arithmetic only)."""
+    lib = _load()
+    lib.qm_estimate_bytes.restype = ctypes.c_size_t
+    lib.qm_estimate_bytes.argtypes = [ctypes.POINTER(_Plc), ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts)]
+    keep = []
+    plc, mesh = _marshal(w, keep)
+    opt = _Opts(float(w.B), float(hmin_factor), 1, 0, 0)
+    return int(lib.qm_estimate_bytes(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opt)))
+
+
 class _SrvStats(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_size_t), ("resident", ctypes.c_size_t), ("queued", ctypes.c_int32),
                 ("running", ctypes.c_int32), ("admitted", ctypes.c_int64), ("refused", ctypes.c_int64),
@@ -353,10 +365,7 @@ class Server:
                      _prof_flag(profile))
 
     def estimate_bytes(self, w, *, hmin_factor=0.5) -> int:
-        keep = []
-        plc, mesh = _marshal(w, keep)
-        opt = self._opts(w, hmin_factor, 1, 0, False)
-        return int(self._lib.qm_estimate_bytes(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opt)))
+        return estimate_bytes(w, hmin_factor=hmin_factor)
 
     def submit(self, w, *, est_bytes=0, hmin_factor=0.5, max_rounds=100000, max_kept=0, profile=False):
         """Ticket of the admitted job, or None when the budget has no room

@@ -40,3 +40,15 @@ def test_binding_has_no_cpu_path(monkeypatch, tmp_path):
     monkeypatch.setattr(qm, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         qm.refine([[0, 0, 0]] * 8, [[0, 1, 2, 3]], [], [], [], [], [], [], B=2.0)
+
+
+@pytest.mark.skipif(not os.path.exists(qm._SO), reason="libqm.so not built")
+def test_server_estimate_is_host_arithmetic():
+    """qm_estimate_bytes needs no device: 256 B per estimated output tet with
+    1.5x growth slack plus 64 MiB; output tets 8x the input at B < 1.6, else 4x."""
+    import qm_inputs as qi
+    w = qi.uniform_cube(60, seed=3, B=2.0)
+    nt = len(w.tets)
+    assert qm.estimate_bytes(w) == int((nt * 4.0 + 4096.0) * 256.0 * 1.5) + (64 << 20)
+    w.B = 1.4
+    assert qm.estimate_bytes(w) == int((nt * 8.0 + 4096.0) * 256.0 * 1.5) + (64 << 20)
