@@ -320,6 +320,9 @@ def main():
                      "launches": prof["launches"][fam], "kernel_ms": kms,
                      "algorithmic_bytes": nbytes, "dominant_family": dominant},
     }
+    from paper_1903_03406_amd import quality
+    qin, qout = quality.report(w.xyz, w.tets, w.B), quality.report(r.xyz, r.tets, w.B)
+    out["quality"] = {"input": {k: v for k, v in qin.items() if k != "dihedral_hist"}, "output": qout}
     if args.dump_rounds:
         with open(args.dump_rounds, "w") as f:
             json.dump({"fields": list(qm.ROUND_NAMES), "rounds": r.rstats.tolist(),
