@@ -67,6 +67,26 @@ def test_surface_parity(n, seed, B, spheres):
     assert_same(g, o, f"surface n={n}")
 
 
+def clustered_instance(n, seed):
+    """A small instance of the 1M-point workload's generator: 90% of the
+    points from 8 Gaussians, 10% uniform, three nested sphere surfaces,
+    B = 1.4 (many small cavities next to the clusters)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ng = 9 * n // 10
+    pts = np.concatenate([qi.gaussmix_interior(rng, ng), qi.uniform_interior(rng, n - ng)])
+    return qi.make_workload(f"clustered_{n}", pts, 1.4, [qi.sphere_inside(r) for r in (0.15, 0.30, 0.45)])
+
+
+def test_clustered_instance_parity():
+    w = clustered_instance(1500, 1577)
+    g, o = run_both(w)
+    assert o.rounds > 100 and len(o.xyz) > len(w.xyz) + 1000
+    assert_same(g, o, "clustered 1500")
+    # the served form runs the same refinement
+    with qm.Server(4 << 30, nworkers=2) as srv:
+        assert_same(srv.result(srv.submit(w)), o, "clustered 1500 served")
+
+
 def test_ellipsoid_instance_parity():
     # a small instance of the batched workload's generator (rotated ellipsoid)
     rng = np.random.Generator(np.random.PCG64(44))
