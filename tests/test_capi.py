@@ -52,3 +52,14 @@ def test_server_estimate_is_host_arithmetic():
     assert qm.estimate_bytes(w) == int((nt * 4.0 + 4096.0) * 256.0 * 1.5) + (64 << 20)
     w.B = 1.4
     assert qm.estimate_bytes(w) == int((nt * 8.0 + 4096.0) * 256.0 * 1.5) + (64 << 20)
+
+
+def test_binding_constants_match_the_header():
+    text = open(os.path.join(ROOT, "include", "qm.h")).read()
+    defs = {m.group(1): m.group(2) for m in re.finditer(r"#define (QM_[A-Z_0-9]+)\s+\(?(-?\w+)\)?", text)}
+    assert int(defs["QM_PROFILE"].rstrip("u")) == qm.QM_PROFILE
+    assert int(defs["QM_PROFILE_GROW"].rstrip("u")) == qm.QM_PROFILE_GROW
+    assert int(defs["QM_ROUND_FIELDS"]) == qm.ROUND_FIELDS
+    assert int(defs["QM_PROF_FAMILIES"]) == len(qm.PROF_FAMILIES)
+    codes = {int(v): k for k, v in defs.items() if k.startswith("QM_E")}
+    assert codes == qm.ERRORS
