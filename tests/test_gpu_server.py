@@ -110,3 +110,35 @@ def test_shutdown_with_pending_jobs(jobs):
     with qm.Server(8 * GiB, nworkers=2) as srv2:
         t = srv2.submit(jobs[1])
         assert same(srv2.result(t), qm.refine_workload(jobs[1]))
+
+
+def test_admission_under_pressure(jobs):
+    """More jobs than the budget holds at once: submissions are refused
+    while it is full and admitted as jobs finish; every job completes with
+    the result it has alone, and the budget drains to zero."""
+    budget = 3 * GiB
+    order = [jobs[k % len(jobs)] for k in range(12)]
+    done, pending, refused = {}, {}, 0
+    with qm.Server(budget, nworkers=4) as srv:
+        nxt = 0
+        while nxt < len(order) or pending:
+            while nxt < len(order):
+                t = srv.submit(order[nxt], est_bytes=GiB)
+                if t is None:
+                    refused += 1
+                    break
+                assert srv.info()["resident"] <= budget
+                pending[t] = nxt
+                nxt += 1
+            for t in list(pending):
+                got = srv.poll(t, wait_ms=5)
+                if got is not None:
+                    res, code, _, _, _ = got
+                    assert code in (0, -4)
+                    done[pending.pop(t)] = res
+        info = srv.info()
+    assert refused > 0 and info["refused"] == refused
+    assert info["admitted"] == len(order) == info["completed"] and info["resident"] == 0
+    alone = {id(w): qm.refine_workload(w) for w in jobs}
+    for k, w in enumerate(order):
+        assert same(done[k], alone[id(w)]), (k, w.name)
