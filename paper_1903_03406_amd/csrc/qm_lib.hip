@@ -105,6 +105,28 @@ __global__ void k_round_reset(int* ctr) {
     if (i < 48 && (i < 11 || i >= 15)) ctr[i] = 0;
 }
 
+// Priority order of a small round (n <= SORT_SMALL candidates), one
+// workgroup: each key's rank among the keys, larger first and equal keys in
+// index order, is its position -- the permutation a stable descending radix
+// sort gives, without that sort's launches.
+constexpr int SORT_SMALL = 256;
+__global__ __launch_bounds__(SORT_SMALL) void k_sort_small_desc(int n, const unsigned long long* key,
+                                                               unsigned long long* skey, int* order) {
+    __shared__ unsigned long long K[SORT_SMALL];
+    const int i = threadIdx.x;
+    if (i < n) K[i] = key[i];
+    __syncthreads();
+    if (i >= n) return;
+    const unsigned long long ki = K[i];
+    int r = 0;
+    for (int j = 0; j < n; ++j) {
+        const unsigned long long kj = K[j];
+        r += (kj > ki) || (kj == ki && j < i);
+    }
+    skey[r] = ki;
+    order[r] = i;
+}
+
 __global__ void k_iota(int n, int* o) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = i;
@@ -533,8 +555,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.pbegin();
         k_split<<<nblk(ncand), 256, 0, s>>>(E.M, cls, ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
                                           E.c_st0.p, E.c_reason0.p);
-        k_iota<<<nblk(ncand), 256, 0, s>>>(ncand, E.order0.p);
-        E.sort_desc(E.c_key0.p, E.skey.p, E.order0.p, E.order1.p, ncand);
+        if (ncand <= SORT_SMALL) {
+            k_sort_small_desc<<<1, SORT_SMALL, 0, s>>>(ncand, E.c_key0.p, E.skey.p, E.order1.p);
+        } else {
+            k_iota<<<nblk(ncand), 256, 0, s>>>(ncand, E.order0.p);
+            E.sort_desc(E.c_key0.p, E.skey.p, E.order0.p, E.order1.p, ncand);
+        }
         k_fix_ties<<<nblk(ncand), 256, 0, s>>>(ncand, E.skey.p, E.order1.p, E.c_tup0.p);
         k_permute<<<nblk(ncand), 256, 0, s>>>(ncand, E.order1.p, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
                                             E.c_st0.p, E.c_reason0.p, E.C);
