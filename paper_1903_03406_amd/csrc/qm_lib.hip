@@ -106,25 +106,34 @@ __global__ void k_round_reset(int* ctr) {
 }
 
 // Priority order of a small round (n <= SORT_SMALL candidates), one
-// workgroup: each key's rank among the keys, larger first and equal keys in
-// index order, is its position -- the permutation a stable descending radix
-// sort gives, without that sort's launches.
+// workgroup: each candidate's position is its rank under the round's order
+// (larger key first; equal keys by ascending tuple, then by index), the
+// order the radix sort and the tie fix give together; the candidate is
+// written straight to that position of the ordered arrays.
 constexpr int SORT_SMALL = 256;
-__global__ __launch_bounds__(SORT_SMALL) void k_sort_small_desc(int n, const unsigned long long* key,
-                                                               unsigned long long* skey, int* order) {
+__global__ __launch_bounds__(SORT_SMALL) void k_order_small(int n, const int* elem, const unsigned long long* key,
+                                                           const int4* tup, const double4* p, const int* st,
+                                                           const int* reason, Cands C) {
     __shared__ unsigned long long K[SORT_SMALL];
+    __shared__ int4 T[SORT_SMALL];
     const int i = threadIdx.x;
-    if (i < n) K[i] = key[i];
+    if (i < n) { K[i] = key[i]; T[i] = tup[i]; }
     __syncthreads();
     if (i >= n) return;
     const unsigned long long ki = K[i];
+    const int4 ti = T[i];
     int r = 0;
     for (int j = 0; j < n; ++j) {
         const unsigned long long kj = K[j];
-        r += (kj > ki) || (kj == ki && j < i);
+        if (kj > ki) { ++r; continue; }
+        if (kj != ki || j == i) continue;
+        const int4 tj = T[j];
+        r += tj.x != ti.x ? tj.x < ti.x : tj.y != ti.y ? tj.y < ti.y : tj.z != ti.z ? tj.z < ti.z
+           : tj.w != ti.w ? tj.w < ti.w : j < i;
     }
-    skey[r] = ki;
-    order[r] = i;
+    C.elem[r] = elem[i]; C.key[r] = ki; C.tup[r] = ti; C.p[r] = p[i];
+    C.st[r] = st[i]; C.reason[r] = reason[i];
+    C.seed[r] = -1; C.qw[r] = make_int2(-1, -1);
 }
 
 __global__ void k_iota(int n, int* o) {
@@ -556,14 +565,15 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         k_split<<<nblk(ncand), 256, 0, s>>>(E.M, cls, ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
                                           E.c_st0.p, E.c_reason0.p);
         if (ncand <= SORT_SMALL) {
-            k_sort_small_desc<<<1, SORT_SMALL, 0, s>>>(ncand, E.c_key0.p, E.skey.p, E.order1.p);
+            k_order_small<<<1, SORT_SMALL, 0, s>>>(ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
+                                                   E.c_st0.p, E.c_reason0.p, E.C);
         } else {
             k_iota<<<nblk(ncand), 256, 0, s>>>(ncand, E.order0.p);
             E.sort_desc(E.c_key0.p, E.skey.p, E.order0.p, E.order1.p, ncand);
+            k_fix_ties<<<nblk(ncand), 256, 0, s>>>(ncand, E.skey.p, E.order1.p, E.c_tup0.p);
+            k_permute<<<nblk(ncand), 256, 0, s>>>(ncand, E.order1.p, E.c_elem0.p, E.c_key0.p, E.c_tup0.p,
+                                                E.c_p0.p, E.c_st0.p, E.c_reason0.p, E.C);
         }
-        k_fix_ties<<<nblk(ncand), 256, 0, s>>>(ncand, E.skey.p, E.order1.p, E.c_tup0.p);
-        k_permute<<<nblk(ncand), 256, 0, s>>>(ncand, E.order1.p, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
-                                            E.c_st0.p, E.c_reason0.p, E.C);
         E.pend(1);
         // step 3: locate
         if (cls != CLS_SS) { E.pbegin(); k_locate<<<nblk(ncand, 64), 64, 0, s>>>(E.M, cls, E.C); E.pend(2); }
