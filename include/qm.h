@@ -85,12 +85,13 @@ typedef struct qm_options {
     uint32_t flags;          /* QM_INPUT_DEVICE | QM_PROFILE | QM_VERBOSE | QM_PROFILE_GROW */
 } qm_options;
 
-/* per-round record (16 int32): class (0 subsegment, 1 subface, 2 tet),
+/* per-round record (17 int32): class (0 subsegment, 1 subface, 2 tet),
    candidates, accepted, rejected, exempted, inserted, exempted by reason
    (non-finite point, walk cap, encroached exempt element, h_min, region
    subface without region tets, invisible boundary face, invisible 2D
-   boundary edge, unclosed cavity boundary), vertices after, tets after */
-#define QM_ROUND_FIELDS 16
+   boundary edge, unclosed cavity boundary, a new face that would not be
+   locally Delaunay), vertices after, tets after */
+#define QM_ROUND_FIELDS 17
 #define QM_PROF_FAMILIES 9
 
 typedef struct qm_stats {

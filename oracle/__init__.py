@@ -19,10 +19,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_qmo.so")
 _lib = None
 
-NSTAT = 16
+NSTAT = 17
 STAT_FIELDS = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
-               "ex_face", "ex_edge2d", "ex_manifold", "nv_after", "nt_after")
+               "ex_face", "ex_edge2d", "ex_manifold", "ex_delaunay", "nv_after", "nt_after")
 
 
 def build() -> str:
@@ -74,16 +74,21 @@ class OracleResult:
     sf_facet: np.ndarray
     ss: np.ndarray
     ss_seg: np.ndarray
-    rstats: np.ndarray        # (rounds, 16)
+    rstats: np.ndarray        # (rounds, NSTAT)
     rounds: int
     status: int               # 0 done, 1 round guard reached
     seconds: float
     last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
+    round_checks: np.ndarray = None  # (rounds, len(CHECK_FIELDS)): check() after every round
 
 
-def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0) -> OracleResult:
-    """Run the oracle on a workload (qm_inputs.Workload or compatible)."""
+def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
+           round_checks=False) -> OracleResult:
+    """Run the oracle on a workload (qm_inputs.Workload or compatible).
+    round_checks: run check() on the mesh at the end of every round."""
     lib = _load()
+    lib.qmo_set_round_check.argtypes = [ctypes.c_int]
+    lib.qmo_set_round_check(1 if round_checks else 0)
     c = lambda a, t: np.ascontiguousarray(a, dtype=t)
     xyz = c(w.xyz, np.float64); tets = c(w.tets, np.int32)
     sf = c(w.sf, np.int32); sff = c(w.sf_facet, np.int32)
@@ -105,6 +110,13 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0) -> OracleR
                        float(lib.qmo_result_seconds(res)))
     lib.qmo_result_copy(res, _ptr(out.xyz), _ptr(out.tets), _ptr(out.sf), _ptr(out.sf_facet),
                         _ptr(out.ss), _ptr(out.ss_seg), _ptr(out.rstats))
+    if round_checks:
+        lib.qmo_result_round_checks.restype = ctypes.c_int
+        lib.qmo_result_round_checks.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        out.round_checks = np.zeros((rounds, len(CHECK_FIELDS)), dtype=np.int32)
+        if rounds:
+            lib.qmo_result_round_checks(res, _ptr(out.round_checks))
+        lib.qmo_set_round_check(0)
     lib.qmo_result_lastc.restype = ctypes.c_int
     lib.qmo_result_lastc.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     nl = lib.qmo_result_lastc(res, None)
@@ -175,8 +187,7 @@ def key(cls, ids) -> int:
 
 
 CHECK_FIELDS = ("neg_orient", "face_overuse", "hull_not_subface", "nonlocal_delaunay",
-                "sf_missing", "ss_missing", "euler", "bad_tets", "chain_broken",
-                "nonlocal_unexcused")
+                "sf_missing", "ss_missing", "euler", "bad_tets", "chain_broken")
 
 
 def check(xyz, tets, sf, ss, ss_seg, B) -> dict:
@@ -185,7 +196,7 @@ def check(xyz, tets, sf, ss, ss_seg, B) -> dict:
     c = lambda a, t: np.ascontiguousarray(a, dtype=t)
     xyz = c(xyz, np.float64); tets = c(tets, np.int32); sf = c(sf, np.int32)
     ss = c(ss, np.int32); ss_seg = c(ss_seg, np.int32)
-    out = np.zeros(10, dtype=np.int32); vol = np.zeros(1)
+    out = np.zeros(len(CHECK_FIELDS), dtype=np.int32); vol = np.zeros(1)
     L.qmo_check.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                             ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]

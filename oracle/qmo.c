@@ -46,7 +46,7 @@
 enum { CLS_SS = 0, CLS_SF = 1, CLS_TET = 2, CLS_NONE = 3 };
 enum { ST_OK = 0, ST_REJECT = 1, ST_EXEMPT = 2 };
 enum { EX_NONE = 0, EX_NONFINITE = 1, EX_WALK = 2, EX_ENC_EXEMPT = 3, EX_HMIN = 4,
-       EX_RFTET = 5, EX_FACE = 6, EX_EDGE2D = 7, EX_MANIFOLD = 8, EX_NREASON = 9 };
+       EX_RFTET = 5, EX_FACE = 6, EX_EDGE2D = 7, EX_MANIFOLD = 8, EX_DELAUNAY = 9, EX_NREASON = 10 };
 #define FL_QUEUED 1
 #define FL_EXEMPT 2
 #define WALK_CAP 1000000
@@ -472,6 +472,13 @@ static int count_bfaces(const Mesh* M, const Cand* c, int x, int y) {
     }
     return cnt;
 }
+/* whether xy is a 2D boundary edge (the new face (x, y, p) is a subface) */
+static int is_bedge(const Cand* c, int x, int y) {
+    if (x > y) { int t = x; x = y; y = t; }
+    for (int q = 0; q < c->bedge.n; q += 4)
+        if (c->bedge.a[q] == x && c->bedge.a[q + 1] == y) return 1;
+    return 0;
+}
 /* 1 for a one-sided 2D boundary edge, else 2 */
 static int want_bfaces(const Cand* c, int x, int y) {
     if (x > y) { int t = x; x = y; y = t; }
@@ -572,6 +579,39 @@ static void validate(Mesh* M, Cand* c, int s) {
     for (int q = 0; q < c->bedge.n; q += 4) {
         int x = c->bedge.a[q], y = c->bedge.a[q + 1];
         if (count_bfaces(M, c, x, y) != want_bfaces(c, x, y)) { c->status = ST_EXEMPT; c->reason = EX_MANIFOLD; return; }
+    }
+    /* (g) the mesh stays a CDT (Section 2: the triangulation is a CDT at the
+       end of every round).  Each new interior face (x, y, p) that is not a
+       new subface separates the new tets on the two boundary faces sharing
+       edge xy; it must be locally Delaunay: the third vertex of the other
+       boundary face is not strictly inside the circumsphere of the first
+       new tet (x, y, z, p), which is positively oriented by (d).  With every
+       other face of the new tets locally Delaunay by construction (an outer
+       tet's sphere excludes p), this keeps every non-subface face of the
+       mesh locally Delaunay, i.e. the mesh a CDT (constrained Delaunay
+       lemma).  Without the check, a cavity that wraps more than half-way
+       around a constraint edge can leave a face that is not. */
+    for (int i = 0; i < c->bface.n; ++i) {
+        const int* v = M->T[c->bface.a[i] >> 2].v;
+        int f = c->bface.a[i] & 3;
+        int fv[3] = {v[FI[f][0]], v[FI[f][1]], v[FI[f][2]]};
+        for (int j = 0; j < 3; ++j) {
+            int x = fv[j], y = fv[(j + 1) % 3];
+            if (is_bedge(c, x, y)) continue;
+            for (int i2 = i + 1; i2 < c->bface.n; ++i2) {
+                const int* w = M->T[c->bface.a[i2] >> 2].v;
+                int g = c->bface.a[i2] & 3;
+                int hx = 0, hy = 0, apex = -1;
+                for (int r = 0; r < 3; ++r) {
+                    int u = w[FI[g][r]];
+                    if (u == x) hx = 1; else if (u == y) hy = 1; else apex = u;
+                }
+                if (!hx || !hy) continue;
+                if (qmo_insphere(X(M, fv[0]), X(M, fv[1]), X(M, fv[2]), p, X(M, apex)) > 0) {
+                    c->status = ST_EXEMPT; c->reason = EX_DELAUNAY; return;
+                }
+            }
+        }
     }
     /* claim set: region tets plus the tets across boundary faces */
     for (int i = 0; i < c->RT.n; ++i) iv_push(&c->claim, c->RT.a[i]);
@@ -732,17 +772,46 @@ static int insert_point(Mesh* M, Cand* c, int pid) {
 }
 
 /* ---------------------------------------------------------------- API */
-#define QMO_NSTAT 16
+#define QMO_NSTAT 17
 /* per-round record: class, candidates, ok, rejected, exempt, kept,
-   exempt by reason [1..8] in slots 6..13, vertices after, tets after */
+   exempt by reason [1..9] in slots 6..14, vertices after, tets after */
+
+#define QMO_NCHECK 9
+int qmo_check(int nv, const double* xyz, int nt, const int* tets, int nsf, const int* sf,
+              int nss, const int* ss, const int* ss_seg, double B, int* out, double* vol);
+
+/* When set, every round ends with qmo_check on the current mesh, and its
+   counts are kept per round (qmo_result_round_checks). */
+static int g_round_check = 0;
+void qmo_set_round_check(int on) { g_round_check = on; }
 
 typedef struct qmo_result {
+    int* rcheck;                  /* QMO_NCHECK ints per round (round checks on) */
     int* lastc; int nlastc;       /* last round: 9 ints per candidate */
     int nv, nt, nsf, nss, rounds, status;
     double* xyz; int* tets; int* sf; int* sf_facet; int* ss; int* ss_seg;
     int* rstats; int nrstats;
     double seconds;
 } qmo_result;
+
+/* the current mesh as plain arrays, checked by qmo_check */
+static void round_check(const Mesh* M, double B, int* out) {
+    int nt = 0;
+    for (int t = 0; t < M->nt; ++t) nt += M->T[t].alive;
+    int* tets = (int*)malloc(sizeof(int) * 4 * (size_t)(nt + 1));
+    for (int t = 0, j = 0; t < M->nt; ++t) if (M->T[t].alive) memcpy(&tets[4 * j++], M->T[t].v, 4 * sizeof(int));
+    int nsf = (int)M->sf.n, nss = (int)M->ss.n;
+    int* sf = (int*)malloc(sizeof(int) * 3 * (size_t)(nsf + 1));
+    int* ss = (int*)malloc(sizeof(int) * 2 * (size_t)(nss + 1));
+    int* sg = (int*)malloc(sizeof(int) * (size_t)(nss + 1));
+    for (size_t i = 0, j = 0; i < M->sf.cap; ++i)
+        if (M->sf.e[i].st == 1) { memcpy(&sf[3 * j], M->sf.e[i].k, 3 * sizeof(int)); j++; }
+    for (size_t i = 0, j = 0; i < M->ss.cap; ++i)
+        if (M->ss.e[i].st == 1) { memcpy(&ss[2 * j], M->ss.e[i].k, 2 * sizeof(int)); sg[j] = M->ss.e[i].v[0]; j++; }
+    double vol;
+    qmo_check(M->nv, &M->V[0][0], nt, tets, nsf, sf, nss, ss, sg, B, out, &vol);
+    free(tets); free(sf); free(ss); free(sg);
+}
 
 static void apply_flags(Mesh* M, CandList* L) {
     for (int i = 0; i < L->n; ++i) {
@@ -836,6 +905,7 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
     qmo_result* R = (qmo_result*)calloc(1, sizeof *R);
     int rcap = 256;
     R->rstats = (int*)calloc((size_t)rcap * QMO_NSTAT, sizeof(int));
+    if (g_round_check) R->rcheck = (int*)calloc((size_t)rcap * QMO_NCHECK, sizeof(int));
     CandList L = {0};
     clock_gettime(CLOCK_MONOTONIC, &t0);
     int round = 0;
@@ -880,14 +950,19 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
         if (round >= rcap) {
             R->rstats = (int*)realloc(R->rstats, sizeof(int) * QMO_NSTAT * (size_t)rcap * 2);
             memset(R->rstats + QMO_NSTAT * rcap, 0, sizeof(int) * QMO_NSTAT * (size_t)rcap);
+            if (R->rcheck) {
+                R->rcheck = (int*)realloc(R->rcheck, sizeof(int) * QMO_NCHECK * (size_t)rcap * 2);
+                memset(R->rcheck + QMO_NCHECK * rcap, 0, sizeof(int) * QMO_NCHECK * (size_t)rcap);
+            }
             rcap *= 2;
         }
         int* rs = R->rstats + QMO_NSTAT * round;
         rs[0] = cls; rs[1] = L.n; rs[2] = nok; rs[3] = nrej; rs[4] = nex; rs[5] = nkept;
         for (int r = 1; r < EX_NREASON; ++r) rs[5 + r] = byr[r];
-        rs[14] = M->nv;
+        rs[15] = M->nv;
         int live = 0; for (int t = 0; t < M->nt; ++t) live += M->T[t].alive;
-        rs[15] = live;
+        rs[16] = live;
+        if (R->rcheck) round_check(M, B, R->rcheck + QMO_NCHECK * round);
         free(R->lastc);
         R->lastc = (int*)malloc(sizeof(int) * 9 * (size_t)(L.n ? L.n : 1));
         R->nlastc = L.n;
@@ -945,13 +1020,18 @@ void qmo_result_copy(const qmo_result* R, double* xyz, int* tets, int* sf, int* 
     memcpy(ss_seg, R->ss_seg, sizeof(int) * (size_t)R->nss);
     memcpy(rstats, R->rstats, sizeof(int) * QMO_NSTAT * (size_t)R->nrstats);
 }
+int qmo_result_round_checks(const qmo_result* R, int* buf) {
+    if (!R->rcheck) return 0;
+    if (buf) memcpy(buf, R->rcheck, sizeof(int) * QMO_NCHECK * (size_t)R->nrstats);
+    return R->nrstats;
+}
 int qmo_result_lastc(const qmo_result* R, int* buf) {
     if (buf) memcpy(buf, R->lastc, sizeof(int) * 9 * (size_t)R->nlastc);
     return R->nlastc;
 }
 void qmo_result_free(qmo_result* R) {
     if (!R) return;
-    free(R->lastc);
+    free(R->lastc); free(R->rcheck);
     free(R->xyz); free(R->tets); free(R->sf); free(R->sf_facet); free(R->ss); free(R->ss_seg); free(R->rstats);
     free(R);
 }
@@ -980,18 +1060,14 @@ uint64_t qmo_c_key(int cls, const int* ids, int n) { return qmo_key(cls, ids, n)
  * out[6]  V - E + F - T (1 for a triangulated ball)
  * out[7]  bad tets (radius-edge ratio > B)
  * out[8]  subsegment chains broken (per segment: endpoint degree test)
- * out[9]  faces counted in out[3] that are not excused: a face is excused
- *         when a subsegment edge of one of its two tets is encroached by a
- *         vertex of the two tets (no CDT need exist around an encroached
- *         subsegment; the next subsegment round splits it)
  * vol[0]  total volume (FP64 sum of det/6)
+ * By the constrained Delaunay lemma, out[3] == 0 (with every subface a face
+ * of the mesh) means the mesh is a CDT of its subfaces and subsegments.
  * ---------------------------------------------------------------------- */
 int qmo_check(int nv, const double* xyz, int nt, const int* tets, int nsf, const int* sf,
               int nss, const int* ss, const int* ss_seg, double B, int* out, double* vol) {
-    memset(out, 0, sizeof(int) * 10);
-    HMap fm, sfm, em, ssm;
-    hm_init(&ssm, (size_t)nss * 4 + 64);
-    for (int i = 0; i < nss; ++i) { int k[4]; key2(k, ss[2 * i], ss[2 * i + 1]); hm_put(&ssm, k); }
+    memset(out, 0, sizeof(int) * 9);
+    HMap fm, sfm, em;
     hm_init(&fm, (size_t)nt * 6); hm_init(&sfm, (size_t)nsf * 4 + 64); hm_init(&em, (size_t)nt * 8);
     const double (*V)[3] = (const double(*)[3])xyz;
     double vsum = 0;
@@ -1021,21 +1097,7 @@ int qmo_check(int nv, const double* xyz, int nt, const int* tets, int nsf, const
             int t = e->v[side] >> 2, o = e->v[1 - side] >> 2, of = e->v[1 - side] & 3;
             const int* v = &tets[4 * t];
             int apex = tets[4 * o + of];
-            if (qmo_insphere(V[v[0]], V[v[1]], V[v[2]], V[v[3]], V[apex]) > 0) {
-                out[3]++;
-                int ids[5] = {v[0], v[1], v[2], v[3], apex}, excused = 0;
-                const int* tt[2] = {&tets[4 * (e->v[0] >> 2)], &tets[4 * (e->v[1] >> 2)]};
-                for (int q = 0; q < 2 && !excused; ++q)
-                    for (int g = 0; g < 6 && !excused; ++g) {
-                        int a = tt[q][EDGE[g][0]], b = tt[q][EDGE[g][1]];
-                        int k2[4]; key2(k2, a, b);
-                        if (!hm_get(&ssm, k2)) continue;
-                        for (int r = 0; r < 5; ++r)
-                            if (ids[r] != a && ids[r] != b && qmo_segdot(V[a], V[b], V[ids[r]]) < 0) { excused = 1; break; }
-                    }
-                if (!excused) out[9]++;
-                break;
-            }
+            if (qmo_insphere(V[v[0]], V[v[1]], V[v[2]], V[v[3]], V[apex]) > 0) { out[3]++; break; }
         }
     }
     for (int i = 0; i < nsf; ++i) { int k[4]; key3(k, sf[3 * i], sf[3 * i + 1], sf[3 * i + 2]); if (!hm_get(&fm, k)) out[4]++; }
@@ -1057,7 +1119,7 @@ int qmo_check(int nv, const double* xyz, int nt, const int* tets, int nsf, const
         if (e->v[0] == 1) { int k[4] = {e->k[0], -1, -1, -1}; HE* q = hm_put(&ends, k); q->v[0] = q->v[0] < 0 ? 1 : q->v[0] + 1; }
     }
     for (size_t i = 0; i < ends.cap; ++i) if (ends.e[i].st == 1 && ends.e[i].v[0] != 2) out[8]++;
-    free(used); hm_free(&fm); hm_free(&sfm); hm_free(&em); hm_free(&ssm); hm_free(&deg); hm_free(&ends);
+    free(used); hm_free(&fm); hm_free(&sfm); hm_free(&em); hm_free(&deg); hm_free(&ends);
     *vol = vsum;
     return 0;
 }

@@ -31,10 +31,10 @@ QM_PROFILE_GROW = 8   # time only the small-tile grow launches (family grow_vali
 QM_VERBOSE = 4
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
                  "scans", "insert", "grow_overflow")
-ROUND_FIELDS = 16
+ROUND_FIELDS = 17
 ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
-               "ex_face", "ex_edge2d", "ex_manifold", "nv_after", "nt_after")
+               "ex_face", "ex_edge2d", "ex_manifold", "ex_delaunay", "nv_after", "nt_after")
 ERRORS = {-1: "QM_EINVAL", -2: "QM_ENONCONFORM", -3: "QM_ENOMEM", -4: "QM_EROUNDS",
           -5: "QM_EDEVICE", -6: "QM_EINTERNAL", -7: "QM_ECAPACITY", -8: "QM_EAGAIN"}
 

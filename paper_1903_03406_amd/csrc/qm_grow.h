@@ -685,6 +685,44 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         return;
     }
 
+    // ---- (g) the mesh stays a CDT (every round ends with one, Section 2):
+    // each new interior face (u, w, p) that is not a new subface lies between
+    // the new tets on the two boundary faces holding edge uw; it must be
+    // locally Delaunay, i.e. the partner face's third vertex is not strictly
+    // inside the circumsphere of (x, y, z, p), positively oriented by (d).
+    // The two new tets give the same sign, so each pair is tested once.
+    {
+        int ecap = 64;
+        while (ecap < 2 * (3 * nbf + nbe)) ecap <<= 1;
+        if (ecap > W.ehcap) ecap = W.ehcap;
+        for (int k = lane; k < 3 * nbf; k += 64) {
+            const int pr = CP[k];
+            const int i = k / 3, l = k % 3;
+            if (pr < 0 || (pr >> 2) < i) continue;
+            const int4 r = CF[i];
+            const int u = l == 0 ? r.y : r.x, w = l == 2 ? r.y : r.z;
+            bool sub = false;                    // uw is a 2D boundary edge: (u, w, p) is a subface
+            if (nbe > 0) {
+                if (W.ehcap) {
+                    const int sl = eget(W.EK, ecap, ekey(u, w));
+                    sub = sl >= 0 && (W.EV[sl].w & 0xFFFF) > 0;
+                } else {
+                    const int lo = u < w ? u : w, hi = u < w ? w : u;
+                    for (int j = 0; j < nbe && !sub; ++j) sub = W.be[j].x == lo && W.be[j].y == hi;
+                }
+            }
+            if (sub) continue;
+            const int apex = at4(CF[pr >> 2], pr & 3);
+            double A[3], B[3], Cc[3], Q[3];
+            xyz(M, r.x, A); xyz(M, r.y, B); xyz(M, r.z, Cc); xyz(M, apex, Q);
+            if (insphere(A, B, Cc, P, Q) > 0) fail(EX_DELAUNAY);
+        }
+        if (phase_end(S)) {
+            if (lane == 0) { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
+            return;
+        }
+    }
+
     ptick(S, BP, 6);
     // ---- accepted: claim set = region tets + tets across boundary faces
     int* cext = W.cx + CXW * W.maxbf;            // extra claims after the face records

@@ -12,7 +12,7 @@ QMD int final_status(const Cands& C, int i) { return C.st[i] != ST_PENDING ? C.s
 // their targets and exempted elements are marked (before insertion, so a
 // flagged element destroyed this round loses its flags with it and new
 // elements start clean); the round statistics [ncand, ok, rejected, exempt,
-// exempt by reason 1..8, unresolved] are counted per block in LDS; accepted
+// exempt by reason 1..9, unresolved] are counted per block in LDS; accepted
 // candidates enter the selection undecided (state 0), the others never do
 // (state 3).
 __global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pools PL, int* stats) {
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pool
                 int nb = M.TA[4 * (size_t)t + f];
                 if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (8 + (nb & 3)));
             } else atomicOr(&M.TI[e], TI_EXEMPT);
-        } else atomicAdd(&bs[12], 1);     // unresolved (internal error)
+        } else atomicAdd(&bs[13], 1);     // unresolved (internal error)
         C.state[i] = st == ST_OK ? 0 : 3;
     }
     __syncthreads();

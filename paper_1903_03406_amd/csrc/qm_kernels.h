@@ -28,7 +28,8 @@ enum { CLS_SS = 0, CLS_SF = 1, CLS_TET = 2, CLS_NONE = 3 };
 enum { ST_OK = 0, ST_REJECT = 1, ST_EXEMPT = 2, ST_PENDING = 3, ST_OVERFLOW = 4, ST_POOLFULL = 5,
        ST_TOOBIG = 6, ST_OVERFLOW2 = 7 };
 enum { EX_NONE = 0, EX_NONFINITE = 1, EX_WALK = 2, EX_ENC_EXEMPT = 3, EX_HMIN = 4,
-       EX_RFTET = 5, EX_FACE = 6, EX_EDGE2D = 7, EX_MANIFOLD = 8, EX_NREASON = 9 };
+       EX_RFTET = 5, EX_FACE = 6, EX_EDGE2D = 7, EX_MANIFOLD = 8, EX_DELAUNAY = 9,
+       EX_NREASON = 10 };
 enum { TI_ALIVE = 1u, TI_EXEMPT = 2u };
 enum { SS_QUEUED = 1u, SS_EXEMPT = 2u };
 constexpr int WALK_CAP = 1000000;

@@ -514,7 +514,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     auto patch_last_record = [&]() {
         if (R->rounds.empty()) return;
         E.dead = hc[14];
-        R->rounds[R->rounds.size() - QM_ROUND_FIELDS + 15] = E.M.nt - (int)E.dead;
+        R->rounds[R->rounds.size() - QM_ROUND_FIELDS + 16] = E.M.nt - (int)E.dead;
     };
     // global-memory tiles: scale 1 first; a region over them (cavities can
     // grow with the number of vertices a point sees, e.g. next to a dense
@@ -725,7 +725,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         }
         const int nkept = hc[11], newt = hc[12], newss = hc[13];
         const int* st = hc + 16;
-        if (st[12]) throw QmError(QM_EINTERNAL, "candidate left unresolved");
+        if (st[13]) throw QmError(QM_EINTERNAL, "candidate left unresolved");
         if (nkept > 0) {
             E.ensure_mesh(E.M.nv + nkept, E.M.nt + newt, E.M.nss + newss);
             k_kept_list<<<nblk(ncand), 256, 0, s>>>(E.C, E.sk.p, E.kept.p);
@@ -739,8 +739,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         if (ncl > 0) k_mis_release<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.owner.p);
         int rec[QM_ROUND_FIELDS] = {cls, st[0], st[1], st[2], st[3], nkept};
         for (int r = 1; r < EX_NREASON; ++r) rec[5 + r] = st[3 + r];
-        rec[14] = E.M.nv;
-        rec[15] = E.M.nt - (int)E.dead;   // completed at the next synchronisation
+        rec[15] = E.M.nv;
+        rec[16] = E.M.nt - (int)E.dead;   // completed at the next synchronisation
         R->rounds.insert(R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
         R->stats.inserted[cls] += nkept;
         if (verbose && std::chrono::steady_clock::now() - last_note > std::chrono::seconds(5)) {

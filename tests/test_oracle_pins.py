@@ -280,7 +280,7 @@ def test_config1_refinement_is_delaunay_and_conforming():
     a1 = oracle.facet_areas(r.xyz, r.sf, r.sf_facet)
     assert set(a0) == set(a1) and max(abs(a0[k] - a1[k]) for k in a0) < 1e-12
     # every remaining bad tet was exempted (the exemption counters bound them)
-    assert c["bad_tets"] <= int(r.rstats[:, 6:14].sum())
+    assert c["bad_tets"] <= int(r.rstats[:, 6:15].sum())
     # Steiner points on the hull stay exactly on their cube face
     hull = r.sf[r.sf_facet < 6]
     for f, axis_side in zip(hull, r.sf_facet[r.sf_facet < 6]):
@@ -309,6 +309,25 @@ def test_sequential_special_case_is_delaunay():
     assert struct_ok(c)
 
 
+@pytest.mark.parametrize("n,seed,B,spheres", [(120, 3, 1.5, (0.3,)), (250, 8, 1.5, (0.3,)),
+                                              (300, 4, 1.4, (0.2, 0.35))])
+def test_surface_refinement_is_cdt_after_every_round(n, seed, B, spheres):
+    """Section 2: the triangulation is a CDT at the end of every round.  With
+    every subface a face of the mesh, a CDT is exactly a mesh whose
+    non-subface faces are all locally Delaunay (constrained Delaunay lemma),
+    which qmo_check counts independently of the refinement code.  The inputs
+    have internal constraint surfaces, where a cavity can wrap around a
+    constraint edge."""
+    w = qi.uniform_cube(n, seed=seed, B=B, spheres=spheres)
+    r = oracle.refine(w, round_checks=True)
+    assert r.status == 0 and r.rounds > 50
+    rc = dict(zip(oracle.CHECK_FIELDS, r.round_checks.T))
+    for k in ("neg_orient", "face_overuse", "hull_not_subface", "nonlocal_delaunay", "sf_missing",
+              "ss_missing", "chain_broken"):
+        assert np.all(rc[k] == 0), (k, np.nonzero(rc[k])[0][:5])
+    assert np.all(rc["euler"] == 1)
+
+
 @pytest.mark.parametrize("n,seed", [(120, 7), (250, 8)])
 def test_surface_refinement_conforms(n, seed):
     w = qi.uniform_cube(n, seed=seed, B=1.5, spheres=(0.3,))
@@ -316,7 +335,7 @@ def test_surface_refinement_conforms(n, seed):
     r = oracle.refine(w)
     assert r.status == 0
     c = oracle.check(r.xyz, r.tets, r.sf, r.ss, r.ss_seg, w.B)
-    assert struct_ok(c)
+    assert struct_ok(c) and c["nonlocal_delaunay"] == 0
     a0 = oracle.facet_areas(w.xyz, w.ftri, w.ftri_facet)
     a1 = oracle.facet_areas(r.xyz, r.sf, r.sf_facet)
     assert set(a0) == set(a1)
