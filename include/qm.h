@@ -76,13 +76,17 @@ typedef struct qm_mesh {
                                 qm_stats.prof_ms and prof_launches; the rest stay 0) with HIP
                                 events on the call's stream; the kernels run as unprofiled.
                                 Ignored with QM_PROFILE */
+#define QM_TEST_ERROR_WORD 16u  /* tests only: raise this call's device error word at set-up, so
+                                   the call ends with QM_EINTERNAL (the word is per call: other
+                                   calls, concurrent or later, are not affected) */
 
 typedef struct qm_options {
     double B;                /* radius-edge bound (> 0) */
     double hmin_factor;      /* h_min = hmin_factor * shortest input edge (0.5 typical) */
     int32_t max_rounds;      /* round guard; QM_EROUNDS when reached */
     int32_t max_kept;        /* > 0: insert at most this many points per round */
-    uint32_t flags;          /* QM_INPUT_DEVICE | QM_PROFILE | QM_VERBOSE | QM_PROFILE_GROW */
+    uint32_t flags;          /* QM_INPUT_DEVICE | QM_PROFILE | QM_VERBOSE | QM_PROFILE_GROW |
+                                QM_TEST_ERROR_WORD */
 } qm_options;
 
 /* per-round record (17 int32): class (0 subsegment, 1 subface, 2 tet),

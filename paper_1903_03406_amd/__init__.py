@@ -29,6 +29,7 @@ QM_INPUT_DEVICE = 1
 QM_PROFILE = 2
 QM_PROFILE_GROW = 8   # time only the small-tile grow launches (family grow_validate)
 QM_VERBOSE = 4
+QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through its own error word
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
                  "scans", "insert", "grow_overflow")
 ROUND_FIELDS = 17
@@ -153,7 +154,8 @@ def _arr(a, dtype):
 
 
 def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None, hmin_factor=0.5,
-           max_rounds=100000, max_kept=0, stream=None, profile=False, verbose=False) -> RefineResult:
+           max_rounds=100000, max_kept=0, stream=None, profile=False, verbose=False,
+           extra_flags=0) -> RefineResult:
     """Refine a CDT.  Arrays are numpy (host) or torch CUDA tensors (device);
     ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle."""
     lib = _load()
@@ -187,7 +189,7 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
     mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
     opts = _Opts(float(B), float(hmin_factor), int(max_rounds), int(max_kept),
                  (QM_INPUT_DEVICE if dev else 0) | (_prof_flag(profile))
-                 | (QM_VERBOSE if verbose else 0))
+                 | (QM_VERBOSE if verbose else 0) | int(extra_flags))
     if stream is None:
         hs = None
     elif hasattr(stream, "cuda_stream"):
@@ -274,16 +276,18 @@ def _marshal(w, keep):
 
 
 def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, max_kept=0,
-                 profile=False) -> list:
+                 profile=False, extra_flags=None, return_codes=False) -> list:
     """Refine independent instances concurrently (qm_refine_batch): each
-    workload exposes the PLC and CDT arrays and B (host arrays)."""
+    workload exposes the PLC and CDT arrays and B (host arrays).  With
+    return_codes, returns (results, per-instance return codes) and raises
+    nothing for failed instances (their result is None)."""
     lib = _load()
     n = len(workloads)
     plcs, meshes, opts, keep = (_Plc * n)(), (_Mesh * n)(), (_Opts * n)(), []
     for i, w in enumerate(workloads):
         plcs[i], meshes[i] = _marshal(w, keep)
         opts[i] = _Opts(float(w.B), float(hmin_factor), int(max_rounds), int(max_kept),
-                        _prof_flag(profile))
+                        _prof_flag(profile) | (int(extra_flags[i]) if extra_flags else 0))
     outs = (ctypes.c_void_p * max(n, 1))()
     codes = (ctypes.c_int32 * max(n, 1))()
     lib.qm_refine_batch.restype = ctypes.c_int
@@ -297,6 +301,8 @@ def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, m
             results.append(_take_result(lib, ctypes.c_void_p(outs[i]), profile))
         else:
             results.append(None)
+    if return_codes:
+        return results, [int(codes[i]) for i in range(n)]
     if rc not in (0, -4):
         raise QmError(rc, lib.qm_last_error().decode())
     return results

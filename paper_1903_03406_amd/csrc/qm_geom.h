@@ -32,9 +32,9 @@ constexpr double kEps = 1.1102230246251565e-16;   // 2^-53
 constexpr double kLat = 9007199254740992.0;       // 2^53
 constexpr double kInvLat = 1.0 / 9007199254740992.0;
 
-// error flag raised by an exact path whose precondition fails (never
-// expected; reported by the host as an internal error)
-__device__ int g_geom_error;
+// Every exact path takes `err`, the calling refinement's own error word: a
+// broken precondition (never expected) sets a bit there, and the host reports
+// it as an internal error of that call only.
 
 // ------------------------------------------------------------ error-free ops
 QMD void two_sum(double a, double b, double& x, double& y) {
@@ -113,12 +113,12 @@ QMD void exp_copy(int n, const double* s, double* d) { for (int i = 0; i < n; ++
 // product of two expansions: sum over b's components of a scaled copy of a.
 // s must hold 2*an, acc and tmp the result bound.
 __device__ inline int exp_mul(int an, const double* a, int bn, const double* b, double* out, double* s,
-                              double* tmp, int cap) {
+                              double* tmp, int cap, int* err) {
     int n = 0;
     for (int j = 0; j < bn; ++j) {
         int sn = exp_scale(an, a, b[j], s);
         int m = exp_sum(n, out, sn, s, tmp);
-        if (m > cap) { atomicOr(&g_geom_error, 1); m = cap; }
+        if (m > cap) { atomicOr(err, 1); m = cap; }
         exp_copy(m, tmp, out);
         n = m;
     }
@@ -131,7 +131,7 @@ __device__ inline int exp_mul(int an, const double* a, int bn, const double* b, 
 // arbitrary finite coordinates: exact fallback in expansion arithmetic.
 
 // sign of det[b-a; c-a; d-a]
-QMN int orient3d_any_exact(const double* a, const double* b, const double* c, const double* d) {
+QMN int orient3d_any_exact(const double* a, const double* b, const double* c, const double* d, int* err) {
     double u[3][2], v[3][2], w[3][2];
     int un[3], vn[3], wn[3];
     for (int k = 0; k < 3; ++k) {
@@ -143,11 +143,11 @@ QMN int orient3d_any_exact(const double* a, const double* b, const double* c, co
     int an = 0;
     for (int k = 0; k < 3; ++k) {
         int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        int n1 = exp_mul(vn[k1], v[k1], wn[k2], w[k2], p1, s, tmp, 8);
-        int n2 = exp_mul(vn[k2], v[k2], wn[k1], w[k1], p2, s, tmp, 8);
+        int n1 = exp_mul(vn[k1], v[k1], wn[k2], w[k2], p1, s, tmp, 8, err);
+        int n2 = exp_mul(vn[k2], v[k2], wn[k1], w[k1], p2, s, tmp, 8, err);
         exp_neg(n2, p2);
         int mnn = exp_sum(n1, p1, n2, p2, mn);
-        int tn = exp_mul(mnn, mn, un[k], u[k], t, s, tmp, 64);
+        int tn = exp_mul(mnn, mn, un[k], u[k], t, s, tmp, 64, err);
         int m = exp_sum(an, acc, tn, t, tmp);
         exp_copy(m, tmp, acc);
         an = m;
@@ -169,24 +169,24 @@ QMD void orient3d_fp(const double* a, const double* b, const double* c, const do
 constexpr double kO3 = (7.0 + 56.0 * kEps) * kEps;
 constexpr double kO2 = (3.0 + 16.0 * kEps) * kEps;
 
-QMD int orient3d_any(const double* a, const double* b, const double* c, const double* d) {
+QMD int orient3d_any(const double* a, const double* b, const double* c, const double* d, int* err) {
     double det, per;
     orient3d_fp(a, b, c, d, det, per);
     double bound = kO3 * per;
     if (det > bound) return 1;
     if (-det > bound) return -1;
-    return orient3d_any_exact(a, b, c, d);
+    return orient3d_any_exact(a, b, c, d, err);
 }
 
 // 2D orientation after dropping coordinate `ax` (kept: ax+1, ax+2 mod 3)
-QMN int orient2d_any_exact(int ax, const double* a, const double* b, const double* c) {
+QMN int orient2d_any_exact(int ax, const double* a, const double* b, const double* c, int* err) {
     int i = (ax + 1) % 3, j = (ax + 2) % 3;
     double ux[2], uy[2], vx[2], vy[2];
     int uxn = exp_diff(b[i], a[i], ux), uyn = exp_diff(b[j], a[j], uy);
     int vxn = exp_diff(c[i], a[i], vx), vyn = exp_diff(c[j], a[j], vy);
     double p1[8], p2[8], s[4], tmp[16], out[16];
-    int n1 = exp_mul(uxn, ux, vyn, vy, p1, s, tmp, 8);
-    int n2 = exp_mul(uyn, uy, vxn, vx, p2, s, tmp, 8);
+    int n1 = exp_mul(uxn, ux, vyn, vy, p1, s, tmp, 8, err);
+    int n2 = exp_mul(uyn, uy, vxn, vx, p2, s, tmp, 8, err);
     exp_neg(n2, p2);
     int n = exp_sum(n1, p1, n2, p2, out);
     return exp_sign(n, out);
@@ -200,13 +200,13 @@ QMD void orient2d_fp(int ax, const double* a, const double* b, const double* c, 
     per = fabs(l) + fabs(r);
 }
 
-QMD int orient2d_any(int ax, const double* a, const double* b, const double* c) {
+QMD int orient2d_any(int ax, const double* a, const double* b, const double* c, int* err) {
     double det, per;
     orient2d_fp(ax, a, b, c, det, per);
     double bound = kO2 * per;
     if (det > bound) return 1;
     if (-det > bound) return -1;
-    return orient2d_any_exact(ax, a, b, c);
+    return orient2d_any_exact(ax, a, b, c, err);
 }
 
 // ------------------------------------------------------- lattice integers
@@ -224,9 +224,9 @@ template <int N> struct Z { uint32_t w[N]; };
 
 // k = x * 2^53 (exact for lattice points of the cube); off-lattice or
 // out-of-cube input is a broken precondition and raises the error flag
-QMD int64_t lat(double x) {
+QMD int64_t lat(double x, int* err) {
     double k = x * kLat;
-    if (!(k >= 0.0 && k <= kLat) || k != rint(k)) atomicOr(&g_geom_error, 256);
+    if (!(k >= 0.0 && k <= kLat) || k != rint(k)) atomicOr(err, 256);
     return (int64_t)k;
 }
 template <int N> QMD Z<N> zfrom(int64_t v) {
@@ -310,7 +310,7 @@ template <int N> QMD int zsign(const Z<N>& a) {
     return o != 0u ? 1 : 0;
 }
 // difference of two lattice coordinates as a 2-limb integer
-QMD Z<2> zd(double x, double y) { return zfrom<2>(lat(x) - lat(y)); }
+QMD Z<2> zd(double x, double y, int* err) { return zfrom<2>(lat(x, err) - lat(y, err)); }
 // p*s - q*r for 2-limb operands (|.| <= 2^53): 109 bits
 QMD Z<4> zdet2(const Z<2>& p, const Z<2>& q, const Z<2>& r, const Z<2>& s) {
     return zsub(zmul<4>(p, s), zmul<4>(q, r));
@@ -328,46 +328,46 @@ QMD Z<6> zdet3(const Z<2>* u, const Z<2>* v, const Z<2>* w) {
 
 // ------------------------------------- predicates on lattice points of the cube
 // orient3d: sign of det[b-a; c-a; d-a]
-QMN int orient3d_exact(const double* a, const double* b, const double* c, const double* d) {
+QMN int orient3d_exact(const double* a, const double* b, const double* c, const double* d, int* err) {
     Z<2> u[3], v[3], w[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { u[k] = zd(b[k], a[k]); v[k] = zd(c[k], a[k]); w[k] = zd(d[k], a[k]); }
+    for (int k = 0; k < 3; ++k) { u[k] = zd(b[k], a[k], err); v[k] = zd(c[k], a[k], err); w[k] = zd(d[k], a[k], err); }
     return zsign(zdet3(u, v, w));
 }
-QMD int orient3d(const double* a, const double* b, const double* c, const double* d) {
+QMD int orient3d(const double* a, const double* b, const double* c, const double* d, int* err) {
     double det, per;
     orient3d_fp(a, b, c, d, det, per);
     double bound = kO3 * per;
     if (det > bound) return 1;
     if (-det > bound) return -1;
-    return orient3d_exact(a, b, c, d);
+    return orient3d_exact(a, b, c, d, err);
 }
 
 // orient2d in the plane of the coordinates other than `ax`
-QMN int orient2d_exact(int ax, const double* a, const double* b, const double* c) {
+QMN int orient2d_exact(int ax, const double* a, const double* b, const double* c, int* err) {
     int i = (ax + 1) % 3, j = (ax + 2) % 3;
-    return zsign(zdet2(zd(b[i], a[i]), zd(b[j], a[j]), zd(c[i], a[i]), zd(c[j], a[j])));
+    return zsign(zdet2(zd(b[i], a[i], err), zd(b[j], a[j], err), zd(c[i], a[i], err), zd(c[j], a[j], err)));
 }
-QMD int orient2d(int ax, const double* a, const double* b, const double* c) {
+QMD int orient2d(int ax, const double* a, const double* b, const double* c, int* err) {
     double det, per;
     orient2d_fp(ax, a, b, c, det, per);
     double bound = kO2 * per;
     if (det > bound) return 1;
     if (-det > bound) return -1;
-    return orient2d_exact(ax, a, b, c);
+    return orient2d_exact(ax, a, b, c, err);
 }
 
 // insphere: > 0 iff e is strictly inside the circumsphere of positively
 // oriented abcd.  With rows r_i = (x_i - e, |x_i - e|^2) the value is
 // -det[r_a; r_b; r_c; r_d], expanded along the lifted column.
 QMN int insphere_exact(const double* a, const double* b, const double* c, const double* d,
-                       const double* e) {
+                       const double* e, int* err) {
     const double* r[4] = {a, b, c, d};
     Z<2> m[4][3];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) m[i][k] = zd(r[i][k], e[k]);
+        for (int k = 0; k < 3; ++k) m[i][k] = zd(r[i][k], e[k], err);
     Z<9> acc = zfrom<9>(0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -378,7 +378,7 @@ QMN int insphere_exact(const double* a, const double* b, const double* c, const 
     }
     return -zsign(acc);
 }
-QMD int insphere(const double* a, const double* b, const double* c, const double* d, const double* e) {
+QMD int insphere(const double* a, const double* b, const double* c, const double* d, const double* e, int* err) {
     const double* r[4] = {a, b, c, d};
     double m[4][4], pm[4][4];
 #pragma unroll
@@ -406,18 +406,18 @@ QMD int insphere(const double* a, const double* b, const double* c, const double
     double bound = (16.0 + 224.0 * kEps) * kEps * per;
     if (-det > bound) return 1;
     if (det > bound) return -1;
-    return insphere_exact(a, b, c, d, e);
+    return insphere_exact(a, b, c, d, e, err);
 }
 
 // segment encroachment: sign of (v-a).(v-b); negative iff v is strictly
 // inside the diametral ball of ab
-QMN int segdot_exact(const double* a, const double* b, const double* v) {
+QMN int segdot_exact(const double* a, const double* b, const double* v, int* err) {
     Z<2> x[3], y[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { x[k] = zd(v[k], a[k]); y[k] = zd(v[k], b[k]); }
+    for (int k = 0; k < 3; ++k) { x[k] = zd(v[k], a[k], err); y[k] = zd(v[k], b[k], err); }
     return zsign(zdot(x, y));
 }
-QMD int segdot(const double* a, const double* b, const double* v) {
+QMD int segdot(const double* a, const double* b, const double* v, int* err) {
     double val = 0.0, per = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -428,7 +428,7 @@ QMD int segdot(const double* a, const double* b, const double* v) {
     double bound = 8.0 * kEps * per;
     if (val > bound) return 1;
     if (-val > bound) return -1;
-    return segdot_exact(a, b, v);
+    return segdot_exact(a, b, v, err);
 }
 
 // face (equatorial ball) encroachment: sign of
@@ -436,10 +436,10 @@ QMD int segdot(const double* a, const double* b, const double* v) {
 // u = b-a, w = c-a, q = v-a, with |u x w|^2 = |u|^2|w|^2 - (u.w)^2;
 // F < 0 iff v is strictly inside the ball whose great circle is the
 // circumcircle of abc
-QMN int facedot_exact(const double* a, const double* b, const double* c, const double* v) {
+QMN int facedot_exact(const double* a, const double* b, const double* c, const double* v, int* err) {
     Z<2> u[3], w[3], q[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { u[k] = zd(b[k], a[k]); w[k] = zd(c[k], a[k]); q[k] = zd(v[k], a[k]); }
+    for (int k = 0; k < 3; ++k) { u[k] = zd(b[k], a[k], err); w[k] = zd(c[k], a[k], err); q[k] = zd(v[k], a[k], err); }
     const Z<4> uu = zdot(u, u), ww = zdot(w, w), uw = zdot(u, w);
     const Z<4> qu = zdot(q, u), qw = zdot(q, w), qq = zdot(q, q);
     Z<7> n2 = zsub(zmul<7>(uu, ww), zmul<7>(uw, uw));
@@ -448,7 +448,7 @@ QMN int facedot_exact(const double* a, const double* b, const double* c, const d
     F = zsub(F, zmul<11>(zmul<7>(qw, uu), zsub(ww, uw)));
     return zsign(F);
 }
-QMD int facedot(const double* a, const double* b, const double* c, const double* v) {
+QMD int facedot(const double* a, const double* b, const double* c, const double* v, int* err) {
     double u0 = b[0] - a[0], u1 = b[1] - a[1], u2 = b[2] - a[2];
     double w0 = c[0] - a[0], w1 = c[1] - a[1], w2 = c[2] - a[2];
     double q0 = v[0] - a[0], q1 = v[1] - a[1], q2 = v[2] - a[2];
@@ -463,7 +463,7 @@ QMD int facedot(const double* a, const double* b, const double* c, const double*
     double bound = 16.0 * kEps * per;
     if (val > bound) return 1;
     if (-val > bound) return -1;
-    return facedot_exact(a, b, c, v);
+    return facedot_exact(a, b, c, v, err);
 }
 
 

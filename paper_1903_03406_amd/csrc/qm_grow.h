@@ -332,7 +332,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 int nf = nh & 3;
                 double A[3], B[3], Cc[3];
                 xyz(M, at4(w, c_FI[nf][0]), A); xyz(M, at4(w, c_FI[nf][1]), B); xyz(M, at4(w, c_FI[nf][2]), Cc);
-                if (facedot(A, B, Cc, P) < 0) add_rf(nh);
+                if (facedot(A, B, Cc, P, M.err) < 0) add_rf(nh);
             }
             __syncthreads();
             head = end;
@@ -367,13 +367,13 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 if (nb < 0) continue;
                 if (M.TF[4 * (size_t)t + f] >= 0 && !in_rf(t, f)) continue;
                 int n = nb >> 2;
-                if (n >= M.nt) { atomicOr(&g_geom_error, 64); continue; }
+                if (n >= M.nt) { atomicOr(M.err, 64); continue; }
                 unsigned key = (unsigned)n + 1u;
                 if (hget(W.H, W.hcap, key) != 0u) continue;
                 int4 v = ld4(M.TV, n);
                 double A[3], B[3], Cc[3], D[3];
                 xyz(M, v.x, A); xyz(M, v.y, B); xyz(M, v.z, Cc); xyz(M, v.w, D);
-                bool inside = insphere(A, B, Cc, D, P) > 0;
+                bool inside = insphere(A, B, Cc, D, P, M.err) > 0;
                 unsigned os;
                 int r = hput(W.H, W.hcap, key, inside ? HS_IN : HS_OUT, &os);
                 if (r < 0) { S.over |= OV_HASH; continue; }
@@ -418,7 +418,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 if (s < 0) continue;
                 double A[3], B[3];
                 xyz(M, at4(v, c_EV[j][0]), A); xyz(M, at4(v, c_EV[j][1]), B);
-                if (segdot(A, B, P) < 0) {
+                if (segdot(A, B, P, M.err) < 0) {
                     int r = qput(W.QH, W.qhcap, ((unsigned long long)s << 1) + 1ull);
                     if (r == 1) { int idx = atomicAdd(&S.nq, 1); if (idx < W.maxq) W.q[idx] = make_int2(0, s); else S.over |= OV_Q; }
                     if (r < 0) S.over |= OV_Q;
@@ -428,7 +428,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 if (at4(tf, f) < 0) continue;
                 double A[3], B[3], Cc[3];
                 xyz(M, at4(v, c_FI[f][0]), A); xyz(M, at4(v, c_FI[f][1]), B); xyz(M, at4(v, c_FI[f][2]), Cc);
-                if (facedot(A, B, Cc, P) < 0) {
+                if (facedot(A, B, Cc, P, M.err) < 0) {
                     int ck = face_ckey(M, t, f);
                     int r = qput(W.QH, W.qhcap, ((unsigned long long)ck << 1) + 2ull);
                     if (r == 1) { int idx = atomicAdd(&S.nq, 1); if (idx < W.maxq) W.q[idx] = make_int2(1, ck); else S.over |= OV_Q; }
@@ -522,7 +522,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             const int x = at4(v, c_FI[f][0]), y = at4(v, c_FI[f][1]), z = at4(v, c_FI[f][2]);
             double A[3], B[3], Cc[3];
             xyz(M, x, A); xyz(M, y, B); xyz(M, z, Cc);
-            if (orient3d(A, B, Cc, P) <= 0) { fail(EX_FACE); continue; }
+            if (orient3d(A, B, Cc, P, M.err) <= 0) { fail(EX_FACE); continue; }
             int idx = atomicAdd(&S.nbf, 1);
             if (idx < W.maxbf) {
                 // stage the face record in the claim scratch (x, y, z, old tet<<2|face)
@@ -560,7 +560,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             int ax = M.FAX[F];
             double A[3], B[3], Z[3];
             xyz(M, x, A); xyz(M, y, B); xyz(M, z, Z);
-            int oz = orient2d(ax, A, B, Z), op = orient2d(ax, A, B, P);
+            int oz = orient2d(ax, A, B, Z, M.err), op = orient2d(ax, A, B, P, M.err);
             if (op == 0 || op != oz) { fail(EX_EDGE2D); continue; }
             int one = M.TA[4 * (size_t)t + f] < 0 ? 1 : 0;
             int idx = atomicAdd(&S.nbe, 1);
@@ -715,7 +715,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             const int apex = at4(CF[pr >> 2], pr & 3);
             double A[3], B[3], Cc[3], Q[3];
             xyz(M, r.x, A); xyz(M, r.y, B); xyz(M, r.z, Cc); xyz(M, apex, Q);
-            if (insphere(A, B, Cc, P, Q) > 0) fail(EX_DELAUNAY);
+            if (insphere(A, B, Cc, P, Q, M.err) > 0) fail(EX_DELAUNAY);
         }
         if (phase_end(S)) {
             if (lane == 0) { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }

@@ -40,6 +40,7 @@ struct Mesh {
     int* TV; int* TA; int* TF; int* TS; unsigned* TI;
     int2* SV; int* SSEG; unsigned* SFL; int* STET;
     const int* FAX;
+    int* err;             // this call's error word (broken preconditions, never expected)
     int nv, nt, nss;
     double B2, hmin2;
 };
@@ -104,11 +105,11 @@ QMD int edge_ss(const Mesh& M, int t, int4 v, int x, int y) {
 // returning true stops the walk.  Returns false if the ring was cut short.
 template <class F>
 __device__ bool ring(const Mesh& M, int t0, int a, int b, F&& visit) {
-    if (t0 < 0 || t0 >= M.nt) { atomicOr(&g_geom_error, 16); return false; }
+    if (t0 < 0 || t0 >= M.nt) { atomicOr(M.err, 16); return false; }
     int4 v0 = ld4(M.TV, t0);
     int o[2], k = 0;
     for (int i = 0; i < 4; ++i) { int x = at4(v0, i); if (x != a && x != b && k < 2) o[k++] = x; }
-    if (k != 2) { atomicOr(&g_geom_error, 16); return false; }   // t0 does not hold the edge
+    if (k != 2) { atomicOr(M.err, 16); return false; }   // t0 does not hold the edge
     if (visit(t0, o[0], o[1])) return true;
     bool closed = false;
     for (int dir = 0; dir < 2 && !closed; ++dir) {
@@ -116,11 +117,11 @@ __device__ bool ring(const Mesh& M, int t0, int a, int b, F&& visit) {
         for (int step = 0; step < RING_CAP; ++step) {
             int4 vt = ld4(M.TV, t);
             int lu = local_of(vt, u);
-            if (lu < 0) { atomicOr(&g_geom_error, 32); return false; }
+            if (lu < 0) { atomicOr(M.err, 32); return false; }
             int nb = M.TA[4 * (size_t)t + lu];
             if (nb < 0) break;                       // hull: go the other way
             int tn = nb >> 2;
-            if (tn >= M.nt) { atomicOr(&g_geom_error, 64); return false; }
+            if (tn >= M.nt) { atomicOr(M.err, 64); return false; }
             if (tn == t0) { closed = true; break; }
             int apex = M.TV[4 * (size_t)tn + (nb & 3)];
             if (visit(tn, w, apex)) return true;

@@ -427,24 +427,17 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     const int* d_ssg = (const int*)stage(in->ss_seg, sizeof(int) * (size_t)nss, b_ssg);
     const int* d_ft = (const int*)stage(plc->ftri, sizeof(int) * 3 * (size_t)nftri, b_ft);
     const int* d_ftf = (const int*)stage(plc->ftri_facet, sizeof(int) * (size_t)nftri, b_ftf);
-    // number of facets = 1 + max facet id over PLC triangles and subfaces
-    {
-        std::vector<int> h(std::max(nftri, nsf));
-        auto maxid = [&](const int* user, int n) {
-            if (n == 0) return -1;
-            if (dev) {
-                HIPCK(hipMemcpyAsync(h.data(), user, sizeof(int) * n, hipMemcpyDeviceToHost, s));
-                HIPCK(hipStreamSynchronize(s));
-            } else std::memcpy(h.data(), user, sizeof(int) * n);
-            return *std::max_element(h.begin(), h.begin() + n);
-        };
-        nfacet = std::max(maxid(plc->ftri_facet, nftri), maxid(in->sf_facet, nsf)) + 1;
-    }
     E.ctr.ensure(64, s, false, 0);
+    // number of facets = 1 + max facet id over PLC triangles and subfaces
+    if (nftri) k_count_ids<<<nblk(nftri), 256, 0, s>>>(nftri, d_ftf, E.ctr.p + 49);
+    if (nsf) k_count_ids<<<nblk(nsf), 256, 0, s>>>(nsf, d_sff, E.ctr.p + 49);
+    nfacet = read1(E.ctr.p + 49, s);
     E.ensure_mesh(nv, nt, std::max(nss, 1));
     E.FAX.ensure(std::max(nfacet, 1), s, false);
     E.bind();
     E.M.nv = nv; E.M.nt = nt; E.M.nss = nss;
+    E.M.err = E.ctr.p + 48;               // this call's error word of the exact paths
+    if (opt->flags & QM_TEST_ERROR_WORD) HIPCK(hipMemsetAsync(E.M.err, 1, 1, s));
     int* err = E.ctr.p + 13;
     auto T1 = std::chrono::steady_clock::now();
     hipEvent_t e0, e1, e2;
@@ -780,9 +773,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         }
     }
 
-    int gerr = 0;
-    HIPCK(hipMemcpyFromSymbolAsync(&gerr, HIP_SYMBOL(g_geom_error), sizeof(int), 0, hipMemcpyDeviceToHost, s));
-    HIPCK(hipStreamSynchronize(s));
+    const int gerr = read1(E.M.err, s);
     if (gerr) throw QmError(QM_EINTERNAL, "exact predicate precondition failed (code " + std::to_string(gerr) + ")");
     // ---- output
     {

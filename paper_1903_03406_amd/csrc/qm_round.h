@@ -25,9 +25,9 @@ __global__ void k_classify_ss(Mesh M, int* cand, int* cnt) {
         ring(M, M.STET[s], ab.x, ab.y, [&](int, int u, int w) {
             double V[3];
             xyz(M, u, V);
-            if (segdot(A, B, V) < 0) { enc = true; return true; }
+            if (segdot(A, B, V, M.err) < 0) { enc = true; return true; }
             xyz(M, w, V);
-            if (segdot(A, B, V) < 0) { enc = true; return true; }
+            if (segdot(A, B, V, M.err) < 0) { enc = true; return true; }
             return false;
         });
     }
@@ -57,8 +57,8 @@ __global__ void k_classify_sf(Mesh M, int* cand, int* cnt) {
             double A[3], B[3], C[3], V[3];
             xyz(M, at4(v, c_FI[f][0]), A); xyz(M, at4(v, c_FI[f][1]), B); xyz(M, at4(v, c_FI[f][2]), C);
             xyz(M, at4(v, f), V);
-            enc = facedot(A, B, C, V) < 0;
-            if (!enc && apex2 >= 0) { xyz(M, apex2, V); enc = facedot(A, B, C, V) < 0; }
+            enc = facedot(A, B, C, V, M.err) < 0;
+            if (!enc && apex2 >= 0) { xyz(M, apex2, V); enc = facedot(A, B, C, V, M.err) < 0; }
         }
         if (enc) cand[atomicAdd(ncand, 1)] = (t << 2) | f;
     }
@@ -180,7 +180,7 @@ __global__ void k_locate(Mesh M, int cls, Cands C) {
                 int f = ord[j];
                 double A[3], B[3], D[3];
                 xyz(M, at4(v, c_FI[f][0]), A); xyz(M, at4(v, c_FI[f][1]), B); xyz(M, at4(v, c_FI[f][2]), D);
-                if (orient3d_any(A, B, D, P) >= 0) continue;
+                if (orient3d_any(A, B, D, P, M.err) >= 0) continue;
                 if (M.TF[4 * (size_t)t + f] >= 0) {
                     bool ex = (M.TI[t] >> (8 + f)) & 1u;
                     C.qw[i] = make_int2(1, face_ckey(M, t, f));
@@ -212,8 +212,8 @@ __global__ void k_locate(Mesh M, int cls, Cands C) {
                 int x = E[j][0], y = E[j][1], z = E[j][2];
                 double Xx[3], Y[3], Z[3];
                 xyz(M, x, Xx); xyz(M, y, Y); xyz(M, z, Z);
-                int oz = orient2d_any(ax, Xx, Y, Z);
-                int op = orient2d_any(ax, Xx, Y, P);
+                int oz = orient2d_any(ax, Xx, Y, Z, M.err);
+                int op = orient2d_any(ax, Xx, Y, P, M.err);
                 if (op == 0 || op != -oz) continue;
                 int s = edge_ss(M, t, v, x, y);
                 if (s >= 0) {

@@ -30,7 +30,7 @@ __global__ void k_setup_tets(int nt, int nv, const int* tin, Mesh M, int* err) {
     } else {
         double A[3], B[3], Cc[3], D[3];
         xyz(M, v.x, A); xyz(M, v.y, B); xyz(M, v.z, Cc); xyz(M, v.w, D);
-        if (orient3d_any(A, B, Cc, D) <= 0) atomicOr(err, 2);
+        if (orient3d_any(A, B, Cc, D, M.err) <= 0) atomicOr(err, 2);
     }
     *reinterpret_cast<int4*>(M.TV + 4 * (size_t)t) = v;
     M.TI[t] = TI_ALIVE;
@@ -97,6 +97,11 @@ __global__ void k_mark_subsegs(int nss, int nv, const int* ss, const int* ssg, c
     M.SV[i] = make_int2(a, b); M.SSEG[i] = ssg[i]; M.SFL[i] = 0u;
 }
 // projection axis of each facet: the dominant normal component of the
+// 1 + the largest id of ids[0..n) into *out (atomic max; *out starts at 0)
+__global__ void k_count_ids(int n, const int* ids, int* out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(out, ids[i] + 1);
+}
 // facet's first PLC triangle (lowest index), ties to the lower axis
 __global__ void k_facet_first(int nftri, const int* ff, int nfacet, int* first, int* err) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -62,3 +62,19 @@ def test_batch_reports_failing_instance(instances):
     # the library is still usable afterwards
     g = qm.refine_batch([instances[4]], nstreams=1)[0]
     assert same(g, qm.refine_workload(instances[4]))
+
+
+def test_error_word_is_per_call(instances):
+    """A call whose device error word is raised (test flag) fails alone: the
+    next call in the process, and instances running beside it in a batch,
+    return QM_OK with their normal output."""
+    w = instances[0]
+    with pytest.raises(qm.QmError, match="EINTERNAL"):
+        qm.refine_workload(w, extra_flags=qm.QM_TEST_ERROR_WORD)
+    assert same(qm.refine_workload(w), oracle.refine(w))
+    trio = [instances[1], instances[2], instances[3]]
+    got, codes = qm.refine_batch(trio, nstreams=3, extra_flags=[0, qm.QM_TEST_ERROR_WORD, 0],
+                                 return_codes=True)
+    print(f"[batch] error word: codes={codes}", flush=True)
+    assert codes == [0, -6, 0] and got[1] is None
+    assert same(got[0], qm.refine_workload(trio[0])) and same(got[2], qm.refine_workload(trio[2]))
