@@ -174,6 +174,46 @@ int qm_result_round_profile(const qm_result* r, double* buf, int32_t cap);
 
 void qm_result_free(qm_result* r);
 
+/* ---- Without allocation ------------------------------------------------ */
+
+/* Bytes of the static device scratch array used by qm_refine_noalloc (per
+   device; held from the first call on that device until the process ends). */
+#define QM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* Output arrays of qm_refine_noalloc: device pointers on the current device,
+   owned by the caller, with their capacities in elements (rows).  The
+   library writes the output mesh into them and its sizes into nv..nss; on
+   QM_ECAPACITY the sizes reached are still written when known. */
+typedef struct qm_mesh_buf {
+    int32_t cap_v, cap_t, cap_sf, cap_ss;
+    double* xyz;             /* [cap_v][3] */
+    int32_t* tet;            /* [cap_t][4] */
+    int32_t* sf;             /* [cap_sf][3] */
+    int32_t* sf_facet;       /* [cap_sf] */
+    int32_t* ss;             /* [cap_ss][2] */
+    int32_t* ss_seg;         /* [cap_ss] */
+    int32_t nv, nt, nsf, nss;
+} qm_mesh_buf;
+
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   refinement as qm_refine, bit for bit, with no hipMalloc, hipFree, pinned
+   host allocation, event or qm_result.  Every working buffer is carved from
+   the library's static device array of QM_NOALLOC_SCRATCH_BYTES, so the
+   meshes it can refine are small (about 10^5 output tets; more rounds with
+   many candidates need more).  Inputs are device arrays (opt->flags must
+   include QM_INPUT_DEVICE; profiling flags are refused).  The output goes to
+   `out` (cap_v >= in->nv, cap_t >= in->nt, cap_ss >= in->nss required; tet
+   slots of removed tets count against cap_t + cap_t/8 + 256) and the
+   statistics to *stats; per-round records are not kept.  Returns
+   QM_ECAPACITY when the scratch array or an output array is too small.
+   Calls on one device share its scratch array; this library makes them take
+   turns (a mutex per device), so calls that overlap in time are serialised,
+   never mixed.  The array keeps the last call's contents, and every call
+   clears what it needs. */
+int qm_refine_noalloc(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream,
+                      qm_mesh_buf* out, qm_stats* stats);
+
 /* ---- Served form: refinement jobs (each one qm_refine, the round loop of
    paper, Section 2) arriving over time on one device -------------------- */
 

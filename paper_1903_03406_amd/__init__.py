@@ -36,6 +36,7 @@ ROUND_FIELDS = 17
 ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
                "ex_face", "ex_edge2d", "ex_manifold", "ex_delaunay", "nv_after", "nt_after")
+NOALLOC_SCRATCH_BYTES = 256 << 20   # QM_NOALLOC_SCRATCH_BYTES
 ERRORS = {-1: "QM_EINVAL", -2: "QM_ENONCONFORM", -3: "QM_ENOMEM", -4: "QM_EROUNDS",
           -5: "QM_EDEVICE", -6: "QM_EINTERNAL", -7: "QM_ECAPACITY", -8: "QM_EAGAIN"}
 
@@ -104,7 +105,7 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
+EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
            "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_poll", "qm_server_info",
            "qm_server_destroy")
@@ -253,6 +254,69 @@ def _take_result(lib, res, profile) -> RefineResult:
                              if profile else None), last)
     finally:
         lib.qm_result_free(res)
+
+
+class _MeshBuf(ctypes.Structure):
+    _fields_ = [("cap_v", ctypes.c_int32), ("cap_t", ctypes.c_int32), ("cap_sf", ctypes.c_int32),
+                ("cap_ss", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("tet", ctypes.c_void_p),
+                ("sf", ctypes.c_void_p), ("sf_facet", ctypes.c_void_p), ("ss", ctypes.c_void_p),
+                ("ss_seg", ctypes.c_void_p), ("nv", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("nsf", ctypes.c_int32), ("nss", ctypes.c_int32)]
+
+
+def refine_noalloc(w, out, *, hmin_factor=0.5, max_rounds=100000, max_kept=0, stream=None):
+    """qm_refine_noalloc: refine workload ``w`` (its arrays are copied to the
+    device here, by torch) into the caller's device tensors ``out`` (a dict:
+    xyz float64 [cap_v,3], tet int32 [cap_t,4], sf int32 [cap_sf,3], sf_facet
+    int32 [cap_sf], ss int32 [cap_ss,2], ss_seg int32 [cap_ss]).  The library
+    allocates nothing.  Returns (sizes dict nv/nt/nsf/nss, stats dict);
+    raises QmError on failure (sizes still in the error's ``sizes``)."""
+    import torch
+    lib = _load()
+    lib.qm_refine_noalloc.restype = ctypes.c_int
+    lib.qm_refine_noalloc.argtypes = [ctypes.POINTER(_Plc), ctypes.POINTER(_Mesh), ctypes.POINTER(_Opts),
+                                      ctypes.c_void_p, ctypes.POINTER(_MeshBuf), ctypes.POINTER(_Stats)]
+    keep = []
+
+    def d(a, dtype, cols):
+        t = torch.as_tensor(_arr(a, dtype).reshape(-1, cols) if cols > 1 else _arr(a, dtype).reshape(-1),
+                            device="cuda").contiguous()
+        keep.append(t)
+        return t.data_ptr(), t.shape[0]
+    pxyz, nv = d(w.xyz, np.float64, 3)
+    ptet, nt = d(w.tets, np.int32, 4)
+    psf, nsf = d(w.sf, np.int32, 3)
+    psff, _ = d(w.sf_facet, np.int32, 1)
+    pss, nss = d(w.ss, np.int32, 2)
+    pssg, _ = d(w.ss_seg, np.int32, 1)
+    pft, nft = d(w.ftri, np.int32, 3)
+    pftf, _ = d(w.ftri_facet, np.int32, 1)
+    pseg, nseg = d(w.seg if w.seg is not None else np.zeros((0, 2), np.int32), np.int32, 2)
+    plc = _Plc(nv, nseg, pseg, nft, pft, pftf)
+    mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
+    opts = _Opts(float(w.B), float(hmin_factor), int(max_rounds), int(max_kept), QM_INPUT_DEVICE)
+    buf = _MeshBuf(out["xyz"].shape[0], out["tet"].shape[0], out["sf"].shape[0], out["ss"].shape[0],
+                   out["xyz"].data_ptr(), out["tet"].data_ptr(), out["sf"].data_ptr(),
+                   out["sf_facet"].data_ptr(), out["ss"].data_ptr(), out["ss_seg"].data_ptr(), -1, -1, -1, -1)
+    st = _Stats()
+    if stream is None:
+        hs = torch.cuda.current_stream().cuda_stream
+    elif hasattr(stream, "cuda_stream"):
+        hs = stream.cuda_stream
+    else:
+        hs = int(stream)
+    torch.cuda.current_stream().synchronize()        # the input copies are complete
+    rc = lib.qm_refine_noalloc(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), hs,
+                               ctypes.byref(buf), ctypes.byref(st))
+    sizes = {"nv": buf.nv, "nt": buf.nt, "nsf": buf.nsf, "nss": buf.nss}
+    if rc not in (0, -4):
+        e = QmError(rc, lib.qm_last_error().decode())
+        e.sizes = sizes
+        raise e
+    stats = {"rounds": int(st.rounds), "status": int(st.status), "inserted": tuple(int(x) for x in st.inserted),
+             "candidates": int(st.candidates), "mis_passes": int(st.mis_passes), "nv_out": int(st.nv_out),
+             "nt_out": int(st.nt_out), "seconds_refine": float(st.seconds_refine)}
+    return sizes, stats
 
 
 def _marshal(w, keep):

@@ -17,6 +17,8 @@
 #include <vector>
 #include <thread>
 #include <atomic>
+#include <memory>
+#include <mutex>
 
 #include "qm.h"
 #include "qm_insert.h"
@@ -42,24 +44,46 @@ struct QmError : std::runtime_error {
 
 inline int nblk(long n, int b = 256) { return (int)std::max(1L, (n + b - 1) / b); }
 
-// growable device buffer (contents kept on growth when asked)
+// Bump allocator over one device region: the no-alloc entry point carves
+// every buffer of a call from the library's static scratch array.  `mark`
+// separates what lives for the whole call (mesh arrays, counters) from what
+// a round carves again (candidates, pools, tiles, sort scratch).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, top = 0, mark = 0, high = 0;
+    void* take(size_t bytes) {
+        const size_t off = (top + 255) & ~(size_t)255;
+        if (off + bytes > cap)
+            throw QmError(QM_ECAPACITY, "the no-alloc scratch (" + std::to_string(cap >> 20) +
+                                            " MiB) is too small for this refinement (" +
+                                            std::to_string((off + bytes) >> 20) + " MiB needed so far)");
+        top = off + bytes;
+        high = std::max(high, top);
+        return base + off;
+    }
+};
+
+// growable device buffer (contents kept on growth when asked); with an
+// arena it is carved from the arena and never freed
 template <class T>
 struct DBuf {
     T* p = nullptr;
     size_t cap = 0;
+    Arena* ar = nullptr;
     void ensure(size_t n, hipStream_t s, bool keep, int fill_byte = -1) {
         if (n <= cap) return;
-        size_t nc = std::max(n, cap + cap / 2 + 1024);
+        size_t nc = ar ? n : std::max(n, cap + cap / 2 + 1024);
         T* q = nullptr;
-        HIPCK(hipMallocAsync((void**)&q, nc * sizeof(T), s));
+        if (ar) q = (T*)ar->take(nc * sizeof(T));
+        else HIPCK(hipMallocAsync((void**)&q, nc * sizeof(T), s));
         if (fill_byte >= 0) HIPCK(hipMemsetAsync(q, fill_byte, nc * sizeof(T), s));
         if (keep && p && cap) HIPCK(hipMemcpyAsync(q, p, cap * sizeof(T), hipMemcpyDeviceToDevice, s));
-        if (p) HIPCK(hipFreeAsync(p, s));
+        if (p && !ar) HIPCK(hipFreeAsync(p, s));
         p = q;
         cap = nc;
     }
     void release(hipStream_t s) {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p && !ar) (void)hipFreeAsync(p, s);
         p = nullptr;
         cap = 0;
     }
@@ -268,6 +292,38 @@ struct Engine {
         ev_used = 0;
     }
 
+    // no-alloc mode: every buffer is carved from `ar`; the mesh arrays are
+    // sized once for the caller's output capacities
+    Arena* ar = nullptr;
+    size_t cap_v = 0, cap_t = 0, cap_s = 0;
+    template <class F>
+    void each_mesh_buf(F&& f) {
+        f(X); f(TV); f(TA); f(TF); f(TS); f(TI); f(SV); f(SSEG); f(STET); f(FAX); f(SFL); f(mark); f(owner);
+        f(ctr); f(pctr);
+    }
+    template <class F>
+    void each_round_buf(F&& f) {
+        for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
+                        &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
+                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &p_cl,
+                        &p_clc})
+            f(*b);
+        f(c_key0); f(skey); f(c_key); f(mis_drop); f(mis_lose); f(c_tup0); f(c_tup); f(c_p0); f(c_p); f(c_qw);
+        f(p_be); f(p_bfr); f(p_q); f(tmp); f(slab); f(eslab);
+    }
+    void attach(Arena* a) {
+        ar = a;
+        each_mesh_buf([&](auto& b) { b.ar = a; });
+        each_round_buf([&](auto& b) { b.ar = a; });
+    }
+    // no-alloc mode, start of a round (or of the output): the carvings of the
+    // previous round are given back
+    void arena_round() {
+        if (!ar) return;
+        ar->top = ar->mark;
+        each_round_buf([&](auto& b) { b.p = nullptr; b.cap = 0; });
+    }
+
     explicit Engine(hipStream_t st) : s(st) {}
     ~Engine() {
         DBuf<char>* bufs_c[] = {&tmp, &slab, &eslab};
@@ -292,6 +348,13 @@ struct Engine {
         M.SV = SV.p; M.SSEG = SSEG.p; M.SFL = SFL.p; M.STET = STET.p; M.FAX = FAX.p;
     }
     void ensure_mesh(int nv, int nt, int nss) {
+        if (ar) {
+            if ((size_t)nv > cap_v || (size_t)nt > cap_t || (size_t)std::max(nss, 1) > cap_s)
+                throw QmError(QM_ECAPACITY, "the output arrays are too small for the refined mesh (vertices " +
+                                                std::to_string(nv) + ", tet slots " + std::to_string(nt) +
+                                                ", subsegments " + std::to_string(nss) + ")");
+            nv = (int)cap_v; nt = (int)cap_t; nss = (int)cap_s;
+        }
         X.ensure(nv, s, true);
         TV.ensure(4 * (size_t)nt, s, true);
         TA.ensure(4 * (size_t)nt, s, true);
@@ -362,7 +425,7 @@ struct Engine {
         b.prof = nullptr;
         return b;
     }
-    void* scratch(size_t bytes) {
+    void* cub_tmp(size_t bytes) {
         tmp.ensure(bytes, s, false);
         return tmp.p;
     }
@@ -371,7 +434,7 @@ struct Engine {
         size_t bytes = 0;
         HIPCK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, kin, kout, vin, vout, n, 0,
                                                            (int)(8 * sizeof(K)), s));
-        void* t = scratch(bytes);
+        void* t = cub_tmp(bytes);
         HIPCK(hipcub::DeviceRadixSort::SortPairsDescending(t, bytes, kin, kout, vin, vout, n, 0,
                                                            (int)(8 * sizeof(K)), s));
     }
@@ -379,13 +442,13 @@ struct Engine {
     void sort_asc(const K* kin, K* kout, const V* vin, V* vout, int n) {
         size_t bytes = 0;
         HIPCK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, n, 0, (int)(8 * sizeof(K)), s));
-        void* t = scratch(bytes);
+        void* t = cub_tmp(bytes);
         HIPCK(hipcub::DeviceRadixSort::SortPairs(t, bytes, kin, kout, vin, vout, n, 0, (int)(8 * sizeof(K)), s));
     }
     void exscan(const int* in, int* out, int n) {
         size_t bytes = 0;
         HIPCK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n, s));
-        void* t = scratch(bytes);
+        void* t = cub_tmp(bytes);
         HIPCK(hipcub::DeviceScan::ExclusiveSum(t, bytes, in, out, n, s));
     }
 };
@@ -394,17 +457,39 @@ struct Engine {
 
 using namespace qm;
 
+// One refinement.  Normal form: buffers from the stream-ordered allocator,
+// result in *out (host arrays).  No-alloc form (ar != nullptr): every device
+// buffer is carved from the arena, inputs are device arrays, the output mesh
+// is written into the caller's device arrays `dout` and the statistics into
+// *dstats; no qm_result, pinned buffer or event is created.
 static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
-                      qm_result** out) {
+                      qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
+                      qm_stats* dstats = nullptr) {
     auto T0 = std::chrono::steady_clock::now();
-    if (!plc || !in || !opt || !out) throw QmError(QM_EINVAL, "null argument");
+    const bool noalloc = ar != nullptr;
+    if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
     if (!(opt->B > 0.0) || !(opt->hmin_factor >= 0.0) || opt->max_rounds < 0)
         throw QmError(QM_EINVAL, "B must be > 0, hmin_factor >= 0, max_rounds >= 0");
     if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
         throw QmError(QM_EINVAL, "bad counts");
     if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
+    if (noalloc) {
+        if (!dev) throw QmError(QM_EINVAL, "the no-alloc entry point takes device arrays (QM_INPUT_DEVICE)");
+        if (opt->flags & (QM_PROFILE | QM_PROFILE_GROW))
+            throw QmError(QM_EINVAL, "profiling flags are not available without allocation");
+        if (dout->cap_v < in->nv || dout->cap_t < in->nt || dout->cap_ss < in->nss || dout->cap_sf < 0 ||
+            !dout->xyz || !dout->tet || (dout->cap_sf > 0 && (!dout->sf || !dout->sf_facet)) ||
+            (dout->cap_ss > 0 && (!dout->ss || !dout->ss_seg)))
+            throw QmError(QM_EINVAL, "output arrays missing or smaller than the input mesh");
+    }
     Engine E(s);
+    if (noalloc) {
+        E.attach(ar);
+        E.cap_v = (size_t)dout->cap_v;
+        E.cap_t = (size_t)dout->cap_t + (size_t)dout->cap_t / 8 + 256;   // slots of removed tets included
+        E.cap_s = (size_t)std::max(dout->cap_ss, 1);
+    }
     E.prof = (opt->flags & QM_PROFILE) != 0;
     E.prof_grow = !E.prof && (opt->flags & QM_PROFILE_GROW) != 0;
     if (E.prof) { E.pctr.ensure(4 + GROW_PHASES, s, false, 0); }
@@ -418,7 +503,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         HIPCK(hipMemcpyAsync(buf.p, p, bytes, hipMemcpyHostToDevice, s));
         return buf.p;
     };
-    DBuf<char> b_xyz, b_tet, b_sf, b_sff, b_ss, b_ssg, b_ft, b_ftf;
+    DBuf<char> b_xyz, b_tet, b_sf, b_sff, b_ss, b_ssg, b_ft, b_ftf;   // (unused with device inputs)
     const double* d_xyz = (const double*)stage(in->xyz, sizeof(double) * 3 * nv, b_xyz);
     const int* d_tet = (const int*)stage(in->tet, sizeof(int) * 4 * (size_t)nt, b_tet);
     const int* d_sf = (const int*)stage(in->sf, sizeof(int) * 3 * (size_t)nsf, b_sf);
@@ -435,20 +520,24 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     E.ensure_mesh(nv, nt, std::max(nss, 1));
     E.FAX.ensure(std::max(nfacet, 1), s, false);
     E.bind();
+    if (noalloc) ar->mark = ar->top;      // what follows is carved again every round
     E.M.nv = nv; E.M.nt = nt; E.M.nss = nss;
     E.M.err = E.ctr.p + 48;               // this call's error word of the exact paths
     if (opt->flags & QM_TEST_ERROR_WORD) HIPCK(hipMemsetAsync(E.M.err, 1, 1, s));
     int* err = E.ctr.p + 13;
     auto T1 = std::chrono::steady_clock::now();
-    hipEvent_t e0, e1, e2;
-    HIPCK(hipEventCreate(&e0)); HIPCK(hipEventCreate(&e1)); HIPCK(hipEventCreate(&e2));
-    HIPCK(hipEventRecord(e0, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (!noalloc) {
+        HIPCK(hipEventCreate(&e0)); HIPCK(hipEventCreate(&e1)); HIPCK(hipEventCreate(&e2));
+        HIPCK(hipEventRecord(e0, s));
+    }
     // ---- device setup
     k_setup_verts<<<nblk(nv), 256, 0, s>>>(nv, d_xyz, E.X.p, err);
     k_setup_tets<<<nblk(nt), 256, 0, s>>>(nt, nv, d_tet, E.M, err);
     {
         DBuf<unsigned long long> k0, k1;
         DBuf<int> v0, v1;
+        k0.ar = k1.ar = ar; v0.ar = v1.ar = ar;
         size_t n4 = 4 * (size_t)nt, n6 = 6 * (size_t)nt;
         k0.ensure(n6, s, false); k1.ensure(n6, s, false); v0.ensure(n6, s, false); v1.ensure(n6, s, false);
         k_face_keys<<<nblk(n4), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
@@ -459,6 +548,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.sort_asc(k0.p, k1.p, v0.p, v1.p, (int)n6);
         if (nss) k_mark_subsegs<<<nblk(nss), 256, 0, s>>>(nss, nv, d_ss, d_ssg, k1.p, v1.p, (int)n6, E.M, err);
         DBuf<int> first;
+        first.ar = ar;
         first.ensure(std::max(nfacet, 1), s, false);
         k_fill<<<nblk(nfacet), 256, 0, s>>>(nfacet, first.p, 0x7fffffff);   // "no triangle yet"
         if (nftri) k_facet_first<<<nblk(nftri), 256, 0, s>>>(nftri, d_ftf, nfacet, first.p, err);
@@ -480,10 +570,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.M.hmin2 = (opt->hmin_factor * opt->hmin_factor) * l2;
         E.M.B2 = opt->B * opt->B;
     }
-    HIPCK(hipEventRecord(e1, s));
+    auto T1s = std::chrono::steady_clock::now();
+    if (!noalloc) HIPCK(hipEventRecord(e1, s));
     // ---- rounds
-    qm_result* R = new qm_result();
-    std::memset(&R->stats, 0, sizeof R->stats);
+    std::unique_ptr<qm_result> R(noalloc ? nullptr : new qm_result());
+    qm_stats ST;
+    std::memset(&ST, 0, sizeof ST);
     int* cnt_d = E.ctr.p + 8;
     int* tot_d = E.ctr.p + 11;
     int* dead_d = E.ctr.p + 14;
@@ -494,8 +586,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     int round = 0, status = 0, last_ncand = 0;
     // host copies of the counters live in pinned memory: the per-round
     // read-backs are then direct copies, not staged through a bounce buffer
-    PinnedInts pin(48 + 46);
-    int* const hc = pin.p;          // ctr[0..48), taken at each synchronisation
+    std::unique_ptr<PinnedInts> pin(noalloc ? nullptr : new PinnedInts(48 + 46));
+    int hloc[48 + 46];              // no-alloc form: pageable copies instead
+    int* const hbase = noalloc ? hloc : pin->p;
+    int* const hc = hbase;          // ctr[0..48), taken at each synchronisation
     auto sync_counters = [&]() {
         HIPCK(hipMemcpyAsync(hc, E.ctr.p, 48 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCK(hipStreamSynchronize(s));
@@ -505,7 +599,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     // the dead-slot count after a round's insertion is read at the next
     // synchronisation; it completes that round's record (tets after)
     auto patch_last_record = [&]() {
-        if (R->rounds.empty()) return;
+        if (!R || R->rounds.empty()) return;
         E.dead = hc[14];
         R->rounds[R->rounds.size() - QM_ROUND_FIELDS + 16] = E.M.nt - (int)E.dead;
     };
@@ -534,6 +628,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     for (;; ++round) {
         if (round >= opt->max_rounds) { status = 1; break; }
         E.cur_round = round;
+        E.arena_round();
         // step 1: classify, in the paper's order (a class is skipped on the
         // device when an earlier one has candidates); one synchronisation
         // candidates go straight to the first candidate array, sized for the
@@ -588,7 +683,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                                                                              pass == 0 ? E.BP : E.BPnoprof(),
                                                                              nullptr, 0, nullptr);
             E.pend(pass == 0 ? 3 : 8);
-            int* const cw = pin.p + 48;  // ctr[0..46) after a grow pass
+            int* const cw = hbase + 48;  // ctr[0..46) after a grow pass
             for (int attempt = 0;; ++attempt) {
                 if (attempt > 0 || pass > 0) {
                     HIPCK(hipMemsetAsync(olist_n, 0, 3 * sizeof(int), s));
@@ -619,7 +714,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 const BfPool BPr = E.BPnoprof();
                 E.pbegin();
                 if (nover > 0) {             // medium LDS tiles
-                    const int grid = std::min(nover, 1024);
+                    const int grid = std::min(nover, noalloc ? 64 : 1024);   // (a grid-stride loop: any grid)
                     E.eslab.ensure((size_t)grid * M_EHCAP * (sizeof(unsigned long long) + sizeof(int4)), s, false);
                     k_grow_lds<QM_TILES_MEDIUM><<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover,
                                                                     E.eslab.p);
@@ -629,6 +724,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                     const size_t slab_block = grow_slab_bytes(BT);
                     int grid = (int)std::min<size_t>({(size_t)nbig, 256,
                                                       std::max<size_t>(1, (2ull << 30) / slab_block)});
+                    if (noalloc) grid = std::min(grid, 2);
                     E.slab.ensure(slab_block * grid, s, false);
                     k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
                                                       slab_block);
@@ -734,23 +830,24 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         for (int r = 1; r < EX_NREASON; ++r) rec[5 + r] = st[3 + r];
         rec[15] = E.M.nv;
         rec[16] = E.M.nt - (int)E.dead;   // completed at the next synchronisation
-        R->rounds.insert(R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
-        R->stats.inserted[cls] += nkept;
+        if (R) R->rounds.insert(R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
+        ST.inserted[cls] += nkept;
         if (verbose && std::chrono::steady_clock::now() - last_note > std::chrono::seconds(5)) {
             last_note = std::chrono::steady_clock::now();
             fprintf(stderr, "qm: round %d class %d candidates %d inserted %d vertices %d\n", round, cls, ncand,
                     nkept, E.M.nv);
         }
         last_ncand = ncand;
-        R->stats.candidates += ncand;
-        R->stats.mis_passes += passes;
+        ST.candidates += ncand;
+        ST.mis_passes += passes;
     }
-    HIPCK(hipEventRecord(e2, s));
+    if (!noalloc) HIPCK(hipEventRecord(e2, s));
     sync_counters();
+    auto T2s = std::chrono::steady_clock::now();
     patch_last_record();
     // verdicts of the last round's candidates: the candidate arrays are only
     // rewritten by a round that has candidates, so they still hold that round
-    if (last_ncand > 0) {
+    if (last_ncand > 0 && !noalloc) {
         const int ncand = last_ncand;
         std::vector<int4> tup(ncand);
         std::vector<int> st0(ncand), gs(ncand), rs0(ncand), grs(ncand), stt(ncand), rn(ncand), bn(ncand);
@@ -775,10 +872,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
 
     const int gerr = read1(E.M.err, s);
     if (gerr) throw QmError(QM_EINTERNAL, "exact predicate precondition failed (code " + std::to_string(gerr) + ")");
-    // ---- output
+    // ---- output: live tets and subfaces compacted in slot order
     {
+        E.arena_round();
         int ntot = E.M.nt;
         DBuf<int> tf, ts, ff, fs;
+        tf.ar = ts.ar = ff.ar = fs.ar = ar;
         tf.ensure(ntot, s, false); ts.ensure(ntot, s, false);
         ff.ensure(4 * (size_t)ntot, s, false); fs.ensure(4 * (size_t)ntot, s, false);
         k_out_flags<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ff.p);
@@ -786,62 +885,87 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.exscan(ff.p, fs.p, 4 * ntot);
         int a = read1(ts.p + ntot - 1, s) + read1(tf.p + ntot - 1, s);
         int b = read1(fs.p + 4 * ntot - 1, s) + read1(ff.p + 4 * ntot - 1, s);
-        DBuf<int> ot, osf, osff;
-        DBuf<double> ox;
-        ot.ensure(4 * (size_t)std::max(a, 1), s, false);
-        osf.ensure(3 * (size_t)std::max(b, 1), s, false);
-        osff.ensure(std::max(b, 1), s, false);
-        ox.ensure(3 * (size_t)E.M.nv, s, false);
-        k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, ot.p);
-        k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, osf.p, osff.p);
-        k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, ox.p);
-        R->xyz.resize(3 * (size_t)E.M.nv);
-        R->tets.resize(4 * (size_t)a);
-        R->sf.resize(3 * (size_t)b);
-        R->sff.resize(b);
-        R->ss.resize(2 * (size_t)E.M.nss);
-        R->ssg.resize(E.M.nss);
-        HIPCK(hipMemcpyAsync(R->xyz.data(), ox.p, sizeof(double) * R->xyz.size(), hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(R->tets.data(), ot.p, sizeof(int) * R->tets.size(), hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(R->sf.data(), osf.p, sizeof(int) * R->sf.size(), hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(R->sff.data(), osff.p, sizeof(int) * R->sff.size(), hipMemcpyDeviceToHost, s));
-        if (E.M.nss) {
-            HIPCK(hipMemcpyAsync(R->ss.data(), E.SV.p, sizeof(int) * R->ss.size(), hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(R->ssg.data(), E.SSEG.p, sizeof(int) * R->ssg.size(), hipMemcpyDeviceToHost, s));
+        if (noalloc) {
+            dout->nv = E.M.nv; dout->nt = a; dout->nsf = b; dout->nss = E.M.nss;
+            if (E.M.nv > dout->cap_v || a > dout->cap_t || b > dout->cap_sf || E.M.nss > dout->cap_ss)
+                throw QmError(QM_ECAPACITY, "the output arrays are too small (vertices " + std::to_string(E.M.nv) +
+                                                ", tets " + std::to_string(a) + ", subfaces " + std::to_string(b) +
+                                                ", subsegments " + std::to_string(E.M.nss) + ")");
+            k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, dout->tet);
+            if (b) k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, dout->sf, dout->sf_facet);
+            k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, dout->xyz);
+            if (E.M.nss) {
+                HIPCK(hipMemcpyAsync(dout->ss, E.SV.p, sizeof(int) * 2 * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+                HIPCK(hipMemcpyAsync(dout->ss_seg, E.SSEG.p, sizeof(int) * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+            }
+            HIPCK(hipStreamSynchronize(s));
+        } else {
+            DBuf<int> ot, osf, osff;
+            DBuf<double> ox;
+            ot.ensure(4 * (size_t)std::max(a, 1), s, false);
+            osf.ensure(3 * (size_t)std::max(b, 1), s, false);
+            osff.ensure(std::max(b, 1), s, false);
+            ox.ensure(3 * (size_t)E.M.nv, s, false);
+            k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, ot.p);
+            k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, osf.p, osff.p);
+            k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, ox.p);
+            R->xyz.resize(3 * (size_t)E.M.nv);
+            R->tets.resize(4 * (size_t)a);
+            R->sf.resize(3 * (size_t)b);
+            R->sff.resize(b);
+            R->ss.resize(2 * (size_t)E.M.nss);
+            R->ssg.resize(E.M.nss);
+            HIPCK(hipMemcpyAsync(R->xyz.data(), ox.p, sizeof(double) * R->xyz.size(), hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(R->tets.data(), ot.p, sizeof(int) * R->tets.size(), hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(R->sf.data(), osf.p, sizeof(int) * R->sf.size(), hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(R->sff.data(), osff.p, sizeof(int) * R->sff.size(), hipMemcpyDeviceToHost, s));
+            if (E.M.nss) {
+                HIPCK(hipMemcpyAsync(R->ss.data(), E.SV.p, sizeof(int) * R->ss.size(), hipMemcpyDeviceToHost, s));
+                HIPCK(hipMemcpyAsync(R->ssg.data(), E.SSEG.p, sizeof(int) * R->ssg.size(), hipMemcpyDeviceToHost, s));
+            }
+            HIPCK(hipStreamSynchronize(s));
+            ot.release(s); osf.release(s); osff.release(s); ox.release(s);
         }
-        HIPCK(hipStreamSynchronize(s));
-        tf.release(s); ts.release(s); ff.release(s); fs.release(s); ot.release(s); osf.release(s);
-        osff.release(s); ox.release(s);
-        R->stats.nt_out = a;
+        tf.release(s); ts.release(s); ff.release(s); fs.release(s);
+        ST.nt_out = a;
     }
     float ms_setup = 0, ms_ref = 0;
-    HIPCK(hipEventElapsedTime(&ms_setup, e0, e1));
-    HIPCK(hipEventElapsedTime(&ms_ref, e1, e2));
-    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
+    if (noalloc) {            // host clock: the call's stream was synchronised at both points
+        ms_setup = (float)std::chrono::duration<double, std::milli>(T1s - T0).count();
+        ms_ref = (float)std::chrono::duration<double, std::milli>(T2s - T1s).count();
+    } else {
+        HIPCK(hipEventElapsedTime(&ms_setup, e0, e1));
+        HIPCK(hipEventElapsedTime(&ms_ref, e1, e2));
+        (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
+    }
     if (E.prof_grow) {             // the stream is synchronised: every pair is complete
         E.pflush();
-        R->stats.prof_ms[3] = E.prof_ms[3];
-        R->stats.prof_launches[3] = E.prof_n[3];
+        ST.prof_ms[3] = E.prof_ms[3];
+        ST.prof_launches[3] = E.prof_n[3];
     }
     if (E.prof) {
-        for (int i = 0; i < QM_PROF_FAMILIES; ++i) { R->stats.prof_ms[i] = E.prof_ms[i]; R->stats.prof_launches[i] = E.prof_n[i]; }
+        for (int i = 0; i < QM_PROF_FAMILIES; ++i) { ST.prof_ms[i] = E.prof_ms[i]; ST.prof_launches[i] = E.prof_n[i]; }
         unsigned long long pc[4 + GROW_PHASES];
         HIPCK(hipMemcpy(pc, E.pctr.p, sizeof pc, hipMemcpyDeviceToHost));
-        for (int i = 0; i < GROW_PHASES; ++i) R->stats.prof_grow_cycles[i] = (int64_t)pc[4 + i];
-        R->stats.prof_tested = (int64_t)pc[0]; R->stats.prof_region = (int64_t)pc[1];
-        R->stats.prof_bfaces = (int64_t)pc[2]; R->stats.prof_claims = (int64_t)pc[3];
-        R->stats.prof_scan_tets = scan_tets; R->stats.prof_scan_verts = scan_verts;
-        R->stats.prof_overflow = E.prof_over;
-        R->stats.prof_poolfull = E.prof_full;
+        for (int i = 0; i < GROW_PHASES; ++i) ST.prof_grow_cycles[i] = (int64_t)pc[4 + i];
+        ST.prof_tested = (int64_t)pc[0]; ST.prof_region = (int64_t)pc[1];
+        ST.prof_bfaces = (int64_t)pc[2]; ST.prof_claims = (int64_t)pc[3];
+        ST.prof_scan_tets = scan_tets; ST.prof_scan_verts = scan_verts;
+        ST.prof_overflow = E.prof_over;
+        ST.prof_poolfull = E.prof_full;
     }
-    R->stats.rounds = round;
-    R->stats.status = status;
-    R->stats.nv_out = E.M.nv;
-    R->stats.seconds_setup = ms_setup * 1e-3;
-    R->stats.seconds_refine = ms_ref * 1e-3;
-    R->stats.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - T0).count();
+    ST.rounds = round;
+    ST.status = status;
+    ST.nv_out = E.M.nv;
+    ST.seconds_setup = ms_setup * 1e-3;
+    ST.seconds_refine = ms_ref * 1e-3;
+    ST.seconds_total = std::chrono::duration<double>(std::chrono::steady_clock::now() - T0).count();
     (void)T1;
-    *out = R;
+    if (noalloc) *dstats = ST;
+    else {
+        R->stats = ST;
+        *out = R.release();
+    }
     return status == 1 ? QM_EROUNDS : QM_OK;
 }
 
@@ -851,6 +975,54 @@ int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void*
     g_err.clear();
     try {
         return run_refine(plc, in, opt, (hipStream_t)hip_stream, out);
+    } catch (const QmError& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return QM_EINTERNAL;
+    } catch (...) {
+        g_err = "unknown failure";
+        return QM_EINTERNAL;
+    }
+}
+
+}  // extern "C"
+
+// ---- scratch of the no-alloc entry point: one array per device (each
+// device that runs the entry point holds its own copy until the process
+// ends).  Host code never names it as an address: its device address is
+// taken once per device with hipGetSymbolAddress and kept below.
+static __device__ __align__(256) char scratch[QM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_rc[kMaxDevices];
+std::mutex g_scratch_mu[kMaxDevices];   // calls on one device take turns
+}  // namespace
+
+extern "C" {
+
+int qm_refine_noalloc(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream,
+                      qm_mesh_buf* out, qm_stats* stats) {
+    g_err.clear();
+    try {
+        int dev = -1;
+        HIPCK(hipGetDevice(&dev));
+        if (dev < 0 || dev >= kMaxDevices) throw QmError(QM_EDEVICE, "device index out of range");
+        std::call_once(g_scratch_once[dev], [dev] {   // the current device is `dev`
+            g_scratch_rc[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+        });
+        if (g_scratch_rc[dev] != hipSuccess || !g_scratch_ptr[dev])
+            throw QmError(QM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                          hipGetErrorString(g_scratch_rc[dev]));
+        std::lock_guard<std::mutex> lock(g_scratch_mu[dev]);
+        Arena A;
+        A.base = static_cast<char*>(g_scratch_ptr[dev]);
+        A.cap = QM_NOALLOC_SCRATCH_BYTES;
+        return run_refine(plc, in, opt, (hipStream_t)hip_stream, nullptr, &A, out, stats);
     } catch (const QmError& e) {
         g_err = e.what();
         return e.code;
