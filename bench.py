@@ -11,11 +11,10 @@ Prints one JSON line:
                device time against the 8 TB/s HBM peak
   cpu_baseline the oracle timed on a bounded sample of the same workload
 
-Default workload: corners + 50 000 uniform points with one sphere surface
-(r = 0.3), B = 1.5.  The 1M-point workload (--workload cfg3: 900 000 points
-from 8 Gaussians + 100 000 uniform, three nested sphere surfaces, B = 1.4)
-is not run by default: its largest cavities need the enlarged global tiles,
-a path that is switched off until a GPU fault there is understood.
+Default workload: the 1M-point PLC (cube corners + 900 000 points from 8
+isotropic Gaussians + 100 000 uniform points, three nested sphere surfaces
+r = 0.15 / 0.30 / 0.45, B = 1.4).  --workload cfg2 runs the 50K-point one
+(one sphere surface, B = 1.5), cfg1 the 1K-point cube (B = 2.0).
 """
 import argparse
 import json
@@ -209,11 +208,12 @@ def bench_serve(args, qm):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-quality", action="store_true", help="skip the output quality report")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single-instance line: the first N instances of the batched "
                          "workload (config 4), batched jobs/s against one-at-a-time jobs/s")
@@ -288,8 +288,11 @@ def main():
         kms = prof["ms"][fam]
     achieved = nbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     dominant = max(prof["ms"], key=lambda k: prof["ms"][k])
+    launches = max(prof["launches"][fam], 1)
+    npts = len(w.xyz) - 8
+    size = f"{npts // 1000000}M" if npts >= 1000000 else f"{npts // 1000}K"
     out = {
-        "metric": "Steiner pts/sec (1M-pt PLC refinement)",
+        "metric": f"Steiner pts/sec ({size}-pt PLC refinement)",
         "value": steiner / sec,
         "unit": "Steiner pts/s",
         "n_gpus": 1,
@@ -309,6 +312,7 @@ def main():
                    "rounds": r.rounds, "device_refine_s": r.seconds_refine, "device_setup_s": r.seconds_setup},
         "profile_ms": {k: round(v, 3) for k, v in prof["ms"].items()},   # the untimed detail step
         "overflow_candidates": prof.get("overflow", 0), "poolfull_candidates": prof.get("poolfull", 0),
+        "grow_tiers": prof.get("tiers"),
         "grow_phase_frac": (lambda c: {n: round(x / max(sum(c), 1), 4) for n, x in zip(
             ("setup_seeds", "facet_region", "tet_region", "encroach", "radius_rftets", "bfaces",
              "edges_closure", "claims_results"), c)})(prof.get("grow_cycles", [0] * 8)),
@@ -317,12 +321,16 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(w.name, prof["launches"][fam]) if fam == "grow_validate"
                                  else None),
-                     "launches": prof["launches"][fam], "kernel_ms": kms,
-                     "algorithmic_bytes": nbytes, "dominant_family": dominant},
+                     "unit_of_bytes": "per launch (traffic and algorithmic_bytes alike)",
+                     "launches": prof["launches"][fam], "kernel_ms_per_step": kms,
+                     "mean_launch_us": kms * 1e3 / launches,
+                     "algorithmic_bytes": nbytes / launches, "dominant_family": dominant},
     }
-    from paper_1903_03406_amd import quality
-    qin, qout = quality.report(w.xyz, w.tets, w.B), quality.report(r.xyz, r.tets, w.B)
-    out["quality"] = {"input": {k: v for k, v in qin.items() if k != "dihedral_hist"}, "output": qout}
+    if not args.no_quality:
+        from paper_1903_03406_amd import quality
+        print("[bench] quality report ...", file=sys.stderr, flush=True)
+        qin, qout = quality.report(w.xyz, w.tets, w.B), quality.report(r.xyz, r.tets, w.B)
+        out["quality"] = {"input": {k: v for k, v in qin.items() if k != "dihedral_hist"}, "output": qout}
     if args.dump_rounds:
         with open(args.dump_rounds, "w") as f:
             json.dump({"fields": list(qm.ROUND_NAMES), "rounds": r.rstats.tolist(),

@@ -129,6 +129,14 @@ typedef struct qm_stats {
        5 boundary faces, 6 2D boundary edges and closure, 7 claims and
        results (phases a candidate leaves early are not counted) */
     int64_t prof_grow_cycles[8];
+    /* QM_PROFILE only: region evaluations by grow tier (0 small LDS tiles,
+       1 medium LDS tiles, 2 global-memory tiles), 16 counters each:
+       evaluations, evaluations that outgrew the tier's tiles, then over the
+       others: tets tested, region tets, boundary faces, and the largest
+       region, tested count and boundary-face count; then how often each
+       tile overflowed (region list, tested-tet hash, facet region, queue,
+       boundary faces, 2D boundary edges, claims, edge table) */
+    int64_t prof_tier[3][16];
 } qm_stats;
 
 typedef struct qm_result qm_result;

@@ -32,6 +32,9 @@ QM_VERBOSE = 4
 QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through its own error word
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
                  "scans", "insert", "grow_overflow")
+TIER_FIELDS = ("evals", "overflowed", "tested", "region", "bfaces", "max_region", "max_tested", "max_bfaces",
+               "ov_region", "ov_hash", "ov_facet_region", "ov_queue", "ov_bfaces", "ov_edges2d", "ov_claims",
+               "ov_edge_table")
 ROUND_FIELDS = 17
 ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
@@ -76,7 +79,8 @@ class _Stats(ctypes.Structure):
                 ("prof_region", ctypes.c_int64), ("prof_bfaces", ctypes.c_int64),
                 ("prof_claims", ctypes.c_int64), ("prof_scan_tets", ctypes.c_int64),
                 ("prof_scan_verts", ctypes.c_int64), ("prof_overflow", ctypes.c_int64),
-                ("prof_poolfull", ctypes.c_int64), ("prof_grow_cycles", ctypes.c_int64 * 8)]
+                ("prof_poolfull", ctypes.c_int64), ("prof_grow_cycles", ctypes.c_int64 * 8),
+                ("prof_tier", (ctypes.c_int64 * 16) * 3)]
 
 
 def _load():
@@ -250,6 +254,8 @@ def _take_result(lib, res, profile) -> RefineResult:
                               "scan_tets": int(st.prof_scan_tets), "scan_verts": int(st.prof_scan_verts),
                               "overflow": int(st.prof_overflow), "poolfull": int(st.prof_poolfull),
                               "grow_cycles": [int(x) for x in st.prof_grow_cycles],
+                              "tiers": [dict(zip(TIER_FIELDS, [int(x) for x in st.prof_tier[k]]))
+                                        for k in range(3)],
                               "round_ms": round_ms}
                              if profile else None), last)
     finally:

@@ -38,7 +38,11 @@ struct GrowTiles {
 //   r3 = (partner across edge yz, across xz, across xy, 0) as m<<2|slot, m the
 //        partner's index among the candidate's faces, -1 on the hull
 constexpr int BFR = 4;
-struct BfPool { int4* r; int cap; unsigned long long* prof; };   // prof: tested, region, bfaces, claims
+// prof: tested, region, bfaces, claims (first small-tile launch); tprof:
+// per-tier evaluation counters (every launch), TPROF_W words per tier
+struct BfPool { int4* r; int cap; unsigned long long* prof; unsigned long long* tprof; };
+constexpr int TPROF_W = 16;   // evals, overflowed, tested, region, bfaces, max region, max tested,
+                              // max bfaces, then the count of each overflow bit (8)
 
 // phases timed by ptick: 0 set-up and seeds, 1 R_F, 2 R_T, 3 encroachment,
 // 4 insertion radius and R_F tets, 5 boundary faces, 6 2D edges and closure,
@@ -55,6 +59,24 @@ struct GrowShared {
 QMD void prof_begin(GrowShared& S) {
     if (threadIdx.x == 0)
         for (int i = 0; i < 4 + GROW_PHASES; ++i) S.prof[i] = 0ull;
+}
+// profiling: one finished evaluation of tier `tier` (lane 0, after grow_one)
+QMD void tier_count(const GrowShared& S, const BfPool& BP, int tier) {
+    if (threadIdx.x != 0 || !BP.tprof) return;
+    unsigned long long* c = BP.tprof + TPROF_W * tier;
+    atomicAdd(&c[0], 1ull);
+    if (S.over) {
+        atomicAdd(&c[1], 1ull);
+        for (int b = 0; b < 8; ++b)
+            if (S.over & (1 << b)) atomicAdd(&c[8 + b], 1ull);
+        return;
+    }
+    atomicAdd(&c[2], (unsigned long long)S.hcount);
+    atomicAdd(&c[3], (unsigned long long)S.nrt);
+    atomicAdd(&c[4], (unsigned long long)S.nbf);
+    atomicMax(&c[5], (unsigned long long)S.nrt);
+    atomicMax(&c[6], (unsigned long long)S.hcount);
+    atomicMax(&c[7], (unsigned long long)S.nbf);
 }
 QMD void prof_flush(const GrowShared& S, const BfPool& BP) {
     if (threadIdx.x == 0 && BP.prof)
@@ -824,6 +846,7 @@ __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools
         }
         grow_one(M, cls, C, PL, BP, cid, W, S);
         __syncthreads();
+        tier_count(S, BP, TIER);
     }
     prof_flush(S, BP);
 }
@@ -852,6 +875,7 @@ __global__ __launch_bounds__(64) void k_grow_global(Mesh M, int cls, Cands C, Po
     for (int i = blockIdx.x; i < nlist; i += gridDim.x) {
         grow_one(M, cls, C, PL, BP, list[i], W, S);
         __syncthreads();
+        tier_count(S, BP, 2);
     }
     prof_flush(S, BP);
 }

@@ -401,6 +401,7 @@ struct Engine {
         PL.be = p_be.p; PL.cl = p_cl.p; PL.clc = p_clc.p; PL.q = p_q.p;
         PL.cap_be = (int)p_be.cap; PL.cap_cl = (int)p_cl.cap; PL.cap_q = (int)p_q.cap; PL.ctr = ctr.p;
         BP.r = p_bfr.p; BP.cap = (int)(p_bfr.cap / BFR); BP.prof = prof ? pctr.p : nullptr;
+        BP.tprof = prof ? pctr.p + 4 + GROW_PHASES : nullptr;
         if (verbose && p_bfr.cap + p_be.cap + p_cl.cap + p_q.cap != before)
             fprintf(stderr, "qm: pools grown: faces %zu (%.2f GB of records), edges %zu, claims %zu, queue %zu "
                     "entries\n", p_bfr.cap / BFR, p_bfr.cap * sizeof(int4) / 1e9, p_be.cap, p_cl.cap, p_q.cap);
@@ -492,7 +493,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     }
     E.prof = (opt->flags & QM_PROFILE) != 0;
     E.prof_grow = !E.prof && (opt->flags & QM_PROFILE_GROW) != 0;
-    if (E.prof) { E.pctr.ensure(4 + GROW_PHASES, s, false, 0); }
+    if (E.prof) { E.pctr.ensure(4 + GROW_PHASES + 3 * TPROF_W, s, false, 0); }
     int64_t scan_tets = 0, scan_verts = 0;
     const int nv = in->nv, nt = in->nt, nsf = in->nsf, nss = in->nss, nftri = plc->nftri;
     int nfacet = 0;
@@ -945,9 +946,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     }
     if (E.prof) {
         for (int i = 0; i < QM_PROF_FAMILIES; ++i) { ST.prof_ms[i] = E.prof_ms[i]; ST.prof_launches[i] = E.prof_n[i]; }
-        unsigned long long pc[4 + GROW_PHASES];
+        unsigned long long pc[4 + GROW_PHASES + 3 * TPROF_W];
         HIPCK(hipMemcpy(pc, E.pctr.p, sizeof pc, hipMemcpyDeviceToHost));
         for (int i = 0; i < GROW_PHASES; ++i) ST.prof_grow_cycles[i] = (int64_t)pc[4 + i];
+        for (int i = 0; i < 3 * TPROF_W; ++i) ST.prof_tier[i / TPROF_W][i % TPROF_W] = (int64_t)pc[4 + GROW_PHASES + i];
         ST.prof_tested = (int64_t)pc[0]; ST.prof_region = (int64_t)pc[1];
         ST.prof_bfaces = (int64_t)pc[2]; ST.prof_claims = (int64_t)pc[3];
         ST.prof_scan_tets = scan_tets; ST.prof_scan_verts = scan_verts;

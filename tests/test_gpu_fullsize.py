@@ -51,11 +51,24 @@ def compare(g, gold, label):
         assert got[k] == gold[k], f"{label}: {k} differs"
 
 
+def assert_cdt(g, w, label):
+    """The output is a valid tetrahedralisation of the cube that conforms to
+    the PLC and is a CDT (every non-subface face locally Delaunay)."""
+    c = oracle.check(g.xyz, g.tets, g.sf, g.ss, g.ss_seg, w.B)
+    print(f"[fullsize] {label} check: {c}", flush=True)
+    for k in ("neg_orient", "face_overuse", "hull_not_subface", "nonlocal_delaunay", "sf_missing", "ss_missing",
+              "chain_broken"):
+        assert c[k] == 0, (k, c)
+    assert c["euler"] == 1 and abs(c["volume"] - 1.0) < 1e-9
+
+
 def test_config2_full_parity():
     gold = load("cfg2.json")
     w = qi.config(2)
     assert w.sha256() == gold["input_sha256"]
-    compare(qm.refine_workload(w), gold, "config2")
+    g = qm.refine_workload(w)
+    compare(g, gold, "config2")
+    assert_cdt(g, w, "config2")
 
 
 @pytest.fixture(scope="module")
@@ -63,30 +76,26 @@ def cfg3():
     return qi.config(3)
 
 
-@pytest.mark.parametrize("name", ["cfg3_rounds8.json", "cfg3_rounds1099.json"])
+@pytest.mark.parametrize("name", ["cfg3_rounds8.json", "cfg3_rounds1099.json", "cfg3_rounds1110.json"])
 def test_config3_first_rounds_parity(cfg3, name):
-    """The first 8 rounds, and every round before the first bad-tet round
-    (1099 subsegment and subface rounds, 386 539 Steiner points)."""
+    """The first 8 rounds, and the first 1099 and 1110 rounds: every round
+    before the first bad-tet round (930) and then 169 and 180 rounds of all
+    three classes."""
     gold = load(name)
     assert cfg3.sha256() == gold["input_sha256"]
     compare(qm.refine_workload(cfg3, max_rounds=gold["max_rounds"]), gold, f"config3 {gold['max_rounds']} rounds")
 
 
-@pytest.mark.skip(reason="the 1M-point refinement faulted the GPU in the round whose largest cavity "
-                         "outgrew the first global-memory tiles; the cause is not yet shown, so this case "
-                         "stays off the GPU")
 def test_config3_full_properties(cfg3):
-    """At full size: the refinement converges, conforms (every subface is a
-    face, every subsegment an edge, segment chains intact, facet areas kept),
-    is a valid tetrahedralisation of the cube (orientation, face use, Euler
+    """At full size: the refinement converges, is a CDT conforming to the PLC
+    (every subface is a face, every subsegment an edge, segment chains
+    intact, facet areas kept, every non-subface face locally Delaunay) and a
+    valid tetrahedralisation of the cube (orientation, face use, Euler
     characteristic, volume)."""
     g = qm.refine_workload(cfg3, verbose=True)
     print(f"[fullsize] config3: rounds={g.rounds} steiner={g.steiner} tets={len(g.tets)}", flush=True)
     assert g.status == 0
-    c = oracle.check(g.xyz, g.tets, g.sf, g.ss, g.ss_seg, cfg3.B)
-    for k in ("neg_orient", "face_overuse", "hull_not_subface", "sf_missing", "ss_missing", "chain_broken"):
-        assert c[k] == 0, (k, c)
-    assert c["euler"] == 1 and abs(c["volume"] - 1.0) < 1e-9
+    assert_cdt(g, cfg3, "config3")
     a0 = oracle.facet_areas(cfg3.xyz, cfg3.ftri, cfg3.ftri_facet)
     a1 = oracle.facet_areas(g.xyz, g.sf, g.sf_facet)
     assert set(a0) == set(a1)
