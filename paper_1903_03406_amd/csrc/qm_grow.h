@@ -1,6 +1,7 @@
 // qm_grow.h -- wavefront-cooperative Delaunay-region growth and validation.
 //
-// One 64-lane wavefront (one workgroup) evaluates one candidate at a time.
+// One workgroup (one 64-lane wavefront for the common small regions, four
+// for the larger tiers) evaluates one candidate at a time.
 // The region is grown breadth-first: each level's (tet, face) pairs are
 // spread over the lanes, every lane runs the exact insphere test for its
 // neighbour, and new region tets are appended to a work list.  A hash set in
@@ -226,18 +227,30 @@ QMD int eget(const unsigned long long* EK, int cap, unsigned long long key) {   
     }
     return -1;
 }
-// table size for n keys (power of two, at least 2n), cleared by all lanes
-QMD int eclear(const GrowTiles& W, int n) {
+// table size for n keys (power of two, at least 2n), cleared by all NT lanes
+template <int NT> QMD int eclear(const GrowTiles& W, int n) {
     int cap = 64;
     while (cap < 2 * n) cap <<= 1;
     if (cap > W.ehcap) cap = W.ehcap;
-    for (int i = threadIdx.x; i < cap; i += 64) { W.EK[i] = 0ull; W.EV[i] = make_int4(0, -1, -1, 0); }
+    for (int i = threadIdx.x; i < cap; i += NT) { W.EK[i] = 0ull; W.EV[i] = make_int4(0, -1, -1, 0); }
     return cap;
 }
 
 QMD double wave_min(double v) {
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
     return v;
+}
+// minimum over the NT lanes of the workgroup (every lane gets it)
+template <int NT> QMD double block_min(double v) {
+    v = wave_min(v);
+    if (NT == 64) return v;
+    __shared__ double part[NT / 64];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = part[0];
+    for (int i = 1; i < NT / 64; ++i) r = fmin(r, part[i]);
+    __syncthreads();
+    return r;
 }
 
 // the three vertices of subface (t,f) in ascending order, and edge e of it
@@ -252,9 +265,12 @@ QMD void sub_edge(int4 v, int f, int e, int& x, int& y, int& z) {
 
 // a region over the tiles: evaluate again with the next tier's tiles, or
 // (largest tiles) report which tile was too small in the counter word
-// PL.ctr[35]
-QMD void over_status(const Cands& C, const Pools& PL, const GrowTiles& W, int cid, int over,
-                     const GrowShared& S) {
+// PL.ctr[35].  A bad tet remembers the tier its region needed (bits 12-13 of
+// its info word: 1 medium, 3 global) so that its evaluations in later
+// rounds start there; the word is rewritten when the slot gets a new tet.
+QMD void over_status(const Mesh& M, int cls, const Cands& C, const Pools& PL, const GrowTiles& W, int cid,
+                     int over, const GrowShared& S) {
+    if (cls == CLS_TET && W.tier < 2) atomicOr(&M.TI[C.elem[cid]], (W.tier == 0 ? 1u : 3u) << TI_HINT_SHIFT);
     if (W.tier == 2) {
         C.gst[cid] = ST_TOOBIG;
         atomicOr(&PL.ctr[35], over);
@@ -268,7 +284,8 @@ QMD void over_status(const Cands& C, const Pools& PL, const GrowTiles& W, int ci
 QMD int poolfull_status(const GrowTiles&) { return ST_POOLFULL; }
 
 // Evaluate candidate `cid` (steps: seeds, grow R_F, grow R_T, validate,
-// write results).  All 64 lanes of the workgroup call this together.
+// write results).  All NT lanes of the workgroup call this together.
+template <int NT>
 __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL, const BfPool& BP,
                          int cid, GrowTiles W, GrowShared& S) {
     const int lane = threadIdx.x;
@@ -282,9 +299,9 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         S.nrt = S.nrf = S.nbf = S.nbe = S.nq = S.ncx = S.hcount = 0;
         S.over = S.fail = 0; S.reason = EX_NONE;
     }
-    for (int i = lane; i < W.hcap; i += 64) W.H[i] = 0u;
-    for (int i = lane; i < W.rfhcap; i += 64) W.RFH[i] = 0u;
-    for (int i = lane; i < W.qhcap; i += 64) W.QH[i] = 0ull;
+    for (int i = lane; i < W.hcap; i += NT) W.H[i] = 0u;
+    for (int i = lane; i < W.rfhcap; i += NT) W.RFH[i] = 0u;
+    for (int i = lane; i < W.qhcap; i += NT) W.QH[i] = 0ull;
     __syncthreads();
 
     auto add_rt = [&](int t) {
@@ -339,7 +356,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             __syncthreads();              // every lane has read the level bounds
             if (stop) break;
             int items = (end - head) * 3;
-            for (int k = lane; k < items; k += 64) {
+            for (int k = lane; k < items; k += NT) {
                 int h = W.rf[head + k / 3];
                 int t = h >> 2, f = h & 3;
                 int4 v = ld4(M.TV, t);
@@ -361,7 +378,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
         // tets on region subfaces are seeds too
         int nrf = S.nrf < W.maxrf ? S.nrf : W.maxrf;
-        for (int k = lane; k < nrf; k += 64) {
+        for (int k = lane; k < nrf; k += NT) {
             int h = W.rf[k];
             add_rt(h >> 2);
             int nb = M.TA[4 * (size_t)(h >> 2) + (h & 3)];
@@ -383,7 +400,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             __syncthreads();              // every lane has read the level bounds
             if (stop) break;
             int items = (end - head) * 4;
-            for (int k = lane; k < items; k += 64) {
+            for (int k = lane; k < items; k += NT) {
                 int t = W.rt[head + (k >> 2)], f = k & 3;
                 int nb = M.TA[4 * (size_t)t + f];
                 if (nb < 0) continue;
@@ -413,7 +430,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
     }
     if (over_rt) {                        // read before the last level barrier
-        if (lane == 0) over_status(C, PL, W, cid, S.over, S);
+        if (lane == 0) over_status(M, cls, C, PL, W, cid, S.over, S);
         return;
     }
     const int nrt = S.nrt, nrf = S.nrf;
@@ -427,7 +444,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     if (cls != CLS_SS) {
         // one region tet per lane: its six edge words and (tet points) four
         // face words are loaded together; most are not constraints
-        for (int k = lane; k < nrt; k += 64) {
+        for (int k = lane; k < nrt; k += NT) {
             const int t = W.rt[k];
             const int* ts = M.TS + 6 * (size_t)t;
             const int s6[6] = {ts[0], ts[1], ts[2], ts[3], ts[4], ts[5]};
@@ -463,7 +480,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         const int nq = S.nq;
         __syncthreads();                  // flags read before any lane goes on
         if (over_q) {
-            if (lane == 0) over_status(C, PL, W, cid, S.over, S);
+            if (lane == 0) over_status(M, cls, C, PL, W, cid, S.over, S);
             return;
         }
         if (nq > 0) {
@@ -471,7 +488,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             __shared__ int any_live;
             if (lane == 0) any_live = 0;
             __syncthreads();
-            for (int k = lane; k < S.nq; k += 64) {
+            for (int k = lane; k < S.nq; k += NT) {
                 int2 e = W.q[k];
                 bool ex = e.x == 0 ? (M.SFL[e.y] & SS_EXEMPT) != 0
                                    : ((M.TI[e.y >> 2] >> (8 + (e.y & 3))) & 1u) != 0;
@@ -489,7 +506,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             }
             __syncthreads();
             if (S.base_q >= 0)
-                for (int k = lane; k < S.nq; k += 64) PL.q[S.base_q + k] = W.q[k];
+                for (int k = lane; k < S.nq; k += NT) PL.q[S.base_q + k] = W.q[k];
             return;
         }
     }
@@ -498,7 +515,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     // ---- (b) insertion radius: nearest region vertex at least h_min away
     {
         double r2 = INFINITY;
-        for (int k = lane; k < nrt + nrf * 3; k += 64) {
+        for (int k = lane; k < nrt + nrf * 3; k += NT) {
             if (k < nrt) {                       // the four vertices of a region tet
                 const int4 v = ld4(M.TV, W.rt[k]);
                 double V0[3], V1[3], V2[3], V3[3];
@@ -511,7 +528,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                 r2 = fmin(r2, d2(V, P));
             }
         }
-        r2 = wave_min(r2);
+        r2 = block_min<NT>(r2);
         if (r2 < M.hmin2) {
             if (lane == 0) { C.gst[cid] = ST_EXEMPT; C.greason[cid] = EX_HMIN; }
             return;
@@ -519,7 +536,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
 
     // ---- (c) every tet on a region subface is a region tet
-    for (int k = lane; k < nrf; k += 64) {
+    for (int k = lane; k < nrf; k += NT) {
         int h = W.rf[k];
         int nb = M.TA[4 * (size_t)(h >> 2) + (h & 3)];
         if (!in_rt(h >> 2) || (nb >= 0 && !in_rt(nb >> 2))) fail(EX_RFTET);
@@ -532,7 +549,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     ptick(S, BP, 4);
     // ---- (d) boundary faces (not region subfaces; other side hull, outside
     // the region, or a constraint) must see p strictly on their inner side
-    for (int k = lane; k < nrt; k += 64) {      // one region tet per lane, its four faces
+    for (int k = lane; k < nrt; k += NT) {      // one region tet per lane, its four faces
         const int t = W.rt[k];
         const int4 tf = ld4(M.TF, t), ta = ld4(M.TA, t), v = ld4(M.TV, t);
         for (int f = 0; f < 4; ++f) {
@@ -554,7 +571,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     if (phase_end(S)) {
         if (lane == 0) {
-            if (S.over) over_status(C, PL, W, cid, S.over, S);
+            if (S.over) over_status(M, cls, C, PL, W, cid, S.over, S);
             else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
         }
         return;
@@ -565,7 +582,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     // ---- (e) 2D boundary edges of R_F must see p strictly inside, in the
     // facet's projection; the subsegment being split is excluded
     if (cls != CLS_TET) {
-        for (int k = lane; k < nrf * 3; k += 64) {
+        for (int k = lane; k < nrf * 3; k += NT) {
             int h = W.rf[k / 3];
             int t = h >> 2, f = h & 3;
             int4 v = ld4(M.TV, t);
@@ -590,7 +607,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
         if (phase_end(S)) {
             if (lane == 0) {
-                if (S.over) over_status(C, PL, W, cid, S.over, S);
+                if (S.over) over_status(M, cls, C, PL, W, cid, S.over, S);
                 else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
             }
             return;
@@ -598,34 +615,34 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         const int nbe = S.nbe;
         // one new subface per edge: no two 2D boundary edges alike
         if (W.ehcap) {
-            const int ecap = eclear(W, 3 * nbf + nbe);
+            const int ecap = eclear<NT>(W, 3 * nbf + nbe);
             __syncthreads();
-            for (int i = lane; i < nbe; i += 64) {
+            for (int i = lane; i < nbe; i += NT) {
                 int4 e = W.be[i];
                 int sl = eput(W.EK, ecap, ekey(e.x, e.y));
                 if (sl < 0) { S.over |= OV_EDGE; continue; }
                 atomicAdd(&W.EV[sl].w, 1 + (e.w ? 0x10000 : 0));
             }
             __syncthreads();
-            for (int i = lane; i < nbe; i += 64) {
+            for (int i = lane; i < nbe; i += NT) {
                 int4 e = W.be[i];
                 int sl = eget(W.EK, ecap, ekey(e.x, e.y));
                 if (sl >= 0 && (W.EV[sl].w & 0xFFFF) > 1) fail(EX_EDGE2D);
             }
         } else {
-            for (int i = lane; i < nbe; i += 64)
+            for (int i = lane; i < nbe; i += NT)
                 for (int j = i + 1; j < nbe; ++j)
                     if (W.be[i].x == W.be[j].x && W.be[i].y == W.be[j].y) fail(EX_EDGE2D);
         }
         if (phase_end(S)) {
             if (lane == 0) {
-                if (S.over) over_status(C, PL, W, cid, S.over, S);
+                if (S.over) over_status(M, cls, C, PL, W, cid, S.over, S);
                 else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
             }
             return;
         }
     } else if (W.ehcap) {
-        eclear(W, 3 * nbf);
+        eclear<NT>(W, 3 * nbf);
     }
     const int nbe = S.nbe;
 
@@ -639,7 +656,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         while (ecap < 2 * (3 * nbf + nbe)) ecap <<= 1;
         if (ecap > W.ehcap) ecap = W.ehcap;
         __syncthreads();                  // table cleared (and 2D boundary edges in)
-        for (int k = lane; k < 3 * nbf; k += 64) {
+        for (int k = lane; k < 3 * nbf; k += NT) {
             const int i = k / 3, l = k % 3;
             const int4 r = CF[i];
             int sl = eput(W.EK, ecap, ekey(l == 0 ? r.y : r.x, l == 2 ? r.y : r.z));
@@ -649,7 +666,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             if (atomicCAS(&W.EV[sl].y, -1, fe) != -1) atomicCAS(&W.EV[sl].z, -1, fe);
         }
         __syncthreads();
-        for (int k = lane; k < 3 * nbf + nbe; k += 64) {
+        for (int k = lane; k < 3 * nbf + nbe; k += NT) {
             unsigned long long key;
             if (k < 3 * nbf) {
                 const int4 r = CF[k / 3];
@@ -669,7 +686,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             }
         }
     } else {
-        for (int k = lane; k < 3 * nbf + nbe; k += 64) {
+        for (int k = lane; k < 3 * nbf + nbe; k += NT) {
             int u, w, i = -1, l = 0;
             if (k < 3 * nbf) {
                 i = k / 3; l = k % 3;
@@ -701,7 +718,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     }
     if (phase_end(S)) {
         if (lane == 0) {
-            if (S.over) over_status(C, PL, W, cid, S.over, S);
+            if (S.over) over_status(M, cls, C, PL, W, cid, S.over, S);
             else { C.gst[cid] = ST_EXEMPT; C.greason[cid] = S.reason; }
         }
         return;
@@ -717,7 +734,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         int ecap = 64;
         while (ecap < 2 * (3 * nbf + nbe)) ecap <<= 1;
         if (ecap > W.ehcap) ecap = W.ehcap;
-        for (int k = lane; k < 3 * nbf; k += 64) {
+        for (int k = lane; k < 3 * nbf; k += NT) {
             const int pr = CP[k];
             const int i = k / 3, l = k % 3;
             if (pr < 0 || (pr >> 2) < i) continue;
@@ -748,7 +765,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     ptick(S, BP, 6);
     // ---- accepted: claim set = region tets + tets across boundary faces
     int* cext = W.cx + CXW * W.maxbf;            // extra claims after the face records
-    for (int i = lane; i < nbf; i += 64) {
+    for (int i = lane; i < nbf; i += NT) {
         int h = CF[i].w;
         int nb = M.TA[4 * (size_t)(h >> 2) + (h & 3)];
         if (nb < 0) continue;
@@ -759,7 +776,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         } else if (r < 0) S.over |= OV_HASH;
     }
     if (phase_end(S)) {
-        if (lane == 0) over_status(C, PL, W, cid, S.over, S);
+        if (lane == 0) over_status(M, cls, C, PL, W, cid, S.over, S);
         return;
     }
     const int ncx = S.ncx;
@@ -787,14 +804,14 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     __syncthreads();
     if (S.base_reg < 0) {
         const int end = S.base_cl + nrt + ncx < PL.cap_cl ? S.base_cl + nrt + ncx : PL.cap_cl;
-        for (int k = S.base_cl + lane; k < end; k += 64) PL.clc[k] = -1;
+        for (int k = S.base_cl + lane; k < end; k += NT) PL.clc[k] = -1;
         return;
     }
     if (lane == 0) { S.prof[2] += nbf; S.prof[3] += nrt + ncx; }
-    for (int k = lane; k < nrt; k += 64) { PL.cl[S.base_cl + k] = W.rt[k]; PL.clc[S.base_cl + k] = cid; }
-    for (int k = lane; k < ncx; k += 64) { PL.cl[S.base_cl + nrt + k] = cext[k]; PL.clc[S.base_cl + nrt + k] = cid; }
-    for (int k = lane; k < nbe; k += 64) PL.be[S.base_be + k] = W.be[k];
-    for (int i = lane; i < nbf; i += 64) {
+    for (int k = lane; k < nrt; k += NT) { PL.cl[S.base_cl + k] = W.rt[k]; PL.clc[S.base_cl + k] = cid; }
+    for (int k = lane; k < ncx; k += NT) { PL.cl[S.base_cl + nrt + k] = cext[k]; PL.clc[S.base_cl + nrt + k] = cid; }
+    for (int k = lane; k < nbe; k += NT) PL.be[S.base_be + k] = W.be[k];
+    for (int i = lane; i < nbf; i += NT) {
         const int4 rc = CF[i];
         const int* pc = CP + 3 * i;
         int x = rc.x, y = rc.y, z = rc.z, h = rc.w;
@@ -813,10 +830,10 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
 
 // LDS tiles; TIER 1 (medium) also takes an edge table of EHCAP entries per
 // workgroup from the global slab `eslab` (EHCAP 0: pairwise scans)
-template <int TIER, int MAXRT, int HCAP, int RFHCAP, int MAXRF, int MAXBE, int QHCAP, int MAXQ, int MAXBF,
-          int EHCAP>
-__global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
-                                                 const int* list, int nlist, char* eslab) {
+template <int NT, int TIER, int MAXRT, int HCAP, int RFHCAP, int MAXRF, int MAXBE, int QHCAP, int MAXQ,
+          int MAXBF, int EHCAP>
+__global__ __launch_bounds__(NT) void k_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                                 const int* list, int nlist, char* eslab, int min_tier) {
     __shared__ int rt[MAXRT];
     __shared__ unsigned H[HCAP];
     __shared__ unsigned RFH[RFHCAP];
@@ -844,7 +861,18 @@ __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools
             if (threadIdx.x == 0) { C.gst[cid] = C.st[cid]; C.greason[cid] = C.reason[cid]; }
             continue;
         }
-        grow_one(M, cls, C, PL, BP, cid, W, S);
+        if (TIER == 0) {            // start at a larger tier: test option, or the tet's remembered tier
+            int start = min_tier;
+            if (cls == CLS_TET) {
+                const unsigned h = (M.TI[C.elem[cid]] >> TI_HINT_SHIFT) & 3u;
+                start = max(start, h == 3u ? 2 : (int)h);
+            }
+            if (start > 0) {
+                if (threadIdx.x == 0) C.gst[cid] = start == 1 ? ST_OVERFLOW : ST_OVERFLOW2;
+                continue;
+            }
+        }
+        grow_one<NT>(M, cls, C, PL, BP, cid, W, S);
         __syncthreads();
         tier_count(S, BP, TIER);
     }
@@ -853,7 +881,8 @@ __global__ __launch_bounds__(64) void k_grow_lds(Mesh M, int cls, Cands C, Pools
 
 // re-run of the candidates that overflowed the LDS tiles (or a pool), with
 // tiles carved from a global scratch slab; `list` holds their ids
-__global__ __launch_bounds__(64) void k_grow_global(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_grow_global(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
                                                     const int* list, int nlist, GrowTiles T, char* slab,
                                                     size_t slab_per_block) {
     __shared__ GrowShared S;
@@ -873,7 +902,7 @@ __global__ __launch_bounds__(64) void k_grow_global(Mesh M, int cls, Cands C, Po
     W.EV = (int4*)carve(sizeof(int4) * T.ehcap);
     prof_begin(S);
     for (int i = blockIdx.x; i < nlist; i += gridDim.x) {
-        grow_one(M, cls, C, PL, BP, list[i], W, S);
+        grow_one<NT>(M, cls, C, PL, BP, list[i], W, S);
         __syncthreads();
         tier_count(S, BP, 2);
     }

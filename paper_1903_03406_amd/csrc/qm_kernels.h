@@ -14,7 +14,7 @@
 //                       of an interior subface carry it)
 //   TS  int[6*nt]       subsegment slot of each tet edge, else -1
 //   TI  uint[nt]        bit0 alive, bit1 exempt, bits 4+f face queued,
-//                       bits 8+f face exempt
+//                       bits 8+f face exempt, bits 12-13 grow-tier hint
 //   SV  int2[nss]       subsegment endpoints (ascending); SSEG segment id;
 //   SFL uint[nss]       bit0 queued, bit1 exempt; STET a tet holding the edge
 // Every decision is a function of vertex ids and coordinates only; slots and
@@ -31,6 +31,7 @@ enum { EX_NONE = 0, EX_NONFINITE = 1, EX_WALK = 2, EX_ENC_EXEMPT = 3, EX_HMIN = 
        EX_RFTET = 5, EX_FACE = 6, EX_EDGE2D = 7, EX_MANIFOLD = 8, EX_DELAUNAY = 9,
        EX_NREASON = 10 };
 enum { TI_ALIVE = 1u, TI_EXEMPT = 2u };
+constexpr int TI_HINT_SHIFT = 12;   // bits 12-13: grow tier a bad tet's region needed (1 medium, 3 global)
 enum { SS_QUEUED = 1u, SS_EXEMPT = 2u };
 constexpr int WALK_CAP = 1000000;
 constexpr int RING_CAP = 4096;

@@ -191,12 +191,13 @@ __global__ void k_round_reset_pools(int* ctr) {
 // (about 12 KB: 12 workgroups per CU, the register limit of this kernel)
 constexpr int G_MAXRT = 192, G_HCAP = 512, G_RFHCAP = 128, G_MAXRF = 48, G_MAXBE = 64, G_QHCAP = 128,
               G_MAXQ = 64, G_MAXBF = 192;
-#define QM_TILES_SMALL 0, G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF, 0
+#define QM_TILES_SMALL 64, 0, G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF, 0
 // medium LDS tiles (about 64 KB: two workgroups per CU) for the regions over
 // the small ones; their edge table (M_EHCAP entries) lives in global memory
+constexpr int M_LANES = 256, B_LANES = 256;   // workgroup widths of the medium and global tiers
 constexpr int M_MAXRT = 1024, M_HCAP = 4096, M_RFHCAP = 512, M_MAXRF = 256, M_MAXBE = 384, M_QHCAP = 256,
               M_MAXQ = 128, M_MAXBF = 1024, M_EHCAP = 8192;
-#define QM_TILES_MEDIUM 1, M_MAXRT, M_HCAP, M_RFHCAP, M_MAXRF, M_MAXBE, M_QHCAP, M_MAXQ, M_MAXBF, M_EHCAP
+#define QM_TILES_MEDIUM M_LANES, 1, M_MAXRT, M_HCAP, M_RFHCAP, M_MAXRF, M_MAXBE, M_QHCAP, M_MAXQ, M_MAXBF, M_EHCAP
 // global-slab tiles of the overflow path
 constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, B_MAXBE = 4096,
               B_QHCAP = 8192, B_MAXQ = 4096, B_MAXBF = 32768;
@@ -618,6 +619,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         return T;
     };
     const bool verbose = (opt->flags & QM_VERBOSE) != 0;
+    const int min_tier = (opt->flags & QM_TEST_TIER2) ? 2 : (opt->flags & QM_TEST_TIER1) ? 1 : 0;
     E.verbose = verbose;
     auto last_note = std::chrono::steady_clock::now();
     // progress inside a long round (verbose): at most one line per 10 s
@@ -682,7 +684,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             E.pbegin(pass == 0 ? 3 : 8);
             k_grow_lds<QM_TILES_SMALL><<<std::min(ncand, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL,
                                                                              pass == 0 ? E.BP : E.BPnoprof(),
-                                                                             nullptr, 0, nullptr);
+                                                                             nullptr, 0, nullptr, min_tier);
             E.pend(pass == 0 ? 3 : 8);
             int* const cw = hbase + 48;  // ctr[0..46) after a grow pass
             for (int attempt = 0;; ++attempt) {
@@ -717,17 +719,18 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 if (nover > 0) {             // medium LDS tiles
                     const int grid = std::min(nover, noalloc ? 64 : 1024);   // (a grid-stride loop: any grid)
                     E.eslab.ensure((size_t)grid * M_EHCAP * (sizeof(unsigned long long) + sizeof(int4)), s, false);
-                    k_grow_lds<QM_TILES_MEDIUM><<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover,
-                                                                    E.eslab.p);
+                    k_grow_lds<QM_TILES_MEDIUM><<<grid, M_LANES, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover,
+                                                                         E.eslab.p, 0);
                 }
                 if (nbig > 0) {              // global-memory tiles
                     const GrowTiles BT = big_tiles(tile_scale);
                     const size_t slab_block = grow_slab_bytes(BT);
-                    int grid = (int)std::min<size_t>({(size_t)nbig, 256,
-                                                      std::max<size_t>(1, (2ull << 30) / slab_block)});
+                    // up to 1024 workgroups (three resident per CU) and 8 GiB of tiles
+                    int grid = (int)std::min<size_t>({(size_t)nbig, 1024,
+                                                      std::max<size_t>(1, (8ull << 30) / slab_block)});
                     if (noalloc) grid = std::min(grid, 2);
                     E.slab.ensure(slab_block * grid, s, false);
-                    k_grow_global<<<grid, 64, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
+                    k_grow_global<B_LANES><<<grid, B_LANES, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
                                                       slab_block);
                 }
                 E.pend(8);

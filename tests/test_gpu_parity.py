@@ -87,6 +87,17 @@ def test_clustered_instance_parity():
         assert_same(srv.result(srv.submit(w)), o, "clustered 1500 served")
 
 
+@pytest.mark.parametrize("flag,label", [(qm.QM_TEST_TIER1, "medium LDS tiles"),
+                                        (qm.QM_TEST_TIER2, "global-memory tiles")])
+def test_larger_tiers_parity(flag, label):
+    """Every region grown by the medium tier (256-lane workgroups, LDS tiles
+    and a global edge table) or by the global-memory tier: the same output
+    as the oracle, bit for bit."""
+    for w in (qi.uniform_cube(300, seed=21, B=1.5, spheres=(0.3,)), clustered_instance(600, 1578)):
+        g = qm.refine_workload(w, extra_flags=flag)
+        assert_same(g, oracle.refine(w), f"{w.name} {label}")
+
+
 def test_ellipsoid_instance_parity():
     # a small instance of the batched workload's generator (rotated ellipsoid)
     rng = np.random.Generator(np.random.PCG64(44))
