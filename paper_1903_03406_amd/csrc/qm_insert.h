@@ -298,9 +298,19 @@ __global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools P
             auto sp = [&](int v) { return v == sa ? s_old : (v == sb ? s_new : -1); };
             int* ts = M.TS + 6 * (size_t)sj;
             ts[0] = r1.z; ts[1] = r2.x; ts[2] = sp(x); ts[3] = r1.w; ts[4] = sp(y); ts[5] = sp(z);
-            M.TI[sj] = TI_ALIVE | ((unsigned)(r1.y & 1) << 7) | ((unsigned)((r1.y >> 1) & 1) << 11);
-            if (r0.w >= 0) M.TA[4 * (size_t)(r0.w >> 2) + (r0.w & 3)] = (sj << 2) | 3;
+            // a fresh info word: no cached classification yet
+            M.TI[sj] = TI_ALIVE | ((unsigned)(r1.y & 1) << 7) | ((unsigned)((r1.y >> 1) & 1) << 11) |
+                       (fid[0] >= 0 ? ti_fsub(0) : 0u) | (fid[1] >= 0 ? ti_fsub(1) : 0u) |
+                       (fid[2] >= 0 ? ti_fsub(2) : 0u) | (r1.x >= 0 ? ti_fsub(3) : 0u);
+            if (r0.w >= 0) {
+                M.TA[4 * (size_t)(r0.w >> 2) + (r0.w & 3)] = (sj << 2) | 3;
+                // the old tet across a boundary subface has a new apex opposite it
+                if (r1.x >= 0) atomicAnd(&M.TI[r0.w >> 2], ~ti_fknown(r0.w & 3));
+            }
             for (int e = 0; e < 6; ++e) if (ts[e] >= 0) M.STET[ts[e]] = sj;
+            // subsegments on the boundary face's edges have new tets in their
+            // link (those through p are new or rewritten below)
+            for (int e : {0, 1, 3}) if (ts[e] >= 0) atomicAnd(&M.SFL[ts[e]], ~SS_KNOWN);
         }
         for (int j = nf + lane; j < nk; j += 64) M.TI[PL.cl[rg0 + j]] = 0u;   // unused region slots
         if (lane == 0 && nk > nf) atomicAdd(dead, nk - nf);

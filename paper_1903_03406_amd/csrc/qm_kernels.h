@@ -14,9 +14,11 @@
 //                       of an interior subface carry it)
 //   TS  int[6*nt]       subsegment slot of each tet edge, else -1
 //   TI  uint[nt]        bit0 alive, bit1 exempt, bits 4+f face queued,
-//                       bits 8+f face exempt, bits 12-13 grow-tier hint
+//                       bits 8+f face exempt, bits 12-13 grow-tier hint,
+//                       bits 14-31 cached classification (see TI_BADK)
 //   SV  int2[nss]       subsegment endpoints (ascending); SSEG segment id;
-//   SFL uint[nss]       bit0 queued, bit1 exempt; STET a tet holding the edge
+//   SFL uint[nss]       bit0 queued, bit1 exempt, bits 2-3 cached link test;
+//                       STET a tet holding the edge
 // Every decision is a function of vertex ids and coordinates only; slots and
 // launch order never change a result.
 #pragma once
@@ -32,7 +34,16 @@ enum { EX_NONE = 0, EX_NONFINITE = 1, EX_WALK = 2, EX_ENC_EXEMPT = 3, EX_HMIN = 
        EX_NREASON = 10 };
 enum { TI_ALIVE = 1u, TI_EXEMPT = 2u };
 constexpr int TI_HINT_SHIFT = 12;   // bits 12-13: grow tier a bad tet's region needed (1 medium, 3 global)
-enum { SS_QUEUED = 1u, SS_EXEMPT = 2u };
+// Cached classification (each is a function of the tet's own vertices, or of
+// a subface's two apexes, so it holds until k_insert rewrites the tet or the
+// neighbour across the face):
+constexpr unsigned TI_BADK = 1u << 14;   // bad-tet test done
+constexpr unsigned TI_BAD = 1u << 15;    // ... and the tet is bad
+QMD unsigned ti_fknown(int f) { return 1u << (16 + f); }   // subface f: status below is current
+QMD unsigned ti_fenc(int f) { return 1u << (20 + f); }     // subface f encroached by an apex
+QMD unsigned ti_fcanon(int f) { return 1u << (24 + f); }   // this tet holds the canonical copy
+QMD unsigned ti_fsub(int f) { return 1u << (28 + f); }     // face f is a subface (TF >= 0)
+enum { SS_QUEUED = 1u, SS_EXEMPT = 2u, SS_KNOWN = 4u, SS_ENC = 8u };   // KNOWN/ENC: cached link test
 constexpr int WALK_CAP = 1000000;
 constexpr int RING_CAP = 4096;
 

@@ -545,7 +545,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         k_face_keys<<<nblk(n4), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
         E.sort_asc(k0.p, k1.p, v0.p, v1.p, (int)n4);
         k_face_match<<<nblk(n4), 256, 0, s>>>((int)n4, k1.p, v1.p, E.TA.p, err);
-        if (nsf) k_mark_subfaces<<<nblk(nsf), 256, 0, s>>>(nsf, nv, nfacet, d_sf, d_sff, k1.p, v1.p, (int)n4, E.TF.p, err);
+        if (nsf) k_mark_subfaces<<<nblk(nsf), 256, 0, s>>>(nsf, nv, nfacet, d_sf, d_sff, k1.p, v1.p, (int)n4, E.TF.p,
+                                                            E.TI.p, err);
         k_edge_keys<<<nblk(n6), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
         E.sort_asc(k0.p, k1.p, v0.p, v1.p, (int)n6);
         if (nss) k_mark_subsegs<<<nblk(nss), 256, 0, s>>>(nss, nv, d_ss, d_ssg, k1.p, v1.p, (int)n6, E.M, err);

@@ -17,9 +17,10 @@ __global__ void k_classify_ss(Mesh M, int* cand, int* cnt) {
     int* ncand = cnt + CLS_SS;
     unsigned fl = M.SFL[s];
     if (fl & SS_EXEMPT) return;
-    int2 ab = M.SV[s];
     bool enc = (fl & SS_QUEUED) != 0;
-    if (!enc) {
+    if (!enc && (fl & SS_KNOWN)) enc = (fl & SS_ENC) != 0;   // link unchanged since the last test
+    else if (!enc) {
+        int2 ab = M.SV[s];
         double A[3], B[3];
         xyz(M, ab.x, A); xyz(M, ab.y, B);
         ring(M, M.STET[s], ab.x, ab.y, [&](int, int u, int w) {
@@ -30,6 +31,7 @@ __global__ void k_classify_ss(Mesh M, int* cand, int* cnt) {
             if (segdot(A, B, V, M.err) < 0) { enc = true; return true; }
             return false;
         });
+        M.SFL[s] = fl | SS_KNOWN | (enc ? SS_ENC : 0u);
     }
     if (enc) cand[atomicAdd(ncand, 1)] = s;
 }
@@ -42,26 +44,34 @@ __global__ void k_classify_sf(Mesh M, int* cand, int* cnt) {
     if (t >= M.nt || cnt[CLS_SS] > 0) return;
     int* ncand = cnt + CLS_SF;
     unsigned ti = M.TI[t];
-    if (!(ti & TI_ALIVE)) return;
-    int4 tf = ld4(M.TF, t);
-    if (tf.x < 0 && tf.y < 0 && tf.z < 0 && tf.w < 0) return;
-    int4 v = ld4(M.TV, t);
+    if (!(ti & TI_ALIVE) || !(ti & 0xF0000000u)) return;     // dead, or no subface
+    unsigned learnt = 0u;
     for (int f = 0; f < 4; ++f) {
-        if (at4(tf, f) < 0) continue;
-        int nb = M.TA[4 * (size_t)t + f];
-        int apex2 = nb >= 0 ? M.TV[4 * (size_t)(nb >> 2) + (nb & 3)] : -1;
-        if (nb >= 0 && apex2 < at4(v, f)) continue;            // not the canonical copy
-        if (ti & (1u << (8 + f))) continue;                    // exempt
-        bool enc = (ti & (1u << (4 + f))) != 0;
-        if (!enc) {
-            double A[3], B[3], C[3], V[3];
-            xyz(M, at4(v, c_FI[f][0]), A); xyz(M, at4(v, c_FI[f][1]), B); xyz(M, at4(v, c_FI[f][2]), C);
-            xyz(M, at4(v, f), V);
-            enc = facedot(A, B, C, V, M.err) < 0;
-            if (!enc && apex2 >= 0) { xyz(M, apex2, V); enc = facedot(A, B, C, V, M.err) < 0; }
+        if (!(ti & ti_fsub(f))) continue;
+        bool canon, enc_apex;
+        if (ti & ti_fknown(f)) {                               // both apexes unchanged since the test
+            canon = (ti & ti_fcanon(f)) != 0;
+            enc_apex = (ti & ti_fenc(f)) != 0;
+        } else {
+            const int4 v = ld4(M.TV, t);
+            const int nb = M.TA[4 * (size_t)t + f];
+            const int apex2 = nb >= 0 ? M.TV[4 * (size_t)(nb >> 2) + (nb & 3)] : -1;
+            canon = !(nb >= 0 && apex2 < at4(v, f));
+            enc_apex = false;
+            if (canon) {
+                double A[3], B[3], C[3], V[3];
+                xyz(M, at4(v, c_FI[f][0]), A); xyz(M, at4(v, c_FI[f][1]), B); xyz(M, at4(v, c_FI[f][2]), C);
+                xyz(M, at4(v, f), V);
+                enc_apex = facedot(A, B, C, V, M.err) < 0;
+                if (!enc_apex && apex2 >= 0) { xyz(M, apex2, V); enc_apex = facedot(A, B, C, V, M.err) < 0; }
+            }
+            learnt |= ti_fknown(f) | (canon ? ti_fcanon(f) : 0u) | (enc_apex ? ti_fenc(f) : 0u);
         }
-        if (enc) cand[atomicAdd(ncand, 1)] = (t << 2) | f;
+        if (!canon) continue;                                  // not the canonical copy
+        if (ti & (1u << (8 + f))) continue;                    // exempt
+        if (enc_apex || (ti & (1u << (4 + f)))) cand[atomicAdd(ncand, 1)] = (t << 2) | f;
     }
+    if (learnt) atomicOr(&M.TI[t], learnt);
 }
 
 // Bad tetrahedron: radius-edge ratio above B (paper, Section 1).
@@ -71,6 +81,10 @@ __global__ void k_classify_tet(Mesh M, int* cand, int* cnt) {
     int* ncand = cnt + CLS_TET;
     unsigned ti = M.TI[t];
     if (!(ti & TI_ALIVE) || (ti & TI_EXEMPT)) return;
+    if (ti & TI_BADK) {                                        // tested when first classified
+        if (ti & TI_BAD) cand[atomicAdd(ncand, 1)] = t;
+        return;
+    }
     int4 v = ld4(M.TV, t);
     int a = v.x, b = v.y, c = v.z, d = v.w, tmp;
     if (b < a) { tmp = a; a = b; b = tmp; }
@@ -80,7 +94,9 @@ __global__ void k_classify_tet(Mesh M, int* cand, int* cnt) {
     if (c < b) { tmp = b; b = c; c = tmp; }
     double A[3], B[3], C[3], D[3];
     xyz(M, a, A); xyz(M, b, B); xyz(M, c, C); xyz(M, d, D);
-    if (is_bad(A, B, C, D, M.B2)) cand[atomicAdd(ncand, 1)] = t;
+    const bool bad = is_bad(A, B, C, D, M.B2);
+    atomicOr(&M.TI[t], TI_BADK | (bad ? TI_BAD : 0u));
+    if (bad) cand[atomicAdd(ncand, 1)] = t;
 }
 
 // ------------------------------------------------------------------ split

@@ -62,7 +62,8 @@ QMD int lower_bound64(const unsigned long long* k, int n, unsigned long long key
     return lo;
 }
 __global__ void k_mark_subfaces(int nsf, int nv, int nfacet, const int* sf, const int* sff,
-                                const unsigned long long* k, const int* v, int n, int* TF, int* err) {
+                                const unsigned long long* k, const int* v, int n, int* TF, unsigned* TI,
+                                int* err) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsf) return;
     int a = sf[3 * (size_t)i], b = sf[3 * (size_t)i + 1], c = sf[3 * (size_t)i + 2], F = sff[i];
@@ -70,7 +71,10 @@ __global__ void k_mark_subfaces(int nsf, int nv, int nfacet, const int* sf, cons
     unsigned long long key = face_key3(a, b, c);
     int j = lower_bound64(k, n, key);
     if (j >= n || k[j] != key) { atomicOr(err, 8); return; }
-    for (; j < n && k[j] == key; ++j) TF[v[j]] = F;
+    for (; j < n && k[j] == key; ++j) {
+        TF[v[j]] = F;
+        atomicOr(&TI[v[j] >> 2], ti_fsub(v[j] & 3));
+    }
 }
 __global__ void k_edge_keys(int nt, const int* TV, unsigned long long* keys, int* vals) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
