@@ -36,7 +36,9 @@ PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_st
                  "scans", "insert", "grow_overflow")
 TIER_FIELDS = ("evals", "overflowed", "tested", "region", "bfaces", "max_region", "max_tested", "max_bfaces",
                "ov_region", "ov_hash", "ov_facet_region", "ov_queue", "ov_bfaces", "ov_edges2d", "ov_claims",
-               "ov_edge_table")
+               "ov_edge_table", "accepted", "acc_region", "acc_bfaces", "acc_claims",
+               "cyc_setup_seeds", "cyc_facet_region", "cyc_tet_region", "cyc_encroach", "cyc_radius_rftets",
+               "cyc_bfaces", "cyc_edges_closure", "cyc_claims_results")
 ROUND_FIELDS = 17
 ROUND_NAMES = ("cls", "ncand", "nok", "nrej", "nexempt", "nkept",
                "ex_nonfinite", "ex_walk", "ex_enc_exempt", "ex_hmin", "ex_rftet",
@@ -82,7 +84,7 @@ class _Stats(ctypes.Structure):
                 ("prof_claims", ctypes.c_int64), ("prof_scan_tets", ctypes.c_int64),
                 ("prof_scan_verts", ctypes.c_int64), ("prof_overflow", ctypes.c_int64),
                 ("prof_poolfull", ctypes.c_int64), ("prof_grow_cycles", ctypes.c_int64 * 8),
-                ("prof_tier", (ctypes.c_int64 * 16) * 3)]
+                ("prof_tier", (ctypes.c_int64 * 28) * 3)]
 
 
 def _load():

@@ -42,8 +42,10 @@ constexpr int BFR = 4;
 // prof: tested, region, bfaces, claims (first small-tile launch); tprof:
 // per-tier evaluation counters (every launch), TPROF_W words per tier
 struct BfPool { int4* r; int cap; unsigned long long* prof; unsigned long long* tprof; };
-constexpr int TPROF_W = 16;   // evals, overflowed, tested, region, bfaces, max region, max tested,
-                              // max bfaces, then the count of each overflow bit (8)
+constexpr int TPROF_W = 28;   // evals, overflowed, tested, region, bfaces, max region, max tested,
+                              // max bfaces, the count of each overflow bit (8), accepted
+                              // evaluations and their region tets, boundary faces and claims,
+                              // then shader-clock cycles of the 8 phases (lane 0)
 
 // phases timed by ptick: 0 set-up and seeds, 1 R_F, 2 R_T, 3 encroachment,
 // 4 insertion radius and R_F tets, 5 boundary faces, 6 2D edges and closure,
@@ -51,7 +53,7 @@ constexpr int TPROF_W = 16;   // evals, overflowed, tested, region, bfaces, max 
 constexpr int GROW_PHASES = 8;
 struct GrowShared {
     int nrt, nrf, nbf, nbe, nq, ncx, hcount;
-    int over, fail, reason;
+    int over, fail, reason, accepted;
     int base_reg, base_bf, base_be, base_cl, base_q;
     unsigned long long prof[4 + GROW_PHASES];   // region counters and phase clocks of this workgroup
     unsigned long long tlast;                   // (flushed at exit)
@@ -78,16 +80,25 @@ QMD void tier_count(const GrowShared& S, const BfPool& BP, int tier) {
     atomicMax(&c[5], (unsigned long long)S.nrt);
     atomicMax(&c[6], (unsigned long long)S.hcount);
     atomicMax(&c[7], (unsigned long long)S.nbf);
+    if (S.accepted) {
+        atomicAdd(&c[16], 1ull);
+        atomicAdd(&c[17], (unsigned long long)S.nrt);
+        atomicAdd(&c[18], (unsigned long long)S.nbf);
+        atomicAdd(&c[19], (unsigned long long)(S.nrt + S.ncx));
+    }
 }
-QMD void prof_flush(const GrowShared& S, const BfPool& BP) {
+QMD void prof_flush(const GrowShared& S, const BfPool& BP, int tier) {
     if (threadIdx.x == 0 && BP.prof)
         for (int i = 0; i < 4 + GROW_PHASES; ++i)
             if (S.prof[i]) atomicAdd(&BP.prof[i], S.prof[i]);
+    if (threadIdx.x == 0 && BP.tprof)
+        for (int i = 0; i < GROW_PHASES; ++i)
+            if (S.prof[4 + i]) atomicAdd(&BP.tprof[TPROF_W * tier + 20 + i], S.prof[4 + i]);
 }
 // shader clock at a phase boundary (profiling only): the cycles since the
 // last boundary go to phase `ph`
 QMD void ptick(GrowShared& S, const BfPool& BP, int ph) {
-    if (BP.prof && threadIdx.x == 0) {
+    if ((BP.prof || BP.tprof) && threadIdx.x == 0) {
         unsigned long long t = clock64();
         if (ph >= 0) S.prof[4 + ph] += t - S.tlast;
         S.tlast = t;
@@ -297,7 +308,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     ptick(S, BP, -1);
     if (lane == 0) {
         S.nrt = S.nrf = S.nbf = S.nbe = S.nq = S.ncx = S.hcount = 0;
-        S.over = S.fail = 0; S.reason = EX_NONE;
+        S.over = S.fail = 0; S.reason = EX_NONE; S.accepted = 0;
     }
     for (int i = lane; i < W.hcap; i += NT) W.H[i] = 0u;
     for (int i = lane; i < W.rfhcap; i += NT) W.RFH[i] = 0u;
@@ -799,6 +810,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
             C.be_off[cid] = be; C.be_n[cid] = nbe;
             C.cl_off[cid] = bc; C.cl_n[cid] = nrt + ncx;
             C.gst[cid] = ST_OK; C.greason[cid] = EX_NONE;
+            S.accepted = 1;
         }
     }
     __syncthreads();
@@ -876,7 +888,51 @@ __global__ __launch_bounds__(NT) void k_grow_lds(Mesh M, int cls, Cands C, Pools
         __syncthreads();
         tier_count(S, BP, TIER);
     }
-    prof_flush(S, BP);
+    prof_flush(S, BP, TIER);
+}
+
+// carve the tiles other than the hash tables from a workgroup's slab block
+QMD void carve_lists(GrowTiles& W, const GrowTiles& T, char* base) {
+    size_t off = 0;
+    auto carve = [&](size_t bytes) { char* p = base + off; off += (bytes + 255) & ~(size_t)255; return p; };
+    W.rt = (int*)carve(sizeof(int) * T.maxrt);
+    W.rf = (int*)carve(sizeof(int) * T.maxrf);
+    W.be = (int4*)carve(sizeof(int4) * T.maxbe);
+    W.q = (int2*)carve(sizeof(int2) * T.maxq);
+    W.cx = (int*)carve(sizeof(int) * (CXW * T.maxbf + T.maxcx));
+    W.EK = (unsigned long long*)carve(sizeof(unsigned long long) * T.ehcap);
+    W.EV = (int4*)carve(sizeof(int4) * T.ehcap);
+}
+inline size_t lists_slab_bytes(const GrowTiles& T) {
+    auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    return r(sizeof(int) * T.maxrt) + r(sizeof(int) * T.maxrf) + r(sizeof(int4) * T.maxbe) +
+           r(sizeof(int2) * T.maxq) + r(sizeof(int) * (CXW * T.maxbf + T.maxcx)) +
+           r(sizeof(unsigned long long) * T.ehcap) + r(sizeof(int4) * T.ehcap);
+}
+
+// Hybrid tier: the three hash tables (tested tets, facet region, queue: the
+// atomic-heavy structures) in LDS, the region list, face records and edge
+// table in the workgroup's block of a global slab.  `list` holds the
+// candidate ids; T carries the capacities (hcap = HCAP, ...).
+template <int NT, int HCAP, int RFHCAP, int QHCAP>
+__global__ __launch_bounds__(NT) void k_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                                    const int* list, int nlist, GrowTiles T, char* slab,
+                                                    size_t slab_per_block) {
+    __shared__ unsigned H[HCAP];
+    __shared__ unsigned RFH[RFHCAP];
+    __shared__ unsigned long long QH[QHCAP];
+    __shared__ GrowShared S;
+    GrowTiles W = T;
+    carve_lists(W, T, slab + slab_per_block * blockIdx.x);
+    W.H = H; W.RFH = RFH; W.QH = QH;
+    W.hcap = HCAP; W.rfhcap = RFHCAP; W.qhcap = QHCAP;
+    prof_begin(S);
+    for (int i = blockIdx.x; i < nlist; i += gridDim.x) {
+        grow_one<NT>(M, cls, C, PL, BP, list[i], W, S);
+        __syncthreads();
+        tier_count(S, BP, 1);
+    }
+    prof_flush(S, BP, 1);
 }
 
 // re-run of the candidates that overflowed the LDS tiles (or a pool), with
@@ -906,7 +962,7 @@ __global__ __launch_bounds__(NT) void k_grow_global(Mesh M, int cls, Cands C, Po
         __syncthreads();
         tier_count(S, BP, 2);
     }
-    prof_flush(S, BP);
+    prof_flush(S, BP, 2);
 }
 
 inline size_t grow_slab_bytes(const GrowTiles& T) {

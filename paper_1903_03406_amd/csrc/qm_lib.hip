@@ -192,12 +192,19 @@ __global__ void k_round_reset_pools(int* ctr) {
 constexpr int G_MAXRT = 192, G_HCAP = 512, G_RFHCAP = 128, G_MAXRF = 48, G_MAXBE = 64, G_QHCAP = 128,
               G_MAXQ = 64, G_MAXBF = 192;
 #define QM_TILES_SMALL 64, 0, G_MAXRT, G_HCAP, G_RFHCAP, G_MAXRF, G_MAXBE, G_QHCAP, G_MAXQ, G_MAXBF, 0
-// medium LDS tiles (about 64 KB: two workgroups per CU) for the regions over
-// the small ones; their edge table (M_EHCAP entries) lives in global memory
-constexpr int M_LANES = 256, B_LANES = 256;   // workgroup widths of the medium and global tiers
-constexpr int M_MAXRT = 1024, M_HCAP = 4096, M_RFHCAP = 512, M_MAXRF = 256, M_MAXBE = 384, M_QHCAP = 256,
-              M_MAXQ = 128, M_MAXBF = 1024, M_EHCAP = 8192;
-#define QM_TILES_MEDIUM M_LANES, 1, M_MAXRT, M_HCAP, M_RFHCAP, M_MAXRF, M_MAXBE, M_QHCAP, M_MAXQ, M_MAXBF, M_EHCAP
+// hybrid tier for the regions over the small tiles: hash tables in LDS
+// (72 KB: two 256-lane workgroups per CU), lists and face records in a
+// global slab (H_SLAB bytes per workgroup); up to 12288 tested tets
+constexpr int H_LANES = 256, B_LANES = 256;   // workgroup widths of the hybrid and global tiers
+constexpr int H_HCAP = 16384, H_RFHCAP = 1024, H_QHCAP = 512;
+inline GrowTiles hybrid_tiles() {
+    GrowTiles T{};
+    T.maxrt = 3 * H_HCAP / 4; T.hcap = H_HCAP; T.rfhcap = H_RFHCAP; T.maxrf = H_RFHCAP / 2;
+    T.maxbe = 4096; T.qhcap = H_QHCAP; T.maxq = H_QHCAP / 2; T.maxbf = 16384; T.maxcx = 16384; T.tier = 1;
+    T.ehcap = 1;
+    while (T.ehcap < 2 * (3 * T.maxbf + T.maxbe)) T.ehcap <<= 1;
+    return T;
+}
 // global-slab tiles of the overflow path
 constexpr int B_MAXRT = 16384, B_HCAP = 65536, B_RFHCAP = 8192, B_MAXRF = 4096, B_MAXBE = 4096,
               B_QHCAP = 8192, B_MAXQ = 4096, B_MAXBF = 32768;
@@ -244,7 +251,7 @@ struct Engine {
                        // undecided per selection pass of a batch [40..40+MIS_BATCH)
     DBuf<char> tmp;    // hipcub scratch
     DBuf<char> slab;   // overflow grow tiles
-    DBuf<char> eslab;  // edge tables of the medium LDS tier
+    DBuf<char> hslab;  // list tiles of the hybrid tier
     Cands C{};
     Pools PL{};
     BfPool BP{};
@@ -310,7 +317,7 @@ struct Engine {
                         &p_clc})
             f(*b);
         f(c_key0); f(skey); f(c_key); f(mis_drop); f(mis_lose); f(c_tup0); f(c_tup); f(c_p0); f(c_p); f(c_qw);
-        f(p_be); f(p_bfr); f(p_q); f(tmp); f(slab); f(eslab);
+        f(p_be); f(p_bfr); f(p_q); f(tmp); f(slab); f(hslab);
     }
     void attach(Arena* a) {
         ar = a;
@@ -327,7 +334,7 @@ struct Engine {
 
     explicit Engine(hipStream_t st) : s(st) {}
     ~Engine() {
-        DBuf<char>* bufs_c[] = {&tmp, &slab, &eslab};
+        DBuf<char>* bufs_c[] = {&tmp, &slab, &hslab};
         for (auto* b : bufs_c) b->release(s);
         X.release(s); TV.release(s); TA.release(s); TF.release(s); TS.release(s); TI.release(s);
         SV.release(s); SSEG.release(s); STET.release(s); FAX.release(s); SFL.release(s);
@@ -717,11 +724,13 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 if (attempt >= 64) throw QmError(QM_EINTERNAL, "regions kept outgrowing the tiles");
                 const BfPool BPr = E.BPnoprof();
                 E.pbegin();
-                if (nover > 0) {             // medium LDS tiles
-                    const int grid = std::min(nover, noalloc ? 64 : 1024);   // (a grid-stride loop: any grid)
-                    E.eslab.ensure((size_t)grid * M_EHCAP * (sizeof(unsigned long long) + sizeof(int4)), s, false);
-                    k_grow_lds<QM_TILES_MEDIUM><<<grid, M_LANES, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.olist.p, nover,
-                                                                         E.eslab.p, 0);
+                if (nover > 0) {             // hybrid tier (a grid-stride loop: any grid)
+                    const GrowTiles HT = hybrid_tiles();
+                    const size_t block = lists_slab_bytes(HT);
+                    const int grid = std::min(nover, noalloc ? 4 : 1024);
+                    E.hslab.ensure(block * grid, s, false);
+                    k_grow_hybrid<H_LANES, H_HCAP, H_RFHCAP, H_QHCAP><<<grid, H_LANES, 0, s>>>(
+                        E.M, cls, E.C, E.PL, BPr, E.olist.p, nover, HT, E.hslab.p, block);
                 }
                 if (nbig > 0) {              // global-memory tiles
                     const GrowTiles BT = big_tiles(tile_scale);
