@@ -89,20 +89,80 @@ __global__ void k_mis_check(int ncl, const int* cl, const int* clc, const int* s
     if (owner[t] >= 0) drop[c] = 1;
     else if (mark[t] != mis_val(pass, c)) lose[c] = 1;
 }
+// (the first pass of a round; the candidates left undecided are appended
+// to the list u_out for the later passes)
 __global__ __launch_bounds__(256) void k_mis_decide(int n, int* state, unsigned char* drop, unsigned char* lose,
-                                                    int* undecided, const int* prev) {
+                                                    int* undecided, const int* prev, int* u_out, int* nu_out) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < n && !(prev && *prev == 0) && state[c] == 0) {
         if (drop[c]) state[c] = 2;
-        else if (lose[c]) atomicAdd(&cnt, 1);
+        else if (lose[c]) { atomicAdd(&cnt, 1); u_out[atomicAdd(nu_out, 1)] = c; }
         else state[c] = 1;
         drop[c] = 0; lose[c] = 0;
     }
     __syncthreads();
     if (threadIdx.x == 0 && cnt) atomicAdd(undecided, cnt);
+}
+
+// Passes after the first: only the candidates still undecided take part
+// (list u_in, count *nu_in, in any order: every step is order-free).  One
+// wave per listed candidate walks its claim range; the decision appends the
+// still-undecided ones to u_out.  The mark kernel clears *nu_out (read
+// again only by the decision kernel of the same pass).
+constexpr int MIS_LIST_GRID = 2048;
+__global__ __launch_bounds__(256) void k_mis_mark_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                       unsigned long long* mark, unsigned pass, int* nu_out) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *nu_out = 0;
+    const int lane = threadIdx.x & 63, n = *nu_in;
+    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+        const int c = u_in[i], off = C.cl_off[c], m = C.cl_n[c];
+        const unsigned long long v = mis_val(pass, c);
+        for (int j = lane; j < m; j += 64) atomicMax(&mark[cl[off + j]], v);
+    }
+}
+__global__ __launch_bounds__(256) void k_mis_check_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                        const unsigned long long* mark, const int* owner,
+                                                        unsigned pass, unsigned char* drop, unsigned char* lose) {
+    const int lane = threadIdx.x & 63, n = *nu_in;
+    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+        const int c = u_in[i], off = C.cl_off[c], m = C.cl_n[c];
+        const unsigned long long v = mis_val(pass, c);
+        for (int j = lane; j < m; j += 64) {
+            const int t = cl[off + j];
+            if (owner[t] >= 0) drop[c] = 1;
+            else if (mark[t] != v) lose[c] = 1;
+        }
+    }
+}
+__global__ __launch_bounds__(256) void k_mis_decide_list(const int* u_in, const int* nu_in, int* state,
+                                                         unsigned char* drop, unsigned char* lose, int* undecided,
+                                                         int* u_out, int* nu_out) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    const int n = *nu_in;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int c = u_in[i];
+        if (drop[c]) state[c] = 2;
+        else if (lose[c]) { atomicAdd(&cnt, 1); u_out[atomicAdd(nu_out, 1)] = c; }
+        else state[c] = 1;
+        drop[c] = 0; lose[c] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd(undecided, cnt);
+}
+__global__ __launch_bounds__(256) void k_mis_commit_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                         const int* state, int* owner) {
+    const int lane = threadIdx.x & 63, n = *nu_in;
+    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+        const int c = u_in[i];
+        if (state[c] != 1) continue;
+        const int off = C.cl_off[c], m = C.cl_n[c];
+        for (int j = lane; j < m; j += 64) owner[cl[off + j]] = c;
+    }
 }
 __global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* state, int* owner,
                              const int* prev) {

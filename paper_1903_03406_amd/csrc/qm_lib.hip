@@ -235,7 +235,7 @@ struct Engine {
     DBuf<int4> c_tup0;
     DBuf<double4> c_p0;
     DBuf<int> c_elem, c_st, c_reason, c_seed, gst, greason, reg_off, reg_n, bf_off, bf_n, be_off, be_n,
-        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, glist;
+        cl_off, cl_n, q_off, q_n, state, vk, vt, vs, sk, st_, ss_, kept, olist, glist, ulist0, ulist1;
     DBuf<unsigned char> mis_drop, mis_lose;   // selection: per-candidate pass flags (kept zero)
     DBuf<unsigned long long> c_key;
     DBuf<int4> c_tup;
@@ -313,7 +313,7 @@ struct Engine {
     void each_round_buf(F&& f) {
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
                         &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
-                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &p_cl,
+                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &ulist0, &ulist1, &p_cl,
                         &p_clc})
             f(*b);
         f(c_key0); f(skey); f(c_key); f(mis_drop); f(mis_lose); f(c_tup0); f(c_tup); f(c_p0); f(c_p); f(c_qw);
@@ -341,7 +341,7 @@ struct Engine {
         mark.release(s); owner.release(s);
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason,
                         &c_seed, &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off,
-                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist,
+                        &cl_n, &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &ulist0, &ulist1,
                         &p_cl, &p_clc, &ctr})
             b->release(s);
         c_key0.release(s); skey.release(s); c_key.release(s); mis_drop.release(s); mis_lose.release(s);
@@ -381,7 +381,7 @@ struct Engine {
         size_t m = std::max(n, 1);
         for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
                         &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
-                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist})
+                        &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &ulist0, &ulist1})
             b->ensure(m, s, false);
         c_key0.ensure(m, s, false); skey.ensure(m, s, false); c_key.ensure(m, s, false);
         mis_drop.ensure(m, s, false, 0); mis_lose.ensure(m, s, false, 0);
@@ -593,6 +593,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     int* olist_n = E.ctr.p + 32;
     int* undec_d = E.ctr.p + 40;
     int* npass_d = E.ctr.p + 38;
+    int* nu_d = E.ctr.p + 46;      // undecided-list lengths of the selection passes (two buffers)
     int round = 0, status = 0, last_ncand = 0;
     // host copies of the counters live in pinned memory: the per-round
     // read-backs are then direct copies, not staged through a bounce buffer
@@ -796,13 +797,31 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 E.pbegin();
                 for (int b = 0; b < MIS_BATCH; ++b) {
                     const unsigned ps = E.pass++;
-                    const int* prev = b ? undec_d + b - 1 : nullptr;
-                    k_mis_mark<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps, prev);
-                    k_mis_check<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, E.owner.p,
-                                                          ps, E.mis_drop.p, E.mis_lose.p, prev);
-                    k_mis_decide<<<nblk(ncand), 256, 0, s>>>(ncand, E.state.p, E.mis_drop.p, E.mis_lose.p,
-                                                             undec_d + b, prev);
-                    k_mis_commit<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p, prev);
+                    const int p = batch * MIS_BATCH + b;     // pass of this round
+                    int* const u_out = (p & 1) ? E.ulist1.p : E.ulist0.p;
+                    int* const nu_out = nu_d + (p & 1);
+                    if (p == 0) {            // every accepted candidate: one thread per claim
+                        k_mis_mark<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps,
+                                                             nullptr);
+                        k_mis_check<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p,
+                                                              E.owner.p, ps, E.mis_drop.p, E.mis_lose.p, nullptr);
+                        k_mis_decide<<<nblk(ncand), 256, 0, s>>>(ncand, E.state.p, E.mis_drop.p, E.mis_lose.p,
+                                                                 undec_d + b, nullptr, u_out, nu_out);
+                        k_mis_commit<<<nblk(ncl), 256, 0, s>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p,
+                                                               nullptr);
+                    } else {                 // the undecided ones only: one wave per candidate
+                        const int* const u_in = (p & 1) ? E.ulist0.p : E.ulist1.p;
+                        const int* const nu_in = nu_d + ((p - 1) & 1);
+                        k_mis_mark_list<<<MIS_LIST_GRID, 256, 0, s>>>(u_in, nu_in, E.C, E.p_cl.p, E.mark.p, ps,
+                                                                      nu_out);
+                        k_mis_check_list<<<MIS_LIST_GRID, 256, 0, s>>>(u_in, nu_in, E.C, E.p_cl.p, E.mark.p,
+                                                                       E.owner.p, ps, E.mis_drop.p, E.mis_lose.p);
+                        k_mis_decide_list<<<MIS_LIST_GRID / 4, 256, 0, s>>>(u_in, nu_in, E.state.p, E.mis_drop.p,
+                                                                            E.mis_lose.p, undec_d + b, u_out,
+                                                                            nu_out);
+                        k_mis_commit_list<<<MIS_LIST_GRID, 256, 0, s>>>(u_in, nu_in, E.C, E.p_cl.p, E.state.p,
+                                                                        E.owner.p);
+                    }
                 }
                 E.pend(5);
             }
