@@ -26,7 +26,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_grow_lds_uniform50k_traffic.md")
 
 
 def kernel_source_sha256():
@@ -41,38 +40,65 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload, launches):
-    """HBM bytes of k_grow_lds per launch from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by the copy-kernel calibration),
-    or None when the summary is for other sources or another workload."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
-        return None
-    kv = {}
-    for line in open(TRAFFIC_SUMMARY):
-        if "=" in line and line.strip().startswith("qm."):
-            k, v = line.strip().split("=", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("qm.source_sha256") != kernel_source_sha256() or kv.get("qm.workload") != workload:
-        return None
-    fetch = float(kv["qm.fetch_kib_total"]) * float(kv["qm.fetch_scale"])
-    write = float(kv["qm.write_kib_total"]) * float(kv["qm.write_scale"])
-    return (fetch + write) * 1024.0 / float(kv["qm.launches"])
+def measured_traffic(workload, family, launches):
+    """HBM bytes per launch of the kernel of `family` from a committed counter
+    summary (profiles/*_traffic.md: FETCH_SIZE and WRITE_SIZE, each scaled by
+    the copy-kernel calibration), or None when no summary is for these kernel
+    sources, this workload and this kernel."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        kv = {}
+        for line in open(path):
+            if "=" in line and line.strip().startswith("qm."):
+                k, v = line.strip().split("=", 1)
+                kv[k.strip()] = v.strip()
+        if (kv.get("qm.source_sha256") == kernel_source_sha256() and kv.get("qm.workload") == workload
+                and kv.get("qm.family") == family and int(kv.get("qm.launches", -1)) == launches):
+            fetch = float(kv["qm.fetch_kib_total"]) * float(kv["qm.fetch_scale"])
+            write = float(kv["qm.write_kib_total"]) * float(kv["qm.write_scale"])
+            return (fetch + write) * 1024.0 / launches
+    return None
 
 
-def grow_bytes(p):
-    """Algorithmic bytes of the grow/validate kernel: each tested tet costs its
-    vertex ids (16 B) and one new vertex (32 B: it is reached across a face
-    whose three vertices are already loaded); each region tet also its
-    neighbour, facet and subsegment words (56 B) and its region and claim
-    entries (8 B); each boundary face its record (52 B); each extra claim 8 B."""
-    return (48 * p["tested"] + 64 * p["region"] + 52 * p["bfaces"]
-            + 8 * max(p["claims"] - p["region"], 0))
+TIER_OF = {"grow_validate": 0, "grow_hybrid": 1}
+KERNEL_OF = {"grow_validate": "k_grow_lds (small LDS tiles, 64 lanes)",
+             "grow_hybrid": "k_grow_hybrid (LDS hash tables, lists in HBM, 256 lanes)"}
 
 
-def classify_bytes(p):
-    """Tet classification scans: vertex ids + info word per tet (20 B) and
-    each vertex's coordinates once (32 B)."""
-    return 20 * p["scan_tets"] + 32 * p["scan_verts"]
+def tier_bytes(t):
+    """Algorithmic bytes of one grow tier's evaluations (its counters from
+    QM_PROFILE): each tested tet costs its vertex ids (16 B) and one new
+    vertex (32 B: it is reached across a face whose three vertices are
+    already loaded); each region tet also its neighbour, facet and
+    subsegment words (56 B) and its region entry (8 B); each boundary face
+    of an accepted candidate its record (52 B); each extra claim 8 B."""
+    return (48 * t["tested"] + 64 * t["region"] + 52 * t["acc_bfaces"]
+            + 8 * max(t["acc_claims"] - t["acc_region"], 0))
+
+
+def survey_bytes(r, prof):
+    """The whole refinement's algorithmic bytes by the per-insertion model:
+    a kept point moves 36(k+s) + 24u + 36f + 4s + 24 + 16(k+s)P bytes, every
+    other candidate 36(k+s) + 16(k+s) + 44, with k region tets, f new tets
+    (boundary faces), s shell tets (claims beyond the region), u cavity
+    vertices (f/2 + 2 for a ball) and P selection passes per round, all
+    means over the accepted candidates of the run."""
+    tiers = prof["tiers"]
+    acc = sum(t["accepted"] for t in tiers)
+    if acc == 0:
+        return 0.0, {}
+    k = sum(t["acc_region"] for t in tiers) / acc
+    f = sum(t["acc_bfaces"] for t in tiers) / acc
+    sh = sum(t["acc_claims"] - t["acc_region"] for t in tiers) / acc
+    u = f / 2 + 2
+    rounds_sel = max(int((r.rstats[:, 2] > 0).sum()), 1)
+    P = r.mis_passes / rounds_sel
+    kept = sum(r.inserted)
+    other = r.candidates - kept
+    per_kept = 36 * (k + sh) + 24 * u + 36 * f + 4 * sh + 24 + 16 * (k + sh) * P
+    per_other = 36 * (k + sh) + 16 * (k + sh) + 44
+    return kept * per_kept + other * per_other, {"k": k, "f": f, "s": sh, "u": u, "P": P,
+                                                 "bytes_per_kept": per_kept, "bytes_per_other": per_other}
 
 
 def make_workload(name):
@@ -279,16 +305,17 @@ def main():
     sec = (t2 - t1) / args.steps
     steiner = r.steiner
     prof = detail.profile
-    fam = max(("grow_validate", "classify"), key=lambda k: prof["ms"][k])
-    nbytes = grow_bytes(prof) if fam == "grow_validate" else classify_bytes(prof)
-    if fam == "grow_validate":      # live: the timed steps' own events
-        kms = sum(x.profile["ms"][fam] for x in results) / len(results)
-        assert all(x.profile["launches"][fam] == prof["launches"][fam] for x in results)
-    else:
-        kms = prof["ms"][fam]
+    # dominant grow kernel by the timed steps' own events; its bytes from the
+    # detail step's counters of the same tier
+    live = {f: sum(x.profile["ms"][f] for x in results) / len(results) for f in TIER_OF}
+    fam = max(live, key=live.get)
+    assert all(x.profile["launches"][fam] == prof["launches"][fam] for x in results)
+    kms = live[fam]
+    nbytes = tier_bytes(prof["tiers"][TIER_OF[fam]])
     achieved = nbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
     dominant = max(prof["ms"], key=lambda k: prof["ms"][k])
     launches = max(prof["launches"][fam], 1)
+    sbytes, smodel = survey_bytes(r, prof)
     npts = len(w.xyz) - 8
     size = f"{npts // 1000000}M" if npts >= 1000000 else f"{npts // 1000}K"
     out = {
@@ -316,15 +343,16 @@ def main():
         "grow_phase_frac": (lambda c: {n: round(x / max(sum(c), 1), 4) for n, x in zip(
             ("setup_seeds", "facet_region", "tet_region", "encroach", "radius_rftets", "bfaces",
              "edges_closure", "claims_results"), c)})(prof.get("grow_cycles", [0] * 8)),
-        "roofline": {"kernel": "k_grow_lds" if fam == "grow_validate" else "k_classify_tet",
+        "roofline": {"kernel": KERNEL_OF[fam],
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic(w.name, prof["launches"][fam]) if fam == "grow_validate"
-                                 else None),
+                     "traffic": measured_traffic(w.name, fam, prof["launches"][fam]),
                      "unit_of_bytes": "per launch (traffic and algorithmic_bytes alike)",
                      "launches": prof["launches"][fam], "kernel_ms_per_step": kms,
                      "mean_launch_us": kms * 1e3 / launches,
                      "algorithmic_bytes": nbytes / launches, "dominant_family": dominant},
+        "whole_step_model": {"bytes": sbytes, "frac_of_hbm_over_step": sbytes / sec / (HBM_PEAK_GBS * 1e9),
+                             **{k: round(v, 2) for k, v in smodel.items()}},
     }
     if not args.no_quality:
         from paper_1903_03406_amd import quality

@@ -72,10 +72,10 @@ typedef struct qm_mesh {
 #define QM_PROFILE 2u        /* time each kernel family with HIP events on the call's
                                 stream and count the region work (qm_stats.prof_*) */
 #define QM_VERBOSE 4u        /* progress line on stderr every few seconds of rounds */
-#define QM_PROFILE_GROW 8u   /* time only the grow launches with small LDS tiles (family 3 of
-                                qm_stats.prof_ms and prof_launches; the rest stay 0) with HIP
-                                events on the call's stream; the kernels run as unprofiled.
-                                Ignored with QM_PROFILE */
+#define QM_PROFILE_GROW 8u   /* time only the grow launches with small LDS tiles and those of
+                                the hybrid tier (families 3 and 8 of qm_stats.prof_ms and
+                                prof_launches; the rest stay 0) with HIP events on the call's
+                                stream; the kernels run as unprofiled. Ignored with QM_PROFILE */
 #define QM_TEST_ERROR_WORD 16u  /* tests only: raise this call's device error word at set-up, so
                                    the call ends with QM_EINTERNAL (the word is per call: other
                                    calls, concurrent or later, are not affected) */
@@ -98,7 +98,7 @@ typedef struct qm_options {
    boundary edge, unclosed cavity boundary, a new face that would not be
    locally Delaunay), vertices after, tets after */
 #define QM_ROUND_FIELDS 17
-#define QM_PROF_FAMILIES 9
+#define QM_PROF_FAMILIES 10
 
 typedef struct qm_stats {
     int32_t rounds;
@@ -111,9 +111,11 @@ typedef struct qm_stats {
     double seconds_refine;   /* round loop (device resident) */
     double seconds_total;    /* whole call incl. transfers */
     /* QM_PROFILE only: device milliseconds and launches per kernel family
-       0 classify, 1 split+order, 2 locate, 3 grow+validate (LDS tiles),
-       4 flags+stats, 5 selection, 6 scans, 7 insert, 8 grow+validate re-run
-       of the regions that outgrew the LDS tiles (global-memory tiles) */
+       0 classify, 1 split+order, 2 locate, 3 grow+validate with the small
+       LDS tiles, 4 flags+stats, 5 selection, 6 scans, 7 insert, 8 grow+
+       validate of the regions over the small tiles (hybrid tier: LDS hash
+       tables, lists in global memory), 9 the same for the regions over the
+       hybrid tier (global-memory tiles) */
     double prof_ms[QM_PROF_FAMILIES];
     int64_t prof_launches[QM_PROF_FAMILIES];
     /* QM_PROFILE only: region work of the grow kernel with LDS tiles (family
@@ -132,13 +134,15 @@ typedef struct qm_stats {
        results (phases a candidate leaves early are not counted) */
     int64_t prof_grow_cycles[8];
     /* QM_PROFILE only: region evaluations by grow tier (0 small LDS tiles,
-       1 medium LDS tiles, 2 global-memory tiles), 16 counters each:
+       1 medium LDS tiles, 2 global-memory tiles), 28 counters each:
        evaluations, evaluations that outgrew the tier's tiles, then over the
        others: tets tested, region tets, boundary faces, and the largest
        region, tested count and boundary-face count; then how often each
        tile overflowed (region list, tested-tet hash, facet region, queue,
-       boundary faces, 2D boundary edges, claims, edge table) */
-    int64_t prof_tier[3][16];
+       boundary faces, 2D boundary edges, claims, edge table), then accepted
+       evaluations and their region tets, boundary faces and claims, then
+       shader-clock cycles of the 8 phases (as prof_grow_cycles) */
+    int64_t prof_tier[3][28];
 } qm_stats;
 
 typedef struct qm_result qm_result;

@@ -33,7 +33,7 @@ QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through 
 QM_TEST_TIER1 = 32        # tests only: every region grown with the medium tiles (or larger)
 QM_TEST_TIER2 = 64        # tests only: every region grown with the global-memory tiles
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
-                 "scans", "insert", "grow_overflow")
+                 "scans", "insert", "grow_hybrid", "grow_global")
 TIER_FIELDS = ("evals", "overflowed", "tested", "region", "bfaces", "max_region", "max_tested", "max_bfaces",
                "ov_region", "ov_hash", "ov_facet_region", "ov_queue", "ov_bfaces", "ov_edges2d", "ov_claims",
                "ov_edge_table", "accepted", "acc_region", "acc_bfaces", "acc_claims",
@@ -78,8 +78,8 @@ class _Stats(ctypes.Structure):
                 ("inserted", ctypes.c_int64 * 3), ("candidates", ctypes.c_int64),
                 ("mis_passes", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
                 ("seconds_setup", ctypes.c_double), ("seconds_refine", ctypes.c_double),
-                ("seconds_total", ctypes.c_double), ("prof_ms", ctypes.c_double * 9),
-                ("prof_launches", ctypes.c_int64 * 9), ("prof_tested", ctypes.c_int64),
+                ("seconds_total", ctypes.c_double), ("prof_ms", ctypes.c_double * 10),
+                ("prof_launches", ctypes.c_int64 * 10), ("prof_tested", ctypes.c_int64),
                 ("prof_region", ctypes.c_int64), ("prof_bfaces", ctypes.c_int64),
                 ("prof_claims", ctypes.c_int64), ("prof_scan_tets", ctypes.c_int64),
                 ("prof_scan_verts", ctypes.c_int64), ("prof_overflow", ctypes.c_int64),

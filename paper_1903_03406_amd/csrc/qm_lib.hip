@@ -259,7 +259,7 @@ struct Engine {
     int64_t dead = 0;
     // kernel-family timing with events on the call's stream (QM_PROFILE)
     bool prof = false;
-    bool prof_grow = false;   // events around the first small-tile grow launch only
+    bool prof_grow = false;   // events around the small-tile and hybrid-tier grow launches only
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_cat, ev_round;
     int ev_used = 0, cur_round = 0;
@@ -267,7 +267,7 @@ struct Engine {
     int64_t prof_n[QM_PROF_FAMILIES] = {0};
     int64_t prof_over = 0, prof_full = 0;
     DBuf<unsigned long long> pctr;
-    bool timed(int cat) const { return prof || (prof_grow && cat == 3); }
+    bool timed(int cat) const { return prof || (prof_grow && (cat == 3 || cat == 8)); }
     void pbegin(int cat = -1) {
         if (!timed(cat)) return;
         if (ev_used + 2 > (int)ev.size()) {
@@ -690,11 +690,11 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         int ncl_final = 0;
         for (int pass = 0;; ++pass) {
             if (pass > 0) k_round_reset_pools<<<1, 64, 0, s>>>(E.ctr.p);
-            E.pbegin(pass == 0 ? 3 : 8);
+            E.pbegin(3);
             k_grow_lds<QM_TILES_SMALL><<<std::min(ncand, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL,
                                                                              pass == 0 ? E.BP : E.BPnoprof(),
                                                                              nullptr, 0, nullptr, min_tier);
-            E.pend(pass == 0 ? 3 : 8);
+            E.pend(3);
             int* const cw = hbase + 48;  // ctr[0..46) after a grow pass
             for (int attempt = 0;; ++attempt) {
                 if (attempt > 0 || pass > 0) {
@@ -724,14 +724,15 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 if (nover + nbig == 0) break;
                 if (attempt >= 64) throw QmError(QM_EINTERNAL, "regions kept outgrowing the tiles");
                 const BfPool BPr = E.BPnoprof();
-                E.pbegin();
                 if (nover > 0) {             // hybrid tier (a grid-stride loop: any grid)
+                    E.pbegin(8);
                     const GrowTiles HT = hybrid_tiles();
                     const size_t block = lists_slab_bytes(HT);
                     const int grid = std::min(nover, noalloc ? 4 : 1024);
                     E.hslab.ensure(block * grid, s, false);
                     k_grow_hybrid<H_LANES, H_HCAP, H_RFHCAP, H_QHCAP><<<grid, H_LANES, 0, s>>>(
                         E.M, cls, E.C, E.PL, BPr, E.olist.p, nover, HT, E.hslab.p, block);
+                    E.pend(8);
                 }
                 if (nbig > 0) {              // global-memory tiles
                     const GrowTiles BT = big_tiles(tile_scale);
@@ -740,11 +741,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                     int grid = (int)std::min<size_t>({(size_t)nbig, 1024,
                                                       std::max<size_t>(1, (8ull << 30) / slab_block)});
                     if (noalloc) grid = std::min(grid, 2);
+                    E.pbegin(9);
                     E.slab.ensure(slab_block * grid, s, false);
                     k_grow_global<B_LANES><<<grid, B_LANES, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
                                                       slab_block);
+                    E.pend(9);
                 }
-                E.pend(8);
             }
             if (!cw[5]) { E.pool_seen(cw, ncand, cls); ncl_final = cw[3]; break; }
             // a pool was full: the counters hold everything this pass reserved
@@ -973,8 +975,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     }
     if (E.prof_grow) {             // the stream is synchronised: every pair is complete
         E.pflush();
-        ST.prof_ms[3] = E.prof_ms[3];
-        ST.prof_launches[3] = E.prof_n[3];
+        for (int f : {3, 8}) { ST.prof_ms[f] = E.prof_ms[f]; ST.prof_launches[f] = E.prof_n[f]; }
     }
     if (E.prof) {
         for (int i = 0; i < QM_PROF_FAMILIES; ++i) { ST.prof_ms[i] = E.prof_ms[i]; ST.prof_launches[i] = E.prof_n[i]; }
