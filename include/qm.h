@@ -81,6 +81,8 @@ typedef struct qm_mesh {
                                    calls, concurrent or later, are not affected) */
 #define QM_TEST_TIER1 32u     /* tests only: every region is grown with the medium tiles (or larger) */
 #define QM_TEST_TIER2 64u     /* tests only: every region is grown with the global-memory tiles */
+#define QM_TEST_KEY_COLLIDE 128u  /* tests only: priority keys keep their top 3 bits (the rest 0),
+                                     so many are equal and the tie rule (ascending tuple) orders them */
 
 typedef struct qm_options {
     double B;                /* radius-edge bound (> 0) */
@@ -88,7 +90,8 @@ typedef struct qm_options {
     int32_t max_rounds;      /* round guard; QM_EROUNDS when reached */
     int32_t max_kept;        /* > 0: insert at most this many points per round */
     uint32_t flags;          /* QM_INPUT_DEVICE | QM_PROFILE | QM_VERBOSE | QM_PROFILE_GROW |
-                                QM_TEST_ERROR_WORD | QM_TEST_TIER1 | QM_TEST_TIER2 */
+                                QM_TEST_ERROR_WORD | QM_TEST_TIER1 | QM_TEST_TIER2 |
+                                QM_TEST_KEY_COLLIDE */
 } qm_options;
 
 /* per-round record (17 int32): class (0 subsegment, 1 subface, 2 tet),

@@ -79,14 +79,21 @@ class OracleResult:
     status: int               # 0 done, 1 round guard reached
     seconds: float
     last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
+    dump: list = None               # dump_round's candidates (see _take_dump)
     round_checks: np.ndarray = None  # (rounds, len(CHECK_FIELDS)): check() after every round
 
 
 def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
-           round_checks=False) -> OracleResult:
+           round_checks=False, dump_round=None, key_mask=None) -> OracleResult:
     """Run the oracle on a workload (qm_inputs.Workload or compatible).
-    round_checks: run check() on the mesh at the end of every round."""
+    round_checks: run check() on the mesh at the end of every round.
+    dump_round: record that round's candidates (result.dump, see dump()).
+    key_mask: AND every priority key with this mask (forces equal keys)."""
     lib = _load()
+    lib.qmo_set_dump_round.argtypes = [ctypes.c_int]
+    lib.qmo_set_dump_round(-1 if dump_round is None else int(dump_round))
+    lib.qmo_set_key_mask.argtypes = [ctypes.c_uint64]
+    lib.qmo_set_key_mask((1 << 64) - 1 if key_mask is None else int(key_mask))
     lib.qmo_set_round_check.argtypes = [ctypes.c_int]
     lib.qmo_set_round_check(1 if round_checks else 0)
     c = lambda a, t: np.ascontiguousarray(a, dtype=t)
@@ -124,6 +131,38 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
     if nl:
         lib.qmo_result_lastc(res, _ptr(out.last_cands))
     lib.qmo_result_free(res)
+    lib.qmo_set_key_mask((1 << 64) - 1)
+    if dump_round is not None:
+        out.dump = _take_dump(lib)
+        lib.qmo_set_dump_round(-1)
+    return out
+
+
+def _take_dump(lib):
+    """The recorded round's candidates in priority order, as dicts: cls,
+    tup, key, status, reason, kept, p, region (set of sorted vertex
+    quadruples), rf (list of sorted triples), claims (set of quadruples)."""
+    lib.qmo_dump_sizes.restype = ctypes.c_int
+    lib.qmo_dump_sizes.argtypes = [ctypes.c_void_p]
+    lib.qmo_dump_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    sz = np.zeros(2, dtype=np.int32)
+    n = lib.qmo_dump_sizes(_ptr(sz))
+    ib = np.zeros(max(int(sz[0]), 1), dtype=np.int32)
+    db = np.zeros(max(int(sz[1]), 1), dtype=np.float64)
+    lib.qmo_dump_copy(_ptr(ib), _ptr(db))
+    out, o = [], 0
+    for i in range(n):
+        cls, ntup = int(ib[o]), int(ib[o + 1])
+        tup = tuple(int(x) for x in ib[o + 2:o + 2 + ntup])
+        key = (int(np.uint32(ib[o + 6])) << 32) | int(np.uint32(ib[o + 7]))
+        status, reason, kept, nrt, nrf, ncl = (int(x) for x in ib[o + 8:o + 14])
+        o += 14
+        quad = lambda m: [tuple(int(x) for x in ib[o + 4 * j:o + 4 * j + 4]) for j in range(m)]
+        region = quad(nrt); o += 4 * nrt
+        claims = quad(ncl); o += 4 * ncl
+        rf = [tuple(int(x) for x in ib[o + 3 * j:o + 3 * j + 3]) for j in range(nrf)]; o += 3 * nrf
+        out.append({"cls": cls, "tup": tup, "key": key, "status": status, "reason": reason, "kept": kept,
+                    "p": db[3 * i:3 * i + 3].copy(), "region": region, "claims": claims, "rf": rf})
     return out
 
 

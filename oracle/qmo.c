@@ -304,13 +304,19 @@ static int rf_has(const IV* RF, const int* g) {
 
 static const double* X(const Mesh* M, int v) { return M->V[v]; }
 
+/* Test hook: keys are ANDed with this mask, so that tests can force equal
+   keys and exercise the tie rule (ascending tuple). */
+static uint64_t g_key_mask = ~(uint64_t)0;
+void qmo_set_key_mask(uint64_t m) { g_key_mask = m; }
+static uint64_t cand_key(const Cand* c) { return qmo_key(c->cls, c->tup, c->ntup) & g_key_mask; }
+
 /* ---- Step 2: splitting point and priority ---------------------------- */
 static void split_point(const Mesh* M, Cand* c) {
     const int* t = c->tup;
     if (c->cls == CLS_SS) qmo_midpoint(X(M, t[0]), X(M, t[1]), c->p);
     else if (c->cls == CLS_SF) qmo_tri_cc(X(M, t[0]), X(M, t[1]), X(M, t[2]), c->p);
     else { double R2; qmo_tet_cc(X(M, t[0]), X(M, t[1]), X(M, t[2]), X(M, t[3]), c->p, &R2); }
-    c->key = qmo_key(c->cls, c->tup, c->ntup);
+    c->key = cand_key(c);
 }
 
 /* queue one element; returns whether it is exempt */
@@ -785,6 +791,49 @@ int qmo_check(int nv, const double* xyz, int nt, const int* tets, int nsf, const
 static int g_round_check = 0;
 void qmo_set_round_check(int on) { g_round_check = on; }
 
+/* Test hook: record every candidate of round g_dump_round after the
+   selection, for the brute-force pins of the region and the greedy set.
+   Per candidate, ints: class, tuple length, tuple (4, -1 padded), key (high,
+   low 32 bits), status, reason, kept, then the counts of region tets, region
+   subfaces and claimed tets, then the region tets and claimed tets as sorted
+   vertex-id quadruples and the region subfaces as sorted triples; doubles:
+   the splitting point. */
+static int g_dump_round = -1;
+static IV g_dump_i;
+static double* g_dump_d = NULL;
+static int g_dump_nd = 0, g_dump_n = 0;
+void qmo_set_dump_round(int r) {
+    g_dump_round = r;
+    iv_free(&g_dump_i);
+    free(g_dump_d); g_dump_d = NULL; g_dump_nd = 0; g_dump_n = 0;
+}
+int qmo_dump_sizes(int* out) { out[0] = g_dump_i.n; out[1] = g_dump_nd; return g_dump_n; }
+void qmo_dump_copy(int* ib, double* db) {
+    if (g_dump_i.n) memcpy(ib, g_dump_i.a, sizeof(int) * (size_t)g_dump_i.n);
+    if (g_dump_nd) memcpy(db, g_dump_d, sizeof(double) * (size_t)g_dump_nd);
+}
+static void dump_tet(const Mesh* M, int t) {
+    int v[4]; memcpy(v, M->T[t].v, sizeof v); sort4(v);
+    for (int k = 0; k < 4; ++k) iv_push(&g_dump_i, v[k]);
+}
+static void dump_round(const Mesh* M, const CandList* L) {
+    g_dump_n = L->n;
+    g_dump_d = (double*)malloc(sizeof(double) * 3 * (size_t)(L->n ? L->n : 1));
+    g_dump_nd = 3 * L->n;
+    for (int i = 0; i < L->n; ++i) {
+        const Cand* c = &L->c[i];
+        iv_push(&g_dump_i, c->cls); iv_push(&g_dump_i, c->ntup);
+        for (int k = 0; k < 4; ++k) iv_push(&g_dump_i, k < c->ntup ? c->tup[k] : -1);
+        iv_push(&g_dump_i, (int)(uint32_t)(c->key >> 32)); iv_push(&g_dump_i, (int)(uint32_t)c->key);
+        iv_push(&g_dump_i, c->status); iv_push(&g_dump_i, c->reason); iv_push(&g_dump_i, c->kept);
+        iv_push(&g_dump_i, c->RT.n); iv_push(&g_dump_i, c->RF.n / 3); iv_push(&g_dump_i, c->claim.n);
+        for (int j = 0; j < c->RT.n; ++j) dump_tet(M, c->RT.a[j]);
+        for (int j = 0; j < c->claim.n; ++j) dump_tet(M, c->claim.a[j]);
+        for (int j = 0; j < c->RF.n; ++j) iv_push(&g_dump_i, c->RF.a[j]);
+        memcpy(g_dump_d + 3 * i, c->p, sizeof c->p);
+    }
+}
+
 typedef struct qmo_result {
     int* rcheck;                  /* QMO_NCHECK ints per round (round checks on) */
     int* lastc; int nlastc;       /* last round: 9 ints per candidate */
@@ -916,7 +965,7 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
         if (cls == CLS_NONE) break;
         for (int i = 0; i < L.n; ++i) {
             Cand* c = &L.c[i];
-            c->key = qmo_key(c->cls, c->tup, c->ntup);
+            c->key = cand_key(c);
         }
         qsort(L.c, (size_t)L.n, sizeof(Cand), cmp_cand);
         int nok = 0, nrej = 0, nex = 0, byr[EX_NREASON] = {0};
@@ -940,6 +989,7 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
             for (int j = 0; j < c->claim.n; ++j) M->claimed[c->claim.a[j]] = round;
             c->kept = 1; nkept++;
         }
+        if (round == g_dump_round) dump_round(M, &L);
         apply_flags(M, &L);
         int pid = M->nv;
         for (int i = 0; i < L.n; ++i) {

@@ -32,6 +32,7 @@ QM_VERBOSE = 4
 QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through its own error word
 QM_TEST_TIER1 = 32        # tests only: every region grown with the medium tiles (or larger)
 QM_TEST_TIER2 = 64        # tests only: every region grown with the global-memory tiles
+QM_TEST_KEY_COLLIDE = 128  # tests only: keys cut to their top 3 bits (equal keys, tie rule)
 PROF_FAMILIES = ("classify", "split_order", "locate", "grow_validate", "flags_stats", "select",
                  "scans", "insert", "grow_hybrid", "grow_global")
 TIER_FIELDS = ("evals", "overflowed", "tested", "region", "bfaces", "max_region", "max_tested", "max_bfaces",

@@ -629,6 +629,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     };
     const bool verbose = (opt->flags & QM_VERBOSE) != 0;
     const int min_tier = (opt->flags & QM_TEST_TIER2) ? 2 : (opt->flags & QM_TEST_TIER1) ? 1 : 0;
+    const unsigned long long key_mask = (opt->flags & QM_TEST_KEY_COLLIDE) ? 0xE000000000000000ull : ~0ull;
     E.verbose = verbose;
     auto last_note = std::chrono::steady_clock::now();
     // progress inside a long round (verbose): at most one line per 10 s
@@ -663,7 +664,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         // step 2: splitting points and priorities, then priority order
         E.pbegin();
         k_split<<<nblk(ncand), 256, 0, s>>>(E.M, cls, ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
-                                          E.c_st0.p, E.c_reason0.p);
+                                          E.c_st0.p, E.c_reason0.p, key_mask);
         if (ncand <= SORT_SMALL) {
             k_order_small<<<1, SORT_SMALL, 0, s>>>(ncand, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p,
                                                    E.c_st0.p, E.c_reason0.p, E.C);

@@ -102,8 +102,9 @@ __global__ void k_classify_tet(Mesh M, int* cand, int* cnt) {
 // ------------------------------------------------------------------ split
 // splitting point (paper, Section 2: midpoint / circumcircle centre /
 // circumsphere centre) and the predetermined priority of each candidate
+// (key_mask: all ones, except in tests that force equal keys)
 __global__ void k_split(Mesh M, int cls, int n, const int* elem, unsigned long long* key, int4* tup,
-                        double4* p, int* st, int* reason) {
+                        double4* p, int* st, int* reason, unsigned long long key_mask) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int e = elem[i];
@@ -130,7 +131,7 @@ __global__ void k_split(Mesh M, int cls, int n, const int* elem, unsigned long l
     if (cls == CLS_SS) midpoint(V[0], V[1], P);
     else if (cls == CLS_SF) tri_cc(V[0], V[1], V[2], P);
     else { double R2; tet_cc(V[0], V[1], V[2], V[3], P, R2); }
-    key[i] = prio_key(cls, ids, k);
+    key[i] = prio_key(cls, ids, k) & key_mask;
     tup[i] = make_int4(ids[0], ids[1], ids[2], ids[3]);
     p[i] = make_double4(P[0], P[1], P[2], 0.0);
     bool fin = isfinite(P[0]) && isfinite(P[1]) && isfinite(P[2]);

@@ -87,15 +87,28 @@ def test_clustered_instance_parity():
         assert_same(srv.result(srv.submit(w)), o, "clustered 1500 served")
 
 
-@pytest.mark.parametrize("flag,label", [(qm.QM_TEST_TIER1, "medium LDS tiles"),
+@pytest.mark.parametrize("flag,label", [(qm.QM_TEST_TIER1, "hybrid tier"),
                                         (qm.QM_TEST_TIER2, "global-memory tiles")])
 def test_larger_tiers_parity(flag, label):
-    """Every region grown by the medium tier (256-lane workgroups, LDS tiles
-    and a global edge table) or by the global-memory tier: the same output
-    as the oracle, bit for bit."""
+    """Every region grown by the hybrid tier (256-lane workgroups, hash
+    tables in LDS, lists in global memory) or by the global-memory tier: the
+    same output as the oracle, bit for bit."""
     for w in (qi.uniform_cube(300, seed=21, B=1.5, spheres=(0.3,)), clustered_instance(600, 1578)):
         g = qm.refine_workload(w, extra_flags=flag)
         assert_same(g, oracle.refine(w), f"{w.name} {label}")
+
+
+@pytest.mark.parametrize("n,seed,B,spheres", [(120, 4, 1.5, (0.3,)), (300, 6, 1.8, ()), (1500, 6, 2.0, (0.2, 0.35))])
+def test_equal_keys_parity(n, seed, B, spheres):
+    """Keys cut to their top 3 bits on both sides: most keys are equal, so
+    the order comes from the tie rule (ascending tuple) in the one-workgroup
+    ranking of small rounds and in the sort's tie fix of large ones; the
+    output still matches the oracle bit for bit."""
+    w = qi.uniform_cube(n, seed=seed, B=B, spheres=spheres)
+    o = oracle.refine(w, key_mask=0xE000000000000000)
+    assert o.rstats[:, 1].max() > 256            # a round takes the sort path
+    g = qm.refine_workload(w, extra_flags=qm.QM_TEST_KEY_COLLIDE)
+    assert_same(g, o, f"equal keys n={n}")
 
 
 def test_ellipsoid_instance_parity():

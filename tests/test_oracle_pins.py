@@ -373,3 +373,157 @@ def test_deterministic_rerun():
     w = qi.uniform_cube(100, seed=4, B=1.5, spheres=(0.3,))
     a, b = oracle.refine(w), oracle.refine(w)
     assert np.array_equal(canon(a)[0], canon(b)[0]) and np.array_equal(a.rstats, b.rstats)
+
+
+# ---------------------------------------------- brute-force region and selection
+def _mesh_state(w, rounds):
+    """The oracle's mesh at the start of round `rounds` (after that many)."""
+    r = oracle.refine(w, max_rounds=rounds)
+    tets = [tuple(int(x) for x in t) for t in r.tets]
+    sfs = {tuple(sorted(int(x) for x in f)): int(F) for f, F in zip(r.sf, r.sf_facet)}
+    sss = {tuple(sorted(int(x) for x in e)) for e in r.ss}
+    faces = {}
+    for i, t in enumerate(tets):
+        for f in range(4):
+            faces.setdefault(tuple(sorted(t[:f] + t[f + 1:])), []).append(i)
+    return r.xyz, tets, sfs, sss, faces
+
+
+def _brute_region(c, xyz, tets, sfs, sss, faces):
+    """Section 2's Delaunay region of candidate c, by brute force: R_F from
+    the seed subfaces (the facet region's definition), then every tet whose
+    circumsphere strictly holds p and that is connected to the seeds across
+    faces that are not subfaces (or are R_F subfaces)."""
+    p = c["p"]
+    q4 = lambda i: tuple(sorted(tets[i]))
+    inside = [oracle.insphere(*(xyz[v] for v in t), p) > 0 for t in tets]
+    rf = []
+    if c["cls"] == 0:
+        a, b = c["tup"]
+        seeds = [i for i, t in enumerate(tets) if a in t and b in t]
+        rf = [f for f in sfs if a in f and b in f]
+    elif c["cls"] == 1:
+        rf = [c["rf"][0]]                      # the located subface (its walk is pinned elsewhere)
+    else:
+        seeds = [i for i, t in enumerate(tets) if q4(i) == c["region"][0]]
+    if c["cls"] != 2:                          # grow R_F within each subface's facet
+        k = 0
+        while k < len(rf):
+            g = rf[k]; k += 1
+            for x, y in ((g[0], g[1]), (g[0], g[2]), (g[1], g[2])):
+                if (x, y) in sss:
+                    continue
+                for h in sfs:
+                    if h != g and x in h and y in h and sfs[h] == sfs[g] and h not in rf:
+                        if oracle.facedot(*(xyz[v] for v in h), p) < 0:
+                            rf.append(h)
+        if c["cls"] == 1:
+            seeds = []
+        for g in rf:
+            seeds += faces[g]
+    region, todo = set(), list(dict.fromkeys(seeds))
+    region.update(todo)
+    while todo:
+        i = todo.pop()
+        t = tets[i]
+        for f in range(4):
+            fk = tuple(sorted(t[:f] + t[f + 1:]))
+            if fk in sfs and fk not in rf:
+                continue
+            for n in faces[fk]:
+                if n != i and n not in region and inside[n]:
+                    region.add(n); todo.append(n)
+    claims = set(region)
+    for i in region:
+        t = tets[i]
+        for f in range(4):
+            fk = tuple(sorted(t[:f] + t[f + 1:]))
+            if fk in rf:
+                continue
+            claims.update(n for n in faces[fk] if n not in region)
+    return {q4(i) for i in region}, sorted(rf), {q4(i) for i in claims}
+
+
+@pytest.mark.parametrize("n,seed,B,spheres", [(40, 3, 1.5, (0.3,)), (55, 8, 1.3, (0.25,)), (50, 11, 1.6, ())])
+def test_regions_and_selection_match_brute_force(n, seed, B, spheres):
+    """For the first round of each class: every candidate's region (R_F and
+    R_T) and claim set equal the brute-force construction from Section 2's
+    definitions, and the kept points are exactly the greedy maximal set of
+    pairwise disjoint claim sets in priority order (key descending, then
+    ascending tuple)."""
+    w = qi.uniform_cube(n, seed=seed, B=B, spheres=spheres)
+    full = oracle.refine(w)
+    cls = full.rstats[:, 0]
+    firsts = [int(np.argmax(cls == k)) for k in range(3) if (cls == k).any()]
+    assert len(firsts) >= 2
+    checked = 0
+    for r in firsts:
+        xyz, tets, sfs, sss, faces = _mesh_state(w, r)
+        d = oracle.refine(w, max_rounds=r + 1, dump_round=r).dump
+        assert d and all(c["cls"] == cls[r] for c in d)
+        # priority order
+        assert [(-c["key"], c["tup"]) for c in d] == sorted((-c["key"], c["tup"]) for c in d)
+        for c in d:
+            if not c["region"]:                # rejected or exempted by the walk, nothing grown
+                continue
+            reg, rf, claims = _brute_region(c, xyz, tets, sfs, sss, faces)
+            assert reg == set(c["region"]), (r, c["tup"])
+            assert rf == sorted(c["rf"]), (r, c["tup"])
+            if c["status"] == 0:
+                assert claims == set(c["claims"]), (r, c["tup"])
+            checked += 1
+        # the greedy maximal disjoint set
+        taken, kept = set(), []
+        for c in d:
+            ok = c["status"] == 0 and not (set(c["claims"]) & taken)
+            if ok:
+                taken |= set(c["claims"])
+            kept.append(int(ok))
+        assert kept == [c["kept"] for c in d]
+    assert checked > 20
+
+
+def test_priority_key_of_longer_tuples():
+    """Keys of 2-4 ids chain SplitMix64's finaliser: key(cls, ids) is the
+    finaliser applied to (previous key XOR next id), starting from the
+    generator's state increment times (cls + 1).  The reference generator
+    below is SplitMix64's published definition; its first outputs are
+    checked against the published reference values first."""
+    M = (1 << 64) - 1
+    G = 0x9E3779B97F4A7C15
+
+    def mix(z):                                # SplitMix64 output function
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+    state, outs = 0, []
+    for _ in range(3):
+        state = (state + G) & M
+        outs.append(mix(state))
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    for cls in range(3):
+        assert oracle.key(cls, [0]) == outs[cls]
+        for ids in ([5, 9], [1, 2, 3], [7, 11, 13, 1 << 20], [2000000, 3, 4, 5]):
+            h = (G * (cls + 1)) & M
+            for i in ids:
+                h = mix(h ^ i)
+            assert oracle.key(cls, ids) == h
+    assert oracle.key(2, [1, 2, 3, 4]) != oracle.key(2, [1, 2, 4, 3])
+
+
+@pytest.mark.parametrize("n,seed,B,spheres", [(120, 4, 1.5, (0.3,)), (300, 6, 1.8, ())])
+def test_equal_keys_are_ordered_by_tuple(n, seed, B, spheres):
+    """With every key cut to its top 3 bits (many equal keys) the round's
+    candidates still come in key-descending, tuple-ascending order, and the
+    refinement still ends in a valid CDT."""
+    w = qi.uniform_cube(n, seed=seed, B=B, spheres=spheres)
+    mask = 0xE000000000000000
+    full = oracle.refine(w, key_mask=mask)
+    assert full.status == 0
+    c = oracle.check(full.xyz, full.tets, full.sf, full.ss, full.ss_seg, B)
+    assert struct_ok(c) and c["nonlocal_delaunay"] == 0
+    big = int(np.argmax(full.rstats[:, 1]))
+    d = oracle.refine(w, max_rounds=big + 1, dump_round=big, key_mask=mask).dump
+    keys = [c["key"] for c in d]
+    assert all(k & ~mask == 0 for k in keys) and len(set(keys)) < len(keys)
+    assert [(-c["key"], c["tup"]) for c in d] == sorted((-c["key"], c["tup"]) for c in d)
