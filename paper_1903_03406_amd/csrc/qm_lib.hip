@@ -6,7 +6,7 @@
 // (class choice, overflow, selection passes, totals) to size launches and
 // buffers.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -129,6 +129,71 @@ __global__ void k_round_reset(int* ctr) {
     if (i < 48 && (i < 11 || i >= 15)) ctr[i] = 0;
 }
 
+// ---- exclusive prefix sums (ints), SCAN_TILE elements per 256-lane
+// workgroup: each lane sums 16 consecutive elements, the lanes' sums are
+// scanned across the workgroup (wave shuffles, then the four wave totals)
+constexpr int SCAN_TILE = 4096;
+QMD int block_exclusive_256(int v, int* total) {
+    __shared__ int wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int pre = 0;
+    for (int i = 0; i < w; ++i) pre += wsum[i];
+    *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    return pre + x - v;
+}
+__global__ __launch_bounds__(256) void k_scan_tile_sums(int n, const int* in, int* sums) {
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * 16;
+    int v = 0;
+    for (int j = 0; j < 16; ++j) v += base + j < n ? in[base + j] : 0;
+    int total;
+    block_exclusive_256(v, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+__global__ __launch_bounds__(1024) void k_scan_sums(int m, int* sums) {   // in place, exclusive
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < m; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = i < m ? sums[i] : 0;
+        int x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        int pre = carry;
+        for (int k = 0; k < w; ++k) pre += wsum[k];
+        if (i < m) sums[i] = pre + x - v;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 16; ++k) carry += wsum[k];
+        __syncthreads();
+    }
+}
+__global__ __launch_bounds__(256) void k_scan_tile(int n, const int* in, int* out, const int* offs) {
+    const int base = blockIdx.x * SCAN_TILE + threadIdx.x * 16;
+    int e[16], v = 0;
+    for (int j = 0; j < 16; ++j) { e[j] = base + j < n ? in[base + j] : 0; v += e[j]; }
+    int total;
+    int run = block_exclusive_256(v, &total) + (offs ? offs[blockIdx.x] : 0);
+    for (int j = 0; j < 16; ++j) {
+        if (base + j < n) out[base + j] = run;
+        run += e[j];
+    }
+}
+
 // Priority order of a small round (n <= SORT_SMALL candidates), one
 // workgroup: each candidate's position is its rank under the round's order
 // (larger key first; equal keys by ascending tuple, then by index), the
@@ -249,7 +314,7 @@ struct Engine {
                        // dead [14], stats [16..31], re-run list counts [32..34] and [36], tile code [35],
                        // passes of a one-workgroup selection [38],
                        // undecided per selection pass of a batch [40..40+MIS_BATCH)
-    DBuf<char> tmp;    // hipcub scratch
+    DBuf<char> tmp;    // sort and scan scratch
     DBuf<char> slab;   // overflow grow tiles
     DBuf<char> hslab;  // list tiles of the hybrid tier
     Cands C{};
@@ -438,27 +503,37 @@ struct Engine {
         tmp.ensure(bytes, s, false);
         return tmp.p;
     }
+    // key-value radix sorts (rocPRIM; stable, so equal keys keep index order)
     template <class K, class V>
     void sort_desc(const K* kin, K* kout, const V* vin, V* vout, int n) {
         size_t bytes = 0;
-        HIPCK(hipcub::DeviceRadixSort::SortPairsDescending(nullptr, bytes, kin, kout, vin, vout, n, 0,
-                                                           (int)(8 * sizeof(K)), s));
+        HIPCK(rocprim::radix_sort_pairs_desc(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0,
+                                             (unsigned)(8 * sizeof(K)), s));
         void* t = cub_tmp(bytes);
-        HIPCK(hipcub::DeviceRadixSort::SortPairsDescending(t, bytes, kin, kout, vin, vout, n, 0,
-                                                           (int)(8 * sizeof(K)), s));
+        HIPCK(rocprim::radix_sort_pairs_desc(t, bytes, kin, kout, vin, vout, (size_t)n, 0,
+                                             (unsigned)(8 * sizeof(K)), s));
     }
     template <class K, class V>
     void sort_asc(const K* kin, K* kout, const V* vin, V* vout, int n) {
         size_t bytes = 0;
-        HIPCK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, n, 0, (int)(8 * sizeof(K)), s));
+        HIPCK(rocprim::radix_sort_pairs(nullptr, bytes, kin, kout, vin, vout, (size_t)n, 0,
+                                        (unsigned)(8 * sizeof(K)), s));
         void* t = cub_tmp(bytes);
-        HIPCK(hipcub::DeviceRadixSort::SortPairs(t, bytes, kin, kout, vin, vout, n, 0, (int)(8 * sizeof(K)), s));
+        HIPCK(rocprim::radix_sort_pairs(t, bytes, kin, kout, vin, vout, (size_t)n, 0, (unsigned)(8 * sizeof(K)), s));
     }
+    // exclusive prefix sum of n ints: tile sums, one workgroup scans them,
+    // then each tile is scanned from its offset (one pass when n fits a tile)
     void exscan(const int* in, int* out, int n) {
-        size_t bytes = 0;
-        HIPCK(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n, s));
-        void* t = cub_tmp(bytes);
-        HIPCK(hipcub::DeviceScan::ExclusiveSum(t, bytes, in, out, n, s));
+        if (n <= 0) return;
+        const int tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+        if (tiles == 1) {
+            k_scan_tile<<<1, 256, 0, s>>>(n, in, out, nullptr);
+            return;
+        }
+        int* sums = (int*)cub_tmp(sizeof(int) * (size_t)tiles);
+        k_scan_tile_sums<<<tiles, 256, 0, s>>>(n, in, sums);
+        k_scan_sums<<<1, 1024, 0, s>>>(tiles, sums);
+        k_scan_tile<<<tiles, 256, 0, s>>>(n, in, out, sums);
     }
 };
 
