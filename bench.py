@@ -240,6 +240,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true", help="skip the output quality report")
+    ap.add_argument("--early-stop", action="store_true",
+                    help="the early-stop blasting mode (not a parity mode: timing decides which points win)")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single-instance line: the first N instances of the batched "
                          "workload (config 4), batched jobs/s against one-at-a-time jobs/s")
@@ -281,7 +283,8 @@ def main():
 
     def step(profile=False):
         return qm.refine(d["xyz"], d["tets"], d["sf"], d["sf_facet"], d["ss"], d["ss_seg"], d["ftri"],
-                         d["ftri_facet"], w.B, stream=stream, profile=profile, verbose=True)
+                         d["ftri_facet"], w.B, stream=stream, profile=profile, verbose=True,
+                         early_stop=args.early_stop)
 
     # The first untimed step runs with every kernel family timed and the
     # region counters on (the algorithmic bytes and the phase split come from
@@ -309,12 +312,16 @@ def main():
     # detail step's counters of the same tier
     live = {f: sum(x.profile["ms"][f] for x in results) / len(results) for f in TIER_OF}
     fam = max(live, key=live.get)
-    assert all(x.profile["launches"][fam] == prof["launches"][fam] for x in results)
     kms = live[fam]
-    nbytes = tier_bytes(prof["tiers"][TIER_OF[fam]])
-    achieved = nbytes / (kms * 1e-3) / 1e9 if kms > 0 else 0.0
-    dominant = max(prof["ms"], key=lambda k: prof["ms"][k])
+    # per launch: the detail step's bytes over its launches, the timed steps'
+    # event time over theirs (the same launches, except in the early-stop
+    # mode, where timing decides the rounds)
     launches = max(prof["launches"][fam], 1)
+    t_launches = max(sum(x.profile["launches"][fam] for x in results) / len(results), 1)
+    nbytes = tier_bytes(prof["tiers"][TIER_OF[fam]])
+    mean_us = kms * 1e3 / t_launches
+    achieved = (nbytes / launches) / (mean_us * 1e-6) / 1e9 if kms > 0 else 0.0
+    dominant = max(prof["ms"], key=lambda k: prof["ms"][k])
     sbytes, smodel = survey_bytes(r, prof)
     npts = len(w.xyz) - 8
     size = f"{npts // 1000000}M" if npts >= 1000000 else f"{npts // 1000}K"
@@ -331,11 +338,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "input_vertices": int(len(w.xyz)), "input_tets": int(len(w.tets)),
+        "config": {"workload": w.name + ("_early_stop" if args.early_stop else ""),
+                   "mode": "early-stop blasting (not a parity mode)" if args.early_stop else "parity",
+                   "input_vertices": int(len(w.xyz)), "input_tets": int(len(w.tets)),
                    "plc_triangles": int(len(w.ftri)), "segments": int(len(w.seg)), "B": w.B,
                    "parallelism": "single instance, one GPU"},
         "tets_per_s": len(r.tets) / sec,
         "output": {"vertices": int(len(r.xyz)), "tets": int(len(r.tets)), "steiner": steiner,
+                   "deferred": r.deferred,
                    "rounds": r.rounds, "device_refine_s": r.seconds_refine, "device_setup_s": r.seconds_setup},
         "profile_ms": {k: round(v, 3) for k, v in prof["ms"].items()},   # the untimed detail step
         "overflow_candidates": prof.get("overflow", 0), "poolfull_candidates": prof.get("poolfull", 0),
@@ -349,7 +359,7 @@ def main():
                      "traffic": measured_traffic(w.name, fam, prof["launches"][fam]),
                      "unit_of_bytes": "per launch (traffic and algorithmic_bytes alike)",
                      "launches": prof["launches"][fam], "kernel_ms_per_step": kms,
-                     "mean_launch_us": kms * 1e3 / launches,
+                     "mean_launch_us": mean_us,
                      "algorithmic_bytes": nbytes / launches, "dominant_family": dominant},
         "whole_step_model": {"bytes": sbytes, "frac_of_hbm_over_step": sbytes / sec / (HBM_PEAK_GBS * 1e9),
                              **{k: round(v, 2) for k, v in smodel.items()}},

@@ -76,6 +76,13 @@ typedef struct qm_mesh {
                                 the hybrid tier (families 3 and 8 of qm_stats.prof_ms and
                                 prof_launches; the rest stay 0) with HIP events on the call's
                                 stream; the kernels run as unprofiled. Ignored with QM_PROFILE */
+#define QM_EARLY_STOP 256u   /* a non-parity mode: early-stop blasting as the paper runs it
+                                (Section 2): while growing, a candidate marks each tet it takes
+                                with its priority and stops, for this round, on meeting a
+                                higher priority's mark.  The kept points still have disjoint
+                                claim sets and full validation, so the output is a CDT of the
+                                same kind, but which points win depends on timing: the result
+                                is not reproducible and not the oracle's. */
 #define QM_TEST_ERROR_WORD 16u  /* tests only: raise this call's device error word at set-up, so
                                    the call ends with QM_EINTERNAL (the word is per call: other
                                    calls, concurrent or later, are not affected) */
@@ -109,6 +116,7 @@ typedef struct qm_stats {
     int64_t inserted[3];     /* Steiner points by class */
     int64_t candidates;      /* candidate evaluations over all rounds */
     int64_t mis_passes;      /* marking passes of the disjoint-set selection */
+    int64_t deferred;        /* QM_EARLY_STOP: evaluations stopped early by a higher priority */
     int64_t nv_out, nt_out;  /* output sizes */
     double seconds_setup;    /* device-side setup from the input arrays */
     double seconds_refine;   /* round loop (device resident) */

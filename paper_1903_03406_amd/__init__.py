@@ -29,6 +29,7 @@ QM_INPUT_DEVICE = 1
 QM_PROFILE = 2
 QM_PROFILE_GROW = 8   # time only the small-tile grow launches (family grow_validate)
 QM_VERBOSE = 4
+QM_EARLY_STOP = 256       # non-parity mode: early-stop blasting (timing-dependent result)
 QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through its own error word
 QM_TEST_TIER1 = 32        # tests only: every region grown with the medium tiles (or larger)
 QM_TEST_TIER2 = 64        # tests only: every region grown with the global-memory tiles
@@ -77,7 +78,7 @@ class _Opts(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("inserted", ctypes.c_int64 * 3), ("candidates", ctypes.c_int64),
-                ("mis_passes", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
+                ("mis_passes", ctypes.c_int64), ("deferred", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
                 ("seconds_setup", ctypes.c_double), ("seconds_refine", ctypes.c_double),
                 ("seconds_total", ctypes.c_double), ("prof_ms", ctypes.c_double * 10),
                 ("prof_launches", ctypes.c_int64 * 10), ("prof_tested", ctypes.c_int64),
@@ -145,6 +146,7 @@ class RefineResult:
     seconds_total: float
     profile: dict = None        # QM_PROFILE: per-family ms/launches and region counters
     last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
+    deferred: int = 0               # QM_EARLY_STOP: evaluations stopped early
 
     @property
     def steiner(self) -> int:
@@ -165,7 +167,7 @@ def _arr(a, dtype):
 
 def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None, hmin_factor=0.5,
            max_rounds=100000, max_kept=0, stream=None, profile=False, verbose=False,
-           extra_flags=0) -> RefineResult:
+           extra_flags=0, early_stop=False) -> RefineResult:
     """Refine a CDT.  Arrays are numpy (host) or torch CUDA tensors (device);
     ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle."""
     lib = _load()
@@ -199,7 +201,7 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
     mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
     opts = _Opts(float(B), float(hmin_factor), int(max_rounds), int(max_kept),
                  (QM_INPUT_DEVICE if dev else 0) | (_prof_flag(profile))
-                 | (QM_VERBOSE if verbose else 0) | int(extra_flags))
+                 | (QM_VERBOSE if verbose else 0) | (QM_EARLY_STOP if early_stop else 0) | int(extra_flags))
     if stream is None:
         hs = None
     elif hasattr(stream, "cuda_stream"):
@@ -262,7 +264,7 @@ def _take_result(lib, res, profile) -> RefineResult:
                               "tiers": [dict(zip(TIER_FIELDS, [int(x) for x in st.prof_tier[k]]))
                                         for k in range(3)],
                               "round_ms": round_ms}
-                             if profile else None), last)
+                             if profile else None), last, int(st.deferred))
     finally:
         lib.qm_result_free(res)
 

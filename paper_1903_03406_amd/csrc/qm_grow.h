@@ -53,7 +53,7 @@ constexpr int TPROF_W = 28;   // evals, overflowed, tested, region, bfaces, max 
 constexpr int GROW_PHASES = 8;
 struct GrowShared {
     int nrt, nrf, nbf, nbe, nq, ncx, hcount;
-    int over, fail, reason, accepted;
+    int over, fail, reason, accepted, lost;
     int base_reg, base_bf, base_be, base_cl, base_q;
     unsigned long long prof[4 + GROW_PHASES];   // region counters and phase clocks of this workgroup
     unsigned long long tlast;                   // (flushed at exit)
@@ -110,7 +110,7 @@ QMD void ptick(GrowShared& S, const BfPool& BP, int ph) {
 // set the flags) before all have read them.  True: stop (over or failed).
 QMD bool phase_end(const GrowShared& S) {
     __syncthreads();
-    const bool stop = S.over != 0 || S.fail != 0;
+    const bool stop = S.over != 0 || S.fail != 0 || S.lost != 0;
     __syncthreads();
     return stop;
 }
@@ -308,18 +308,28 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
     ptick(S, BP, -1);
     if (lane == 0) {
         S.nrt = S.nrf = S.nbf = S.nbe = S.nq = S.ncx = S.hcount = 0;
-        S.over = S.fail = 0; S.reason = EX_NONE; S.accepted = 0;
+        S.over = S.fail = 0; S.reason = EX_NONE; S.accepted = 0; S.lost = 0;
     }
     for (int i = lane; i < W.hcap; i += NT) W.H[i] = 0u;
     for (int i = lane; i < W.rfhcap; i += NT) W.RFH[i] = 0u;
     for (int i = lane; i < W.qhcap; i += NT) W.QH[i] = 0ull;
     __syncthreads();
 
+    // Early-stop blasting (non-parity mode, Section 2's blasting as the paper
+    // runs it): every tet the candidate takes is marked with its priority in
+    // this pass; meeting a mark of higher priority stops the candidate, which
+    // waits for a later round.
+    const unsigned long long es_v =
+        ((unsigned long long)PL.es_pass << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)cid);
+    auto es_take = [&](int t) {
+        if (PL.es_mark && atomicMax(&PL.es_mark[t], es_v) > es_v) S.lost = 1;
+    };
     auto add_rt = [&](int t) {
         unsigned os;
         int r = hput(W.H, W.hcap, (unsigned)t + 1u, HS_IN, &os);
         if (r < 0) { S.over |= OV_HASH; return; }
         if (r == 1) {
+            es_take(t);
             int c = atomicAdd(&S.hcount, 1);
             if (4 * c > 3 * W.hcap) S.over |= OV_HASH;
             int idx = atomicAdd(&S.nrt, 1);
@@ -406,7 +416,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         int head = 0;
         while (true) {
             const int end = S.nrt;
-            over_rt = S.over != 0;
+            over_rt = S.over != 0 || S.lost != 0;
             const bool stop = head >= end || over_rt;
             __syncthreads();              // every lane has read the level bounds
             if (stop) break;
@@ -431,6 +441,7 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
                     int c = atomicAdd(&S.hcount, 1);
                     if (4 * c > 3 * W.hcap) S.over |= OV_HASH;
                     if (inside) {
+                        es_take(n);
                         int idx = atomicAdd(&S.nrt, 1);
                         if (idx < W.maxrt) W.rt[idx] = n; else S.over |= OV_RT;
                     }
@@ -441,7 +452,10 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         }
     }
     if (over_rt) {                        // read before the last level barrier
-        if (lane == 0) over_status(M, cls, C, PL, W, cid, S.over, S);
+        if (lane == 0) {
+            if (S.lost) C.gst[cid] = ST_LOST;
+            else over_status(M, cls, C, PL, W, cid, S.over, S);
+        }
         return;
     }
     const int nrt = S.nrt, nrf = S.nrf;
@@ -782,12 +796,16 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
         if (nb < 0) continue;
         int r = hclaim(W.H, W.hcap, (unsigned)(nb >> 2) + 1u);
         if (r == 1) {
+            es_take(nb >> 2);
             int idx = atomicAdd(&S.ncx, 1);
             if (idx < W.maxcx) cext[idx] = nb >> 2; else S.over |= OV_CX;
         } else if (r < 0) S.over |= OV_HASH;
     }
     if (phase_end(S)) {
-        if (lane == 0) over_status(M, cls, C, PL, W, cid, S.over, S);
+        if (lane == 0) {
+            if (S.lost) C.gst[cid] = ST_LOST;
+            else over_status(M, cls, C, PL, W, cid, S.over, S);
+        }
         return;
     }
     const int ncx = S.ncx;

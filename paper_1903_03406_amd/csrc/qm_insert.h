@@ -49,7 +49,8 @@ __global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pool
                 int nb = M.TA[4 * (size_t)t + f];
                 if (nb >= 0) atomicOr(&M.TI[nb >> 2], 1u << (8 + (nb & 3)));
             } else atomicOr(&M.TI[e], TI_EXEMPT);
-        } else atomicAdd(&bs[13], 1);     // unresolved (internal error)
+        } else if (st == ST_LOST) atomicAdd(&bs[14], 1);   // stopped early: evaluated again later
+        else atomicAdd(&bs[13], 1);     // unresolved (internal error)
         C.state[i] = st == ST_OK ? 0 : 3;
     }
     __syncthreads();

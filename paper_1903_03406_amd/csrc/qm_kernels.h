@@ -28,7 +28,7 @@ namespace qm {
 
 enum { CLS_SS = 0, CLS_SF = 1, CLS_TET = 2, CLS_NONE = 3 };
 enum { ST_OK = 0, ST_REJECT = 1, ST_EXEMPT = 2, ST_PENDING = 3, ST_OVERFLOW = 4, ST_POOLFULL = 5,
-       ST_TOOBIG = 6, ST_OVERFLOW2 = 7 };
+       ST_TOOBIG = 6, ST_OVERFLOW2 = 7, ST_LOST = 8 };   // LOST: stopped early (early-stop mode)
 enum { EX_NONE = 0, EX_NONFINITE = 1, EX_WALK = 2, EX_ENC_EXEMPT = 3, EX_HMIN = 4,
        EX_RFTET = 5, EX_FACE = 6, EX_EDGE2D = 7, EX_MANIFOLD = 8, EX_DELAUNAY = 9,
        EX_NREASON = 10 };
@@ -82,6 +82,10 @@ struct Pools {
     int4* be; int* cl; int* clc; int2* q;
     int cap_be, cap_cl, cap_q;
     int* ctr;             // [1] face records, [2] be, [3] cl, [4] q, [5] pool overflow
+    // early-stop blasting (a non-parity mode): per-tet priority marks of this
+    // grow pass, or null
+    unsigned long long* es_mark;
+    unsigned es_pass;
 };
 
 __constant__ int c_FI[4][3] = {{1, 3, 2}, {0, 2, 3}, {0, 3, 1}, {0, 1, 2}};

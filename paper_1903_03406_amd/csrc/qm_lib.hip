@@ -704,6 +704,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     };
     const bool verbose = (opt->flags & QM_VERBOSE) != 0;
     const int min_tier = (opt->flags & QM_TEST_TIER2) ? 2 : (opt->flags & QM_TEST_TIER1) ? 1 : 0;
+    const bool early_stop = (opt->flags & QM_EARLY_STOP) != 0;
     const unsigned long long key_mask = (opt->flags & QM_TEST_KEY_COLLIDE) ? 0xE000000000000000ull : ~0ull;
     E.verbose = verbose;
     auto last_note = std::chrono::steady_clock::now();
@@ -766,6 +767,9 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         int ncl_final = 0;
         for (int pass = 0;; ++pass) {
             if (pass > 0) k_round_reset_pools<<<1, 64, 0, s>>>(E.ctr.p);
+            // early-stop mode: this pass's marks compare above every earlier one
+            E.PL.es_mark = early_stop ? E.mark.p : nullptr;
+            E.PL.es_pass = early_stop ? E.pass++ : 0u;
             E.pbegin(3);
             k_grow_lds<QM_TILES_SMALL><<<std::min(ncand, 16384), 64, 0, s>>>(E.M, cls, E.C, E.PL,
                                                                              pass == 0 ? E.BP : E.BPnoprof(),
@@ -951,6 +955,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         last_ncand = ncand;
         ST.candidates += ncand;
         ST.mis_passes += passes;
+        ST.deferred += st[14];
     }
     if (!noalloc) HIPCK(hipEventRecord(e2, s));
     sync_counters();
