@@ -117,6 +117,7 @@ typedef struct qm_stats {
     int64_t candidates;      /* candidate evaluations over all rounds */
     int64_t mis_passes;      /* marking passes of the disjoint-set selection */
     int64_t deferred;        /* QM_EARLY_STOP: evaluations stopped early by a higher priority */
+    int64_t device_bytes_peak;   /* most device memory the call held at once (its own buffers) */
     int64_t nv_out, nt_out;  /* output sizes */
     double seconds_setup;    /* device-side setup from the input arrays */
     double seconds_refine;   /* round loop (device resident) */
@@ -252,10 +253,12 @@ typedef struct qm_server_stats {
     int64_t admitted, refused, completed;   /* since creation; refused = QM_EAGAIN */
 } qm_server_stats;
 
-/* Device bytes the library budgets for refining this instance: an upper
-   estimate from the input tet count and B (tighter bounds insert more
-   points), including over-allocation of growing buffers.  0 for bad
-   arguments. */
+/* Device bytes the library budgets for refining this instance: 16 KB per
+   input tet for B < 1.6, 8 KB otherwise, plus 320 MiB.  An upper estimate
+   from measured peaks (qm_stats.device_bytes_peak), not a bound: a served
+   job runs with its estimate as its budget, so the slab tiles of the larger
+   grow tiers shrink to a quarter of it, but its mesh and result pools take what
+   the refinement needs.  0 for bad arguments. */
 size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options* opt);
 
 /* Create a server on the calling thread's current device with `nworkers`

@@ -78,7 +78,7 @@ class _Opts(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("inserted", ctypes.c_int64 * 3), ("candidates", ctypes.c_int64),
-                ("mis_passes", ctypes.c_int64), ("deferred", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
+                ("mis_passes", ctypes.c_int64), ("deferred", ctypes.c_int64), ("device_bytes_peak", ctypes.c_int64), ("nv_out", ctypes.c_int64), ("nt_out", ctypes.c_int64),
                 ("seconds_setup", ctypes.c_double), ("seconds_refine", ctypes.c_double),
                 ("seconds_total", ctypes.c_double), ("prof_ms", ctypes.c_double * 10),
                 ("prof_launches", ctypes.c_int64 * 10), ("prof_tested", ctypes.c_int64),
@@ -147,6 +147,7 @@ class RefineResult:
     profile: dict = None        # QM_PROFILE: per-family ms/launches and region counters
     last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
     deferred: int = 0               # QM_EARLY_STOP: evaluations stopped early
+    device_bytes_peak: int = 0      # most device memory the call held at once
 
     @property
     def steiner(self) -> int:
@@ -264,7 +265,7 @@ def _take_result(lib, res, profile) -> RefineResult:
                               "tiers": [dict(zip(TIER_FIELDS, [int(x) for x in st.prof_tier[k]]))
                                         for k in range(3)],
                               "round_ms": round_ms}
-                             if profile else None), last, int(st.deferred))
+                             if profile else None), last, int(st.deferred), int(st.device_bytes_peak))
     finally:
         lib.qm_result_free(res)
 

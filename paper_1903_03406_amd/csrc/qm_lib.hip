@@ -63,6 +63,13 @@ struct Arena {
     }
 };
 
+// device bytes a call holds (allocated and not yet freed) and their peak
+struct Acct {
+    size_t now = 0, peak = 0;
+    void add(size_t b) { now += b; peak = std::max(peak, now); }
+    void sub(size_t b) { now -= std::min(now, b); }
+};
+
 // growable device buffer (contents kept on growth when asked); with an
 // arena it is carved from the arena and never freed
 template <class T>
@@ -70,22 +77,47 @@ struct DBuf {
     T* p = nullptr;
     size_t cap = 0;
     Arena* ar = nullptr;
+    Acct* acct = nullptr;
     void ensure(size_t n, hipStream_t s, bool keep, int fill_byte = -1) {
         if (n <= cap) return;
         size_t nc = ar ? n : std::max(n, cap + cap / 2 + 1024);
+        if (!keep && p && !ar) {        // contents not needed: free first, so both never coexist
+            HIPCK(hipFreeAsync(p, s));
+            if (acct) acct->sub(cap * sizeof(T));
+            p = nullptr;
+            cap = 0;
+        }
         T* q = nullptr;
         if (ar) q = (T*)ar->take(nc * sizeof(T));
         else HIPCK(hipMallocAsync((void**)&q, nc * sizeof(T), s));
+        if (acct && !ar) acct->add(nc * sizeof(T));
         if (fill_byte >= 0) HIPCK(hipMemsetAsync(q, fill_byte, nc * sizeof(T), s));
         if (keep && p && cap) HIPCK(hipMemcpyAsync(q, p, cap * sizeof(T), hipMemcpyDeviceToDevice, s));
-        if (p && !ar) HIPCK(hipFreeAsync(p, s));
+        if (p && !ar) {
+            HIPCK(hipFreeAsync(p, s));
+            if (acct) acct->sub(cap * sizeof(T));
+        }
         p = q;
         cap = nc;
     }
     void release(hipStream_t s) {
-        if (p && !ar) (void)hipFreeAsync(p, s);
+        if (p && !ar) {
+            (void)hipFreeAsync(p, s);
+            if (acct) acct->sub(cap * sizeof(T));
+        }
         p = nullptr;
         cap = 0;
+    }
+    // exactly n elements (no growth slack), contents not kept
+    void ensure_exact(size_t n, hipStream_t s) {
+        if (n <= cap) return;
+        release(s);
+        if (ar) p = (T*)ar->take(n * sizeof(T));
+        else {
+            HIPCK(hipMallocAsync((void**)&p, n * sizeof(T), s));
+            if (acct) acct->add(n * sizeof(T));
+        }
+        cap = n;
     }
 };
 
@@ -265,7 +297,7 @@ constexpr int H_HCAP = 16384, H_RFHCAP = 1024, H_QHCAP = 512;
 inline GrowTiles hybrid_tiles() {
     GrowTiles T{};
     T.maxrt = 3 * H_HCAP / 4; T.hcap = H_HCAP; T.rfhcap = H_RFHCAP; T.maxrf = H_RFHCAP / 2;
-    T.maxbe = 4096; T.qhcap = H_QHCAP; T.maxq = H_QHCAP / 2; T.maxbf = 16384; T.maxcx = 16384; T.tier = 1;
+    T.maxbe = 4096; T.qhcap = H_QHCAP; T.maxq = H_QHCAP / 2; T.maxbf = 8192; T.maxcx = 8192; T.tier = 1;
     T.ehcap = 1;
     while (T.ehcap < 2 * (3 * T.maxbf + T.maxbe)) T.ehcap <<= 1;
     return T;
@@ -397,7 +429,26 @@ struct Engine {
         each_round_buf([&](auto& b) { b.p = nullptr; b.cap = 0; });
     }
 
-    explicit Engine(hipStream_t st) : s(st) {}
+    // device bytes of this call, and the budget the slab grids keep within
+    // (0: none)
+    Acct acct;
+    size_t mem_cap = 0;
+    explicit Engine(hipStream_t st) : s(st) {
+        each_mesh_buf([&](auto& b) { b.acct = &acct; });
+        each_round_buf([&](auto& b) { b.acct = &acct; });
+    }
+    // Slab workgroups that fit the budget (at least one): the slab being
+    // replaced (`held` bytes) is freed first, and the slabs together keep to
+    // a quarter of the budget, leaving the rest to the mesh and the result
+    // pools.
+    int slab_grid(int grid, size_t block, size_t held) const {
+        if (!mem_cap) return grid;
+        const size_t others = acct.now - std::min(acct.now, held);
+        const size_t slabs = slab.cap + hslab.cap - held;
+        const size_t room = std::min(mem_cap > others ? mem_cap - others : 0,
+                                     mem_cap / 4 > slabs ? mem_cap / 4 - slabs : 0);
+        return (int)std::max<size_t>(1, std::min<size_t>((size_t)grid, room / block));
+    }
     ~Engine() {
         DBuf<char>* bufs_c[] = {&tmp, &slab, &hslab};
         for (auto* b : bufs_c) b->release(s);
@@ -499,6 +550,44 @@ struct Engine {
         b.prof = nullptr;
         return b;
     }
+    // Renumber the live tets in Morton order of their centroids (dead slots
+    // dropped); the selection words are cleared, which every round expects
+    // between rounds anyway.  Not used without allocation.
+    int nt_ordered = 0;
+    void reorder() {
+        const int nt = M.nt;
+        DBuf<unsigned long long> k0, k1;
+        DBuf<int> v0, v1, perm;
+        for (auto* b : {&v0, &v1, &perm}) b->acct = &acct;
+        k0.acct = k1.acct = &acct;
+        k0.ensure(nt, s, false); k1.ensure(nt, s, false); v0.ensure(nt, s, false); v1.ensure(nt, s, false);
+        perm.ensure(nt, s, false);
+        int* nlive_d = ctr.p + 50;
+        HIPCK(hipMemsetAsync(nlive_d, 0, sizeof(int), s));
+        k_order_keys<<<nblk(nt), 256, 0, s>>>(M, k0.p, v0.p, nlive_d);
+        sort_asc(k0.p, k1.p, v0.p, v1.p, nt);
+        k_order_perm<<<nblk(nt), 256, 0, s>>>(nt, v1.p, perm.p);
+        const int nlive = read1(nlive_d, s);
+        DBuf<int> nTV, nTA, nTF, nTS;
+        DBuf<unsigned> nTI;
+        for (auto* b : {&nTV, &nTA, &nTF, &nTS}) b->acct = &acct;
+        nTI.acct = &acct;
+        nTV.ensure(TV.cap, s, false); nTA.ensure(TA.cap, s, false); nTF.ensure(TF.cap, s, false);
+        nTS.ensure(TS.cap, s, false); nTI.ensure(TI.cap, s, false);
+        k_order_gather<<<nblk(nlive), 256, 0, s>>>(nlive, v1.p, perm.p, M, nTV.p, nTA.p, nTF.p, nTS.p, nTI.p);
+        if (M.nss) k_order_stet<<<nblk(M.nss), 256, 0, s>>>(M.nss, perm.p, STET.p);
+        auto swap_in = [](auto& a, auto& b) { std::swap(a.p, b.p); std::swap(a.cap, b.cap); };
+        swap_in(TV, nTV); swap_in(TA, nTA); swap_in(TF, nTF); swap_in(TS, nTS); swap_in(TI, nTI);
+        nTV.release(s); nTA.release(s); nTF.release(s); nTS.release(s); nTI.release(s);
+        k0.release(s); k1.release(s); v0.release(s); v1.release(s); perm.release(s);
+        HIPCK(hipMemsetAsync(mark.p, 0, mark.cap * sizeof(unsigned long long), s));
+        HIPCK(hipMemsetAsync(owner.p, 0xFF, owner.cap * sizeof(int), s));
+        HIPCK(hipMemsetAsync(ctr.p + 14, 0, sizeof(int), s));   // no dead slots left
+        M.nt = nlive;
+        dead = 0;
+        nt_ordered = nlive;
+        bind();
+    }
     void* cub_tmp(size_t bytes) {
         tmp.ensure(bytes, s, false);
         return tmp.p;
@@ -548,7 +637,7 @@ using namespace qm;
 // *dstats; no qm_result, pinned buffer or event is created.
 static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
                       qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
-                      qm_stats* dstats = nullptr) {
+                      qm_stats* dstats = nullptr, size_t mem_cap = 0) {
     auto T0 = std::chrono::steady_clock::now();
     const bool noalloc = ar != nullptr;
     if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
@@ -568,6 +657,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
             throw QmError(QM_EINVAL, "output arrays missing or smaller than the input mesh");
     }
     Engine E(s);
+    E.mem_cap = mem_cap;
     if (noalloc) {
         E.attach(ar);
         E.cap_v = (size_t)dout->cap_v;
@@ -588,6 +678,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         return buf.p;
     };
     DBuf<char> b_xyz, b_tet, b_sf, b_sff, b_ss, b_ssg, b_ft, b_ftf;   // (unused with device inputs)
+    for (auto* b : {&b_xyz, &b_tet, &b_sf, &b_sff, &b_ss, &b_ssg, &b_ft, &b_ftf}) b->acct = &E.acct;
     const double* d_xyz = (const double*)stage(in->xyz, sizeof(double) * 3 * nv, b_xyz);
     const int* d_tet = (const int*)stage(in->tet, sizeof(int) * 4 * (size_t)nt, b_tet);
     const int* d_sf = (const int*)stage(in->sf, sizeof(int) * 3 * (size_t)nsf, b_sf);
@@ -607,6 +698,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     if (noalloc) ar->mark = ar->top;      // what follows is carved again every round
     E.M.nv = nv; E.M.nt = nt; E.M.nss = nss;
     E.M.err = E.ctr.p + 48;               // this call's error word of the exact paths
+    E.nt_ordered = nt;
     if (opt->flags & QM_TEST_ERROR_WORD) HIPCK(hipMemsetAsync(E.M.err, 1, 1, s));
     int* err = E.ctr.p + 13;
     auto T1 = std::chrono::steady_clock::now();
@@ -622,6 +714,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         DBuf<unsigned long long> k0, k1;
         DBuf<int> v0, v1;
         k0.ar = k1.ar = ar; v0.ar = v1.ar = ar;
+        k0.acct = k1.acct = &E.acct; v0.acct = v1.acct = &E.acct;
         size_t n4 = 4 * (size_t)nt, n6 = 6 * (size_t)nt;
         k0.ensure(n6, s, false); k1.ensure(n6, s, false); v0.ensure(n6, s, false); v1.ensure(n6, s, false);
         k_face_keys<<<nblk(n4), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
@@ -634,6 +727,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         if (nss) k_mark_subsegs<<<nblk(nss), 256, 0, s>>>(nss, nv, d_ss, d_ssg, k1.p, v1.p, (int)n6, E.M, err);
         DBuf<int> first;
         first.ar = ar;
+        first.acct = &E.acct;
         first.ensure(std::max(nfacet, 1), s, false);
         k_fill<<<nblk(nfacet), 256, 0, s>>>(nfacet, first.p, 0x7fffffff);   // "no triangle yet"
         if (nftri) k_facet_first<<<nblk(nftri), 256, 0, s>>>(nftri, d_ftf, nfacet, first.p, err);
@@ -718,6 +812,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         if (round >= opt->max_rounds) { status = 1; break; }
         E.cur_round = round;
         E.arena_round();
+        // slots appended since the last renumbering are in priority order,
+        // scattered in space: renumber once they are a tenth of the mesh
+        if (!noalloc && E.M.nt - E.nt_ordered > std::max(E.M.nt / 10, 65536)) {
+            E.reorder();
+            if (verbose) fprintf(stderr, "qm: round %d: tets renumbered in Morton order (%d live)\n", round, E.M.nt);
+        }
         // step 1: classify, in the paper's order (a class is skipped on the
         // device when an earlier one has candidates); one synchronisation
         // candidates go straight to the first candidate array, sized for the
@@ -808,8 +908,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                     E.pbegin(8);
                     const GrowTiles HT = hybrid_tiles();
                     const size_t block = lists_slab_bytes(HT);
-                    const int grid = std::min(nover, noalloc ? 4 : 1024);
-                    E.hslab.ensure(block * grid, s, false);
+                    const int grid = E.slab_grid(std::min(nover, noalloc ? 4 : 1024), block, E.hslab.cap);
+                    E.hslab.ensure_exact(block * grid, s);
                     k_grow_hybrid<H_LANES, H_HCAP, H_RFHCAP, H_QHCAP><<<grid, H_LANES, 0, s>>>(
                         E.M, cls, E.C, E.PL, BPr, E.olist.p, nover, HT, E.hslab.p, block);
                     E.pend(8);
@@ -821,8 +921,9 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                     int grid = (int)std::min<size_t>({(size_t)nbig, 1024,
                                                       std::max<size_t>(1, (8ull << 30) / slab_block)});
                     if (noalloc) grid = std::min(grid, 2);
+                    grid = E.slab_grid(grid, slab_block, E.slab.cap);
                     E.pbegin(9);
-                    E.slab.ensure(slab_block * grid, s, false);
+                    E.slab.ensure_exact(slab_block * grid, s);
                     k_grow_global<B_LANES><<<grid, B_LANES, 0, s>>>(E.M, cls, E.C, E.PL, BPr, E.glist.p, nbig, BT, E.slab.p,
                                                       slab_block);
                     E.pend(9);
@@ -994,6 +1095,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         int ntot = E.M.nt;
         DBuf<int> tf, ts, ff, fs;
         tf.ar = ts.ar = ff.ar = fs.ar = ar;
+        tf.acct = ts.acct = ff.acct = fs.acct = &E.acct;
         tf.ensure(ntot, s, false); ts.ensure(ntot, s, false);
         ff.ensure(4 * (size_t)ntot, s, false); fs.ensure(4 * (size_t)ntot, s, false);
         k_out_flags<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ff.p);
@@ -1018,6 +1120,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         } else {
             DBuf<int> ot, osf, osff;
             DBuf<double> ox;
+            ot.acct = osf.acct = osff.acct = &E.acct;
+            ox.acct = &E.acct;
             ot.ensure(4 * (size_t)std::max(a, 1), s, false);
             osf.ensure(3 * (size_t)std::max(b, 1), s, false);
             osff.ensure(std::max(b, 1), s, false);
@@ -1072,6 +1176,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     }
     ST.rounds = round;
     ST.status = status;
+    ST.device_bytes_peak = (int64_t)E.acct.peak;
     ST.nv_out = E.M.nv;
     ST.seconds_setup = ms_setup * 1e-3;
     ST.seconds_refine = ms_ref * 1e-3;
@@ -1085,12 +1190,15 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     return status == 1 ? QM_EROUNDS : QM_OK;
 }
 
-extern "C" {
-
-int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream, qm_result** out) {
+// One refinement with errors turned into return codes; mem_cap > 0 bounds
+// the slab tiles of the larger grow tiers to what fits beside the call's
+// other buffers in that many bytes (the served form passes each job's
+// admitted estimate).
+static int refine_within(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
+                         qm_result** out, size_t mem_cap) {
     g_err.clear();
     try {
-        return run_refine(plc, in, opt, (hipStream_t)hip_stream, out);
+        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap);
     } catch (const QmError& e) {
         g_err = e.what();
         return e.code;
@@ -1101,6 +1209,12 @@ int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void*
         g_err = "unknown failure";
         return QM_EINTERNAL;
     }
+}
+
+extern "C" {
+
+int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream, qm_result** out) {
+    return refine_within(plc, in, opt, (hipStream_t)hip_stream, out, 0);
 }
 
 }  // extern "C"

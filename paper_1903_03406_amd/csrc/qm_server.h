@@ -87,7 +87,7 @@ void srv_worker(qm_server* S) {
         const auto t_start = srv_clock::now();
         SrvDone d;
         if (ok) {
-            d.code = qm_refine(&J->plc, &J->mesh, &J->opt, st, &d.res);
+            d.code = refine_within(&J->plc, &J->mesh, &J->opt, st, &d.res, J->est);
             if (d.code != QM_OK && d.code != QM_EROUNDS) d.msg = qm_last_error();
         } else {
             d.code = QM_EDEVICE;
@@ -117,14 +117,14 @@ extern "C" {
 
 size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options* opt) {
     if (!plc || !in || !opt || in->nt < 0 || in->nv < 0) return 0;
-    // Output tets per input tet: Steiner points grow the mesh a few times at
-    // moderate bounds and more at tight ones.  Per output tet the device holds
-    // the mesh arrays (vertices, adjacency, face and edge marks, 84 B), the
-    // per-candidate arrays and the grow pools of a round; 256 B covers them,
-    // and growable buffers over-allocate by up to half again.
-    const double grow = opt->B < 1.6 ? 8.0 : 4.0;
-    const double tets = (double)in->nt * grow + 4096.0;
-    return (size_t)(tets * 256.0 * 1.5) + ((size_t)64 << 20);
+    // Measured peaks of single refinements (qm_stats.device_bytes_peak) stay
+    // below 8 KB per input tet at B >= 1.6 and 16 KB at tighter bounds once
+    // the slab tiles are held to a quarter of the budget: the mesh grows 2-4x (7x at
+    // B = 1.4), and a bad-tet round's candidate arrays, result pools and
+    // selection words dominate.  320 MiB covers the fixed buffers; a served
+    // job runs with its estimate as its budget.
+    const double per_tet = opt->B < 1.6 ? 16384.0 : 8192.0;
+    return (size_t)((double)in->nt * per_tet) + ((size_t)320 << 20);
 }
 
 int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out) {

@@ -144,6 +144,56 @@ __global__ void k_min_edge(int nt, Mesh M, unsigned long long* out) {
     atomicMin(out, (unsigned long long)__double_as_longlong(m));
 }
 
+// ------------------------------------------------------------------ slot order
+// Tets are renumbered now and then in Morton order of their centroids, so
+// that tets near each other in space sit near each other in memory and one
+// cache line serves several gathers of a region.  Slots never decide a
+// result, so the order is free.
+QMD unsigned spread3(unsigned x) {      // 10 bits -> every third of 30 bits
+    x &= 0x3FFu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+__global__ void k_order_keys(Mesh M, unsigned long long* key, int* val, int* nalive) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M.nt) return;
+    val[t] = t;
+    if (!(M.TI[t] & TI_ALIVE)) { key[t] = 0xFFFFFFFF00000000ull | (unsigned)t; return; }
+    atomicAdd(nalive, 1);
+    const int4 v = ld4(M.TV, t);
+    const double4 a = M.X[v.x], b = M.X[v.y], c = M.X[v.z], d = M.X[v.w];
+    auto q = [](double s) { int k = (int)(s * 256.0); return (unsigned)(k < 0 ? 0 : (k > 1023 ? 1023 : k)); };
+    const unsigned m = spread3(q(a.x + b.x + c.x + d.x)) | (spread3(q(a.y + b.y + c.y + d.y)) << 1) |
+                       (spread3(q(a.z + b.z + c.z + d.z)) << 2);
+    key[t] = ((unsigned long long)m << 32) | (unsigned)t;
+}
+// new slot of every old slot (dead ones land after the live ones)
+__global__ void k_order_perm(int nt, const int* order, int* perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nt) perm[order[i]] = i;
+}
+// live tets gathered into their new slots, neighbour links renumbered
+__global__ void k_order_gather(int nlive, const int* order, const int* perm, Mesh M, int* TV, int* TA, int* TF,
+                               int* TS, unsigned* TI) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlive) return;
+    const int t = order[i];
+    *reinterpret_cast<int4*>(TV + 4 * (size_t)i) = ld4(M.TV, t);
+    *reinterpret_cast<int4*>(TF + 4 * (size_t)i) = ld4(M.TF, t);
+    int4 a = ld4(M.TA, t);
+    auto re = [&](int nb) { return nb < 0 ? -1 : (perm[nb >> 2] << 2) | (nb & 3); };
+    *reinterpret_cast<int4*>(TA + 4 * (size_t)i) = make_int4(re(a.x), re(a.y), re(a.z), re(a.w));
+    for (int e = 0; e < 6; ++e) TS[6 * (size_t)i + e] = M.TS[6 * (size_t)t + e];
+    TI[i] = M.TI[t];
+}
+__global__ void k_order_stet(int nss, const int* perm, int* STET) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nss) STET[s] = perm[STET[s]];
+}
+
 // ------------------------------------------------------------------ output
 __global__ void k_out_flags(Mesh M, int* tflag, int* sfflag) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;

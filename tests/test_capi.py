@@ -44,14 +44,14 @@ def test_binding_has_no_cpu_path(monkeypatch, tmp_path):
 
 @pytest.mark.skipif(not os.path.exists(qm._SO), reason="libqm.so not built")
 def test_server_estimate_is_host_arithmetic():
-    """qm_estimate_bytes needs no device: 256 B per estimated output tet with
-    1.5x growth slack plus 64 MiB; output tets 8x the input at B < 1.6, else 4x."""
+    """qm_estimate_bytes needs no device: 8 KB per input tet at B >= 1.6,
+    16 KB below, plus 320 MiB."""
     import qm_inputs as qi
     w = qi.uniform_cube(60, seed=3, B=2.0)
     nt = len(w.tets)
-    assert qm.estimate_bytes(w) == int((nt * 4.0 + 4096.0) * 256.0 * 1.5) + (64 << 20)
+    assert qm.estimate_bytes(w) == nt * 8192 + (320 << 20)
     w.B = 1.4
-    assert qm.estimate_bytes(w) == int((nt * 8.0 + 4096.0) * 256.0 * 1.5) + (64 << 20)
+    assert qm.estimate_bytes(w) == nt * 16384 + (320 << 20)
 
 
 def test_binding_constants_match_the_header():

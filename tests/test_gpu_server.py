@@ -79,10 +79,21 @@ def test_admission_against_the_budget(big, jobs):
 
 
 def test_estimate_covers_the_job(jobs):
-    with qm.Server(8 * GiB, nworkers=1) as srv:
-        for w in jobs:
+    """Every served job's own peak of device memory (its buffers, including
+    the larger grow tiers' slab tiles, which shrink to the job's budget)
+    stays within the estimate it was admitted with, also for a clustered job
+    whose regions are large for its size."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    pts = np.concatenate([qi.gaussmix_interior(rng, 9000), qi.uniform_interior(rng, 1000)])
+    clustered = qi.make_workload("srv_clustered10k", pts, 1.4, [qi.sphere_inside(r) for r in (0.15, 0.30, 0.45)])
+    with qm.Server(64 * GiB, nworkers=2) as srv:
+        for w in jobs + [clustered]:
             est = srv.estimate_bytes(w)
-            assert est >= (64 << 20) + 256 * len(w.tets)
+            got = srv.result(srv.submit(w))
+            print(f"[server] {w.name}: peak {got.device_bytes_peak >> 20} MiB, estimate {est >> 20} MiB",
+                  flush=True)
+            assert 0 < got.device_bytes_peak <= est, w.name
+            assert same(got, qm.refine_workload(w)), w.name
 
 
 def test_job_errors_and_tickets(jobs):
