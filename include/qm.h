@@ -296,6 +296,20 @@ int qm_server_info(qm_server* srv, qm_server_stats* info);
    concurrently with it or follow it. */
 void qm_server_destroy(qm_server* srv);
 
+/* Tests only: evaluate the device's exact predicates or FP64 constructions
+   on n point tuples (host arrays; the call copies them to the device and
+   back).  op and the tuple layout of `in` (points as x, y, z doubles):
+     0 orient3d(a,b,c,d)  1 insphere(a,b,c,d,e)  2 orient2d dropping axis
+     `param` (a,b,c)  3 segment encroachment (a,b,v)  4 equatorial-ball
+     encroachment (a,b,c,v)  5 orient3d for any finite points (a,b,c,d):
+     out[4i] is the sign (-1, 0, +1);
+     10 midpoint(a,b)  11 triangle circumcentre(a,b,c)  12 tet circumcentre
+     (a,b,c,d), out[4i..4i+3] = point and squared radius;  13 radius-edge
+     ratio above B = `param` (a,b,c,d): out[4i] = 1 or 0.
+   Ops 0-4 require lattice points of the cube (Section 1's exact
+   predicates; QM_EINVAL otherwise).  out holds 4 doubles per tuple. */
+int qm_test_geometry(int32_t op, int32_t n, const double* in, double param, double* out);
+
 /* Message of the last failure on this thread ("" if none). */
 const char* qm_last_error(void);
 

@@ -115,7 +115,7 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
+EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
            "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_poll", "qm_server_info",
            "qm_server_destroy")
@@ -391,6 +391,22 @@ def refine_workload(w, **kw) -> RefineResult:
     (xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, seg, B)."""
     return refine(w.xyz, w.tets, w.sf, w.sf_facet, w.ss, w.ss_seg, w.ftri, w.ftri_facet,
                   kw.pop("B", w.B), seg=w.seg, **kw)
+
+
+def test_geometry(op, tuples, param=0.0):
+    """Tests only (qm_test_geometry): the device predicates (ops 0-5, signs)
+    or constructions (10-13) on an (n, k, 3) array of point tuples; returns
+    an (n, 4) array."""
+    lib = _load()
+    lib.qm_test_geometry.restype = ctypes.c_int
+    lib.qm_test_geometry.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double,
+                                     ctypes.c_void_p]
+    a = np.ascontiguousarray(tuples, dtype=np.float64)
+    out = np.zeros((len(a), 4))
+    rc = lib.qm_test_geometry(int(op), len(a), a.ctypes.data, float(param), out.ctypes.data)
+    if rc != 0:
+        raise QmError(rc, lib.qm_last_error().decode())
+    return out
 
 
 def version() -> str:

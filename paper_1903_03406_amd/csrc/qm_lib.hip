@@ -1265,6 +1265,31 @@ int qm_refine_noalloc(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     }
 }
 
+// ---- tests only: the device predicates and constructions on given points
+__global__ void k_test_geometry(int op, int n, const double* in, double param, double* out, int* err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int w = op == 0 || op == 4 || op == 5 || op == 12 || op == 13 ? 12 : op == 1 ? 15 : op == 10 ? 6 : 9;
+    const double* q = in + (size_t)w * i;
+    double p[4] = {0, 0, 0, 0};
+    double* o = out + 4 * (size_t)i;
+    switch (op) {
+        case 0: o[0] = orient3d(q, q + 3, q + 6, q + 9, err); break;
+        case 1: o[0] = insphere(q, q + 3, q + 6, q + 9, q + 12, err); break;
+        case 2: o[0] = orient2d((int)param, q, q + 3, q + 6, err); break;
+        case 3: o[0] = segdot(q, q + 3, q + 6, err); break;
+        case 4: o[0] = facedot(q, q + 3, q + 6, q + 9, err); break;
+        case 5: o[0] = orient3d_any(q, q + 3, q + 6, q + 9, err); break;
+        case 10: midpoint(q, q + 3, p); break;
+        case 11: tri_cc(q, q + 3, q + 6, p); break;
+        case 12: tet_cc(q, q + 3, q + 6, q + 9, p, p[3]); break;
+        case 13: o[0] = is_bad(q, q + 3, q + 6, q + 9, param * param) ? 1.0 : 0.0; break;
+        default: atomicOr(err, 1 << 30); return;
+    }
+    if (op >= 10 && op <= 12)
+        for (int k = 0; k < 4; ++k) o[k] = p[k];
+}
+
 // Instances of a batch run concurrently: worker threads, each with its own
 // stream on the caller's device, take the instances in index order.
 int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
@@ -1336,6 +1361,38 @@ int qm_result_round_profile(const qm_result* r, double* buf, int32_t cap) {
 }
 
 void qm_result_free(qm_result* r) { delete r; }
+
+int qm_test_geometry(int32_t op, int32_t n, const double* in, double param, double* out) {
+    g_err.clear();
+    try {
+        if (n < 0 || (n > 0 && (!in || !out)) || !((op >= 0 && op <= 5) || (op >= 10 && op <= 13)))
+            throw QmError(QM_EINVAL, "bad arguments");
+        if (n == 0) return QM_OK;
+        const int w = op == 0 || op == 4 || op == 5 || op == 12 || op == 13 ? 12 : op == 1 ? 15 : op == 10 ? 6 : 9;
+        double *din = nullptr, *dout = nullptr;
+        int* derr = nullptr;
+        HIPCK(hipMalloc((void**)&din, sizeof(double) * w * (size_t)n));
+        HIPCK(hipMalloc((void**)&dout, sizeof(double) * 4 * (size_t)n));
+        HIPCK(hipMalloc((void**)&derr, sizeof(int)));
+        HIPCK(hipMemset(derr, 0, sizeof(int)));
+        HIPCK(hipMemcpy(din, in, sizeof(double) * w * (size_t)n, hipMemcpyHostToDevice));
+        k_test_geometry<<<nblk(n), 256>>>(op, n, din, param, dout, derr);
+        HIPCK(hipGetLastError());
+        int e = 0;
+        HIPCK(hipMemcpy(out, dout, sizeof(double) * 4 * (size_t)n, hipMemcpyDeviceToHost));
+        HIPCK(hipMemcpy(&e, derr, sizeof(int), hipMemcpyDeviceToHost));
+        (void)hipFree(din); (void)hipFree(dout); (void)hipFree(derr);
+        if (e) throw QmError(QM_EINVAL, "a point is off the lattice or outside the cube (error word " +
+                                            std::to_string(e) + ")");
+        return QM_OK;
+    } catch (const QmError& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return QM_EINTERNAL;
+    }
+}
 
 const char* qm_last_error(void) { return g_err.c_str(); }
 
