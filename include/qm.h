@@ -83,6 +83,9 @@ typedef struct qm_mesh {
                                 claim sets and full validation, so the output is a CDT of the
                                 same kind, but which points win depends on timing: the result
                                 is not reproducible and not the oracle's. */
+#define QM_OUTPUT_DEVICE 512u   /* the result's output arrays stay on the device (same device):
+                                   qm_result_view returns device pointers, valid until
+                                   qm_result_free; records and statistics stay on the host */
 #define QM_TEST_ERROR_WORD 16u  /* tests only: raise this call's device error word at set-up, so
                                    the call ends with QM_EINTERNAL (the word is per call: other
                                    calls, concurrent or later, are not affected) */
@@ -175,9 +178,10 @@ int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void*
 int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
                     int32_t nstreams, qm_result** outs, int32_t* codes);
 
-/* Host view of a result: the output mesh (Steiner vertices appended after the
-   input vertices, numbered by round and priority) and the statistics.
-   Pointers stay valid until qm_result_free. */
+/* View of a result: the output mesh (Steiner vertices appended after the
+   input vertices, numbered by round and priority) and the statistics.  The
+   arrays are host memory, or device memory when the refinement ran with
+   QM_OUTPUT_DEVICE.  Pointers stay valid until qm_result_free. */
 int qm_result_view(const qm_result* r, qm_mesh* view, qm_stats* stats);
 
 /* Copy at most `cap` rounds of per-round records (QM_ROUND_FIELDS each) into
@@ -263,7 +267,9 @@ size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options*
 
 /* Create a server on the calling thread's current device with `nworkers`
    (1..64) worker threads, each owning a HIP stream (non-blocking, default
-   priority) on which it runs one job at a time.  `hbm_budget_bytes` bounds
+   priority) on which it runs one job at a time.  With nworkers = 0 the
+   server is stepped: admitted jobs stay resident on the device between
+   rounds and advance only through qm_server_step.  `hbm_budget_bytes` bounds
    the summed estimates of admitted, unfinished jobs.  *out is freed with
    qm_server_destroy. */
 int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out);
@@ -287,6 +293,15 @@ int qm_server_submit(qm_server* srv, const qm_plc* plc, const qm_mesh* in, const
    completion.  A ticket is collected once; unknown tickets give QM_EINVAL. */
 int qm_server_poll(qm_server* srv, uint64_t ticket, int32_t wait_ms, qm_result** out, int32_t* code,
                    double* seconds);
+
+/* Stepped server only: jobs admitted since the last step are set up on the
+   device (each on a stream of its own), then every resident job runs one
+   round of the paper's round loop (Section 2), all concurrently; returns
+   when every one has completed it.  Jobs that finish (no work left, or
+   their round guard) hand their result to qm_server_poll.  *nresident
+   receives the number of jobs still resident.  QM_EINVAL on a server with
+   workers. */
+int qm_server_step(qm_server* srv, int32_t* nresident);
 
 /* Counters of the server (a consistent snapshot). */
 int qm_server_info(qm_server* srv, qm_server_stats* info);

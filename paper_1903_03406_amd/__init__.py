@@ -30,6 +30,7 @@ QM_PROFILE = 2
 QM_PROFILE_GROW = 8   # time only the small-tile grow launches (family grow_validate)
 QM_VERBOSE = 4
 QM_EARLY_STOP = 256       # non-parity mode: early-stop blasting (timing-dependent result)
+QM_OUTPUT_DEVICE = 512    # the result's arrays stay on the device
 QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through its own error word
 QM_TEST_TIER1 = 32        # tests only: every region grown with the medium tiles (or larger)
 QM_TEST_TIER2 = 64        # tests only: every region grown with the global-memory tiles
@@ -117,7 +118,8 @@ def _load():
 
 EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
-           "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_poll", "qm_server_info",
+           "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_step", "qm_server_poll",
+           "qm_server_info",
            "qm_server_destroy")
 
 
@@ -409,6 +411,40 @@ def test_geometry(op, tuples, param=0.0):
     return out
 
 
+def refine_to_device(w, *, hmin_factor=0.5, max_rounds=100000):
+    """Refine workload w with QM_OUTPUT_DEVICE: the output mesh stays in
+    device memory.  Returns (dict of torch CUDA tensors copied device to
+    device from the result's arrays: xyz, tets, sf, sf_facet, ss, ss_seg;
+    the result's statistics)."""
+    import torch
+    lib = _load()
+    keep = []
+    plc, mesh = _marshal(w, keep)
+    opts = _Opts(float(w.B), float(hmin_factor), int(max_rounds), 0, QM_OUTPUT_DEVICE)
+    res = ctypes.c_void_p()
+    rc = lib.qm_refine(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(res))
+    if rc not in (0, -4):
+        raise QmError(rc, lib.qm_last_error().decode())
+    try:
+        view, st = _Mesh(), _Stats()
+        lib.qm_result_view(res, ctypes.byref(view), ctypes.byref(st))
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        out = {}
+        for name, p, n, cols, dt in (("xyz", view.xyz, view.nv, 3, torch.float64), ("tets", view.tet, view.nt, 4, torch.int32),
+                                     ("sf", view.sf, view.nsf, 3, torch.int32), ("sf_facet", view.sf_facet, view.nsf, 1, torch.int32),
+                                     ("ss", view.ss, view.nss, 2, torch.int32), ("ss_seg", view.ss_seg, view.nss, 1, torch.int32)):
+            t = torch.empty((n, cols) if cols > 1 else (n,), dtype=dt, device="cuda")
+            if n:
+                e = hip.hipMemcpy(t.data_ptr(), p, t.numel() * t.element_size(), 3)   # device to device
+                if e != 0:
+                    raise QmError(-5, f"hipMemcpy failed ({e})")
+            out[name] = t
+        return out, {"rounds": int(st.rounds), "nv_out": int(st.nv_out), "nt_out": int(st.nt_out)}
+    finally:
+        lib.qm_result_free(res)
+
+
 def version() -> str:
     return _load().qm_version().decode()
 
@@ -466,6 +502,17 @@ class Server:
 
     def estimate_bytes(self, w, *, hmin_factor=0.5) -> int:
         return estimate_bytes(w, hmin_factor=hmin_factor)
+
+    def step(self) -> int:
+        """Stepped server (nworkers=0): one round for every resident job
+        (qm_server_step); returns the number still resident."""
+        self._lib.qm_server_step.restype = ctypes.c_int
+        self._lib.qm_server_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+        n = ctypes.c_int32()
+        rc = self._lib.qm_server_step(self._h, ctypes.byref(n))
+        if rc:
+            raise QmError(rc, self._lib.qm_last_error().decode())
+        return int(n.value)
 
     def submit(self, w, *, est_bytes=0, hmin_factor=0.5, max_rounds=100000, max_kept=0, profile=False):
         """Ticket of the admitted job, or None when the budget has no room

@@ -19,6 +19,7 @@
 #include <atomic>
 #include <memory>
 #include <mutex>
+#include <condition_variable>
 
 #include "qm.h"
 #include "qm_insert.h"
@@ -146,6 +147,15 @@ T read1(const T* dptr, hipStream_t s) {
 struct qm_result {
     std::vector<double> xyz;
     std::vector<int32_t> tets, sf, sff, ss, ssg;
+    // QM_OUTPUT_DEVICE: the output arrays stay on the device (hipMalloc)
+    bool on_device = false;
+    double* d_xyz = nullptr;
+    int32_t *d_tets = nullptr, *d_sf = nullptr, *d_sff = nullptr, *d_ss = nullptr, *d_ssg = nullptr;
+    int32_t dnv = 0, dnt = 0, dnsf = 0, dnss = 0;
+    ~qm_result() {
+        for (void* p : {(void*)d_xyz, (void*)d_tets, (void*)d_sf, (void*)d_sff, (void*)d_ss, (void*)d_ssg})
+            if (p) (void)hipFree(p);
+    }
     std::vector<int32_t> rounds;   // QM_ROUND_FIELDS per round
     std::vector<int32_t> last;     // last round's candidates, 9 per candidate
     std::vector<double> round_ms;  // QM_PROFILE: QM_PROF_FAMILIES device ms per round
@@ -630,6 +640,45 @@ struct Engine {
 
 using namespace qm;
 
+// Stepped serving: a job's round loop waits at this gate before each round
+// until the server grants it one, and reports each finished round; the
+// server's step grants one round to every resident job and waits for all.
+struct RoundGate {
+    std::mutex mu;
+    std::condition_variable cv;
+    int granted = 0, done = 0;
+    bool finished = false, cancel = false;
+    void begin_round() {              // job side
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return granted > done || cancel; });
+        if (cancel) throw QmError(QM_EAGAIN, "job cancelled by the server's shutdown");
+    }
+    void end_round() {
+        std::lock_guard<std::mutex> lk(mu);
+        ++done;
+        cv.notify_all();
+    }
+    void finish() {
+        std::lock_guard<std::mutex> lk(mu);
+        finished = true;
+        cv.notify_all();
+    }
+    void grant() {                    // server side
+        std::lock_guard<std::mutex> lk(mu);
+        ++granted;
+        cv.notify_all();
+    }
+    void wait_round() {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return done >= granted || finished; });
+    }
+    void stop() {
+        std::lock_guard<std::mutex> lk(mu);
+        cancel = true;
+        cv.notify_all();
+    }
+};
+
 // One refinement.  Normal form: buffers from the stream-ordered allocator,
 // result in *out (host arrays).  No-alloc form (ar != nullptr): every device
 // buffer is carved from the arena, inputs are device arrays, the output mesh
@@ -637,7 +686,7 @@ using namespace qm;
 // *dstats; no qm_result, pinned buffer or event is created.
 static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
                       qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
-                      qm_stats* dstats = nullptr, size_t mem_cap = 0) {
+                      qm_stats* dstats = nullptr, size_t mem_cap = 0, RoundGate* gate = nullptr) {
     auto T0 = std::chrono::steady_clock::now();
     const bool noalloc = ar != nullptr;
     if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
@@ -809,6 +858,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         fprintf(stderr, "qm: round %d class %d %s (%d)\n", round_, cls_, phase, n_);
     };
     for (;; ++round) {
+        if (gate) gate->begin_round();        // stepped serving: wait for the server's step
         if (round >= opt->max_rounds) { status = 1; break; }
         E.cur_round = round;
         E.arena_round();
@@ -1057,6 +1107,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         ST.candidates += ncand;
         ST.mis_passes += passes;
         ST.deferred += st[14];
+        if (gate) {                           // the round is complete on the device
+            HIPCK(hipStreamSynchronize(s));
+            gate->end_round();
+        }
     }
     if (!noalloc) HIPCK(hipEventRecord(e2, s));
     sync_counters();
@@ -1117,6 +1171,24 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 HIPCK(hipMemcpyAsync(dout->ss_seg, E.SSEG.p, sizeof(int) * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
             }
             HIPCK(hipStreamSynchronize(s));
+        } else if (opt->flags & QM_OUTPUT_DEVICE) {   // the result stays on the device
+            HIPCK(hipStreamSynchronize(s));
+            auto dalloc = [&](auto** p, size_t n) {
+                HIPCK(hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(**p)));
+            };
+            dalloc(&R->d_xyz, 3 * (size_t)E.M.nv); dalloc(&R->d_tets, 4 * (size_t)a);
+            dalloc(&R->d_sf, 3 * (size_t)b); dalloc(&R->d_sff, (size_t)b);
+            dalloc(&R->d_ss, 2 * (size_t)E.M.nss); dalloc(&R->d_ssg, (size_t)E.M.nss);
+            k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, R->d_tets);
+            if (b) k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, R->d_sf, R->d_sff);
+            k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, R->d_xyz);
+            if (E.M.nss) {
+                HIPCK(hipMemcpyAsync(R->d_ss, E.SV.p, sizeof(int) * 2 * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+                HIPCK(hipMemcpyAsync(R->d_ssg, E.SSEG.p, sizeof(int) * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+            }
+            HIPCK(hipStreamSynchronize(s));
+            R->on_device = true;
+            R->dnv = E.M.nv; R->dnt = a; R->dnsf = b; R->dnss = E.M.nss;
         } else {
             DBuf<int> ot, osf, osff;
             DBuf<double> ox;
@@ -1195,10 +1267,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
 // other buffers in that many bytes (the served form passes each job's
 // admitted estimate).
 static int refine_within(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
-                         qm_result** out, size_t mem_cap) {
+                         qm_result** out, size_t mem_cap, RoundGate* gate = nullptr) {
     g_err.clear();
     try {
-        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap);
+        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap, gate);
     } catch (const QmError& e) {
         g_err = e.what();
         return e.code;
@@ -1329,7 +1401,11 @@ int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const 
 
 int qm_result_view(const qm_result* r, qm_mesh* v, qm_stats* st) {
     if (!r) { g_err = "null result"; return QM_EINVAL; }
-    if (v) {
+    if (v && r->on_device) {
+        v->nv = r->dnv; v->xyz = r->d_xyz; v->nt = r->dnt; v->tet = r->d_tets;
+        v->nsf = r->dnsf; v->sf = r->d_sf; v->sf_facet = r->d_sff;
+        v->nss = r->dnss; v->ss = r->d_ss; v->ss_seg = r->d_ssg;
+    } else if (v) {
         v->nv = (int32_t)(r->xyz.size() / 3); v->xyz = r->xyz.data();
         v->nt = (int32_t)(r->tets.size() / 4); v->tet = r->tets.data();
         v->nsf = (int32_t)r->sff.size(); v->sf = r->sf.data(); v->sf_facet = r->sff.data();

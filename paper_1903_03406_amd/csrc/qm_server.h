@@ -9,6 +9,11 @@
 // admitted and not finished; otherwise submission returns QM_EAGAIN and the
 // caller retries later.  Workers take admitted jobs first come, first served;
 // a finished job's estimate is released before its result is handed out.
+//
+// Stepped form (created with no workers): admitted jobs become resident on
+// the device, each set up by a thread of its own on its own stream, and
+// advance only when the caller calls qm_server_step, which gives every
+// resident job one round and returns when all have completed it.
 #pragma once
 
 #include <chrono>
@@ -40,6 +45,15 @@ struct SrvDone {
     double wait_s = 0, total_s = 0;
 };
 
+// a resident job of the stepped form: its refinement runs in `th` and waits
+// at `gate` before every round
+struct SrvResident {
+    std::unique_ptr<SrvJob> J;
+    RoundGate gate;
+    std::thread th;
+    SrvDone d;
+};
+
 // copy n*cols elements of a borrowed host array; false when a non-empty
 // array has no pointer
 template <class T>
@@ -66,6 +80,8 @@ struct qm_server {
     int running = 0;
     int64_t admitted = 0, refused = 0, completed = 0;
     std::vector<std::thread> workers;
+    bool stepped = false;                                  // no workers: qm_server_step drives the jobs
+    std::vector<std::unique_ptr<SrvResident>> resident_jobs;
 };
 
 namespace {
@@ -111,6 +127,27 @@ void srv_worker(qm_server* S) {
     }
 }
 
+// the thread of one resident job of the stepped form
+void srv_resident_run(int dev, SrvResident* R) {
+    hipStream_t st = nullptr;
+    const auto t_start = srv_clock::now();
+    if (hipSetDevice(dev) == hipSuccess && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess) {
+        R->d.code = refine_within(&R->J->plc, &R->J->mesh, &R->J->opt, st, &R->d.res, R->J->est, &R->gate);
+        if (R->d.code != QM_OK && R->d.code != QM_EROUNDS) R->d.msg = qm_last_error();
+    } else {
+        R->d.code = QM_EDEVICE;
+        R->d.msg = "resident job has no HIP stream";
+    }
+    if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    const auto t_end = srv_clock::now();
+    R->d.wait_s = std::chrono::duration<double>(t_start - R->J->t_sub).count();
+    R->d.total_s = std::chrono::duration<double>(t_end - R->J->t_sub).count();
+    R->gate.finish();
+}
+
 }  // namespace
 
 extern "C" {
@@ -129,7 +166,7 @@ size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options*
 
 int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out) {
     g_err.clear();
-    if (!out || nworkers < 1 || nworkers > 64 || hbm_budget_bytes == 0) {
+    if (!out || nworkers < 0 || nworkers > 64 || hbm_budget_bytes == 0) {
         g_err = "bad server arguments";
         return QM_EINVAL;
     }
@@ -137,6 +174,7 @@ int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out)
     auto S = std::make_unique<qm_server>();
     if (hipGetDevice(&S->dev) != hipSuccess) { g_err = "no HIP device"; return QM_EDEVICE; }
     S->budget = hbm_budget_bytes;
+    S->stepped = nworkers == 0;
     try {
         for (int i = 0; i < nworkers; ++i) S->workers.emplace_back(srv_worker, S.get());
     } catch (const std::exception& e) {
@@ -224,6 +262,58 @@ int qm_server_poll(qm_server* S, uint64_t ticket, int32_t wait_ms, qm_result** o
     return QM_OK;
 }
 
+int qm_server_step(qm_server* S, int32_t* nresident) {
+    g_err.clear();
+    if (!S) { g_err = "null argument"; return QM_EINVAL; }
+    if (!S->stepped) { g_err = "this server runs its jobs with its own workers"; return QM_EINVAL; }
+    try {
+        // admitted jobs become resident: set up on the device by their thread
+        std::vector<std::unique_ptr<SrvJob>> fresh;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            while (!S->queue.empty()) {
+                fresh.push_back(std::move(S->queue.front()));
+                S->queue.pop_front();
+            }
+        }
+        for (auto& J : fresh) {
+            auto R = std::make_unique<SrvResident>();
+            R->J = std::move(J);
+            R->th = std::thread(srv_resident_run, S->dev, R.get());
+            S->resident_jobs.push_back(std::move(R));
+        }
+        // one round for every resident job, all at once
+        for (auto& R : S->resident_jobs) R->gate.grant();
+        for (auto& R : S->resident_jobs) R->gate.wait_round();
+        // finished jobs hand out their results
+        std::vector<std::unique_ptr<SrvResident>> keep;
+        for (auto& R : S->resident_jobs) {
+            bool fin;
+            {
+                std::lock_guard<std::mutex> lk(R->gate.mu);
+                fin = R->gate.finished;
+            }
+            if (!fin) { keep.push_back(std::move(R)); continue; }
+            R->th.join();
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->resident -= R->J->est;
+            ++S->completed;
+            S->done[R->J->ticket] = std::move(R->d);
+        }
+        S->resident_jobs = std::move(keep);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->running = (int)S->resident_jobs.size();
+        }
+        S->cv_done.notify_all();
+        if (nresident) *nresident = (int32_t)S->resident_jobs.size();
+        return QM_OK;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return QM_EINTERNAL;
+    }
+}
+
 int qm_server_info(qm_server* S, qm_server_stats* info) {
     g_err.clear();
     if (!S || !info) { g_err = "null argument"; return QM_EINVAL; }
@@ -248,6 +338,11 @@ void qm_server_destroy(qm_server* S) {
     }
     S->cv_work.notify_all();
     for (auto& t : S->workers) t.join();
+    for (auto& R : S->resident_jobs) {      // stepped form: unfinished jobs are stopped
+        R->gate.stop();
+        R->th.join();
+        qm_result_free(R->d.res);
+    }
     for (auto& kv : S->done) qm_result_free(kv.second.res);
     delete S;
 }

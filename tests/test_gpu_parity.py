@@ -111,6 +111,21 @@ def test_equal_keys_parity(n, seed, B, spheres):
     assert_same(g, o, f"equal keys n={n}")
 
 
+def test_device_resident_output():
+    """QM_OUTPUT_DEVICE: the output mesh stays in device memory; copied out,
+    it equals the host result bit for bit."""
+    w = qi.uniform_cube(600, seed=5, B=1.6, spheres=(0.25,))
+    d, st = qm.refine_to_device(w)
+    h = qm.refine_workload(w)
+    assert all(t.is_cuda for t in d.values())
+    assert st["rounds"] == h.rounds and st["nt_out"] == len(h.tets)
+    assert np.array_equal(d["xyz"].cpu().numpy().view(np.uint64), h.xyz.view(np.uint64))
+    assert np.array_equal(canon_tets(d["tets"].cpu().numpy()), canon_tets(h.tets))
+    assert np.array_equal(canon_tri(d["sf"].cpu().numpy(), d["sf_facet"].cpu().numpy()),
+                          canon_tri(h.sf, h.sf_facet))
+    assert np.array_equal(canon_tri(d["ss"].cpu().numpy(), d["ss_seg"].cpu().numpy()), canon_tri(h.ss, h.ss_seg))
+
+
 def test_ellipsoid_instance_parity():
     # a small instance of the batched workload's generator (rotated ellipsoid)
     rng = np.random.Generator(np.random.PCG64(44))

@@ -153,3 +153,43 @@ def test_admission_under_pressure(jobs):
     alone = {id(w): qm.refine_workload(w) for w in jobs}
     for k, w in enumerate(order):
         assert same(done[k], alone[id(w)]), (k, w.name)
+
+
+def test_stepped_server_advances_one_round_per_step(jobs):
+    """With no workers the server is stepped (qm_server_step): resident jobs
+    stay on the device and each step runs one round of every one of them,
+    so the jobs finish after as many steps as their rounds (plus the last
+    classification, which finds no work), with the results they have alone.
+    A job submitted between steps joins at the next one; a server destroyed
+    with resident jobs stops them."""
+    first, late = jobs[1:4], jobs[4]
+    alone = {w.name: qm.refine_workload(w) for w in first + [late]}
+    with qm.Server(8 * GiB, nworkers=0) as srv:
+        tickets = {srv.submit(w): w for w in first}
+        steps, t_late = 0, None
+        while True:
+            n = srv.step()
+            steps += 1
+            if steps == 3:
+                t_late = srv.submit(late)
+                tickets[t_late] = late
+            if n == 0 and steps > 3:
+                break
+        got = {w.name: srv.result(t) for t, w in tickets.items()}
+        with pytest.raises(qm.QmError, match="EINVAL"):
+            qm.Server(GiB, nworkers=1).step()
+    for name, g in got.items():
+        assert same(g, alone[name]), name
+    want = max(max(alone[w.name].rounds + 1 for w in first), 3 + alone[late.name].rounds + 1)
+    print(f"[server] stepped: {steps} steps, expected {want}", flush=True)
+    assert steps == want
+    srv = qm.Server(8 * GiB, nworkers=0)
+    srv.submit(jobs[0])
+    srv.step()
+    srv.step()
+    srv.close()                                          # stops the resident job
+    with qm.Server(8 * GiB, nworkers=0) as srv2:         # the device is usable afterwards
+        t = srv2.submit(jobs[4])
+        while srv2.step():
+            pass
+        assert same(srv2.result(t), alone[jobs[4].name])
