@@ -178,6 +178,20 @@ int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void*
 int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
                     int32_t nstreams, qm_result** outs, int32_t* codes);
 
+/* Refine n independent instances in lockstep on one stream: every instance
+   runs the round loop of paper, Section 2, on its own mesh, and each phase
+   of a round (classification, splitting points, location, region growth and
+   validation, verdicts, selection, insertion) is one launch over the work of
+   all instances in that phase, each instance picking its own class.  Each
+   result is bit-identical to qm_refine on the same instance.  Arguments as
+   qm_refine_batch, with `hip_stream` (a hipStream_t, NULL: default stream)
+   in place of the stream count.  Options may not ask for profiling
+   (QM_PROFILE, QM_PROFILE_GROW), QM_EARLY_STOP or max_kept > 0: such an
+   instance ends with QM_EINVAL and the others go on.  Every instance's mesh
+   stays on the device until it finishes. */
+int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                       void* hip_stream, qm_result** outs, int32_t* codes);
+
 /* View of a result: the output mesh (Steiner vertices appended after the
    input vertices, numbered by round and priority) and the statistics.  The
    arrays are host memory, or device memory when the refinement ran with

@@ -116,7 +116,7 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
+EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_refine_lockstep", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
            "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_step", "qm_server_poll",
            "qm_server_info",
@@ -381,6 +381,35 @@ def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, m
             results.append(_take_result(lib, ctypes.c_void_p(outs[i]), profile))
         else:
             results.append(None)
+    if return_codes:
+        return results, [int(codes[i]) for i in range(n)]
+    if rc not in (0, -4):
+        raise QmError(rc, lib.qm_last_error().decode())
+    return results
+
+
+def refine_lockstep(workloads, *, hmin_factor=0.5, max_rounds=100000, extra_flags=None, return_codes=False,
+                    max_kept=0) -> list:
+    """Refine independent instances in lockstep (qm_refine_lockstep): one
+    launch per phase per round over all instances, on the default stream.
+    max_rounds may be one value or one per instance.  Results and
+    return_codes as refine_batch."""
+    lib = _load()
+    n = len(workloads)
+    plcs, meshes, opts, keep = (_Plc * n)(), (_Mesh * n)(), (_Opts * n)(), []
+    for i, w in enumerate(workloads):
+        plcs[i], meshes[i] = _marshal(w, keep)
+        mr = max_rounds[i] if isinstance(max_rounds, (list, tuple)) else max_rounds
+        opts[i] = _Opts(float(w.B), float(hmin_factor), int(mr), int(max_kept),
+                        int(extra_flags[i]) if extra_flags else 0)
+    outs = (ctypes.c_void_p * max(n, 1))()
+    codes = (ctypes.c_int32 * max(n, 1))()
+    lib.qm_refine_lockstep.restype = ctypes.c_int
+    lib.qm_refine_lockstep.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    rc = lib.qm_refine_lockstep(n, ctypes.addressof(plcs), ctypes.addressof(meshes), ctypes.addressof(opts),
+                                None, ctypes.addressof(outs), ctypes.addressof(codes))
+    results = [_take_result(lib, ctypes.c_void_p(outs[i]), False) if outs[i] else None for i in range(n)]
     if return_codes:
         return results, [int(codes[i]) for i in range(n)]
     if rc not in (0, -4):

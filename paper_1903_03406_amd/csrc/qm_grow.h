@@ -862,8 +862,8 @@ __device__ void grow_one(const Mesh& M, int cls, const Cands& C, const Pools& PL
 // workgroup from the global slab `eslab` (EHCAP 0: pairwise scans)
 template <int NT, int TIER, int MAXRT, int HCAP, int RFHCAP, int MAXRF, int MAXBE, int QHCAP, int MAXQ,
           int MAXBF, int EHCAP>
-__global__ __launch_bounds__(NT) void k_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
-                                                 const int* list, int nlist, char* eslab, int min_tier) {
+QMD void d_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP, const int* list, int nlist, char* eslab,
+                    int min_tier, const int bid, const int gdim) {
     __shared__ int rt[MAXRT];
     __shared__ unsigned H[HCAP];
     __shared__ unsigned RFH[RFHCAP];
@@ -877,7 +877,7 @@ __global__ __launch_bounds__(NT) void k_grow_lds(Mesh M, int cls, Cands C, Pools
     GrowTiles W{rt, H, RFH, rf, be, QH, q, cx, MAXRT, HCAP, RFHCAP, MAXRF, MAXBE, QHCAP, MAXQ, MAXBF, MAXBF, TIER,
                 nullptr, nullptr, 0};
     if (EHCAP > 0) {
-        char* base = eslab + (size_t)blockIdx.x * EHCAP * (sizeof(unsigned long long) + sizeof(int4));
+        char* base = eslab + (size_t)bid * EHCAP * (sizeof(unsigned long long) + sizeof(int4));
         W.EK = (unsigned long long*)base;
         W.EV = (int4*)(base + (size_t)EHCAP * sizeof(unsigned long long));
         W.ehcap = EHCAP;
@@ -885,7 +885,7 @@ __global__ __launch_bounds__(NT) void k_grow_lds(Mesh M, int cls, Cands C, Pools
     prof_begin(S);
     // all candidates in priority order, or the re-run list (pool-full ones)
     const int n = list ? nlist : C.n;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    for (int i = bid; i < n; i += gdim) {
         const int cid = list ? list[i] : i;
         if (C.st[cid] != ST_PENDING) {
             if (threadIdx.x == 0) { C.gst[cid] = C.st[cid]; C.greason[cid] = C.reason[cid]; }
@@ -907,6 +907,13 @@ __global__ __launch_bounds__(NT) void k_grow_lds(Mesh M, int cls, Cands C, Pools
         tier_count(S, BP, TIER);
     }
     prof_flush(S, BP, TIER);
+}
+template <int NT, int TIER, int MAXRT, int HCAP, int RFHCAP, int MAXRF, int MAXBE, int QHCAP, int MAXQ,
+          int MAXBF, int EHCAP>
+__global__ __launch_bounds__(NT) void k_grow_lds(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                                 const int* list, int nlist, char* eslab, int min_tier) {
+    d_grow_lds<NT, TIER, MAXRT, HCAP, RFHCAP, MAXRF, MAXBE, QHCAP, MAXQ, MAXBF, EHCAP>(
+        M, cls, C, PL, BP, list, nlist, eslab, min_tier, blockIdx.x, gridDim.x);
 }
 
 // carve the tiles other than the hash tables from a workgroup's slab block
@@ -932,35 +939,40 @@ inline size_t lists_slab_bytes(const GrowTiles& T) {
 // atomic-heavy structures) in LDS, the region list, face records and edge
 // table in the workgroup's block of a global slab.  `list` holds the
 // candidate ids; T carries the capacities (hcap = HCAP, ...).
+// (`block`: this workgroup's block of the slab)
 template <int NT, int HCAP, int RFHCAP, int QHCAP>
-__global__ __launch_bounds__(NT) void k_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
-                                                    const int* list, int nlist, GrowTiles T, char* slab,
-                                                    size_t slab_per_block) {
+QMD void d_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP, const int* list, int nlist,
+                       const GrowTiles& T, char* block, const int bid, const int gdim) {
     __shared__ unsigned H[HCAP];
     __shared__ unsigned RFH[RFHCAP];
     __shared__ unsigned long long QH[QHCAP];
     __shared__ GrowShared S;
     GrowTiles W = T;
-    carve_lists(W, T, slab + slab_per_block * blockIdx.x);
+    carve_lists(W, T, block);
     W.H = H; W.RFH = RFH; W.QH = QH;
     W.hcap = HCAP; W.rfhcap = RFHCAP; W.qhcap = QHCAP;
     prof_begin(S);
-    for (int i = blockIdx.x; i < nlist; i += gridDim.x) {
+    for (int i = bid; i < nlist; i += gdim) {
         grow_one<NT>(M, cls, C, PL, BP, list[i], W, S);
         __syncthreads();
         tier_count(S, BP, 1);
     }
     prof_flush(S, BP, 1);
 }
+template <int NT, int HCAP, int RFHCAP, int QHCAP>
+__global__ __launch_bounds__(NT) void k_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                                    const int* list, int nlist, GrowTiles T, char* slab,
+                                                    size_t slab_per_block) {
+    d_grow_hybrid<NT, HCAP, RFHCAP, QHCAP>(M, cls, C, PL, BP, list, nlist, T, slab + slab_per_block * blockIdx.x,
+                                           blockIdx.x, gridDim.x);
+}
 
 // re-run of the candidates that overflowed the LDS tiles (or a pool), with
 // tiles carved from a global scratch slab; `list` holds their ids
 template <int NT>
-__global__ __launch_bounds__(NT) void k_grow_global(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
-                                                    const int* list, int nlist, GrowTiles T, char* slab,
-                                                    size_t slab_per_block) {
+QMD void d_grow_global(Mesh M, int cls, Cands C, Pools PL, BfPool BP, const int* list, int nlist,
+                       const GrowTiles& T, char* base, const int bid, const int gdim) {
     __shared__ GrowShared S;
-    char* base = slab + slab_per_block * blockIdx.x;
     GrowTiles W = T;
     size_t off = 0;
     auto carve = [&](size_t bytes) { char* p = base + off; off += (bytes + 255) & ~(size_t)255; return p; };
@@ -975,12 +987,19 @@ __global__ __launch_bounds__(NT) void k_grow_global(Mesh M, int cls, Cands C, Po
     W.EK = (unsigned long long*)carve(sizeof(unsigned long long) * T.ehcap);
     W.EV = (int4*)carve(sizeof(int4) * T.ehcap);
     prof_begin(S);
-    for (int i = blockIdx.x; i < nlist; i += gridDim.x) {
+    for (int i = bid; i < nlist; i += gdim) {
         grow_one<NT>(M, cls, C, PL, BP, list[i], W, S);
         __syncthreads();
         tier_count(S, BP, 2);
     }
     prof_flush(S, BP, 2);
+}
+template <int NT>
+__global__ __launch_bounds__(NT) void k_grow_global(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                                    const int* list, int nlist, GrowTiles T, char* slab,
+                                                    size_t slab_per_block) {
+    d_grow_global<NT>(M, cls, C, PL, BP, list, nlist, T, slab + slab_per_block * blockIdx.x, blockIdx.x,
+                      gridDim.x);
 }
 
 inline size_t grow_slab_bytes(const GrowTiles& T) {

@@ -15,11 +15,11 @@ QMD int final_status(const Cands& C, int i) { return C.st[i] != ST_PENDING ? C.s
 // exempt by reason 1..9, unresolved] are counted per block in LDS; accepted
 // candidates enter the selection undecided (state 0), the others never do
 // (state 3).
-__global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pools PL, int* stats) {
+QMD void d_verdicts(Mesh M, int cls, Cands C, Pools PL, int* stats, const int bid, const int gdim) {
     __shared__ int bs[16];
     if (threadIdx.x < 16) bs[threadIdx.x] = 0;
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = bid * blockDim.x + threadIdx.x;
     if (i < C.n) {
         const int st = C.st[i] != ST_PENDING ? C.st[i] : C.gst[i];
         auto queue = [&](int2 e) {
@@ -56,6 +56,9 @@ __global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pool
     __syncthreads();
     if (threadIdx.x < 16 && bs[threadIdx.x]) atomicAdd(&stats[threadIdx.x], bs[threadIdx.x]);
 }
+__global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pools PL, int* stats) {
+    d_verdicts(M, cls, C, PL, stats, blockIdx.x, gridDim.x);
+}
 
 // ------------------------------------------------------------- selection
 // Iterated local maxima with fixed priorities: in each pass every undecided
@@ -67,22 +70,26 @@ __global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pool
 QMD unsigned long long mis_val(unsigned pass, int c) {
     return ((unsigned long long)pass << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)c);
 }
-__global__ void k_mis_mark(int ncl, const int* cl, const int* clc, const int* state,
-                           unsigned long long* mark, unsigned pass, const int* prev) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_mis_mark(int ncl, const int* cl, const int* clc, const int* state,
+                           unsigned long long* mark, unsigned pass, const int* prev, const int bid, const int gdim) {
+    int e = bid * blockDim.x + threadIdx.x;
     if (e >= ncl || (prev && *prev == 0)) return;
     int c = clc[e];
     if (c < 0) return;                 // void range (reservation that did not fit)
     if (state[c] != 0) return;
     atomicMax(&mark[cl[e]], mis_val(pass, c));
 }
+__global__ void k_mis_mark(int ncl, const int* cl, const int* clc, const int* state,
+                           unsigned long long* mark, unsigned pass, const int* prev) {
+    d_mis_mark(ncl, cl, clc, state, mark, pass, prev, blockIdx.x, gridDim.x);
+}
 // per claim entry of an undecided candidate: touching a kept claim drops it
 // (drop[c]), a tet marked by a higher priority leaves it undecided (lose[c]);
 // every writer stores the same value, so plain stores suffice
-__global__ void k_mis_check(int ncl, const int* cl, const int* clc, const int* state,
+QMD void d_mis_check(int ncl, const int* cl, const int* clc, const int* state,
                             const unsigned long long* mark, const int* owner, unsigned pass,
-                            unsigned char* drop, unsigned char* lose, const int* prev) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+                            unsigned char* drop, unsigned char* lose, const int* prev, const int bid, const int gdim) {
+    int e = bid * blockDim.x + threadIdx.x;
     if (e >= ncl || (prev && *prev == 0)) return;
     int c = clc[e];
     if (c < 0 || state[c] != 0) return;
@@ -90,14 +97,19 @@ __global__ void k_mis_check(int ncl, const int* cl, const int* clc, const int* s
     if (owner[t] >= 0) drop[c] = 1;
     else if (mark[t] != mis_val(pass, c)) lose[c] = 1;
 }
+__global__ void k_mis_check(int ncl, const int* cl, const int* clc, const int* state,
+                            const unsigned long long* mark, const int* owner, unsigned pass,
+                            unsigned char* drop, unsigned char* lose, const int* prev) {
+    d_mis_check(ncl, cl, clc, state, mark, owner, pass, drop, lose, prev, blockIdx.x, gridDim.x);
+}
 // (the first pass of a round; the candidates left undecided are appended
 // to the list u_out for the later passes)
-__global__ __launch_bounds__(256) void k_mis_decide(int n, int* state, unsigned char* drop, unsigned char* lose,
-                                                    int* undecided, const int* prev, int* u_out, int* nu_out) {
+QMD void d_mis_decide(int n, int* state, unsigned char* drop, unsigned char* lose,
+                                                    int* undecided, const int* prev, int* u_out, int* nu_out, const int bid, const int gdim) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = bid * blockDim.x + threadIdx.x;
     if (c < n && !(prev && *prev == 0) && state[c] == 0) {
         if (drop[c]) state[c] = 2;
         else if (lose[c]) { atomicAdd(&cnt, 1); u_out[atomicAdd(nu_out, 1)] = c; }
@@ -107,6 +119,10 @@ __global__ __launch_bounds__(256) void k_mis_decide(int n, int* state, unsigned 
     __syncthreads();
     if (threadIdx.x == 0 && cnt) atomicAdd(undecided, cnt);
 }
+__global__ __launch_bounds__(256) void k_mis_decide(int n, int* state, unsigned char* drop, unsigned char* lose,
+                                                    int* undecided, const int* prev, int* u_out, int* nu_out) {
+    d_mis_decide(n, state, drop, lose, undecided, prev, u_out, nu_out, blockIdx.x, gridDim.x);
+}
 
 // Passes after the first: only the candidates still undecided take part
 // (list u_in, count *nu_in, in any order: every step is order-free).  One
@@ -114,21 +130,25 @@ __global__ __launch_bounds__(256) void k_mis_decide(int n, int* state, unsigned 
 // still-undecided ones to u_out.  The mark kernel clears *nu_out (read
 // again only by the decision kernel of the same pass).
 constexpr int MIS_LIST_GRID = 2048;
-__global__ __launch_bounds__(256) void k_mis_mark_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
-                                                       unsigned long long* mark, unsigned pass, int* nu_out) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *nu_out = 0;
+QMD void d_mis_mark_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                       unsigned long long* mark, unsigned pass, int* nu_out, const int bid, const int gdim) {
+    if (bid == 0 && threadIdx.x == 0) *nu_out = 0;
     const int lane = threadIdx.x & 63, n = *nu_in;
-    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+    for (int i = bid * 4 + (threadIdx.x >> 6); i < n; i += gdim * 4) {
         const int c = u_in[i], off = C.cl_off[c], m = C.cl_n[c];
         const unsigned long long v = mis_val(pass, c);
         for (int j = lane; j < m; j += 64) atomicMax(&mark[cl[off + j]], v);
     }
 }
-__global__ __launch_bounds__(256) void k_mis_check_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+__global__ __launch_bounds__(256) void k_mis_mark_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                       unsigned long long* mark, unsigned pass, int* nu_out) {
+    d_mis_mark_list(u_in, nu_in, C, cl, mark, pass, nu_out, blockIdx.x, gridDim.x);
+}
+QMD void d_mis_check_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
                                                         const unsigned long long* mark, const int* owner,
-                                                        unsigned pass, unsigned char* drop, unsigned char* lose) {
+                                                        unsigned pass, unsigned char* drop, unsigned char* lose, const int bid, const int gdim) {
     const int lane = threadIdx.x & 63, n = *nu_in;
-    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+    for (int i = bid * 4 + (threadIdx.x >> 6); i < n; i += gdim * 4) {
         const int c = u_in[i], off = C.cl_off[c], m = C.cl_n[c];
         const unsigned long long v = mis_val(pass, c);
         for (int j = lane; j < m; j += 64) {
@@ -138,14 +158,19 @@ __global__ __launch_bounds__(256) void k_mis_check_list(const int* u_in, const i
         }
     }
 }
-__global__ __launch_bounds__(256) void k_mis_decide_list(const int* u_in, const int* nu_in, int* state,
+__global__ __launch_bounds__(256) void k_mis_check_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                        const unsigned long long* mark, const int* owner,
+                                                        unsigned pass, unsigned char* drop, unsigned char* lose) {
+    d_mis_check_list(u_in, nu_in, C, cl, mark, owner, pass, drop, lose, blockIdx.x, gridDim.x);
+}
+QMD void d_mis_decide_list(const int* u_in, const int* nu_in, int* state,
                                                          unsigned char* drop, unsigned char* lose, int* undecided,
-                                                         int* u_out, int* nu_out) {
+                                                         int* u_out, int* nu_out, const int bid, const int gdim) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     const int n = *nu_in;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int i = bid * blockDim.x + threadIdx.x; i < n; i += gdim * blockDim.x) {
         const int c = u_in[i];
         if (drop[c]) state[c] = 2;
         else if (lose[c]) { atomicAdd(&cnt, 1); u_out[atomicAdd(nu_out, 1)] = c; }
@@ -155,30 +180,43 @@ __global__ __launch_bounds__(256) void k_mis_decide_list(const int* u_in, const 
     __syncthreads();
     if (threadIdx.x == 0 && cnt) atomicAdd(undecided, cnt);
 }
-__global__ __launch_bounds__(256) void k_mis_commit_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
-                                                         const int* state, int* owner) {
+__global__ __launch_bounds__(256) void k_mis_decide_list(const int* u_in, const int* nu_in, int* state,
+                                                         unsigned char* drop, unsigned char* lose, int* undecided,
+                                                         int* u_out, int* nu_out) {
+    d_mis_decide_list(u_in, nu_in, state, drop, lose, undecided, u_out, nu_out, blockIdx.x, gridDim.x);
+}
+QMD void d_mis_commit_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                         const int* state, int* owner, const int bid, const int gdim) {
     const int lane = threadIdx.x & 63, n = *nu_in;
-    for (int i = blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += gridDim.x * 4) {
+    for (int i = bid * 4 + (threadIdx.x >> 6); i < n; i += gdim * 4) {
         const int c = u_in[i];
         if (state[c] != 1) continue;
         const int off = C.cl_off[c], m = C.cl_n[c];
         for (int j = lane; j < m; j += 64) owner[cl[off + j]] = c;
     }
 }
-__global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* state, int* owner,
-                             const int* prev) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_mis_commit_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
+                                                         const int* state, int* owner) {
+    d_mis_commit_list(u_in, nu_in, C, cl, state, owner, blockIdx.x, gridDim.x);
+}
+QMD void d_mis_commit(int ncl, const int* cl, const int* clc, const int* state, int* owner,
+                             const int* prev, const int bid, const int gdim) {
+    int e = bid * blockDim.x + threadIdx.x;
     if (e >= ncl || (prev && *prev == 0)) return;
     int c = clc[e];
     if (c < 0) return;
     if (state[c] == 1) owner[cl[e]] = c;
 }
+__global__ void k_mis_commit(int ncl, const int* cl, const int* clc, const int* state, int* owner,
+                             const int* prev) {
+    d_mis_commit(ncl, cl, clc, state, owner, prev, blockIdx.x, gridDim.x);
+}
 // All passes of a small round in one workgroup (phases separated by block
 // barriers): one launch instead of four per pass.  *npass receives the
 // passes run, or -1 when max_pass passes did not finish.
-__global__ __launch_bounds__(1024) void k_mis_small(int ncl, const int* cl, const int* clc, int n, int* state,
+QMD void d_mis_small(int ncl, const int* cl, const int* clc, int n, int* state,
                                                     unsigned long long* mark, int* owner, unsigned char* drop,
-                                                    unsigned char* lose, unsigned pass0, int max_pass, int* npass) {
+                                                    unsigned char* lose, unsigned pass0, int max_pass, int* npass, const int bid, const int gdim) {
     __shared__ int undecided;
     for (int k = 0; k < max_pass; ++k) {
         const unsigned pass = pass0 + (unsigned)k;
@@ -217,13 +255,21 @@ __global__ __launch_bounds__(1024) void k_mis_small(int ncl, const int* cl, cons
     }
     if (threadIdx.x == 0) *npass = -1;
 }
+__global__ __launch_bounds__(1024) void k_mis_small(int ncl, const int* cl, const int* clc, int n, int* state,
+                                                    unsigned long long* mark, int* owner, unsigned char* drop,
+                                                    unsigned char* lose, unsigned pass0, int max_pass, int* npass) {
+    d_mis_small(ncl, cl, clc, n, state, mark, owner, drop, lose, pass0, max_pass, npass, blockIdx.x, gridDim.x);
+}
 
 // clear every ownership of this round (kept candidates, and kept ones that
 // a per-round cap demoted afterwards)
-__global__ void k_mis_release(int ncl, const int* cl, const int* clc, int* owner) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_mis_release(int ncl, const int* cl, const int* clc, int* owner, const int bid, const int gdim) {
+    int e = bid * blockDim.x + threadIdx.x;
     if (e >= ncl || clc[e] < 0) return;
     if (owner[cl[e]] == clc[e]) owner[cl[e]] = -1;
+}
+__global__ void k_mis_release(int ncl, const int* cl, const int* clc, int* owner) {
+    d_mis_release(ncl, cl, clc, owner, blockIdx.x, gridDim.x);
 }
 
 // per-candidate values to scan: kept flag, new tet slots (f - k), new
@@ -246,8 +292,8 @@ QMD int3 scan_vals(const Cands& C, int cls, int c) {
 // Exclusive scans of the three values and their totals in one workgroup
 // (rounds with few candidates: one launch instead of a device-wide scan per
 // value).  sk/st/ss as from k_scan_vals + exclusive sums; tot = k_totals.
-__global__ __launch_bounds__(1024) void k_scan_small(Cands C, int cls, int n, int* sk, int* st, int* ss,
-                                                     int* tot) {
+QMD void d_scan_small(Cands C, int cls, int n, int* sk, int* st, int* ss,
+                                                     int* tot, const int bid, const int gdim) {
     __shared__ int3 wsum[16];
     __shared__ int3 carry;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -277,6 +323,10 @@ __global__ __launch_bounds__(1024) void k_scan_small(Cands C, int cls, int n, in
     }
     if (threadIdx.x == 0) { tot[0] = carry.x; tot[1] = carry.y; tot[2] = carry.z; }
 }
+__global__ __launch_bounds__(1024) void k_scan_small(Cands C, int cls, int n, int* sk, int* st, int* ss,
+                                                     int* tot) {
+    d_scan_small(C, cls, n, sk, st, ss, tot, blockIdx.x, gridDim.x);
+}
 
 // optional cap on insertions per round: only the first `cap` kept survive
 __global__ void k_cap_kept(Cands C, const int* sk, int cap) {
@@ -284,10 +334,13 @@ __global__ void k_cap_kept(Cands C, const int* sk, int cap) {
     if (c >= C.n) return;
     if (C.state[c] == 1 && sk[c] >= cap) C.state[c] = 2;
 }
-__global__ void k_kept_list(Cands C, const int* sk, int* list) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_kept_list(Cands C, const int* sk, int* list, const int bid, const int gdim) {
+    int c = bid * blockDim.x + threadIdx.x;
     if (c >= C.n) return;
     if (C.state[c] == 1) list[sk[c]] = c;
+}
+__global__ void k_kept_list(Cands C, const int* sk, int* list) {
+    d_kept_list(C, sk, list, blockIdx.x, gridDim.x);
 }
 __global__ void k_totals(int n, const int* a, const int* av, const int* b, const int* bv, const int* d,
                          const int* dv, int* out) {
@@ -304,10 +357,10 @@ __global__ void k_totals(int n, const int* a, const int* av, const int* b, const
 // faces through p are linked by matching boundary edges, the outer face to
 // the old neighbour (whose back link is patched), subfaces (p, e) are created
 // on 2D boundary edges, and a split subsegment becomes (a,p) + (p,b).
-__global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+QMD void d_insert(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
                                                const int* kept, int nkept, const int* sk, const int* st_,
-                                               const int* ss_, int nv0, int nt0, int nss0, int* dead) {
-    for (int kk = blockIdx.x; kk < nkept; kk += gridDim.x) {
+                                               const int* ss_, int nv0, int nt0, int nss0, int* dead, const int bid, const int gdim) {
+    for (int kk = bid; kk < nkept; kk += gdim) {
         const int c = kept[kk];
         const int lane = threadIdx.x;
         const int pid = nv0 + sk[c];
@@ -386,6 +439,11 @@ __global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools P
         }
         __syncthreads();
     }
+}
+__global__ __launch_bounds__(64) void k_insert(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
+                                               const int* kept, int nkept, const int* sk, const int* st_,
+                                               const int* ss_, int nv0, int nt0, int nss0, int* dead) {
+    d_insert(M, cls, C, PL, BP, kept, nkept, sk, st_, ss_, nv0, nt0, nss0, dead, blockIdx.x, gridDim.x);
 }
 
 }  // namespace qm

@@ -15,6 +15,7 @@
 #include <stdexcept>
 #include <string>
 #include <vector>
+#include <utility>
 #include <thread>
 #include <atomic>
 #include <memory>
@@ -242,9 +243,9 @@ __global__ __launch_bounds__(256) void k_scan_tile(int n, const int* in, int* ou
 // order the radix sort and the tie fix give together; the candidate is
 // written straight to that position of the ordered arrays.
 constexpr int SORT_SMALL = 256;
-__global__ __launch_bounds__(SORT_SMALL) void k_order_small(int n, const int* elem, const unsigned long long* key,
+QMD void d_order_small(int n, const int* elem, const unsigned long long* key,
                                                            const int4* tup, const double4* p, const int* st,
-                                                           const int* reason, Cands C) {
+                                                           const int* reason, Cands C, const int bid, const int gdim) {
     __shared__ unsigned long long K[SORT_SMALL];
     __shared__ int4 T[SORT_SMALL];
     const int i = threadIdx.x;
@@ -266,6 +267,11 @@ __global__ __launch_bounds__(SORT_SMALL) void k_order_small(int n, const int* el
     C.st[r] = st[i]; C.reason[r] = reason[i];
     C.seed[r] = -1; C.qw[r] = make_int2(-1, -1);
 }
+__global__ __launch_bounds__(SORT_SMALL) void k_order_small(int n, const int* elem, const unsigned long long* key,
+                                                           const int4* tup, const double4* p, const int* st,
+                                                           const int* reason, Cands C) {
+    d_order_small(n, elem, key, tup, p, st, reason, C, blockIdx.x, gridDim.x);
+}
 
 __global__ void k_iota(int n, int* o) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -279,14 +285,17 @@ __global__ void k_fill(int n, int* o, int v) {
 // count n[0]) and regions over the medium LDS tiles or the global-memory
 // tiles (list c, n[4]); n[1] counts candidates whose results did not fit a
 // pool, n[2] the regions over the global-memory tiles
-__global__ void k_overflow_list(Cands C, int* la, int* lc, int* n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_overflow_list(Cands C, int* la, int* lc, int* n, const int bid, const int gdim) {
+    int i = bid * blockDim.x + threadIdx.x;
     if (i >= C.n || C.st[i] != ST_PENDING) return;
     const int g = C.gst[i];
     if (g == ST_OVERFLOW) la[atomicAdd(&n[0], 1)] = i;
     else if (g == ST_POOLFULL) atomicAdd(&n[1], 1);
     else if (g == ST_OVERFLOW2 || g == ST_TOOBIG) lc[atomicAdd(&n[4], 1)] = i;
     if (g == ST_TOOBIG) atomicAdd(&n[2], 1);
+}
+__global__ void k_overflow_list(Cands C, int* la, int* lc, int* n) {
+    d_overflow_list(C, la, lc, n, blockIdx.x, gridDim.x);
 }
 // a pass over again: zero the pool counters and the full flag
 __global__ void k_round_reset_pools(int* ctr) {
@@ -679,44 +688,16 @@ struct RoundGate {
     }
 };
 
-// One refinement.  Normal form: buffers from the stream-ordered allocator,
-// result in *out (host arrays).  No-alloc form (ar != nullptr): every device
-// buffer is carved from the arena, inputs are device arrays, the output mesh
-// is written into the caller's device arrays `dout` and the statistics into
-// *dstats; no qm_result, pinned buffer or event is created.
-static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
-                      qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
-                      qm_stats* dstats = nullptr, size_t mem_cap = 0, RoundGate* gate = nullptr) {
-    auto T0 = std::chrono::steady_clock::now();
+// Device setup of one refinement, whose input is a CDT of the PLC (paper,
+// Section 2): inputs staged (or used in place when they are device arrays),
+// adjacency by face matching, subfaces and subsegments marked, facet
+// projection axes, the h_min bound.  Input errors become QmError.  `e0`
+// (optional) is recorded when the setup kernels start.
+static void setup_mesh(Engine& E, const qm_plc* plc, const qm_mesh* in, const qm_options* opt, Arena* ar,
+                       hipEvent_t e0) {
+    const hipStream_t s = E.s;
     const bool noalloc = ar != nullptr;
-    if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
-    if (!(opt->B > 0.0) || !(opt->hmin_factor >= 0.0) || opt->max_rounds < 0)
-        throw QmError(QM_EINVAL, "B must be > 0, hmin_factor >= 0, max_rounds >= 0");
-    if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
-        throw QmError(QM_EINVAL, "bad counts");
-    if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
-    if (noalloc) {
-        if (!dev) throw QmError(QM_EINVAL, "the no-alloc entry point takes device arrays (QM_INPUT_DEVICE)");
-        if (opt->flags & (QM_PROFILE | QM_PROFILE_GROW))
-            throw QmError(QM_EINVAL, "profiling flags are not available without allocation");
-        if (dout->cap_v < in->nv || dout->cap_t < in->nt || dout->cap_ss < in->nss || dout->cap_sf < 0 ||
-            !dout->xyz || !dout->tet || (dout->cap_sf > 0 && (!dout->sf || !dout->sf_facet)) ||
-            (dout->cap_ss > 0 && (!dout->ss || !dout->ss_seg)))
-            throw QmError(QM_EINVAL, "output arrays missing or smaller than the input mesh");
-    }
-    Engine E(s);
-    E.mem_cap = mem_cap;
-    if (noalloc) {
-        E.attach(ar);
-        E.cap_v = (size_t)dout->cap_v;
-        E.cap_t = (size_t)dout->cap_t + (size_t)dout->cap_t / 8 + 256;   // slots of removed tets included
-        E.cap_s = (size_t)std::max(dout->cap_ss, 1);
-    }
-    E.prof = (opt->flags & QM_PROFILE) != 0;
-    E.prof_grow = !E.prof && (opt->flags & QM_PROFILE_GROW) != 0;
-    if (E.prof) { E.pctr.ensure(4 + GROW_PHASES + 3 * TPROF_W, s, false, 0); }
-    int64_t scan_tets = 0, scan_verts = 0;
     const int nv = in->nv, nt = in->nt, nsf = in->nsf, nss = in->nss, nftri = plc->nftri;
     int nfacet = 0;
     // staging of the input arrays on the device
@@ -726,8 +707,16 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         HIPCK(hipMemcpyAsync(buf.p, p, bytes, hipMemcpyHostToDevice, s));
         return buf.p;
     };
-    DBuf<char> b_xyz, b_tet, b_sf, b_sff, b_ss, b_ssg, b_ft, b_ftf;   // (unused with device inputs)
-    for (auto* b : {&b_xyz, &b_tet, &b_sf, &b_sff, &b_ss, &b_ssg, &b_ft, &b_ftf}) b->acct = &E.acct;
+    // staged copies (unused with device inputs), freed on the stream when setup ends
+    struct Staged {
+        DBuf<char> b[8];
+        hipStream_t s;
+        ~Staged() { for (auto& x : b) x.release(s); }
+    } stg;
+    stg.s = s;
+    for (auto& b : stg.b) b.acct = &E.acct;
+    DBuf<char>&b_xyz = stg.b[0], &b_tet = stg.b[1], &b_sf = stg.b[2], &b_sff = stg.b[3], &b_ss = stg.b[4],
+             &b_ssg = stg.b[5], &b_ft = stg.b[6], &b_ftf = stg.b[7];
     const double* d_xyz = (const double*)stage(in->xyz, sizeof(double) * 3 * nv, b_xyz);
     const int* d_tet = (const int*)stage(in->tet, sizeof(int) * 4 * (size_t)nt, b_tet);
     const int* d_sf = (const int*)stage(in->sf, sizeof(int) * 3 * (size_t)nsf, b_sf);
@@ -750,12 +739,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     E.nt_ordered = nt;
     if (opt->flags & QM_TEST_ERROR_WORD) HIPCK(hipMemsetAsync(E.M.err, 1, 1, s));
     int* err = E.ctr.p + 13;
-    auto T1 = std::chrono::steady_clock::now();
-    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
-    if (!noalloc) {
-        HIPCK(hipEventCreate(&e0)); HIPCK(hipEventCreate(&e1)); HIPCK(hipEventCreate(&e2));
-        HIPCK(hipEventRecord(e0, s));
-    }
+    if (e0) HIPCK(hipEventRecord(e0, s));
     // ---- device setup
     k_setup_verts<<<nblk(nv), 256, 0, s>>>(nv, d_xyz, E.X.p, err);
     k_setup_tets<<<nblk(nt), 256, 0, s>>>(nt, nv, d_tet, E.M, err);
@@ -798,6 +782,163 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.M.hmin2 = (opt->hmin_factor * opt->hmin_factor) * l2;
         E.M.B2 = opt->B * opt->B;
     }
+}
+
+// Verdicts of the last round's candidates (9 values per candidate): the
+// candidate arrays are only rewritten by a round that has candidates, so
+// they still hold that round.
+static void read_last_round(Engine& E, qm_result* R, int ncand) {
+    const hipStream_t s = E.s;
+    std::vector<int4> tup(ncand);
+    std::vector<int> st0(ncand), gs(ncand), rs0(ncand), grs(ncand), stt(ncand), rn(ncand), bn(ncand);
+    HIPCK(hipMemcpyAsync(tup.data(), E.c_tup.p, sizeof(int4) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(st0.data(), E.c_st.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(gs.data(), E.gst.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(rs0.data(), E.c_reason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(grs.data(), E.greason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(stt.data(), E.state.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(rn.data(), E.reg_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipMemcpyAsync(bn.data(), E.bf_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
+    HIPCK(hipStreamSynchronize(s));
+    R->last.assign(9 * (size_t)ncand, 0);
+    for (int i = 0; i < ncand; ++i) {
+        int* o = R->last.data() + 9 * (size_t)i;
+        int fs = st0[i] != ST_PENDING ? st0[i] : gs[i];
+        o[0] = tup[i].x; o[1] = tup[i].y; o[2] = tup[i].z; o[3] = tup[i].w;
+        o[4] = fs; o[5] = fs == ST_EXEMPT ? (st0[i] != ST_PENDING ? rs0[i] : grs[i]) : 0;
+        o[6] = stt[i] == 1; o[7] = fs == ST_OK ? rn[i] : 0; o[8] = fs == ST_OK ? bn[i] : 0;
+    }
+}
+
+// Output of one refinement: live tets and subfaces compacted in slot order,
+// then written to the caller's device arrays (no-alloc form), to device
+// arrays the result owns (QM_OUTPUT_DEVICE) or downloaded into the result.
+// Returns the number of output tets.
+static int emit_output(Engine& E, qm_result* R, const qm_options* opt, Arena* ar, qm_mesh_buf* dout) {
+    const hipStream_t s = E.s;
+    const bool noalloc = ar != nullptr;
+    E.arena_round();
+    int ntot = E.M.nt;
+    DBuf<int> tf, ts, ff, fs;
+    tf.ar = ts.ar = ff.ar = fs.ar = ar;
+    tf.acct = ts.acct = ff.acct = fs.acct = &E.acct;
+    tf.ensure(ntot, s, false); ts.ensure(ntot, s, false);
+    ff.ensure(4 * (size_t)ntot, s, false); fs.ensure(4 * (size_t)ntot, s, false);
+    k_out_flags<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ff.p);
+    E.exscan(tf.p, ts.p, ntot);
+    E.exscan(ff.p, fs.p, 4 * ntot);
+    int a = read1(ts.p + ntot - 1, s) + read1(tf.p + ntot - 1, s);
+    int b = read1(fs.p + 4 * ntot - 1, s) + read1(ff.p + 4 * ntot - 1, s);
+    if (noalloc) {
+        dout->nv = E.M.nv; dout->nt = a; dout->nsf = b; dout->nss = E.M.nss;
+        if (E.M.nv > dout->cap_v || a > dout->cap_t || b > dout->cap_sf || E.M.nss > dout->cap_ss)
+            throw QmError(QM_ECAPACITY, "the output arrays are too small (vertices " + std::to_string(E.M.nv) +
+                                            ", tets " + std::to_string(a) + ", subfaces " + std::to_string(b) +
+                                            ", subsegments " + std::to_string(E.M.nss) + ")");
+        k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, dout->tet);
+        if (b) k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, dout->sf, dout->sf_facet);
+        k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, dout->xyz);
+        if (E.M.nss) {
+            HIPCK(hipMemcpyAsync(dout->ss, E.SV.p, sizeof(int) * 2 * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+            HIPCK(hipMemcpyAsync(dout->ss_seg, E.SSEG.p, sizeof(int) * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+        }
+        HIPCK(hipStreamSynchronize(s));
+    } else if (opt->flags & QM_OUTPUT_DEVICE) {   // the result stays on the device
+        HIPCK(hipStreamSynchronize(s));
+        auto dalloc = [&](auto** p, size_t n) {
+            HIPCK(hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(**p)));
+        };
+        dalloc(&R->d_xyz, 3 * (size_t)E.M.nv); dalloc(&R->d_tets, 4 * (size_t)a);
+        dalloc(&R->d_sf, 3 * (size_t)b); dalloc(&R->d_sff, (size_t)b);
+        dalloc(&R->d_ss, 2 * (size_t)E.M.nss); dalloc(&R->d_ssg, (size_t)E.M.nss);
+        k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, R->d_tets);
+        if (b) k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, R->d_sf, R->d_sff);
+        k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, R->d_xyz);
+        if (E.M.nss) {
+            HIPCK(hipMemcpyAsync(R->d_ss, E.SV.p, sizeof(int) * 2 * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+            HIPCK(hipMemcpyAsync(R->d_ssg, E.SSEG.p, sizeof(int) * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
+        }
+        HIPCK(hipStreamSynchronize(s));
+        R->on_device = true;
+        R->dnv = E.M.nv; R->dnt = a; R->dnsf = b; R->dnss = E.M.nss;
+    } else {
+        DBuf<int> ot, osf, osff;
+        DBuf<double> ox;
+        ot.acct = osf.acct = osff.acct = &E.acct;
+        ox.acct = &E.acct;
+        ot.ensure(4 * (size_t)std::max(a, 1), s, false);
+        osf.ensure(3 * (size_t)std::max(b, 1), s, false);
+        osff.ensure(std::max(b, 1), s, false);
+        ox.ensure(3 * (size_t)E.M.nv, s, false);
+        k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, ot.p);
+        k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, osf.p, osff.p);
+        k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, ox.p);
+        R->xyz.resize(3 * (size_t)E.M.nv);
+        R->tets.resize(4 * (size_t)a);
+        R->sf.resize(3 * (size_t)b);
+        R->sff.resize(b);
+        R->ss.resize(2 * (size_t)E.M.nss);
+        R->ssg.resize(E.M.nss);
+        HIPCK(hipMemcpyAsync(R->xyz.data(), ox.p, sizeof(double) * R->xyz.size(), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(R->tets.data(), ot.p, sizeof(int) * R->tets.size(), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(R->sf.data(), osf.p, sizeof(int) * R->sf.size(), hipMemcpyDeviceToHost, s));
+        HIPCK(hipMemcpyAsync(R->sff.data(), osff.p, sizeof(int) * R->sff.size(), hipMemcpyDeviceToHost, s));
+        if (E.M.nss) {
+            HIPCK(hipMemcpyAsync(R->ss.data(), E.SV.p, sizeof(int) * R->ss.size(), hipMemcpyDeviceToHost, s));
+            HIPCK(hipMemcpyAsync(R->ssg.data(), E.SSEG.p, sizeof(int) * R->ssg.size(), hipMemcpyDeviceToHost, s));
+        }
+        HIPCK(hipStreamSynchronize(s));
+        ot.release(s); osf.release(s); osff.release(s); ox.release(s);
+    }
+    tf.release(s); ts.release(s); ff.release(s); fs.release(s);
+    return a;
+}
+
+// One refinement.  Normal form: buffers from the stream-ordered allocator,
+// result in *out (host arrays).  No-alloc form (ar != nullptr): every device
+// buffer is carved from the arena, inputs are device arrays, the output mesh
+// is written into the caller's device arrays `dout` and the statistics into
+// *dstats; no qm_result, pinned buffer or event is created.
+static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
+                      qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
+                      qm_stats* dstats = nullptr, size_t mem_cap = 0, RoundGate* gate = nullptr) {
+    auto T0 = std::chrono::steady_clock::now();
+    const bool noalloc = ar != nullptr;
+    if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
+    if (!(opt->B > 0.0) || !(opt->hmin_factor >= 0.0) || opt->max_rounds < 0)
+        throw QmError(QM_EINVAL, "B must be > 0, hmin_factor >= 0, max_rounds >= 0");
+    if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
+        throw QmError(QM_EINVAL, "bad counts");
+    if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
+    const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
+    if (noalloc) {
+        if (!dev) throw QmError(QM_EINVAL, "the no-alloc entry point takes device arrays (QM_INPUT_DEVICE)");
+        if (opt->flags & (QM_PROFILE | QM_PROFILE_GROW))
+            throw QmError(QM_EINVAL, "profiling flags are not available without allocation");
+        if (dout->cap_v < in->nv || dout->cap_t < in->nt || dout->cap_ss < in->nss || dout->cap_sf < 0 ||
+            !dout->xyz || !dout->tet || (dout->cap_sf > 0 && (!dout->sf || !dout->sf_facet)) ||
+            (dout->cap_ss > 0 && (!dout->ss || !dout->ss_seg)))
+            throw QmError(QM_EINVAL, "output arrays missing or smaller than the input mesh");
+    }
+    Engine E(s);
+    E.mem_cap = mem_cap;
+    if (noalloc) {
+        E.attach(ar);
+        E.cap_v = (size_t)dout->cap_v;
+        E.cap_t = (size_t)dout->cap_t + (size_t)dout->cap_t / 8 + 256;   // slots of removed tets included
+        E.cap_s = (size_t)std::max(dout->cap_ss, 1);
+    }
+    E.prof = (opt->flags & QM_PROFILE) != 0;
+    E.prof_grow = !E.prof && (opt->flags & QM_PROFILE_GROW) != 0;
+    if (E.prof) { E.pctr.ensure(4 + GROW_PHASES + 3 * TPROF_W, s, false, 0); }
+    int64_t scan_tets = 0, scan_verts = 0;
+    auto T1 = std::chrono::steady_clock::now();
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+    if (!noalloc) {
+        HIPCK(hipEventCreate(&e0)); HIPCK(hipEventCreate(&e1)); HIPCK(hipEventCreate(&e2));
+    }
+    setup_mesh(E, plc, in, opt, ar, e0);
+
     auto T1s = std::chrono::steady_clock::now();
     if (!noalloc) HIPCK(hipEventRecord(e1, s));
     // ---- rounds
@@ -1118,109 +1259,13 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     patch_last_record();
     // verdicts of the last round's candidates: the candidate arrays are only
     // rewritten by a round that has candidates, so they still hold that round
-    if (last_ncand > 0 && !noalloc) {
-        const int ncand = last_ncand;
-        std::vector<int4> tup(ncand);
-        std::vector<int> st0(ncand), gs(ncand), rs0(ncand), grs(ncand), stt(ncand), rn(ncand), bn(ncand);
-        HIPCK(hipMemcpyAsync(tup.data(), E.c_tup.p, sizeof(int4) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(st0.data(), E.c_st.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(gs.data(), E.gst.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(rs0.data(), E.c_reason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(grs.data(), E.greason.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(stt.data(), E.state.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(rn.data(), E.reg_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipMemcpyAsync(bn.data(), E.bf_n.p, sizeof(int) * ncand, hipMemcpyDeviceToHost, s));
-        HIPCK(hipStreamSynchronize(s));
-        R->last.assign(9 * (size_t)ncand, 0);
-        for (int i = 0; i < ncand; ++i) {
-            int* o = R->last.data() + 9 * (size_t)i;
-            int fs = st0[i] != ST_PENDING ? st0[i] : gs[i];
-            o[0] = tup[i].x; o[1] = tup[i].y; o[2] = tup[i].z; o[3] = tup[i].w;
-            o[4] = fs; o[5] = fs == ST_EXEMPT ? (st0[i] != ST_PENDING ? rs0[i] : grs[i]) : 0;
-            o[6] = stt[i] == 1; o[7] = fs == ST_OK ? rn[i] : 0; o[8] = fs == ST_OK ? bn[i] : 0;
-        }
-    }
+    if (last_ncand > 0 && !noalloc) read_last_round(E, R.get(), last_ncand);
+
 
     const int gerr = read1(E.M.err, s);
     if (gerr) throw QmError(QM_EINTERNAL, "exact predicate precondition failed (code " + std::to_string(gerr) + ")");
     // ---- output: live tets and subfaces compacted in slot order
-    {
-        E.arena_round();
-        int ntot = E.M.nt;
-        DBuf<int> tf, ts, ff, fs;
-        tf.ar = ts.ar = ff.ar = fs.ar = ar;
-        tf.acct = ts.acct = ff.acct = fs.acct = &E.acct;
-        tf.ensure(ntot, s, false); ts.ensure(ntot, s, false);
-        ff.ensure(4 * (size_t)ntot, s, false); fs.ensure(4 * (size_t)ntot, s, false);
-        k_out_flags<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ff.p);
-        E.exscan(tf.p, ts.p, ntot);
-        E.exscan(ff.p, fs.p, 4 * ntot);
-        int a = read1(ts.p + ntot - 1, s) + read1(tf.p + ntot - 1, s);
-        int b = read1(fs.p + 4 * ntot - 1, s) + read1(ff.p + 4 * ntot - 1, s);
-        if (noalloc) {
-            dout->nv = E.M.nv; dout->nt = a; dout->nsf = b; dout->nss = E.M.nss;
-            if (E.M.nv > dout->cap_v || a > dout->cap_t || b > dout->cap_sf || E.M.nss > dout->cap_ss)
-                throw QmError(QM_ECAPACITY, "the output arrays are too small (vertices " + std::to_string(E.M.nv) +
-                                                ", tets " + std::to_string(a) + ", subfaces " + std::to_string(b) +
-                                                ", subsegments " + std::to_string(E.M.nss) + ")");
-            k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, dout->tet);
-            if (b) k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, dout->sf, dout->sf_facet);
-            k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, dout->xyz);
-            if (E.M.nss) {
-                HIPCK(hipMemcpyAsync(dout->ss, E.SV.p, sizeof(int) * 2 * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
-                HIPCK(hipMemcpyAsync(dout->ss_seg, E.SSEG.p, sizeof(int) * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
-            }
-            HIPCK(hipStreamSynchronize(s));
-        } else if (opt->flags & QM_OUTPUT_DEVICE) {   // the result stays on the device
-            HIPCK(hipStreamSynchronize(s));
-            auto dalloc = [&](auto** p, size_t n) {
-                HIPCK(hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(**p)));
-            };
-            dalloc(&R->d_xyz, 3 * (size_t)E.M.nv); dalloc(&R->d_tets, 4 * (size_t)a);
-            dalloc(&R->d_sf, 3 * (size_t)b); dalloc(&R->d_sff, (size_t)b);
-            dalloc(&R->d_ss, 2 * (size_t)E.M.nss); dalloc(&R->d_ssg, (size_t)E.M.nss);
-            k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, R->d_tets);
-            if (b) k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, R->d_sf, R->d_sff);
-            k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, R->d_xyz);
-            if (E.M.nss) {
-                HIPCK(hipMemcpyAsync(R->d_ss, E.SV.p, sizeof(int) * 2 * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
-                HIPCK(hipMemcpyAsync(R->d_ssg, E.SSEG.p, sizeof(int) * (size_t)E.M.nss, hipMemcpyDeviceToDevice, s));
-            }
-            HIPCK(hipStreamSynchronize(s));
-            R->on_device = true;
-            R->dnv = E.M.nv; R->dnt = a; R->dnsf = b; R->dnss = E.M.nss;
-        } else {
-            DBuf<int> ot, osf, osff;
-            DBuf<double> ox;
-            ot.acct = osf.acct = osff.acct = &E.acct;
-            ox.acct = &E.acct;
-            ot.ensure(4 * (size_t)std::max(a, 1), s, false);
-            osf.ensure(3 * (size_t)std::max(b, 1), s, false);
-            osff.ensure(std::max(b, 1), s, false);
-            ox.ensure(3 * (size_t)E.M.nv, s, false);
-            k_out_tets<<<nblk(ntot), 256, 0, s>>>(E.M, tf.p, ts.p, ot.p);
-            k_out_sf<<<nblk(4L * ntot), 256, 0, s>>>(E.M, ff.p, fs.p, osf.p, osff.p);
-            k_out_xyz<<<nblk(E.M.nv), 256, 0, s>>>(E.M.nv, E.X.p, ox.p);
-            R->xyz.resize(3 * (size_t)E.M.nv);
-            R->tets.resize(4 * (size_t)a);
-            R->sf.resize(3 * (size_t)b);
-            R->sff.resize(b);
-            R->ss.resize(2 * (size_t)E.M.nss);
-            R->ssg.resize(E.M.nss);
-            HIPCK(hipMemcpyAsync(R->xyz.data(), ox.p, sizeof(double) * R->xyz.size(), hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(R->tets.data(), ot.p, sizeof(int) * R->tets.size(), hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(R->sf.data(), osf.p, sizeof(int) * R->sf.size(), hipMemcpyDeviceToHost, s));
-            HIPCK(hipMemcpyAsync(R->sff.data(), osff.p, sizeof(int) * R->sff.size(), hipMemcpyDeviceToHost, s));
-            if (E.M.nss) {
-                HIPCK(hipMemcpyAsync(R->ss.data(), E.SV.p, sizeof(int) * R->ss.size(), hipMemcpyDeviceToHost, s));
-                HIPCK(hipMemcpyAsync(R->ssg.data(), E.SSEG.p, sizeof(int) * R->ssg.size(), hipMemcpyDeviceToHost, s));
-            }
-            HIPCK(hipStreamSynchronize(s));
-            ot.release(s); osf.release(s); osff.release(s); ox.release(s);
-        }
-        tf.release(s); ts.release(s); ff.release(s); fs.release(s);
-        ST.nt_out = a;
-    }
+    ST.nt_out = emit_output(E, R.get(), opt, ar, dout);
     float ms_setup = 0, ms_ref = 0;
     if (noalloc) {            // host clock: the call's stream was synchronised at both points
         ms_setup = (float)std::chrono::duration<double, std::milli>(T1s - T0).count();
@@ -1476,4 +1521,5 @@ const char* qm_version(void) { return "qm 0.1 (gfx950)"; }
 
 }  // extern "C"
 
+#include "qm_lockstep.h"
 #include "qm_server.h"

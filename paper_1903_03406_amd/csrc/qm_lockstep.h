@@ -1,0 +1,731 @@
+// qm_lockstep.h -- lockstep batched form: independent refinements advance
+// round by round together, and each phase of a round is one launch over the
+// work of every instance that takes part in it.
+//
+// The round is the paper's (Section 2: classify, split, locate, grow and
+// validate, select, insert); each instance runs exactly the rounds it runs
+// alone and ends with the same output bits.  What changes is the launch
+// shape: a batched launch carries a part table (the instances it covers and
+// each one's first workgroup), every workgroup finds its part with two wave
+// ballots and runs the single-instance kernel body on that instance's arrays
+// with its workgroup index inside the part.  Per-instance pointers and
+// counts sit in a device table of `LsInst` records that the host refreshes
+// (one copy) whenever one of them changes.  Each instance still picks its
+// own class, so a round mixes subsegment, subface and tet work of different
+// instances in one launch.  Work whose size makes launch cost irrelevant
+// (sorting more than 256 candidates, scanning more than 32768, selecting
+// among more than 65536 claims, renumbering tet slots) runs per instance.
+#pragma once
+
+namespace qm {
+
+// device view of one instance in a batched launch
+struct LsInst {
+    Mesh M;
+    Cands C;
+    Pools PL;
+    BfPool BP;
+    int* ctr;
+    int* c_elem0;
+    unsigned long long* c_key0;
+    int4* c_tup0;
+    double4* c_p0;
+    int *c_st0, *c_reason0;
+    int *olist, *glist, *sk, *st_, *ss_, *kept;
+    unsigned long long* mark;
+    int* owner;
+    unsigned char *mis_drop, *mis_lose;
+    unsigned long long key_mask;
+    unsigned pass;
+    int cls, ncand, ncl, nkept, min_tier, nover, nbig, nv0, nt0, nss0;
+};
+
+// Parts of one batched launch, passed by value: part k covers workgroups
+// [pre[k], pre[k+1]) and instance table entry map[k].
+constexpr int LS_PARTS = 256;
+struct LsParts {
+    int np;
+    int pre[LS_PARTS + 1];
+    int map[LS_PARTS];
+};
+
+// the part of workgroup b: the last k with pre[k] <= b (parts are never
+// empty), searched 64 parts at a time by wave ballots (np <= 4096)
+QMD int ls_find_part(const LsParts& P, int b) {
+    const int lane = threadIdx.x & 63;
+    const int step = (P.np + 63) >> 6;
+    int j = lane * step;
+    unsigned long long m = __ballot(j < P.np && P.pre[j] <= b);
+    const int base = (63 - __clzll((long long)m)) * step;
+    j = base + lane;
+    m = __ballot(lane < step && j < P.np && P.pre[j] <= b);
+    return base + (63 - __clzll((long long)m));
+}
+
+template <int NT, class F>
+__global__ __launch_bounds__(NT) void k_each(const LsInst* __restrict__ D, const LsParts P, const F f) {
+    const int k = ls_find_part(P, (int)blockIdx.x);
+    f(D[P.map[k]], k, (int)blockIdx.x - P.pre[k], P.pre[k + 1] - P.pre[k]);
+}
+
+// ---- per-phase bodies (instance record, part index, workgroup, workgroups)
+struct FReset {                 // k_round_reset
+    QMD void operator()(const LsInst& d, int, int, int) const {
+        const int i = threadIdx.x;
+        if (i < 48 && (i < 11 || i >= 15)) d.ctr[i] = 0;
+    }
+};
+struct FClassifySS {
+    QMD void operator()(const LsInst& d, int, int b, int g) const { d_classify_ss(d.M, d.c_elem0, d.ctr + 8, b, g); }
+};
+struct FClassifySF {
+    QMD void operator()(const LsInst& d, int, int b, int g) const { d_classify_sf(d.M, d.c_elem0, d.ctr + 8, b, g); }
+};
+struct FClassifyTet {
+    QMD void operator()(const LsInst& d, int, int b, int g) const { d_classify_tet(d.M, d.c_elem0, d.ctr + 8, b, g); }
+};
+struct FGather {                // counters of each part, side by side
+    int* out;
+    QMD void operator()(const LsInst& d, int k, int, int) const {
+        for (int i = threadIdx.x; i < 48; i += blockDim.x) out[48 * k + i] = d.ctr[i];
+    }
+};
+struct FSplit {
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_split(d.M, d.cls, d.ncand, d.c_elem0, d.c_key0, d.c_tup0, d.c_p0, d.c_st0, d.c_reason0, d.key_mask, b, g);
+    }
+};
+struct FOrderSmall {
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_order_small(d.ncand, d.c_elem0, d.c_key0, d.c_tup0, d.c_p0, d.c_st0, d.c_reason0, d.C, b, g);
+    }
+};
+struct FLocate {
+    QMD void operator()(const LsInst& d, int, int b, int g) const { d_locate(d.M, d.cls, d.C, b, g); }
+};
+struct FResetPools {            // k_round_reset_pools
+    QMD void operator()(const LsInst& d, int, int, int) const {
+        if (threadIdx.x < 8) d.ctr[threadIdx.x] = 0;
+    }
+};
+struct FGrowSmall {
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_grow_lds<QM_TILES_SMALL>(d.M, d.cls, d.C, d.PL, d.BP, nullptr, 0, nullptr, d.min_tier, b, g);
+    }
+};
+struct FListReset {             // re-run list counts [32..35) and [36]
+    QMD void operator()(const LsInst& d, int, int, int) const {
+        const int i = threadIdx.x;
+        if (i < 5 && i != 3) d.ctr[32 + i] = 0;
+    }
+};
+struct FOverflowList {
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_overflow_list(d.C, d.olist, d.glist, d.ctr + 32, b, g);
+    }
+};
+struct FGrowHybrid {            // workgroup w of the launch uses block w of the shared slab
+    GrowTiles T;
+    char* slab;
+    size_t block;
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_grow_hybrid<H_LANES, H_HCAP, H_RFHCAP, H_QHCAP>(d.M, d.cls, d.C, d.PL, d.BP, d.olist, d.nover, T,
+                                                          slab + block * blockIdx.x, b, g);
+    }
+};
+struct FGrowGlobal {
+    GrowTiles T;
+    char* slab;
+    size_t block;
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_grow_global<B_LANES>(d.M, d.cls, d.C, d.PL, d.BP, d.glist, d.nbig, T, slab + block * blockIdx.x, b, g);
+    }
+};
+struct FVerdicts {
+    QMD void operator()(const LsInst& d, int, int b, int g) const { d_verdicts(d.M, d.cls, d.C, d.PL, d.ctr + 16, b, g); }
+};
+struct FMisSmall {
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_mis_small(d.ncl, d.PL.cl, d.PL.clc, d.ncand, d.C.state, d.mark, d.owner, d.mis_drop, d.mis_lose, d.pass,
+                    MIS_SMALL_PASSES, d.ctr + 38, b, g);
+    }
+};
+struct FScanSmall {
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_scan_small(d.C, d.cls, d.ncand, d.sk, d.st_, d.ss_, d.ctr + 11, b, g);
+    }
+};
+struct FKeptList {
+    QMD void operator()(const LsInst& d, int, int b, int g) const { d_kept_list(d.C, d.sk, d.kept, b, g); }
+};
+struct FInsert {
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        d_insert(d.M, d.cls, d.C, d.PL, d.BP, d.kept, d.nkept, d.sk, d.st_, d.ss_, d.nv0, d.nt0, d.nss0, d.ctr + 14,
+                 b, g);
+    }
+};
+struct FMisRelease {
+    QMD void operator()(const LsInst& d, int, int b, int g) const { d_mis_release(d.ncl, d.PL.cl, d.PL.clc, d.owner, b, g); }
+};
+
+}  // namespace qm
+
+namespace {
+
+using namespace qm;
+
+// host and device halves of the staging ring for the instance tables: the
+// ring restarts after every stream synchronisation, when every earlier copy
+// out of it has completed
+struct LsStage {
+    char* h = nullptr;
+    DBuf<char> d;
+    size_t cap = 0, off = 0;
+    hipStream_t s;
+    explicit LsStage(hipStream_t st) : s(st) {}
+    ~LsStage() {
+        if (h) (void)hipHostFree(h);
+        d.release(s);
+    }
+    void reserve(size_t bytes) {
+        if (bytes <= cap) return;
+        HIPCK(hipStreamSynchronize(s));
+        if (h) (void)hipHostFree(h);
+        h = nullptr;
+        cap = std::max(bytes, (size_t)4 << 20);
+        HIPCK(hipHostMalloc((void**)&h, cap, hipHostMallocDefault));
+        d.ensure_exact(cap, s);
+        off = 0;
+    }
+    // copy n records to the device; returns their device address
+    template <class T>
+    const T* put(const T* src, size_t n) {
+        const size_t bytes = ((n * sizeof(T)) + 255) & ~(size_t)255;
+        if (off + bytes > cap) {            // full: wait for the copies in flight
+            HIPCK(hipStreamSynchronize(s));
+            off = 0;
+            reserve(bytes);
+        }
+        std::memcpy(h + off, src, n * sizeof(T));
+        HIPCK(hipMemcpyAsync(d.p + off, h + off, n * sizeof(T), hipMemcpyHostToDevice, s));
+        const T* r = reinterpret_cast<const T*>(d.p + off);
+        off += bytes;
+        return r;
+    }
+    void synced() { off = 0; }
+};
+
+// One instance of a lockstep batch: its engine (all device buffers), result
+// and round state.
+struct LsJob {
+    uint64_t tag = 0;
+    const qm_options* opt = nullptr;
+    qm_options opt_copy{};
+    std::unique_ptr<Engine> E;
+    std::unique_ptr<qm_result> R;
+    qm_stats ST{};
+    int round = 0, status = 0, last_ncand = 0;
+    int cls = CLS_NONE, ncand = 0, ncl = 0, nkept = 0, newt = 0, newss = 0, nover = 0, nbig = 0;
+    int passes = 0, ncl_final = 0, pool_pass = 0, attempt = 0;
+    bool small_sel = false, pool_done = false, list_done = false;
+    unsigned long long key_mask = ~0ull;
+    int min_tier = 0;
+    const int* hc = nullptr;        // its counters at the last gather
+    std::chrono::steady_clock::time_point t_add, t_ready;
+};
+
+struct LsDone {
+    uint64_t tag;
+    qm_result* res;
+    int code;
+    std::string msg;
+};
+
+class Lockstep {
+public:
+    explicit Lockstep(hipStream_t s) : s_(s), stage_(s) {}
+    ~Lockstep() {
+        for (auto& d : done_) qm_result_free(d.res);
+        jobs_.clear();
+        hslab_.release(s_); gslab_.release(s_); gath_.release(s_);
+        if (hgath_) (void)hipHostFree(hgath_);
+        (void)hipStreamSynchronize(s_);
+    }
+    int live() const { return (int)jobs_.size(); }
+    // Set an instance up on the device; it takes part from the next step.
+    // A failing set-up (or refused options) ends it at once, in take_done().
+    void add(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, uint64_t tag) {
+        auto J = std::make_unique<LsJob>();
+        J->tag = tag;
+        J->t_add = std::chrono::steady_clock::now();
+        try {
+            if (!plc || !in || !opt) throw QmError(QM_EINVAL, "null argument");
+            if (!(opt->B > 0.0) || !(opt->hmin_factor >= 0.0) || opt->max_rounds < 0)
+                throw QmError(QM_EINVAL, "B must be > 0, hmin_factor >= 0, max_rounds >= 0");
+            if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
+                throw QmError(QM_EINVAL, "bad counts");
+            if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
+            if (opt->flags & (QM_PROFILE | QM_PROFILE_GROW | QM_EARLY_STOP) || opt->max_kept > 0)
+                throw QmError(QM_EINVAL, "the lockstep form takes no profiling, early stop or insertion cap");
+            J->opt_copy = *opt;
+            J->opt = &J->opt_copy;
+            J->key_mask = (opt->flags & QM_TEST_KEY_COLLIDE) ? 0xE000000000000000ull : ~0ull;
+            J->min_tier = (opt->flags & QM_TEST_TIER2) ? 2 : (opt->flags & QM_TEST_TIER1) ? 1 : 0;
+            J->E = std::make_unique<Engine>(s_);
+            J->R = std::make_unique<qm_result>();
+            setup_mesh(*J->E, plc, in, J->opt, nullptr, nullptr);
+            J->t_ready = std::chrono::steady_clock::now();
+            jobs_.push_back(std::move(J));
+        } catch (const QmError& e) {
+            fail(*J, e.code, e.what());
+        } catch (const std::exception& e) {
+            fail(*J, QM_EINTERNAL, e.what());
+        }
+    }
+    // One round of every live instance; instances that finish (no candidate
+    // left, round limit, failure) move to take_done().
+    void step();
+    std::vector<LsDone> take_done() { return std::exchange(done_, {}); }
+
+private:
+    hipStream_t s_;
+    LsStage stage_;
+    std::vector<std::unique_ptr<LsJob>> jobs_;
+    std::vector<LsDone> done_;
+    std::vector<LsInst> table_;
+    const LsInst* dtab_ = nullptr;
+    DBuf<int> gath_;
+    int* hgath_ = nullptr;
+    size_t hgath_cap_ = 0;
+    DBuf<char> hslab_, gslab_;
+
+    void fail(LsJob& J, int code, const std::string& msg) {
+        J.E.reset();                         // frees its buffers in stream order
+        done_.push_back({J.tag, nullptr, code, msg});
+    }
+    // current device view of every live instance (one copy)
+    void upload() {
+        table_.resize(jobs_.size());
+        for (size_t i = 0; i < jobs_.size(); ++i) {
+            LsJob& J = *jobs_[i];
+            if (!J.E) continue;                  // ended this step (never listed again)
+            Engine& E = *J.E;
+            LsInst& t = table_[i];
+            t.M = E.M; t.C = E.C; t.PL = E.PL; t.BP = E.BP;
+            t.ctr = E.ctr.p;
+            t.c_elem0 = E.c_elem0.p; t.c_key0 = E.c_key0.p; t.c_tup0 = E.c_tup0.p; t.c_p0 = E.c_p0.p;
+            t.c_st0 = E.c_st0.p; t.c_reason0 = E.c_reason0.p;
+            t.olist = E.olist.p; t.glist = E.glist.p; t.sk = E.sk.p; t.st_ = E.st_.p; t.ss_ = E.ss_.p;
+            t.kept = E.kept.p; t.mark = E.mark.p; t.owner = E.owner.p;
+            t.mis_drop = E.mis_drop.p; t.mis_lose = E.mis_lose.p;
+            t.key_mask = J.key_mask; t.pass = E.pass;
+            t.cls = J.cls; t.ncand = J.ncand; t.ncl = J.ncl; t.nkept = J.nkept; t.min_tier = J.min_tier;
+            t.nover = J.nover; t.nbig = J.nbig; t.nv0 = E.M.nv; t.nt0 = E.M.nt; t.nss0 = E.M.nss;
+        }
+        stage_.reserve(sizeof(LsInst) * table_.size() + 256);
+        dtab_ = stage_.put(table_.data(), table_.size());
+    }
+    // one batched launch over the instances `idx` (indices into jobs_) with
+    // blocks(i) workgroups each (instances with none are left out), in
+    // launches of at most LS_PARTS parts
+    template <int NT, class F, class B>
+    void launch(const std::vector<int>& idx, B blocks, const F& f) {
+        LsParts P;
+        P.np = 0;
+        P.pre[0] = 0;
+        auto go = [&]() {
+            if (!P.np) return;
+            k_each<NT, F><<<P.pre[P.np], NT, 0, s_>>>(dtab_, P, f);
+            P.np = 0;
+            P.pre[0] = 0;
+        };
+        for (int i : idx) {
+            const long nb = blocks(*jobs_[i]);
+            if (nb <= 0) continue;
+            if (P.np == LS_PARTS || (long)P.pre[P.np] + nb > (1L << 30)) go();
+            P.map[P.np] = i;
+            P.pre[P.np + 1] = P.pre[P.np] + (int)nb;
+            ++P.np;
+        }
+        go();
+    }
+    // the counters of the instances `idx` to the host (one copy, one
+    // synchronisation); J.hc points at each one's 48 values
+    void gather(const std::vector<int>& idx) {
+        const size_t n = idx.size();
+        gath_.ensure(48 * std::max<size_t>(n, 1), s_, false);
+        if (48 * n > hgath_cap_) {
+            HIPCK(hipStreamSynchronize(s_));
+            if (hgath_) (void)hipHostFree(hgath_);
+            hgath_ = nullptr;
+            hgath_cap_ = 48 * std::max<size_t>(n, 64);
+            HIPCK(hipHostMalloc((void**)&hgath_, sizeof(int) * hgath_cap_, hipHostMallocDefault));
+        }
+        // parts in idx order: part k of chunk c is entry c * LS_PARTS + k
+        for (size_t c = 0; c < n; c += LS_PARTS) {
+            std::vector<int> sub(idx.begin() + c, idx.begin() + std::min(n, c + LS_PARTS));
+            FGather g{gath_.p + 48 * c};
+            launch<64>(sub, [](const LsJob&) { return 1L; }, g);
+        }
+        HIPCK(hipMemcpyAsync(hgath_, gath_.p, sizeof(int) * 48 * n, hipMemcpyDeviceToHost, s_));
+        HIPCK(hipStreamSynchronize(s_));
+        stage_.synced();
+        for (size_t k = 0; k < n; ++k) jobs_[idx[k]]->hc = hgath_ + 48 * k;
+    }
+    void finish(LsJob& J);
+    void patch_last_record(LsJob& J) {
+        if (J.R->rounds.empty()) return;
+        J.E->dead = J.hc[14];
+        J.R->rounds[J.R->rounds.size() - QM_ROUND_FIELDS + 16] = J.E->M.nt - (int)J.E->dead;
+    }
+    void select_large(LsJob& J);
+    void scans_large(LsJob& J);
+    void sort_large(LsJob& J);
+    // run fn on each listed job; a job whose host logic throws ends with
+    // that error (its device work so far is harmless: nothing reads it)
+    template <class Fn>
+    void each(std::vector<int>& idx, Fn fn) {
+        bool dropped = false;
+        for (int i : idx) {
+            LsJob& J = *jobs_[i];
+            if (!J.E) continue;
+            try {
+                fn(J);
+            } catch (const QmError& e) {
+                fail(J, e.code, e.what());
+                dropped = true;
+            } catch (const std::exception& e) {
+                fail(J, QM_EINTERNAL, e.what());
+                dropped = true;
+            }
+        }
+        if (dropped) idx.erase(std::remove_if(idx.begin(), idx.end(), [&](int i) { return !jobs_[i]->E; }), idx.end());
+    }
+    void compact() {        // drop finished and failed jobs from the live list
+        jobs_.erase(std::remove_if(jobs_.begin(), jobs_.end(), [](const std::unique_ptr<LsJob>& J) { return !J->E; }),
+                    jobs_.end());
+    }
+};
+
+void Lockstep::finish(LsJob& J) {
+    Engine& E = *J.E;
+    if (J.last_ncand > 0) read_last_round(E, J.R.get(), J.last_ncand);
+    const int gerr = read1(E.M.err, s_);
+    if (gerr) throw QmError(QM_EINTERNAL, "exact predicate precondition failed (code " + std::to_string(gerr) + ")");
+    J.ST.nt_out = emit_output(E, J.R.get(), J.opt, nullptr, nullptr);
+    const auto now = std::chrono::steady_clock::now();
+    J.ST.rounds = J.round;
+    J.ST.status = J.status;
+    J.ST.device_bytes_peak = (int64_t)E.acct.peak;
+    J.ST.nv_out = E.M.nv;
+    J.ST.seconds_setup = std::chrono::duration<double>(J.t_ready - J.t_add).count();
+    J.ST.seconds_refine = std::chrono::duration<double>(now - J.t_ready).count();
+    J.ST.seconds_total = std::chrono::duration<double>(now - J.t_add).count();
+    J.R->stats = J.ST;
+    J.E.reset();
+    done_.push_back({J.tag, J.R.release(), J.status == 1 ? QM_EROUNDS : QM_OK, ""});
+}
+
+// more than 256 candidates: radix sort by key, then the tie fix
+void Lockstep::sort_large(LsJob& J) {
+    Engine& E = *J.E;
+    const int n = J.ncand;
+    k_iota<<<nblk(n), 256, 0, s_>>>(n, E.order0.p);
+    E.sort_desc(E.c_key0.p, E.skey.p, E.order0.p, E.order1.p, n);
+    k_fix_ties<<<nblk(n), 256, 0, s_>>>(n, E.skey.p, E.order1.p, E.c_tup0.p);
+    k_permute<<<nblk(n), 256, 0, s_>>>(n, E.order1.p, E.c_elem0.p, E.c_key0.p, E.c_tup0.p, E.c_p0.p, E.c_st0.p,
+                                       E.c_reason0.p, E.C);
+}
+
+// more than SCAN_SMALL candidates: device-wide scans of the three values
+void Lockstep::scans_large(LsJob& J) {
+    Engine& E = *J.E;
+    const int n = J.ncand;
+    k_scan_vals<<<nblk(n), 256, 0, s_>>>(E.C, J.cls, E.vk.p, E.vt.p, E.vs.p);
+    E.exscan(E.vk.p, E.sk.p, n);
+    E.exscan(E.vt.p, E.st_.p, n);
+    E.exscan(E.vs.p, E.ss_.p, n);
+    k_totals<<<1, 1, 0, s_>>>(n, E.sk.p, E.vk.p, E.st_.p, E.vt.p, E.ss_.p, E.vs.p, E.ctr.p + 11);
+}
+
+// more than MIS_SMALL claims or candidates: batches of selection passes,
+// each batch followed by the scans and a look at the undecided counts
+void Lockstep::select_large(LsJob& J) {
+    Engine& E = *J.E;
+    const int ncl = J.ncl, ncand = J.ncand;
+    int* undec_d = E.ctr.p + 40;
+    int* nu_d = E.ctr.p + 46;
+    int hc[48];
+    J.passes = 0;
+    for (int batch = 0;; ++batch) {
+        if (batch > 0) HIPCK(hipMemsetAsync(undec_d, 0, MIS_BATCH * sizeof(int), s_));
+        for (int b = 0; b < MIS_BATCH; ++b) {
+            const unsigned ps = E.pass++;
+            const int p = batch * MIS_BATCH + b;
+            int* const u_out = (p & 1) ? E.ulist1.p : E.ulist0.p;
+            int* const nu_out = nu_d + (p & 1);
+            if (p == 0) {
+                k_mis_mark<<<nblk(ncl), 256, 0, s_>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps, nullptr);
+                k_mis_check<<<nblk(ncl), 256, 0, s_>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, E.owner.p, ps,
+                                                       E.mis_drop.p, E.mis_lose.p, nullptr);
+                k_mis_decide<<<nblk(ncand), 256, 0, s_>>>(ncand, E.state.p, E.mis_drop.p, E.mis_lose.p, undec_d + b,
+                                                          nullptr, u_out, nu_out);
+                k_mis_commit<<<nblk(ncl), 256, 0, s_>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p, nullptr);
+            } else {
+                const int* const u_in = (p & 1) ? E.ulist0.p : E.ulist1.p;
+                const int* const nu_in = nu_d + ((p - 1) & 1);
+                k_mis_mark_list<<<MIS_LIST_GRID, 256, 0, s_>>>(u_in, nu_in, E.C, E.p_cl.p, E.mark.p, ps, nu_out);
+                k_mis_check_list<<<MIS_LIST_GRID, 256, 0, s_>>>(u_in, nu_in, E.C, E.p_cl.p, E.mark.p, E.owner.p, ps,
+                                                                E.mis_drop.p, E.mis_lose.p);
+                k_mis_decide_list<<<MIS_LIST_GRID / 4, 256, 0, s_>>>(u_in, nu_in, E.state.p, E.mis_drop.p,
+                                                                     E.mis_lose.p, undec_d + b, u_out, nu_out);
+                k_mis_commit_list<<<MIS_LIST_GRID, 256, 0, s_>>>(u_in, nu_in, E.C, E.p_cl.p, E.state.p, E.owner.p);
+            }
+        }
+        if (ncand <= SCAN_SMALL)
+            k_scan_small<<<1, 1024, 0, s_>>>(E.C, J.cls, ncand, E.sk.p, E.st_.p, E.ss_.p, E.ctr.p + 11);
+        else
+            scans_large(J);
+        HIPCK(hipMemcpyAsync(hc, E.ctr.p, sizeof hc, hipMemcpyDeviceToHost, s_));
+        HIPCK(hipStreamSynchronize(s_));
+        for (int b = 0; b < MIS_BATCH; ++b) {
+            ++J.passes;
+            if (hc[40 + b] == 0) break;
+        }
+        if (hc[40 + MIS_BATCH - 1] == 0) break;
+    }
+    stage_.synced();
+}
+
+void Lockstep::step() {
+    std::vector<int> L(jobs_.size());
+    for (size_t i = 0; i < jobs_.size(); ++i) L[i] = (int)i;
+    // round start: the round limit, slot renumbering, candidate space
+    each(L, [&](LsJob& J) {
+        Engine& E = *J.E;
+        if (J.round >= J.opt->max_rounds) {
+            int hc[48];
+            HIPCK(hipMemcpyAsync(hc, E.ctr.p, sizeof hc, hipMemcpyDeviceToHost, s_));
+            HIPCK(hipStreamSynchronize(s_));
+            J.hc = hc;
+            patch_last_record(J);
+            J.hc = nullptr;
+            J.status = 1;
+            finish(J);
+            return;
+        }
+        if (E.M.nt - E.nt_ordered > std::max(E.M.nt / 10, 65536)) E.reorder();
+        E.c_elem0.ensure(std::max((size_t)E.M.nss, 4 * (size_t)E.M.nt), s_, false);
+    });
+    L.erase(std::remove_if(L.begin(), L.end(), [&](int i) { return !jobs_[i]->E; }), L.end());
+    if (L.empty()) { compact(); return; }
+    stage_.synced();        // the round-limit and renumbering paths synchronised the stream
+    // step 1: classify
+    upload();
+    launch<64>(L, [](const LsJob&) { return 1L; }, FReset{});
+    launch<256>(L, [](const LsJob& J) { return J.E->M.nss ? (long)nblk(J.E->M.nss) : 0L; }, FClassifySS{});
+    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt); }, FClassifySF{});
+    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt); }, FClassifyTet{});
+    gather(L);
+    each(L, [&](LsJob& J) {
+        patch_last_record(J);
+        J.cls = CLS_NONE;
+        J.ncand = 0;
+        for (int c = CLS_SS; c <= CLS_TET && J.cls == CLS_NONE; ++c)
+            if (J.hc[8 + c] > 0) { J.cls = c; J.ncand = J.hc[8 + c]; }
+        if (J.cls == CLS_NONE) { finish(J); return; }
+        Engine& E = *J.E;
+        E.ensure_cands(J.ncand);
+        E.ensure_pools(E.pool_need(1, J.ncand, J.cls), E.pool_need(2, J.ncand, J.cls), E.pool_need(3, J.ncand, J.cls),
+                       E.pool_need(4, J.ncand, J.cls));
+        J.pool_pass = 0;
+        J.pool_done = false;
+        J.nover = J.nbig = 0;
+    });
+    L.erase(std::remove_if(L.begin(), L.end(), [&](int i) { return !jobs_[i]->E; }), L.end());
+    if (L.empty()) { compact(); return; }
+    // step 2: splitting points, priorities and their order
+    upload();
+    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.ncand); }, FSplit{});
+    launch<SORT_SMALL>(L, [](const LsJob& J) { return J.ncand <= SORT_SMALL ? 1L : 0L; }, FOrderSmall{});
+    each(L, [&](LsJob& J) { if (J.ncand > SORT_SMALL) sort_large(J); });
+    // step 3: locate
+    launch<64>(L, [](const LsJob& J) { return J.cls != CLS_SS ? (long)nblk(J.ncand, 64) : 0L; }, FLocate{});
+    // steps 4-5: grow and validate; a pass is repeated (with larger pools) by
+    // the instances whose result pools were full
+    std::vector<int> P = L;
+    for (int pass = 0; !P.empty(); ++pass) {
+        if (pass > 0) {
+            upload();
+            launch<64>(P, [](const LsJob&) { return 1L; }, FResetPools{});
+        }
+        launch<64>(P, [](const LsJob& J) { return (long)std::min(J.ncand, 16384); }, FGrowSmall{});
+        std::vector<int> A = P;
+        for (int attempt = 0; !A.empty(); ++attempt) {
+            launch<64>(A, [](const LsJob&) { return 1L; }, FListReset{});
+            launch<256>(A, [](const LsJob& J) { return (long)nblk(J.ncand); }, FOverflowList{});
+            gather(A);
+            long hyb_total = 0, big_total = 0;
+            each(A, [&](LsJob& J) {
+                J.nover = J.hc[32];
+                J.nbig = J.hc[36];
+                if (J.hc[34])
+                    throw QmError(QM_ECAPACITY, "a region exceeds the largest supported size (round " +
+                                                    std::to_string(J.round) + ", class " + std::to_string(J.cls) + ")");
+                if (J.nover + J.nbig == 0) {            // this pass is evaluated: were the pools large enough?
+                    if (!J.hc[5]) {
+                        J.E->pool_seen(J.hc, J.ncand, J.cls);
+                        J.ncl_final = J.hc[3];
+                        J.pool_done = true;
+                    } else {
+                        if (pass >= 8) throw QmError(QM_ENOMEM, "result pools kept overflowing");
+                        Engine& E = *J.E;
+                        auto need = [](int used, size_t cap) {
+                            return std::max(cap, (size_t)used + (size_t)used / 8 + 4096);
+                        };
+                        E.ensure_pools(need(J.hc[1], E.p_bfr.cap / BFR), need(J.hc[2], E.p_be.cap),
+                                       need(J.hc[3], E.p_cl.cap), need(J.hc[4], E.p_q.cap));
+                    }
+                    return;
+                }
+                if (attempt >= 64) throw QmError(QM_EINTERNAL, "regions kept outgrowing the tiles");
+                hyb_total += std::min(J.nover, 1024);
+                big_total += std::min(J.nbig, 1024);
+            });
+            A.erase(std::remove_if(A.begin(), A.end(), [&](int i) { return !jobs_[i]->E || jobs_[i]->nover + jobs_[i]->nbig == 0; }),
+                    A.end());
+            if (A.empty()) break;
+            upload();
+            if (hyb_total > 0) {            // hybrid tier: at most 1024 workgroups over all instances
+                const GrowTiles HT = hybrid_tiles();
+                const size_t block = lists_slab_bytes(HT);
+                const long cap = 1024;
+                auto share = [&](const LsJob& J) -> long {
+                    if (J.nover <= 0) return 0L;
+                    const long want = std::min(J.nover, 1024);
+                    return hyb_total <= cap ? want : std::max(1L, want * cap / hyb_total);
+                };
+                long total = 0;
+                for (int i : A) total += share(*jobs_[i]);
+                hslab_.ensure_exact(block * (size_t)std::min<long>(total, LS_PARTS * 1024L), s_);
+                launch<H_LANES>(A, share, FGrowHybrid{HT, hslab_.p, block});
+            }
+            if (big_total > 0) {            // global-memory tiles: at most 256 workgroups over all instances
+                GrowTiles BT{};
+                BT.maxrt = B_MAXRT; BT.hcap = B_HCAP; BT.rfhcap = B_RFHCAP; BT.maxrf = B_MAXRF; BT.maxbe = B_MAXBE;
+                BT.qhcap = B_QHCAP; BT.maxq = B_MAXQ; BT.maxbf = B_MAXBF; BT.maxcx = B_MAXBF; BT.tier = 2;
+                BT.ehcap = 1;
+                while (BT.ehcap < 2 * (3 * BT.maxbf + BT.maxbe)) BT.ehcap <<= 1;
+                const size_t block = grow_slab_bytes(BT);
+                const long cap = 256;
+                auto share = [&](const LsJob& J) -> long {
+                    if (J.nbig <= 0) return 0L;
+                    const long want = std::min(J.nbig, 1024);
+                    return big_total <= cap ? want : std::max(1L, want * cap / big_total);
+                };
+                long total = 0;
+                for (int i : A) total += share(*jobs_[i]);
+                gslab_.ensure_exact(block * (size_t)std::min<long>(total, LS_PARTS * 1024L), s_);
+                launch<B_LANES>(A, share, FGrowGlobal{BT, gslab_.p, block});
+            }
+        }
+        P.erase(std::remove_if(P.begin(), P.end(), [&](int i) { return !jobs_[i]->E || jobs_[i]->pool_done; }), P.end());
+    }
+    L.erase(std::remove_if(L.begin(), L.end(), [&](int i) { return !jobs_[i]->E; }), L.end());
+    if (L.empty()) { compact(); return; }
+    // verdicts, then step 6: selection, with the step-7 scans
+    each(L, [&](LsJob& J) {
+        Engine& E = *J.E;
+        J.ncl = std::min(J.ncl_final, E.PL.cap_cl);
+        J.small_sel = J.ncl > 0 && J.ncl <= MIS_SMALL && J.ncand <= MIS_SMALL;
+        J.passes = 0;
+    });
+    upload();
+    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.ncand); }, FVerdicts{});
+    launch<1024>(L, [](const LsJob& J) { return J.small_sel ? 1L : 0L; }, FMisSmall{});
+    each(L, [&](LsJob& J) { if (J.ncl > 0 && !J.small_sel) select_large(J); });
+    launch<1024>(L, [](const LsJob& J) { return (J.small_sel || J.ncl == 0) && J.ncand <= SCAN_SMALL ? 1L : 0L; },
+                 FScanSmall{});
+    each(L, [&](LsJob& J) { if ((J.small_sel || J.ncl == 0) && J.ncand > SCAN_SMALL) scans_large(J); });
+    gather(L);
+    // step 7: insertion
+    each(L, [&](LsJob& J) {
+        Engine& E = *J.E;
+        if (J.small_sel) {
+            if (J.hc[38] < 0) throw QmError(QM_EINTERNAL, "selection did not finish");
+            J.passes = J.hc[38];
+            E.pass += (unsigned)J.passes;
+        }
+        J.nkept = J.hc[11];
+        J.newt = J.hc[12];
+        J.newss = J.hc[13];
+        if (J.hc[16 + 13]) throw QmError(QM_EINTERNAL, "candidate left unresolved");
+        if (J.nkept > 0) E.ensure_mesh(E.M.nv + J.nkept, E.M.nt + J.newt, E.M.nss + J.newss);
+    });
+    upload();
+    launch<256>(L, [](const LsJob& J) { return J.nkept > 0 ? (long)nblk(J.ncand) : 0L; }, FKeptList{});
+    launch<64>(L, [](const LsJob& J) { return (long)std::min(J.nkept, 16384); }, FInsert{});
+    launch<256>(L, [](const LsJob& J) { return J.ncl > 0 ? (long)nblk(J.ncl) : 0L; }, FMisRelease{});
+    each(L, [&](LsJob& J) {
+        Engine& E = *J.E;
+        const int* st = J.hc + 16;
+        E.M.nv += J.nkept; E.M.nt += J.newt; E.M.nss += J.newss;
+        int rec[QM_ROUND_FIELDS] = {J.cls, st[0], st[1], st[2], st[3], J.nkept};
+        for (int r = 1; r < EX_NREASON; ++r) rec[5 + r] = st[3 + r];
+        rec[15] = E.M.nv;
+        rec[16] = E.M.nt - (int)E.dead;   // completed at the next synchronisation
+        J.R->rounds.insert(J.R->rounds.end(), rec, rec + QM_ROUND_FIELDS);
+        J.ST.inserted[J.cls] += J.nkept;
+        J.last_ncand = J.ncand;
+        J.ST.candidates += J.ncand;
+        J.ST.mis_passes += J.passes;
+        J.ST.deferred += st[14];
+        ++J.round;
+    });
+    compact();
+}
+
+}  // namespace
+
+extern "C" {
+
+int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                       void* hip_stream, qm_result** outs, int32_t* codes) {
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!plcs || !meshes || !opts || !outs || !codes))) {
+        g_err = "bad batch arguments";
+        return QM_EINVAL;
+    }
+    for (int i = 0; i < n; ++i) { outs[i] = nullptr; codes[i] = QM_EINTERNAL; }
+    std::vector<std::string> msgs(n);
+    try {
+        Lockstep B((hipStream_t)hip_stream);
+        auto collect = [&]() {
+            for (auto& d : B.take_done()) {
+                outs[d.tag] = d.res;
+                codes[d.tag] = d.code;
+                msgs[d.tag] = d.msg;
+            }
+        };
+        for (int i = 0; i < n; ++i) B.add(&plcs[i], &meshes[i], &opts[i], (uint64_t)i);
+        collect();
+        while (B.live() > 0) {
+            B.step();
+            collect();
+        }
+    } catch (const QmError& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return QM_EINTERNAL;
+    }
+    for (int i = 0; i < n; ++i)
+        if (codes[i] != QM_OK && codes[i] != QM_EROUNDS) {
+            g_err = "instance " + std::to_string(i) + ": " + msgs[i];
+            return codes[i];
+        }
+    return QM_OK;
+}
+
+}  // extern "C"

@@ -11,8 +11,8 @@ namespace qm {
 // Each classification kernel counts its class in cnt[cls] and writes the
 // candidates to cand; a class is skipped when an earlier one has candidates
 // (the paper's order), which the kernel reads from cnt itself.
-__global__ void k_classify_ss(Mesh M, int* cand, int* cnt) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_classify_ss(Mesh M, int* cand, int* cnt, const int bid, const int gdim) {
+    int s = bid * blockDim.x + threadIdx.x;
     if (s >= M.nss) return;
     int* ncand = cnt + CLS_SS;
     unsigned fl = M.SFL[s];
@@ -35,12 +35,15 @@ __global__ void k_classify_ss(Mesh M, int* cand, int* cnt) {
     }
     if (enc) cand[atomicAdd(ncand, 1)] = s;
 }
+__global__ void k_classify_ss(Mesh M, int* cand, int* cnt) {
+    d_classify_ss(M, cand, cnt, blockIdx.x, gridDim.x);
+}
 
 // Subface abc is encroached when queued, or when the apex of one of its
 // tets lies strictly inside its equatorial ball.  Each subface is taken from
 // the tet whose apex has the smaller id (or its only tet).
-__global__ void k_classify_sf(Mesh M, int* cand, int* cnt) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_classify_sf(Mesh M, int* cand, int* cnt, const int bid, const int gdim) {
+    int t = bid * blockDim.x + threadIdx.x;
     if (t >= M.nt || cnt[CLS_SS] > 0) return;
     int* ncand = cnt + CLS_SF;
     unsigned ti = M.TI[t];
@@ -73,10 +76,13 @@ __global__ void k_classify_sf(Mesh M, int* cand, int* cnt) {
     }
     if (learnt) atomicOr(&M.TI[t], learnt);
 }
+__global__ void k_classify_sf(Mesh M, int* cand, int* cnt) {
+    d_classify_sf(M, cand, cnt, blockIdx.x, gridDim.x);
+}
 
 // Bad tetrahedron: radius-edge ratio above B (paper, Section 1).
-__global__ void k_classify_tet(Mesh M, int* cand, int* cnt) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_classify_tet(Mesh M, int* cand, int* cnt, const int bid, const int gdim) {
+    int t = bid * blockDim.x + threadIdx.x;
     if (t >= M.nt || cnt[CLS_SS] > 0 || cnt[CLS_SF] > 0) return;
     int* ncand = cnt + CLS_TET;
     unsigned ti = M.TI[t];
@@ -98,14 +104,17 @@ __global__ void k_classify_tet(Mesh M, int* cand, int* cnt) {
     atomicOr(&M.TI[t], TI_BADK | (bad ? TI_BAD : 0u));
     if (bad) cand[atomicAdd(ncand, 1)] = t;
 }
+__global__ void k_classify_tet(Mesh M, int* cand, int* cnt) {
+    d_classify_tet(M, cand, cnt, blockIdx.x, gridDim.x);
+}
 
 // ------------------------------------------------------------------ split
 // splitting point (paper, Section 2: midpoint / circumcircle centre /
 // circumsphere centre) and the predetermined priority of each candidate
 // (key_mask: all ones, except in tests that force equal keys)
-__global__ void k_split(Mesh M, int cls, int n, const int* elem, unsigned long long* key, int4* tup,
-                        double4* p, int* st, int* reason, unsigned long long key_mask) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_split(Mesh M, int cls, int n, const int* elem, unsigned long long* key, int4* tup,
+                        double4* p, int* st, int* reason, unsigned long long key_mask, const int bid, const int gdim) {
+    int i = bid * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int e = elem[i];
     int ids[4] = {-1, -1, -1, -1}, k = 0;
@@ -137,6 +146,10 @@ __global__ void k_split(Mesh M, int cls, int n, const int* elem, unsigned long l
     bool fin = isfinite(P[0]) && isfinite(P[1]) && isfinite(P[2]);
     st[i] = fin ? ST_PENDING : ST_EXEMPT;
     reason[i] = fin ? EX_NONE : EX_NONFINITE;
+}
+__global__ void k_split(Mesh M, int cls, int n, const int* elem, unsigned long long* key, int4* tup,
+                        double4* p, int* st, int* reason, unsigned long long key_mask) {
+    d_split(M, cls, n, elem, key, tup, p, st, reason, key_mask, blockIdx.x, gridDim.x);
 }
 
 // order candidates: key descending (radix sort on ~key), equal keys by
@@ -179,8 +192,8 @@ __global__ void k_permute(int n, const int* order, const int* elem, const unsign
 // rejects the point and queues that subface.
 // SF: walk on the facet in its 2D projection, edges in ascending order;
 // crossing a subsegment rejects the point and queues that subsegment.
-__global__ void k_locate(Mesh M, int cls, Cands C) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+QMD void d_locate(Mesh M, int cls, Cands C, const int bid, const int gdim) {
+    int i = bid * blockDim.x + threadIdx.x;
     if (i >= C.n || C.st[i] != ST_PENDING) return;
     double4 pp = C.p[i];
     double P[3] = {pp.x, pp.y, pp.z};
@@ -249,6 +262,9 @@ __global__ void k_locate(Mesh M, int cls, Cands C) {
         }
         C.st[i] = ST_EXEMPT; C.reason[i] = EX_WALK;
     }
+}
+__global__ void k_locate(Mesh M, int cls, Cands C) {
+    d_locate(M, cls, C, blockIdx.x, gridDim.x);
 }
 
 }  // namespace qm
