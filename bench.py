@@ -132,35 +132,51 @@ def cpu_baseline(w, target_s):
 
 def bench_batch(args, qm):
     """Batched workload (config 4 instances 0..N-1, uniform points + a rotated
-    ellipsoid surface, B = 2.0): the whole set refined by qm_refine_batch on
-    --streams streams, against the same set refined one instance at a time.
-    Host arrays in, host results out in both forms."""
+    ellipsoid surface, B = 2.0): the whole set refined in lockstep by
+    qm_refine_lockstep (one launch per phase per round over all instances),
+    against the same set on --streams concurrent streams (qm_refine_batch)
+    and one instance at a time.  Host arrays in, host results out in every
+    form; the three must give the same rounds and vertex counts."""
     import numpy as np
     import qm_inputs as qi
     t0 = time.time()
-    ws = [qi.config(4, i) for i in range(args.batch)]
+    ws = []
+    for i in range(args.batch):
+        ws.append(qi.config(4, i))
+        if (i + 1) % 16 == 0:
+            print(f"[bench] {i + 1} instances built", file=sys.stderr, flush=True)
     npts = [len(w.xyz) - 8 for w in ws]
     print(f"[bench] {len(ws)} instances, {sum(npts)} points (min {min(npts)}, max {max(npts)}), "
           f"built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     qm.refine_batch(ws[:min(4, len(ws))], nstreams=args.streams)          # warm-up
+    qm.refine_lockstep(ws[:min(4, len(ws))])
     t1 = time.perf_counter()
-    lat = []
+    res_l = qm.refine_lockstep(ws)
+    t2 = time.perf_counter()
+    print(f"[bench] lockstep: {t2 - t1:.2f}s", file=sys.stderr, flush=True)
+    res_b = qm.refine_batch(ws, nstreams=args.streams)
+    t3 = time.perf_counter()
+    print(f"[bench] {args.streams} streams: {t3 - t2:.2f}s", file=sys.stderr, flush=True)
+    lat, res_1 = [], []
     for w in ws:
         a = time.perf_counter()
-        qm.refine_workload(w)
+        res_1.append(qm.refine_workload(w))
         lat.append(time.perf_counter() - a)
-    t2 = time.perf_counter()
-    res = qm.refine_batch(ws, nstreams=args.streams)
-    t3 = time.perf_counter()
-    steiner = sum(r.steiner for r in res)
-    seq, bat = t2 - t1, t3 - t2
+    t4 = time.perf_counter()
+    print(f"[bench] one at a time: {t4 - t3:.2f}s", file=sys.stderr, flush=True)
+    for a, b, c in zip(res_l, res_b, res_1):
+        assert a.rounds == b.rounds == c.rounds and len(a.xyz) == len(b.xyz) == len(c.xyz), "forms disagree"
+    steiner = sum(r.steiner for r in res_l)
+    ls, st, seq = t2 - t1, t3 - t2, t4 - t3
     out = {
-        "metric": "batched jobs/sec (config 4 instances)", "value": len(ws) / bat, "unit": "jobs/s",
+        "metric": "batched jobs/sec (config 4 instances)", "value": len(ws) / ls, "unit": "jobs/s",
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"cfg4_instances_0_{len(ws) - 1}", "instances": len(ws), "points": int(sum(npts)),
-                   "streams": args.streams},
-        "one_at_a_time_jobs_per_s": len(ws) / seq, "speedup": seq / bat,
-        "steiner_per_s_batched": steiner / bat,
+                   "form": "lockstep"},
+        "streams_jobs_per_s": len(ws) / st, "streams": args.streams,
+        "one_at_a_time_jobs_per_s": len(ws) / seq,
+        "speedup_vs_one_at_a_time": seq / ls, "speedup_vs_streams": st / ls,
+        "steiner_per_s_lockstep": steiner / ls, "max_rounds": max(r.rounds for r in res_l),
         "latency_one_at_a_time_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
     }
     print(json.dumps(out), flush=True)

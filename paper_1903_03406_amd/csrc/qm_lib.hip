@@ -273,6 +273,38 @@ __global__ __launch_bounds__(SORT_SMALL) void k_order_small(int n, const int* el
     d_order_small(n, elem, key, tup, p, st, reason, C, blockIdx.x, gridDim.x);
 }
 
+// Priority order of a mid-size round (up to CAP candidates) in one
+// workgroup of NT lanes: the same rank rule as k_order_small, keys staged in
+// LDS, tuples read only for equal keys.
+template <int NT, int CAP>
+QMD void d_order_rank(int n, const int* elem, const unsigned long long* key, const int4* tup, const double4* p,
+                      const int* st, const int* reason, Cands C) {
+    __shared__ unsigned long long K[CAP];
+    for (int i = threadIdx.x; i < n; i += NT) K[i] = key[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const unsigned long long ki = K[i];
+        int r = 0, eq = 0;
+        for (int j = 0; j < n; ++j) {
+            const unsigned long long kj = K[j];
+            r += kj > ki;
+            eq += kj == ki;
+        }
+        if (eq > 1) {                                 // equal keys: ascending tuple, then index
+            const int4 ti = tup[i];
+            for (int j = 0; j < n; ++j) {
+                if (K[j] != ki || j == i) continue;
+                const int4 tj = tup[j];
+                r += tj.x != ti.x ? tj.x < ti.x : tj.y != ti.y ? tj.y < ti.y : tj.z != ti.z ? tj.z < ti.z
+                   : tj.w != ti.w ? tj.w < ti.w : j < i;
+            }
+        }
+        C.elem[r] = elem[i]; C.key[r] = ki; C.tup[r] = tup[i]; C.p[r] = p[i];
+        C.st[r] = st[i]; C.reason[r] = reason[i];
+        C.seed[r] = -1; C.qw[r] = make_int2(-1, -1);
+    }
+}
+
 __global__ void k_iota(int n, int* o) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) o[i] = i;
@@ -455,6 +487,7 @@ struct Engine {
     explicit Engine(hipStream_t st) : s(st) {
         each_mesh_buf([&](auto& b) { b.acct = &acct; });
         each_round_buf([&](auto& b) { b.acct = &acct; });
+        cblock.acct = &acct;
     }
     // Slab workgroups that fit the budget (at least one): the slab being
     // replaced (`held` bytes) is freed first, and the slabs together keep to
@@ -469,7 +502,7 @@ struct Engine {
         return (int)std::max<size_t>(1, std::min<size_t>((size_t)grid, room / block));
     }
     ~Engine() {
-        DBuf<char>* bufs_c[] = {&tmp, &slab, &hslab};
+        DBuf<char>* bufs_c[] = {&tmp, &slab, &hslab, &cblock};
         for (auto* b : bufs_c) b->release(s);
         X.release(s); TV.release(s); TA.release(s); TF.release(s); TS.release(s); TI.release(s);
         SV.release(s); SSEG.release(s); STET.release(s); FAX.release(s); SFL.release(s);
@@ -512,16 +545,38 @@ struct Engine {
         STET.ensure(std::max(nss, 1), s, true);
         bind();
     }
-    void ensure_cands(int n) {
-        size_t m = std::max(n, 1);
-        for (auto* b : {&c_elem0, &c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
+    // Per-candidate arrays (contents not kept from round to round).  Without
+    // an arena they are carved from one block, so a larger round costs one
+    // allocation instead of one per array; the first-stage element list
+    // c_elem0 (sized by the classification) stays a buffer of its own.
+    DBuf<char> cblock;
+    Arena cband;
+    size_t cand_cap = 0;
+    template <class F>
+    void each_cand_buf(F&& f) {
+        for (auto* b : {&c_st0, &c_reason0, &order0, &order1, &c_elem, &c_st, &c_reason, &c_seed,
                         &gst, &greason, &reg_off, &reg_n, &bf_off, &bf_n, &be_off, &be_n, &cl_off, &cl_n,
                         &q_off, &q_n, &state, &vk, &vt, &vs, &sk, &st_, &ss_, &kept, &olist, &glist, &ulist0, &ulist1})
-            b->ensure(m, s, false);
-        c_key0.ensure(m, s, false); skey.ensure(m, s, false); c_key.ensure(m, s, false);
-        mis_drop.ensure(m, s, false, 0); mis_lose.ensure(m, s, false, 0);
-        c_tup0.ensure(m, s, false); c_tup.ensure(m, s, false);
-        c_p0.ensure(m, s, false); c_p.ensure(m, s, false); c_qw.ensure(m, s, false);
+            f(*b, 0);
+        f(c_key0, 0); f(skey, 0); f(c_key, 0); f(mis_drop, 1); f(mis_lose, 1);
+        f(c_tup0, 0); f(c_tup, 0); f(c_p0, 0); f(c_p, 0); f(c_qw, 0);
+    }
+    void ensure_cands(int n) {
+        size_t m = std::max(n, 1);
+        if (ar) {
+            c_elem0.ensure(m, s, false);
+            each_cand_buf([&](auto& b, int zero) { b.ensure(m, s, false, zero ? 0 : -1); });
+        } else if (m > cand_cap) {
+            const size_t cap = std::max(m, cand_cap + cand_cap / 2 + 1024);
+            size_t bytes = 0;
+            each_cand_buf([&](auto& b, int) { bytes += (cap * sizeof(*b.p) + 255) & ~(size_t)255; });
+            each_cand_buf([&](auto& b, int) { b.p = nullptr; b.cap = 0; });
+            cblock.release(s);
+            cblock.ensure_exact(bytes, s);
+            cband.base = cblock.p; cband.cap = bytes; cband.top = 0;
+            each_cand_buf([&](auto& b, int zero) { b.ar = &cband; b.ensure(cap, s, false, zero ? 0 : -1); });
+            cand_cap = cap;
+        }
         C.n = n;
         C.elem = c_elem.p; C.key = c_key.p; C.tup = c_tup.p; C.p = c_p.p; C.st = c_st.p; C.reason = c_reason.p;
         C.seed = c_seed.p; C.qw = c_qw.p; C.gst = gst.p; C.greason = greason.p;

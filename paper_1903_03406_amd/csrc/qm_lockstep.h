@@ -13,8 +13,8 @@
 // (one copy) whenever one of them changes.  Each instance still picks its
 // own class, so a round mixes subsegment, subface and tet work of different
 // instances in one launch.  Work whose size makes launch cost irrelevant
-// (sorting more than 256 candidates, scanning more than 32768, selecting
-// among more than 65536 claims, renumbering tet slots) runs per instance.
+// (radix sorts of more than 4096 candidates, device-wide scans of more than
+// 32768, renumbering tet slots) runs per instance.
 #pragma once
 
 namespace qm {
@@ -31,7 +31,7 @@ struct LsInst {
     int4* c_tup0;
     double4* c_p0;
     int *c_st0, *c_reason0;
-    int *olist, *glist, *sk, *st_, *ss_, *kept;
+    int *olist, *glist, *sk, *st_, *ss_, *kept, *ulist0, *ulist1;
     unsigned long long* mark;
     int* owner;
     unsigned char *mis_drop, *mis_lose;
@@ -75,14 +75,36 @@ struct FReset {                 // k_round_reset
         if (i < 48 && (i < 11 || i >= 15)) d.ctr[i] = 0;
     }
 };
+// classification: each workgroup takes LS_CTILES consecutive 256-element
+// tiles of its instance (one part lookup for all of them)
+constexpr int LS_CTILES = 8;
+// (each body starts from local copies of the record's fields: stores of the
+// body cannot then force the record to be read again)
 struct FClassifySS {
-    QMD void operator()(const LsInst& d, int, int b, int g) const { d_classify_ss(d.M, d.c_elem0, d.ctr + 8, b, g); }
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        const Mesh M = d.M;
+        int* const cand = d.c_elem0;
+        int* const cnt = d.ctr + 8;
+        for (int v = 0; v < LS_CTILES; ++v) d_classify_ss(M, cand, cnt, b * LS_CTILES + v, g * LS_CTILES);
+    }
 };
 struct FClassifySF {
-    QMD void operator()(const LsInst& d, int, int b, int g) const { d_classify_sf(d.M, d.c_elem0, d.ctr + 8, b, g); }
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        int* const cnt = d.ctr + 8;
+        if (cnt[CLS_SS] > 0) return;                 // an earlier class has candidates
+        const Mesh M = d.M;
+        int* const cand = d.c_elem0;
+        for (int v = 0; v < LS_CTILES; ++v) d_classify_sf(M, cand, cnt, b * LS_CTILES + v, g * LS_CTILES);
+    }
 };
 struct FClassifyTet {
-    QMD void operator()(const LsInst& d, int, int b, int g) const { d_classify_tet(d.M, d.c_elem0, d.ctr + 8, b, g); }
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        int* const cnt = d.ctr + 8;
+        if (cnt[CLS_SS] > 0 || cnt[CLS_SF] > 0) return;
+        const Mesh M = d.M;
+        int* const cand = d.c_elem0;
+        for (int v = 0; v < LS_CTILES; ++v) d_classify_tet(M, cand, cnt, b * LS_CTILES + v, g * LS_CTILES);
+    }
 };
 struct FGather {                // counters of each part, side by side
     int* out;
@@ -100,8 +122,18 @@ struct FOrderSmall {
         d_order_small(d.ncand, d.c_elem0, d.c_key0, d.c_tup0, d.c_p0, d.c_st0, d.c_reason0, d.C, b, g);
     }
 };
+constexpr int LS_ORDER_CAP = 4096;    // one 1024-lane workgroup ranks up to this many candidates
+struct FOrderMid {
+    QMD void operator()(const LsInst& d, int, int, int) const {
+        d_order_rank<1024, LS_ORDER_CAP>(d.ncand, d.c_elem0, d.c_key0, d.c_tup0, d.c_p0, d.c_st0, d.c_reason0, d.C);
+    }
+};
 struct FLocate {
-    QMD void operator()(const LsInst& d, int, int b, int g) const { d_locate(d.M, d.cls, d.C, b, g); }
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        const Mesh M = d.M;
+        const Cands C = d.C;
+        d_locate(M, d.cls, C, b, g);
+    }
 };
 struct FResetPools {            // k_round_reset_pools
     QMD void operator()(const LsInst& d, int, int, int) const {
@@ -110,7 +142,11 @@ struct FResetPools {            // k_round_reset_pools
 };
 struct FGrowSmall {
     QMD void operator()(const LsInst& d, int, int b, int g) const {
-        d_grow_lds<QM_TILES_SMALL>(d.M, d.cls, d.C, d.PL, d.BP, nullptr, 0, nullptr, d.min_tier, b, g);
+        const Mesh M = d.M;
+        const Cands C = d.C;
+        const Pools PL = d.PL;
+        const BfPool BP = d.BP;
+        d_grow_lds<QM_TILES_SMALL>(M, d.cls, C, PL, BP, nullptr, 0, nullptr, d.min_tier, b, g);
     }
 };
 struct FListReset {             // re-run list counts [32..35) and [36]
@@ -129,7 +165,11 @@ struct FGrowHybrid {            // workgroup w of the launch uses block w of the
     char* slab;
     size_t block;
     QMD void operator()(const LsInst& d, int, int b, int g) const {
-        d_grow_hybrid<H_LANES, H_HCAP, H_RFHCAP, H_QHCAP>(d.M, d.cls, d.C, d.PL, d.BP, d.olist, d.nover, T,
+        const Mesh M = d.M;
+        const Cands C = d.C;
+        const Pools PL = d.PL;
+        const BfPool BP = d.BP;
+        d_grow_hybrid<H_LANES, H_HCAP, H_RFHCAP, H_QHCAP>(M, d.cls, C, PL, BP, d.olist, d.nover, T,
                                                           slab + block * blockIdx.x, b, g);
     }
 };
@@ -138,16 +178,89 @@ struct FGrowGlobal {
     char* slab;
     size_t block;
     QMD void operator()(const LsInst& d, int, int b, int g) const {
-        d_grow_global<B_LANES>(d.M, d.cls, d.C, d.PL, d.BP, d.glist, d.nbig, T, slab + block * blockIdx.x, b, g);
+        const Mesh M = d.M;
+        const Cands C = d.C;
+        const Pools PL = d.PL;
+        const BfPool BP = d.BP;
+        d_grow_global<B_LANES>(M, d.cls, C, PL, BP, d.glist, d.nbig, T, slab + block * blockIdx.x, b, g);
     }
 };
 struct FVerdicts {
-    QMD void operator()(const LsInst& d, int, int b, int g) const { d_verdicts(d.M, d.cls, d.C, d.PL, d.ctr + 16, b, g); }
+    QMD void operator()(const LsInst& d, int, int b, int g) const {
+        const Mesh M = d.M;
+        const Cands C = d.C;
+        const Pools PL = d.PL;
+        d_verdicts(M, d.cls, C, PL, d.ctr + 16, b, g);
+    }
 };
 struct FMisSmall {
     QMD void operator()(const LsInst& d, int, int b, int g) const {
         d_mis_small(d.ncl, d.PL.cl, d.PL.clc, d.ncand, d.C.state, d.mark, d.owner, d.mis_drop, d.mis_lose, d.pass,
                     MIS_SMALL_PASSES, d.ctr + 38, b, g);
+    }
+};
+// selection passes over several workgroups per instance (claims or
+// candidates beyond one workgroup): pass b of a batch of MIS_BATCH, pass p
+// of the round (its parity picks the undecided lists)
+struct FUndecReset {
+    QMD void operator()(const LsInst& d, int, int, int) const {
+        if (threadIdx.x < MIS_BATCH) d.ctr[40 + threadIdx.x] = 0;
+    }
+};
+struct FMisMark {
+    int b;
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        d_mis_mark(d.ncl, d.PL.cl, d.PL.clc, d.C.state, d.mark, d.pass + (unsigned)b, nullptr, x, g);
+    }
+};
+struct FMisCheck {
+    int b;
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        d_mis_check(d.ncl, d.PL.cl, d.PL.clc, d.C.state, d.mark, d.owner, d.pass + (unsigned)b, d.mis_drop,
+                    d.mis_lose, nullptr, x, g);
+    }
+};
+struct FMisDecide {
+    int b;
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        d_mis_decide(d.ncand, d.C.state, d.mis_drop, d.mis_lose, d.ctr + 40 + b, nullptr, d.ulist0, d.ctr + 46, x, g);
+    }
+};
+struct FMisCommit {
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        d_mis_commit(d.ncl, d.PL.cl, d.PL.clc, d.C.state, d.owner, nullptr, x, g);
+    }
+};
+struct FMisMarkList {
+    int b, p;
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        const int* u_in = (p & 1) ? d.ulist0 : d.ulist1;
+        d_mis_mark_list(u_in, d.ctr + 46 + ((p - 1) & 1), d.C, d.PL.cl, d.mark, d.pass + (unsigned)b,
+                        d.ctr + 46 + (p & 1), x, g);
+    }
+};
+struct FMisCheckList {
+    int b, p;
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        const int* u_in = (p & 1) ? d.ulist0 : d.ulist1;
+        d_mis_check_list(u_in, d.ctr + 46 + ((p - 1) & 1), d.C, d.PL.cl, d.mark, d.owner, d.pass + (unsigned)b,
+                         d.mis_drop, d.mis_lose, x, g);
+    }
+};
+struct FMisDecideList {
+    int b, p;
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        const int* u_in = (p & 1) ? d.ulist0 : d.ulist1;
+        int* u_out = (p & 1) ? d.ulist1 : d.ulist0;
+        d_mis_decide_list(u_in, d.ctr + 46 + ((p - 1) & 1), d.C.state, d.mis_drop, d.mis_lose, d.ctr + 40 + b, u_out,
+                          d.ctr + 46 + (p & 1), x, g);
+    }
+};
+struct FMisCommitList {
+    int p;
+    QMD void operator()(const LsInst& d, int, int x, int g) const {
+        const int* u_in = (p & 1) ? d.ulist0 : d.ulist1;
+        d_mis_commit_list(u_in, d.ctr + 46 + ((p - 1) & 1), d.C, d.PL.cl, d.C.state, d.owner, x, g);
     }
 };
 struct FScanSmall {
@@ -160,8 +273,11 @@ struct FKeptList {
 };
 struct FInsert {
     QMD void operator()(const LsInst& d, int, int b, int g) const {
-        d_insert(d.M, d.cls, d.C, d.PL, d.BP, d.kept, d.nkept, d.sk, d.st_, d.ss_, d.nv0, d.nt0, d.nss0, d.ctr + 14,
-                 b, g);
+        const Mesh M = d.M;
+        const Cands C = d.C;
+        const Pools PL = d.PL;
+        const BfPool BP = d.BP;
+        d_insert(M, d.cls, C, PL, BP, d.kept, d.nkept, d.sk, d.st_, d.ss_, d.nv0, d.nt0, d.nss0, d.ctr + 14, b, g);
     }
 };
 struct FMisRelease {
@@ -174,9 +290,11 @@ namespace {
 
 using namespace qm;
 
-// host and device halves of the staging ring for the instance tables: the
-// ring restarts after every stream synchronisation, when every earlier copy
-// out of it has completed
+// host and device halves of the staging ring for the instance tables.  A
+// region of the pinned half is the source of a copy that runs in stream
+// order, so it may be written again only once that copy has run: the ring
+// restarts only right after a stream synchronisation (synced(), called by
+// the code that synchronised) or when it is full (put() synchronises).
 struct LsStage {
     char* h = nullptr;
     DBuf<char> d;
@@ -227,7 +345,8 @@ struct LsJob {
     int round = 0, status = 0, last_ncand = 0;
     int cls = CLS_NONE, ncand = 0, ncl = 0, nkept = 0, newt = 0, newss = 0, nover = 0, nbig = 0;
     int passes = 0, ncl_final = 0, pool_pass = 0, attempt = 0;
-    bool small_sel = false, pool_done = false, list_done = false;
+    int undecided = 0;              // selection: undecided candidates after the last batch
+    bool small_sel = false, pool_done = false, sel_done = false;
     unsigned long long key_mask = ~0ull;
     int min_tier = 0;
     const int* hc = nullptr;        // its counters at the last gather
@@ -316,7 +435,7 @@ private:
             t.c_elem0 = E.c_elem0.p; t.c_key0 = E.c_key0.p; t.c_tup0 = E.c_tup0.p; t.c_p0 = E.c_p0.p;
             t.c_st0 = E.c_st0.p; t.c_reason0 = E.c_reason0.p;
             t.olist = E.olist.p; t.glist = E.glist.p; t.sk = E.sk.p; t.st_ = E.st_.p; t.ss_ = E.ss_.p;
-            t.kept = E.kept.p; t.mark = E.mark.p; t.owner = E.owner.p;
+            t.kept = E.kept.p; t.ulist0 = E.ulist0.p; t.ulist1 = E.ulist1.p; t.mark = E.mark.p; t.owner = E.owner.p;
             t.mis_drop = E.mis_drop.p; t.mis_lose = E.mis_lose.p;
             t.key_mask = J.key_mask; t.pass = E.pass;
             t.cls = J.cls; t.ncand = J.ncand; t.ncl = J.ncl; t.nkept = J.nkept; t.min_tier = J.min_tier;
@@ -378,7 +497,6 @@ private:
         J.E->dead = J.hc[14];
         J.R->rounds[J.R->rounds.size() - QM_ROUND_FIELDS + 16] = J.E->M.nt - (int)J.E->dead;
     }
-    void select_large(LsJob& J);
     void scans_large(LsJob& J);
     void sort_large(LsJob& J);
     // run fn on each listed job; a job whose host logic throws ends with
@@ -448,55 +566,6 @@ void Lockstep::scans_large(LsJob& J) {
     k_totals<<<1, 1, 0, s_>>>(n, E.sk.p, E.vk.p, E.st_.p, E.vt.p, E.ss_.p, E.vs.p, E.ctr.p + 11);
 }
 
-// more than MIS_SMALL claims or candidates: batches of selection passes,
-// each batch followed by the scans and a look at the undecided counts
-void Lockstep::select_large(LsJob& J) {
-    Engine& E = *J.E;
-    const int ncl = J.ncl, ncand = J.ncand;
-    int* undec_d = E.ctr.p + 40;
-    int* nu_d = E.ctr.p + 46;
-    int hc[48];
-    J.passes = 0;
-    for (int batch = 0;; ++batch) {
-        if (batch > 0) HIPCK(hipMemsetAsync(undec_d, 0, MIS_BATCH * sizeof(int), s_));
-        for (int b = 0; b < MIS_BATCH; ++b) {
-            const unsigned ps = E.pass++;
-            const int p = batch * MIS_BATCH + b;
-            int* const u_out = (p & 1) ? E.ulist1.p : E.ulist0.p;
-            int* const nu_out = nu_d + (p & 1);
-            if (p == 0) {
-                k_mis_mark<<<nblk(ncl), 256, 0, s_>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, ps, nullptr);
-                k_mis_check<<<nblk(ncl), 256, 0, s_>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.mark.p, E.owner.p, ps,
-                                                       E.mis_drop.p, E.mis_lose.p, nullptr);
-                k_mis_decide<<<nblk(ncand), 256, 0, s_>>>(ncand, E.state.p, E.mis_drop.p, E.mis_lose.p, undec_d + b,
-                                                          nullptr, u_out, nu_out);
-                k_mis_commit<<<nblk(ncl), 256, 0, s_>>>(ncl, E.p_cl.p, E.p_clc.p, E.state.p, E.owner.p, nullptr);
-            } else {
-                const int* const u_in = (p & 1) ? E.ulist0.p : E.ulist1.p;
-                const int* const nu_in = nu_d + ((p - 1) & 1);
-                k_mis_mark_list<<<MIS_LIST_GRID, 256, 0, s_>>>(u_in, nu_in, E.C, E.p_cl.p, E.mark.p, ps, nu_out);
-                k_mis_check_list<<<MIS_LIST_GRID, 256, 0, s_>>>(u_in, nu_in, E.C, E.p_cl.p, E.mark.p, E.owner.p, ps,
-                                                                E.mis_drop.p, E.mis_lose.p);
-                k_mis_decide_list<<<MIS_LIST_GRID / 4, 256, 0, s_>>>(u_in, nu_in, E.state.p, E.mis_drop.p,
-                                                                     E.mis_lose.p, undec_d + b, u_out, nu_out);
-                k_mis_commit_list<<<MIS_LIST_GRID, 256, 0, s_>>>(u_in, nu_in, E.C, E.p_cl.p, E.state.p, E.owner.p);
-            }
-        }
-        if (ncand <= SCAN_SMALL)
-            k_scan_small<<<1, 1024, 0, s_>>>(E.C, J.cls, ncand, E.sk.p, E.st_.p, E.ss_.p, E.ctr.p + 11);
-        else
-            scans_large(J);
-        HIPCK(hipMemcpyAsync(hc, E.ctr.p, sizeof hc, hipMemcpyDeviceToHost, s_));
-        HIPCK(hipStreamSynchronize(s_));
-        for (int b = 0; b < MIS_BATCH; ++b) {
-            ++J.passes;
-            if (hc[40 + b] == 0) break;
-        }
-        if (hc[40 + MIS_BATCH - 1] == 0) break;
-    }
-    stage_.synced();
-}
-
 void Lockstep::step() {
     std::vector<int> L(jobs_.size());
     for (size_t i = 0; i < jobs_.size(); ++i) L[i] = (int)i;
@@ -519,13 +588,14 @@ void Lockstep::step() {
     });
     L.erase(std::remove_if(L.begin(), L.end(), [&](int i) { return !jobs_[i]->E; }), L.end());
     if (L.empty()) { compact(); return; }
-    stage_.synced();        // the round-limit and renumbering paths synchronised the stream
-    // step 1: classify
+    // step 1: classify (the staging ring is not rewound here: the last
+    // round's insertion table may still be waiting for its copy)
     upload();
     launch<64>(L, [](const LsJob&) { return 1L; }, FReset{});
-    launch<256>(L, [](const LsJob& J) { return J.E->M.nss ? (long)nblk(J.E->M.nss) : 0L; }, FClassifySS{});
-    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt); }, FClassifySF{});
-    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt); }, FClassifyTet{});
+    launch<256>(L, [](const LsJob& J) { return J.E->M.nss ? (long)nblk(J.E->M.nss, 256 * LS_CTILES) : 0L; },
+                FClassifySS{});
+    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt, 256 * LS_CTILES); }, FClassifySF{});
+    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt, 256 * LS_CTILES); }, FClassifyTet{});
     gather(L);
     each(L, [&](LsJob& J) {
         patch_last_record(J);
@@ -548,7 +618,9 @@ void Lockstep::step() {
     upload();
     launch<256>(L, [](const LsJob& J) { return (long)nblk(J.ncand); }, FSplit{});
     launch<SORT_SMALL>(L, [](const LsJob& J) { return J.ncand <= SORT_SMALL ? 1L : 0L; }, FOrderSmall{});
-    each(L, [&](LsJob& J) { if (J.ncand > SORT_SMALL) sort_large(J); });
+    launch<1024>(L, [](const LsJob& J) { return J.ncand > SORT_SMALL && J.ncand <= LS_ORDER_CAP ? 1L : 0L; },
+                 FOrderMid{});
+    each(L, [&](LsJob& J) { if (J.ncand > LS_ORDER_CAP) sort_large(J); });
     // step 3: locate
     launch<64>(L, [](const LsJob& J) { return J.cls != CLS_SS ? (long)nblk(J.ncand, 64) : 0L; }, FLocate{});
     // steps 4-5: grow and validate; a pass is repeated (with larger pools) by
@@ -607,7 +679,7 @@ void Lockstep::step() {
                 };
                 long total = 0;
                 for (int i : A) total += share(*jobs_[i]);
-                hslab_.ensure_exact(block * (size_t)std::min<long>(total, LS_PARTS * 1024L), s_);
+                hslab_.ensure(block * (size_t)std::min<long>(total, LS_PARTS * 1024L), s_, false);
                 launch<H_LANES>(A, share, FGrowHybrid{HT, hslab_.p, block});
             }
             if (big_total > 0) {            // global-memory tiles: at most 256 workgroups over all instances
@@ -625,7 +697,7 @@ void Lockstep::step() {
                 };
                 long total = 0;
                 for (int i : A) total += share(*jobs_[i]);
-                gslab_.ensure_exact(block * (size_t)std::min<long>(total, LS_PARTS * 1024L), s_);
+                gslab_.ensure(block * (size_t)std::min<long>(total, LS_PARTS * 1024L), s_, false);
                 launch<B_LANES>(A, share, FGrowGlobal{BT, gslab_.p, block});
             }
         }
@@ -638,15 +710,57 @@ void Lockstep::step() {
         Engine& E = *J.E;
         J.ncl = std::min(J.ncl_final, E.PL.cap_cl);
         J.small_sel = J.ncl > 0 && J.ncl <= MIS_SMALL && J.ncand <= MIS_SMALL;
+        J.sel_done = false;
         J.passes = 0;
     });
     upload();
     launch<256>(L, [](const LsJob& J) { return (long)nblk(J.ncand); }, FVerdicts{});
     launch<1024>(L, [](const LsJob& J) { return J.small_sel ? 1L : 0L; }, FMisSmall{});
-    each(L, [&](LsJob& J) { if (J.ncl > 0 && !J.small_sel) select_large(J); });
-    launch<1024>(L, [](const LsJob& J) { return (J.small_sel || J.ncl == 0) && J.ncand <= SCAN_SMALL ? 1L : 0L; },
-                 FScanSmall{});
-    each(L, [&](LsJob& J) { if ((J.small_sel || J.ncl == 0) && J.ncand > SCAN_SMALL) scans_large(J); });
+    // the other selections: batches of MIS_BATCH passes over several
+    // workgroups per instance, one look at the undecided counts per batch
+    std::vector<int> S;
+    for (int i : L)
+        if (jobs_[i]->ncl > 0 && !jobs_[i]->small_sel) S.push_back(i);
+    for (int batch = 0; !S.empty(); ++batch) {
+        if (batch > 0) {
+            upload();                       // pass stamps moved on
+            launch<64>(S, [](const LsJob&) { return 1L; }, FUndecReset{});
+        }
+        for (int b = 0; b < MIS_BATCH; ++b) {
+            const int p = batch * MIS_BATCH + b;
+            if (p == 0) {
+                launch<256>(S, [](const LsJob& J) { return (long)nblk(J.ncl); }, FMisMark{b});
+                launch<256>(S, [](const LsJob& J) { return (long)nblk(J.ncl); }, FMisCheck{b});
+                launch<256>(S, [](const LsJob& J) { return (long)nblk(J.ncand); }, FMisDecide{b});
+                launch<256>(S, [](const LsJob& J) { return (long)nblk(J.ncl); }, FMisCommit{});
+            } else {                        // list lengths are bounded by the last undecided count
+                auto wave = [](const LsJob& J) { return (long)std::min(MIS_LIST_GRID, nblk(J.undecided, 4)); };
+                auto lane = [](const LsJob& J) { return (long)std::min(MIS_LIST_GRID / 4, nblk(J.undecided)); };
+                launch<256>(S, wave, FMisMarkList{b, p});
+                launch<256>(S, wave, FMisCheckList{b, p});
+                launch<256>(S, lane, FMisDecideList{b, p});
+                launch<256>(S, wave, FMisCommitList{p});
+            }
+            if (p == 0) for (int i : S) jobs_[i]->undecided = jobs_[i]->ncand;
+        }
+        gather(S);
+        each(S, [&](LsJob& J) {
+            for (int b = 0; b < MIS_BATCH; ++b) {
+                ++J.passes;
+                if (J.hc[40 + b] == 0) break;
+            }
+            J.E->pass += MIS_BATCH;
+            J.undecided = J.hc[40 + MIS_BATCH - 1];
+            J.sel_done = J.undecided == 0;
+        });
+        S.erase(std::remove_if(S.begin(), S.end(), [&](int i) { return !jobs_[i]->E || jobs_[i]->sel_done; }),
+                S.end());
+    }
+    L.erase(std::remove_if(L.begin(), L.end(), [&](int i) { return !jobs_[i]->E; }), L.end());
+    if (L.empty()) { compact(); return; }
+    // step-7 scans (kept ids, new tet slots, new subsegment slots)
+    launch<1024>(L, [](const LsJob& J) { return J.ncand <= SCAN_SMALL ? 1L : 0L; }, FScanSmall{});
+    each(L, [&](LsJob& J) { if (J.ncand > SCAN_SMALL) scans_large(J); });
     gather(L);
     // step 7: insertion
     each(L, [&](LsJob& J) {

@@ -124,3 +124,19 @@ def test_lockstep_edge_cases(mix):
     got, codes = qm.refine_lockstep([mix[9], mix[0]], extra_flags=[qm.QM_EARLY_STOP, qm.QM_PROFILE_GROW],
                                     return_codes=True)
     assert codes == [-1, -1] and got == [None, None]
+
+
+def test_lockstep_repeated_small_batches(mix):
+    """Regression: the host staging of the instance tables must not reuse a
+    pinned region whose copy to the device has not run yet (a rewind at the
+    start of a round without a synchronisation let the next round's table
+    replace the insertion table).  Several batches in a row, each equal to
+    the single runs."""
+    small = [w for w in mix if len(w.xyz) <= 1300]
+    alone = [qm.refine_workload(w) for w in small]
+    for rep in range(5):
+        got, codes = qm.refine_lockstep(small, return_codes=True)
+        print(f"[lockstep] repeat {rep}: codes {codes}", flush=True)
+        assert codes == [0] * len(small)
+        for w, g, s in zip(small, got, alone):
+            assert same(g, s), (rep, w.name)
