@@ -184,13 +184,17 @@ int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const 
    validation, verdicts, selection, insertion) is one launch over the work of
    all instances in that phase, each instance picking its own class.  Each
    result is bit-identical to qm_refine on the same instance.  Arguments as
-   qm_refine_batch, with `hip_stream` (a hipStream_t, NULL: default stream)
-   in place of the stream count.  Options may not ask for profiling
+   qm_refine_batch.  With ngroups = 1 the instances form one lockstep group
+   on `hip_stream` (a hipStream_t, NULL: default stream); with ngroups > 1
+   (at most 64) they are dealt, largest input first, to that many groups,
+   each run by a host thread of its own on a stream of its own (default
+   priority) of the current device, so that one group's long workgroups
+   overlap another group's work.  Options may not ask for profiling
    (QM_PROFILE, QM_PROFILE_GROW), QM_EARLY_STOP or max_kept > 0: such an
    instance ends with QM_EINVAL and the others go on.  Every instance's mesh
    stays on the device until it finishes. */
 int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
-                       void* hip_stream, qm_result** outs, int32_t* codes);
+                       void* hip_stream, int32_t ngroups, qm_result** outs, int32_t* codes);
 
 /* View of a result: the output mesh (Steiner vertices appended after the
    input vertices, numbered by round and priority) and the statistics.  The

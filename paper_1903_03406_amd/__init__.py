@@ -388,10 +388,11 @@ def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, m
     return results
 
 
-def refine_lockstep(workloads, *, hmin_factor=0.5, max_rounds=100000, extra_flags=None, return_codes=False,
-                    max_kept=0) -> list:
+def refine_lockstep(workloads, *, groups=1, hmin_factor=0.5, max_rounds=100000, extra_flags=None,
+                    return_codes=False, max_kept=0) -> list:
     """Refine independent instances in lockstep (qm_refine_lockstep): one
-    launch per phase per round over all instances, on the default stream.
+    launch per phase per round over all instances of a group; one group on
+    the default stream, or `groups` groups on streams of their own.
     max_rounds may be one value or one per instance.  Results and
     return_codes as refine_batch."""
     lib = _load()
@@ -406,9 +407,9 @@ def refine_lockstep(workloads, *, hmin_factor=0.5, max_rounds=100000, extra_flag
     codes = (ctypes.c_int32 * max(n, 1))()
     lib.qm_refine_lockstep.restype = ctypes.c_int
     lib.qm_refine_lockstep.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     rc = lib.qm_refine_lockstep(n, ctypes.addressof(plcs), ctypes.addressof(meshes), ctypes.addressof(opts),
-                                None, ctypes.addressof(outs), ctypes.addressof(codes))
+                                None, int(groups), ctypes.addressof(outs), ctypes.addressof(codes))
     results = [_take_result(lib, ctypes.c_void_p(outs[i]), False) if outs[i] else None for i in range(n)]
     if return_codes:
         return results, [int(codes[i]) for i in range(n)]

@@ -799,21 +799,14 @@ void Lockstep::step() {
     compact();
 }
 
-}  // namespace
-
-extern "C" {
-
-int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
-                       void* hip_stream, qm_result** outs, int32_t* codes) {
-    g_err.clear();
-    if (n < 0 || (n > 0 && (!plcs || !meshes || !opts || !outs || !codes))) {
-        g_err = "bad batch arguments";
-        return QM_EINVAL;
-    }
-    for (int i = 0; i < n; ++i) { outs[i] = nullptr; codes[i] = QM_EINTERNAL; }
-    std::vector<std::string> msgs(n);
+// One lockstep group: its instances (indices `mine`) on stream s, driven by
+// the calling thread.  A failure that ends the whole group (a HIP error)
+// lands in gcode/gmsg; per-instance failures in codes/msgs.
+void run_lockstep_group(hipStream_t s, const std::vector<int>& mine, const qm_plc* plcs, const qm_mesh* meshes,
+                        const qm_options* opts, qm_result** outs, int32_t* codes, std::vector<std::string>& msgs,
+                        int& gcode, std::string& gmsg) {
     try {
-        Lockstep B((hipStream_t)hip_stream);
+        Lockstep B(s);
         auto collect = [&]() {
             for (auto& d : B.take_done()) {
                 outs[d.tag] = d.res;
@@ -821,19 +814,75 @@ int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, con
                 msgs[d.tag] = d.msg;
             }
         };
-        for (int i = 0; i < n; ++i) B.add(&plcs[i], &meshes[i], &opts[i], (uint64_t)i);
+        for (int i : mine) B.add(&plcs[i], &meshes[i], &opts[i], (uint64_t)i);
         collect();
         while (B.live() > 0) {
             B.step();
             collect();
         }
     } catch (const QmError& e) {
-        g_err = e.what();
-        return e.code;
+        gcode = e.code;
+        gmsg = e.what();
     } catch (const std::exception& e) {
-        g_err = e.what();
-        return QM_EINTERNAL;
+        gcode = QM_EINTERNAL;
+        gmsg = e.what();
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                       void* hip_stream, int32_t ngroups, qm_result** outs, int32_t* codes) {
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!plcs || !meshes || !opts || !outs || !codes)) || ngroups < 1 || ngroups > 64) {
+        g_err = "bad batch arguments";
+        return QM_EINVAL;
+    }
+    for (int i = 0; i < n; ++i) { outs[i] = nullptr; codes[i] = QM_EINTERNAL; }
+    std::vector<std::string> msgs(n);
+    const int G = std::max(1, std::min<int>(ngroups, n));
+    // instances dealt to the groups in decreasing input size (snake order),
+    // so that the groups carry similar work
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int na = meshes[a].nt, nb = meshes[b].nt;
+        return na > nb;
+    });
+    std::vector<std::vector<int>> part(G);
+    for (int k = 0; k < n; ++k) {
+        const int r = k / G, c = k % G;
+        part[(r & 1) ? G - 1 - c : c].push_back(order[k]);
+    }
+    std::vector<int> gcode(G, QM_OK);
+    std::vector<std::string> gmsg(G);
+    if (G == 1) {
+        run_lockstep_group((hipStream_t)hip_stream, part[0], plcs, meshes, opts, outs, codes, msgs, gcode[0], gmsg[0]);
+    } else {                      // one stream (default priority) and one host thread per group
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) { g_err = "no HIP device"; return QM_EDEVICE; }
+        std::vector<std::thread> th;
+        for (int g = 0; g < G; ++g)
+            th.emplace_back([&, g]() {
+                hipStream_t st = nullptr;
+                if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+                    gcode[g] = QM_EDEVICE;
+                    gmsg[g] = "no stream for a lockstep group";
+                    return;
+                }
+                run_lockstep_group(st, part[g], plcs, meshes, opts, outs, codes, msgs, gcode[g], gmsg[g]);
+                (void)hipStreamSynchronize(st);
+                (void)hipStreamDestroy(st);
+            });
+        for (auto& t : th) t.join();
+    }
+    for (int g = 0; g < G; ++g)
+        if (gcode[g] != QM_OK) {
+            g_err = gmsg[g];
+            return gcode[g];
+        }
     for (int i = 0; i < n; ++i)
         if (codes[i] != QM_OK && codes[i] != QM_EROUNDS) {
             g_err = "instance " + std::to_string(i) + ": " + msgs[i];

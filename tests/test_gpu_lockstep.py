@@ -60,6 +60,16 @@ def test_lockstep_matches_single_instances(mix):
         assert same(g, s), w.name
 
 
+def test_lockstep_groups_match_single_instances(mix):
+    """The batch split into lockstep groups on streams of their own."""
+    for groups in (3, 12):
+        got = qm.refine_lockstep(mix, groups=groups)
+        for w, g in zip(mix, got):
+            assert same(g, qm.refine_workload(w)), (groups, w.name)
+    got, codes = qm.refine_lockstep(mix[:4], groups=2, extra_flags=[0, qm.QM_PROFILE, 0, 0], return_codes=True)
+    assert codes == [0, -1, 0, 0] and got[1] is None
+
+
 def test_lockstep_small_instances_match_oracle(mix):
     small = [w for w in mix if len(w.xyz) <= 1300]
     got = qm.refine_lockstep(small)
