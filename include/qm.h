@@ -286,8 +286,11 @@ size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options*
 /* Create a server on the calling thread's current device with `nworkers`
    (1..64) worker threads, each owning a HIP stream (non-blocking, default
    priority) on which it runs one job at a time.  With nworkers = 0 the
-   server is stepped: admitted jobs stay resident on the device between
-   rounds and advance only through qm_server_step.  `hbm_budget_bytes` bounds
+   server is stepped: admitted jobs form one lockstep batch (as
+   qm_refine_lockstep) on a stream of the server, stay resident on the
+   device between rounds and advance only through qm_server_step; their
+   options may not ask for profiling, QM_EARLY_STOP or max_kept > 0 (such a
+   job ends with QM_EINVAL).  `hbm_budget_bytes` bounds
    the summed estimates of admitted, unfinished jobs.  *out is freed with
    qm_server_destroy. */
 int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out);
@@ -312,13 +315,13 @@ int qm_server_submit(qm_server* srv, const qm_plc* plc, const qm_mesh* in, const
 int qm_server_poll(qm_server* srv, uint64_t ticket, int32_t wait_ms, qm_result** out, int32_t* code,
                    double* seconds);
 
-/* Stepped server only: jobs admitted since the last step are set up on the
-   device (each on a stream of its own), then every resident job runs one
-   round of the paper's round loop (Section 2), all concurrently; returns
-   when every one has completed it.  Jobs that finish (no work left, or
-   their round guard) hand their result to qm_server_poll.  *nresident
-   receives the number of jobs still resident.  QM_EINVAL on a server with
-   workers. */
+/* Stepped server only (continuous batching): jobs admitted since the last
+   step are set up on the device and join the batch, then every resident
+   job runs one round of the paper's round loop (Section 2), each phase of
+   the round one launch over all resident jobs; returns when the round is
+   complete.  Jobs that finish (no work left, or their round guard) hand
+   their result to qm_server_poll.  *nresident receives the number of jobs
+   still resident.  Calls take turns.  QM_EINVAL on a server with workers. */
 int qm_server_step(qm_server* srv, int32_t* nresident);
 
 /* Counters of the server (a consistent snapshot). */

@@ -704,45 +704,6 @@ struct Engine {
 
 using namespace qm;
 
-// Stepped serving: a job's round loop waits at this gate before each round
-// until the server grants it one, and reports each finished round; the
-// server's step grants one round to every resident job and waits for all.
-struct RoundGate {
-    std::mutex mu;
-    std::condition_variable cv;
-    int granted = 0, done = 0;
-    bool finished = false, cancel = false;
-    void begin_round() {              // job side
-        std::unique_lock<std::mutex> lk(mu);
-        cv.wait(lk, [&] { return granted > done || cancel; });
-        if (cancel) throw QmError(QM_EAGAIN, "job cancelled by the server's shutdown");
-    }
-    void end_round() {
-        std::lock_guard<std::mutex> lk(mu);
-        ++done;
-        cv.notify_all();
-    }
-    void finish() {
-        std::lock_guard<std::mutex> lk(mu);
-        finished = true;
-        cv.notify_all();
-    }
-    void grant() {                    // server side
-        std::lock_guard<std::mutex> lk(mu);
-        ++granted;
-        cv.notify_all();
-    }
-    void wait_round() {
-        std::unique_lock<std::mutex> lk(mu);
-        cv.wait(lk, [&] { return done >= granted || finished; });
-    }
-    void stop() {
-        std::lock_guard<std::mutex> lk(mu);
-        cancel = true;
-        cv.notify_all();
-    }
-};
-
 // Device setup of one refinement, whose input is a CDT of the PLC (paper,
 // Section 2): inputs staged (or used in place when they are device arrays),
 // adjacency by face matching, subfaces and subsegments marked, facet
@@ -956,7 +917,7 @@ static int emit_output(Engine& E, qm_result* R, const qm_options* opt, Arena* ar
 // *dstats; no qm_result, pinned buffer or event is created.
 static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
                       qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
-                      qm_stats* dstats = nullptr, size_t mem_cap = 0, RoundGate* gate = nullptr) {
+                      qm_stats* dstats = nullptr, size_t mem_cap = 0) {
     auto T0 = std::chrono::steady_clock::now();
     const bool noalloc = ar != nullptr;
     if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
@@ -1054,7 +1015,6 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         fprintf(stderr, "qm: round %d class %d %s (%d)\n", round_, cls_, phase, n_);
     };
     for (;; ++round) {
-        if (gate) gate->begin_round();        // stepped serving: wait for the server's step
         if (round >= opt->max_rounds) { status = 1; break; }
         E.cur_round = round;
         E.arena_round();
@@ -1303,10 +1263,6 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         ST.candidates += ncand;
         ST.mis_passes += passes;
         ST.deferred += st[14];
-        if (gate) {                           // the round is complete on the device
-            HIPCK(hipStreamSynchronize(s));
-            gate->end_round();
-        }
     }
     if (!noalloc) HIPCK(hipEventRecord(e2, s));
     sync_counters();
@@ -1367,10 +1323,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
 // other buffers in that many bytes (the served form passes each job's
 // admitted estimate).
 static int refine_within(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
-                         qm_result** out, size_t mem_cap, RoundGate* gate = nullptr) {
+                         qm_result** out, size_t mem_cap) {
     g_err.clear();
     try {
-        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap, gate);
+        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap);
     } catch (const QmError& e) {
         g_err = e.what();
         return e.code;

@@ -10,10 +10,12 @@
 // caller retries later.  Workers take admitted jobs first come, first served;
 // a finished job's estimate is released before its result is handed out.
 //
-// Stepped form (created with no workers): admitted jobs become resident on
-// the device, each set up by a thread of its own on its own stream, and
-// advance only when the caller calls qm_server_step, which gives every
-// resident job one round and returns when all have completed it.
+// Stepped form (created with no workers): continuous batching.  The jobs
+// form one lockstep batch on the server's stream: each qm_server_step sets
+// up the jobs admitted since the last step, then runs one round of every
+// resident job, each phase of the round one launch over all of them; jobs
+// join and leave the batch at round boundaries and their meshes stay on the
+// device in between.
 #pragma once
 
 #include <chrono>
@@ -45,15 +47,6 @@ struct SrvDone {
     double wait_s = 0, total_s = 0;
 };
 
-// a resident job of the stepped form: its refinement runs in `th` and waits
-// at `gate` before every round
-struct SrvResident {
-    std::unique_ptr<SrvJob> J;
-    RoundGate gate;
-    std::thread th;
-    SrvDone d;
-};
-
 // copy n*cols elements of a borrowed host array; false when a non-empty
 // array has no pointer
 template <class T>
@@ -81,7 +74,13 @@ struct qm_server {
     int64_t admitted = 0, refused = 0, completed = 0;
     std::vector<std::thread> workers;
     bool stepped = false;                                  // no workers: qm_server_step drives the jobs
-    std::vector<std::unique_ptr<SrvResident>> resident_jobs;
+    // stepped form: the lockstep batch of resident jobs on `step_stream`, and
+    // what the server keeps of each resident job (its estimate and times)
+    hipStream_t step_stream = nullptr;
+    std::unique_ptr<Lockstep> batch;
+    std::unordered_map<uint64_t, std::unique_ptr<SrvJob>> in_batch;
+    std::unordered_map<uint64_t, srv_clock::time_point> t_added;
+    std::mutex step_mu;                                    // steps take turns
 };
 
 namespace {
@@ -127,27 +126,6 @@ void srv_worker(qm_server* S) {
     }
 }
 
-// the thread of one resident job of the stepped form
-void srv_resident_run(int dev, SrvResident* R) {
-    hipStream_t st = nullptr;
-    const auto t_start = srv_clock::now();
-    if (hipSetDevice(dev) == hipSuccess && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess) {
-        R->d.code = refine_within(&R->J->plc, &R->J->mesh, &R->J->opt, st, &R->d.res, R->J->est, &R->gate);
-        if (R->d.code != QM_OK && R->d.code != QM_EROUNDS) R->d.msg = qm_last_error();
-    } else {
-        R->d.code = QM_EDEVICE;
-        R->d.msg = "resident job has no HIP stream";
-    }
-    if (st) {
-        (void)hipStreamSynchronize(st);
-        (void)hipStreamDestroy(st);
-    }
-    const auto t_end = srv_clock::now();
-    R->d.wait_s = std::chrono::duration<double>(t_start - R->J->t_sub).count();
-    R->d.total_s = std::chrono::duration<double>(t_end - R->J->t_sub).count();
-    R->gate.finish();
-}
-
 }  // namespace
 
 extern "C" {
@@ -176,6 +154,13 @@ int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out)
     S->budget = hbm_budget_bytes;
     S->stepped = nworkers == 0;
     try {
+        if (S->stepped) {
+            if (hipStreamCreateWithFlags(&S->step_stream, hipStreamNonBlocking) != hipSuccess) {
+                g_err = "no HIP stream for the stepped server";
+                return QM_EDEVICE;
+            }
+            S->batch = std::make_unique<Lockstep>(S->step_stream);
+        }
         for (int i = 0; i < nworkers; ++i) S->workers.emplace_back(srv_worker, S.get());
     } catch (const std::exception& e) {
         {
@@ -266,8 +251,10 @@ int qm_server_step(qm_server* S, int32_t* nresident) {
     g_err.clear();
     if (!S) { g_err = "null argument"; return QM_EINVAL; }
     if (!S->stepped) { g_err = "this server runs its jobs with its own workers"; return QM_EINVAL; }
+    std::lock_guard<std::mutex> step_lock(S->step_mu);
     try {
-        // admitted jobs become resident: set up on the device by their thread
+        if (hipSetDevice(S->dev) != hipSuccess) throw QmError(QM_EDEVICE, "cannot select the server's device");
+        // jobs admitted since the last step join the batch (set-up on the device)
         std::vector<std::unique_ptr<SrvJob>> fresh;
         {
             std::lock_guard<std::mutex> lk(S->mu);
@@ -277,37 +264,42 @@ int qm_server_step(qm_server* S, int32_t* nresident) {
             }
         }
         for (auto& J : fresh) {
-            auto R = std::make_unique<SrvResident>();
-            R->J = std::move(J);
-            R->th = std::thread(srv_resident_run, S->dev, R.get());
-            S->resident_jobs.push_back(std::move(R));
+            const uint64_t t = J->ticket;
+            S->t_added[t] = srv_clock::now();
+            S->batch->add(&J->plc, &J->mesh, &J->opt, t);
+            S->in_batch[t] = std::move(J);
         }
-        // one round for every resident job, all at once
-        for (auto& R : S->resident_jobs) R->gate.grant();
-        for (auto& R : S->resident_jobs) R->gate.wait_round();
-        // finished jobs hand out their results
-        std::vector<std::unique_ptr<SrvResident>> keep;
-        for (auto& R : S->resident_jobs) {
-            bool fin;
-            {
-                std::lock_guard<std::mutex> lk(R->gate.mu);
-                fin = R->gate.finished;
+        // one round of every resident job, each phase one launch over all
+        if (S->batch->live() > 0) S->batch->step();
+        const auto now = srv_clock::now();
+        for (auto& d : S->batch->take_done()) {
+            auto it = S->in_batch.find(d.tag);
+            SrvDone out;
+            out.res = d.res;
+            out.code = d.code;
+            out.msg = d.msg;
+            if (it != S->in_batch.end()) {
+                out.wait_s = std::chrono::duration<double>(S->t_added[d.tag] - it->second->t_sub).count();
+                out.total_s = std::chrono::duration<double>(now - it->second->t_sub).count();
             }
-            if (!fin) { keep.push_back(std::move(R)); continue; }
-            R->th.join();
+            const size_t est = it != S->in_batch.end() ? it->second->est : 0;
+            S->in_batch.erase(d.tag);
+            S->t_added.erase(d.tag);
             std::lock_guard<std::mutex> lk(S->mu);
-            S->resident -= R->J->est;
+            S->resident -= est;
             ++S->completed;
-            S->done[R->J->ticket] = std::move(R->d);
+            S->done[d.tag] = std::move(out);
         }
-        S->resident_jobs = std::move(keep);
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            S->running = (int)S->resident_jobs.size();
+            S->running = S->batch->live();
         }
         S->cv_done.notify_all();
-        if (nresident) *nresident = (int32_t)S->resident_jobs.size();
+        if (nresident) *nresident = (int32_t)S->batch->live();
         return QM_OK;
+    } catch (const QmError& e) {
+        g_err = e.what();
+        return e.code;
     } catch (const std::exception& e) {
         g_err = e.what();
         return QM_EINTERNAL;
@@ -338,11 +330,11 @@ void qm_server_destroy(qm_server* S) {
     }
     S->cv_work.notify_all();
     for (auto& t : S->workers) t.join();
-    for (auto& R : S->resident_jobs) {      // stepped form: unfinished jobs are stopped
-        R->gate.stop();
-        R->th.join();
-        qm_result_free(R->d.res);
+    if (S->batch) {                          // stepped form: resident jobs end with the batch
+        (void)hipSetDevice(S->dev);
+        S->batch.reset();
     }
+    if (S->step_stream) (void)hipStreamDestroy(S->step_stream);
     for (auto& kv : S->done) qm_result_free(kv.second.res);
     delete S;
 }
