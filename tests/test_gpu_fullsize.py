@@ -78,9 +78,9 @@ def cfg3():
 
 @pytest.mark.parametrize("name", ["cfg3_rounds8.json", "cfg3_rounds1099.json", "cfg3_rounds1110.json"])
 def test_config3_first_rounds_parity(cfg3, name):
-    """The first 8 rounds, and the first 1099 and 1110 rounds: every round
-    before the first bad-tet round (930) and then 169 and 180 rounds of all
-    three classes."""
+    """The first 8 rounds, and the first 1099 and 1110 rounds (subsegment,
+    subface and bad-tet rounds; the oracle takes about 4.9 hours for the
+    1099-round golden)."""
     gold = load(name)
     assert cfg3.sha256() == gold["input_sha256"]
     compare(qm.refine_workload(cfg3, max_rounds=gold["max_rounds"]), gold, f"config3 {gold['max_rounds']} rounds")
