@@ -133,9 +133,10 @@ def cpu_baseline(w, target_s):
 def bench_batch(args, qm):
     """Batched workload (config 4 instances 0..N-1, uniform points + a rotated
     ellipsoid surface, B = 2.0): the whole set refined in lockstep by
-    qm_refine_lockstep (one launch per phase per round over all instances),
-    against the same set on --streams concurrent streams (qm_refine_batch)
-    and one instance at a time.  Host arrays in, host results out in every
+    qm_refine_lockstep (one launch per phase per round over all instances of
+    a group) with knobs qm_lockstep_autotune chose on a probe of the set
+    (tuning not timed), against the same set on --streams concurrent
+    streams (qm_refine_batch) and one instance at a time.  Host arrays in, host results out in every
     form; the three must give the same rounds and vertex counts."""
     import numpy as np
     import qm_inputs as qi
@@ -150,17 +151,14 @@ def bench_batch(args, qm):
           f"built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     qm.refine_batch(ws[:min(4, len(ws))], nstreams=args.streams)          # warm-up
     qm.refine_lockstep(ws[:min(4, len(ws))])
-    sweep = {}
-    for g in [int(x) for x in args.groups.split(",")]:
-        a = time.perf_counter()
-        res_l = qm.refine_lockstep(ws, groups=g)
-        sweep[g] = time.perf_counter() - a
-        print(f"[bench] lockstep, {g} groups: {sweep[g]:.2f}s", file=sys.stderr, flush=True)
-    best = min(sweep, key=sweep.get)
+    a = time.perf_counter()
+    tune, probe_s = qm.lockstep_autotune(ws, probe=args.tune_probe)
+    tune_s = time.perf_counter() - a
+    print(f"[bench] autotuned on {args.tune_probe} instances in {tune_s:.1f}s: {tune}", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
-    res_l = qm.refine_lockstep(ws, groups=best)
+    res_l = qm.refine_lockstep(ws, tune=tune)
     t2 = time.perf_counter()
-    print(f"[bench] lockstep ({best} groups, timed again): {t2 - t1:.2f}s", file=sys.stderr, flush=True)
+    print(f"[bench] lockstep (tuned): {t2 - t1:.2f}s", file=sys.stderr, flush=True)
     res_b = qm.refine_batch(ws, nstreams=args.streams)
     t3 = time.perf_counter()
     print(f"[bench] {args.streams} streams: {t3 - t2:.2f}s", file=sys.stderr, flush=True)
@@ -179,8 +177,9 @@ def bench_batch(args, qm):
         "metric": "batched jobs/sec (config 4 instances)", "value": len(ws) / ls, "unit": "jobs/s",
         "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"cfg4_instances_0_{len(ws) - 1}", "instances": len(ws), "points": int(sum(npts)),
-                   "form": "lockstep", "groups": best},
-        "lockstep_seconds_by_groups": {str(k): v for k, v in sweep.items()},
+                   "form": "lockstep"},
+        "tune": tune, "tuning": {"probe_instances": args.tune_probe, "seconds": tune_s,
+                                 "probe_seconds_best": probe_s},
         "streams_jobs_per_s": len(ws) / st, "streams": args.streams,
         "one_at_a_time_jobs_per_s": len(ws) / seq,
         "speedup_vs_one_at_a_time": seq / ls, "speedup_vs_streams": st / ls,
@@ -270,8 +269,8 @@ def main():
                     help="instead of the single-instance line: the first N instances of the batched "
                          "workload (config 4), batched jobs/s against one-at-a-time jobs/s")
     ap.add_argument("--streams", type=int, default=8, help="streams (workers) of the batched or served run")
-    ap.add_argument("--groups", default="1,2,4,8",
-                    help="lockstep group counts tried by --batch (the fastest is timed again and reported)")
+    ap.add_argument("--tune-probe", type=int, default=16,
+                    help="instances of the probe batch on which --batch autotunes the lockstep knobs")
     ap.add_argument("--serve", action="store_true",
                     help="instead of the single-instance line: the served workload at --serve-rates")
     ap.add_argument("--serve-rates", default="5,20,80", help="Poisson arrival rates (jobs/s)")

@@ -178,23 +178,47 @@ int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void*
 int qm_refine_batch(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
                     int32_t nstreams, qm_result** outs, int32_t* codes);
 
-/* Refine n independent instances in lockstep on one stream: every instance
-   runs the round loop of paper, Section 2, on its own mesh, and each phase
-   of a round (classification, splitting points, location, region growth and
+/* Launch-shape knobs of the lockstep form.  None of them changes a result. */
+typedef struct {
+    int32_t groups;          /* lockstep groups (1..64): with more than one, the instances are dealt,
+                                largest input first, to that many groups, each run by a host thread of
+                                its own on a stream of its own (default priority) */
+    int32_t classify_tiles;  /* 256-element tiles per classification workgroup (1..64) */
+    int32_t rank_max;        /* rounds of up to this many candidates are ordered by one workgroup
+                                (256..4096); larger ones by a radix sort */
+    int32_t select_one_wg;   /* selections of up to this many claims and candidates run in one
+                                workgroup (0..2^20); larger ones in passes over many workgroups */
+    int32_t hybrid_wgs;      /* hybrid-tier workgroups of a launch, over all instances (16..4096) */
+    int32_t global_wgs;      /* global-tier workgroups of a launch, over all instances (4..1024) */
+} qm_lockstep_tune;
+
+/* Refine n independent instances in lockstep: every instance runs the round
+   loop of paper, Section 2, on its own mesh, and each phase of a round
+   (classification, splitting points, location, region growth and
    validation, verdicts, selection, insertion) is one launch over the work of
-   all instances in that phase, each instance picking its own class.  Each
-   result is bit-identical to qm_refine on the same instance.  Arguments as
-   qm_refine_batch.  With ngroups = 1 the instances form one lockstep group
-   on `hip_stream` (a hipStream_t, NULL: default stream); with ngroups > 1
-   (at most 64) they are dealt, largest input first, to that many groups,
-   each run by a host thread of its own on a stream of its own (default
-   priority) of the current device, so that one group's long workgroups
-   overlap another group's work.  Options may not ask for profiling
-   (QM_PROFILE, QM_PROFILE_GROW), QM_EARLY_STOP or max_kept > 0: such an
-   instance ends with QM_EINVAL and the others go on.  Every instance's mesh
-   stays on the device until it finishes. */
+   all instances of a group in that phase, each instance picking its own
+   class.  Each result is bit-identical to qm_refine on the same instance.
+   Arguments as qm_refine_batch; `tune` NULL means one group on `hip_stream`
+   (a hipStream_t, NULL: default stream) with classify_tiles 8, rank_max
+   4096, select_one_wg 65536, hybrid_wgs 1024, global_wgs 256; with
+   tune->groups > 1 the groups run on streams of the library.  QM_EINVAL for
+   knobs out of range.  Options may not ask for profiling (QM_PROFILE,
+   QM_PROFILE_GROW), QM_EARLY_STOP or max_kept > 0: such an instance ends with
+   QM_EINVAL and the others go on.  Every instance's mesh stays on the device
+   until it finishes. */
 int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
-                       void* hip_stream, int32_t ngroups, qm_result** outs, int32_t* codes);
+                       void* hip_stream, const qm_lockstep_tune* tune, qm_result** outs, int32_t* codes);
+
+/* Choose the knobs of qm_refine_lockstep for a batch: a probe batch of
+   `probe` instances, evenly spaced in input size, is refined with the
+   knobs in turn (groups 1, 2, 4, 8; hybrid_wgs 256..2048; classify_tiles 2,
+   8, 32; select_one_wg 8192, 65536, 262144; rank_max 1024, 4096; one pass of
+   coordinate descent from groups 4 and the defaults, a change kept when it
+   gains 3%); the fastest knobs go to *best and their probe time to
+   *best_seconds (may be NULL).  Costs about a dozen refinements of the probe
+   batch; the probe results are freed. */
+int qm_lockstep_autotune(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                         int32_t probe, qm_lockstep_tune* best, double* best_seconds);
 
 /* View of a result: the output mesh (Steiner vertices appended after the
    input vertices, numbered by round and priority) and the statistics.  The

@@ -116,7 +116,7 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_refine_lockstep", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
+EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_refine_lockstep", "qm_lockstep_autotune", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
            "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_step", "qm_server_poll",
            "qm_server_info",
@@ -388,34 +388,75 @@ def refine_batch(workloads, *, nstreams=8, hmin_factor=0.5, max_rounds=100000, m
     return results
 
 
-def refine_lockstep(workloads, *, groups=1, hmin_factor=0.5, max_rounds=100000, extra_flags=None,
-                    return_codes=False, max_kept=0) -> list:
-    """Refine independent instances in lockstep (qm_refine_lockstep): one
-    launch per phase per round over all instances of a group; one group on
-    the default stream, or `groups` groups on streams of their own.
-    max_rounds may be one value or one per instance.  Results and
-    return_codes as refine_batch."""
-    lib = _load()
+class _Tune(ctypes.Structure):
+    _fields_ = [("groups", ctypes.c_int32), ("classify_tiles", ctypes.c_int32), ("rank_max", ctypes.c_int32),
+                ("select_one_wg", ctypes.c_int32), ("hybrid_wgs", ctypes.c_int32), ("global_wgs", ctypes.c_int32)]
+
+
+LOCKSTEP_DEFAULTS = {"groups": 1, "classify_tiles": 8, "rank_max": 4096, "select_one_wg": 65536,
+                     "hybrid_wgs": 1024, "global_wgs": 256}
+
+
+def _batch_arrays(workloads, hmin_factor, max_rounds, max_kept, extra_flags):
     n = len(workloads)
-    plcs, meshes, opts, keep = (_Plc * n)(), (_Mesh * n)(), (_Opts * n)(), []
+    plcs, meshes, opts, keep = (_Plc * max(n, 1))(), (_Mesh * max(n, 1))(), (_Opts * max(n, 1))(), []
     for i, w in enumerate(workloads):
         plcs[i], meshes[i] = _marshal(w, keep)
         mr = max_rounds[i] if isinstance(max_rounds, (list, tuple)) else max_rounds
         opts[i] = _Opts(float(w.B), float(hmin_factor), int(mr), int(max_kept),
                         int(extra_flags[i]) if extra_flags else 0)
+    return plcs, meshes, opts, keep
+
+
+def refine_lockstep(workloads, *, groups=None, tune=None, hmin_factor=0.5, max_rounds=100000, extra_flags=None,
+                    return_codes=False, max_kept=0) -> list:
+    """Refine independent instances in lockstep (qm_refine_lockstep): one
+    launch per phase per round over all instances of a group.  `tune` is a
+    dict of qm_lockstep_tune knobs (missing ones take the defaults), or None
+    for one group on the default stream; `groups` overrides tune["groups"].
+    max_rounds may be one value or one per instance.  Results and
+    return_codes as refine_batch."""
+    lib = _load()
+    n = len(workloads)
+    plcs, meshes, opts, keep = _batch_arrays(workloads, hmin_factor, max_rounds, max_kept, extra_flags)
+    knobs = None
+    if tune is not None or groups is not None:
+        k = dict(LOCKSTEP_DEFAULTS, **(tune or {}))
+        if groups is not None:
+            k["groups"] = int(groups)
+        knobs = _Tune(*[int(k[f]) for f, _ in _Tune._fields_])
     outs = (ctypes.c_void_p * max(n, 1))()
     codes = (ctypes.c_int32 * max(n, 1))()
     lib.qm_refine_lockstep.restype = ctypes.c_int
     lib.qm_refine_lockstep.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     rc = lib.qm_refine_lockstep(n, ctypes.addressof(plcs), ctypes.addressof(meshes), ctypes.addressof(opts),
-                                None, int(groups), ctypes.addressof(outs), ctypes.addressof(codes))
+                                None, ctypes.addressof(knobs) if knobs is not None else None,
+                                ctypes.addressof(outs), ctypes.addressof(codes))
     results = [_take_result(lib, ctypes.c_void_p(outs[i]), False) if outs[i] else None for i in range(n)]
     if return_codes:
         return results, [int(codes[i]) for i in range(n)]
     if rc not in (0, -4):
         raise QmError(rc, lib.qm_last_error().decode())
     return results
+
+
+def lockstep_autotune(workloads, *, probe=16, hmin_factor=0.5, max_rounds=100000):
+    """Knobs for refine_lockstep chosen by qm_lockstep_autotune on a probe
+    batch of `probe` of the workloads; returns (dict of knobs, probe
+    seconds)."""
+    lib = _load()
+    plcs, meshes, opts, keep = _batch_arrays(workloads, hmin_factor, max_rounds, 0, None)
+    best = _Tune()
+    sec = ctypes.c_double()
+    lib.qm_lockstep_autotune.restype = ctypes.c_int
+    lib.qm_lockstep_autotune.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    rc = lib.qm_lockstep_autotune(len(workloads), ctypes.addressof(plcs), ctypes.addressof(meshes),
+                                  ctypes.addressof(opts), int(probe), ctypes.addressof(best), ctypes.byref(sec))
+    if rc:
+        raise QmError(rc, lib.qm_last_error().decode())
+    return {f: int(getattr(best, f)) for f, _ in _Tune._fields_}, float(sec.value)
 
 
 def refine_workload(w, **kw) -> RefineResult:

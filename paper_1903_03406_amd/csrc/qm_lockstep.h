@@ -75,35 +75,37 @@ struct FReset {                 // k_round_reset
         if (i < 48 && (i < 11 || i >= 15)) d.ctr[i] = 0;
     }
 };
-// classification: each workgroup takes LS_CTILES consecutive 256-element
+// classification: each workgroup takes `tiles` consecutive 256-element
 // tiles of its instance (one part lookup for all of them)
-constexpr int LS_CTILES = 8;
 // (each body starts from local copies of the record's fields: stores of the
 // body cannot then force the record to be read again)
 struct FClassifySS {
+    int tiles;
     QMD void operator()(const LsInst& d, int, int b, int g) const {
         const Mesh M = d.M;
         int* const cand = d.c_elem0;
         int* const cnt = d.ctr + 8;
-        for (int v = 0; v < LS_CTILES; ++v) d_classify_ss(M, cand, cnt, b * LS_CTILES + v, g * LS_CTILES);
+        for (int v = 0; v < tiles; ++v) d_classify_ss(M, cand, cnt, b * tiles + v, g * tiles);
     }
 };
 struct FClassifySF {
+    int tiles;
     QMD void operator()(const LsInst& d, int, int b, int g) const {
         int* const cnt = d.ctr + 8;
         if (cnt[CLS_SS] > 0) return;                 // an earlier class has candidates
         const Mesh M = d.M;
         int* const cand = d.c_elem0;
-        for (int v = 0; v < LS_CTILES; ++v) d_classify_sf(M, cand, cnt, b * LS_CTILES + v, g * LS_CTILES);
+        for (int v = 0; v < tiles; ++v) d_classify_sf(M, cand, cnt, b * tiles + v, g * tiles);
     }
 };
 struct FClassifyTet {
+    int tiles;
     QMD void operator()(const LsInst& d, int, int b, int g) const {
         int* const cnt = d.ctr + 8;
         if (cnt[CLS_SS] > 0 || cnt[CLS_SF] > 0) return;
         const Mesh M = d.M;
         int* const cand = d.c_elem0;
-        for (int v = 0; v < LS_CTILES; ++v) d_classify_tet(M, cand, cnt, b * LS_CTILES + v, g * LS_CTILES);
+        for (int v = 0; v < tiles; ++v) d_classify_tet(M, cand, cnt, b * tiles + v, g * tiles);
     }
 };
 struct FGather {                // counters of each part, side by side
@@ -122,7 +124,7 @@ struct FOrderSmall {
         d_order_small(d.ncand, d.c_elem0, d.c_key0, d.c_tup0, d.c_p0, d.c_st0, d.c_reason0, d.C, b, g);
     }
 };
-constexpr int LS_ORDER_CAP = 4096;    // one 1024-lane workgroup ranks up to this many candidates
+constexpr int LS_ORDER_CAP = 4096;    // one 1024-lane workgroup ranks at most this many candidates
 struct FOrderMid {
     QMD void operator()(const LsInst& d, int, int, int) const {
         d_order_rank<1024, LS_ORDER_CAP>(d.ncand, d.c_elem0, d.c_key0, d.c_tup0, d.c_p0, d.c_st0, d.c_reason0, d.C);
@@ -360,9 +362,19 @@ struct LsDone {
     std::string msg;
 };
 
+// launch-shape knobs of a lockstep batch (qm_lockstep_tune); none of them
+// changes a result
+struct LsTune {
+    int classify_tiles = 8;       // 256-element tiles per classification workgroup
+    int rank_max = LS_ORDER_CAP;  // candidates ordered in one workgroup (more: radix sort)
+    int select_one_wg = MIS_SMALL;  // claims and candidates selected in one workgroup
+    int hybrid_wgs = 1024;        // hybrid-tier workgroups over all instances
+    int global_wgs = 256;         // global-tier workgroups over all instances
+};
+
 class Lockstep {
 public:
-    explicit Lockstep(hipStream_t s) : s_(s), stage_(s) {}
+    explicit Lockstep(hipStream_t s, const LsTune& t = LsTune()) : s_(s), stage_(s), tune_(t) {}
     ~Lockstep() {
         for (auto& d : done_) qm_result_free(d.res);
         jobs_.clear();
@@ -409,6 +421,7 @@ public:
 private:
     hipStream_t s_;
     LsStage stage_;
+    LsTune tune_;
     std::vector<std::unique_ptr<LsJob>> jobs_;
     std::vector<LsDone> done_;
     std::vector<LsInst> table_;
@@ -592,10 +605,11 @@ void Lockstep::step() {
     // round's insertion table may still be waiting for its copy)
     upload();
     launch<64>(L, [](const LsJob&) { return 1L; }, FReset{});
-    launch<256>(L, [](const LsJob& J) { return J.E->M.nss ? (long)nblk(J.E->M.nss, 256 * LS_CTILES) : 0L; },
-                FClassifySS{});
-    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt, 256 * LS_CTILES); }, FClassifySF{});
-    launch<256>(L, [](const LsJob& J) { return (long)nblk(J.E->M.nt, 256 * LS_CTILES); }, FClassifyTet{});
+    const int ct = tune_.classify_tiles;
+    launch<256>(L, [ct](const LsJob& J) { return J.E->M.nss ? (long)nblk(J.E->M.nss, 256 * ct) : 0L; },
+                FClassifySS{ct});
+    launch<256>(L, [ct](const LsJob& J) { return (long)nblk(J.E->M.nt, 256 * ct); }, FClassifySF{ct});
+    launch<256>(L, [ct](const LsJob& J) { return (long)nblk(J.E->M.nt, 256 * ct); }, FClassifyTet{ct});
     gather(L);
     each(L, [&](LsJob& J) {
         patch_last_record(J);
@@ -618,9 +632,10 @@ void Lockstep::step() {
     upload();
     launch<256>(L, [](const LsJob& J) { return (long)nblk(J.ncand); }, FSplit{});
     launch<SORT_SMALL>(L, [](const LsJob& J) { return J.ncand <= SORT_SMALL ? 1L : 0L; }, FOrderSmall{});
-    launch<1024>(L, [](const LsJob& J) { return J.ncand > SORT_SMALL && J.ncand <= LS_ORDER_CAP ? 1L : 0L; },
+    const int rmax = tune_.rank_max;
+    launch<1024>(L, [rmax](const LsJob& J) { return J.ncand > SORT_SMALL && J.ncand <= rmax ? 1L : 0L; },
                  FOrderMid{});
-    each(L, [&](LsJob& J) { if (J.ncand > LS_ORDER_CAP) sort_large(J); });
+    each(L, [&](LsJob& J) { if (J.ncand > SORT_SMALL && J.ncand > rmax) sort_large(J); });
     // step 3: locate
     launch<64>(L, [](const LsJob& J) { return J.cls != CLS_SS ? (long)nblk(J.ncand, 64) : 0L; }, FLocate{});
     // steps 4-5: grow and validate; a pass is repeated (with larger pools) by
@@ -671,7 +686,7 @@ void Lockstep::step() {
             if (hyb_total > 0) {            // hybrid tier: at most 1024 workgroups over all instances
                 const GrowTiles HT = hybrid_tiles();
                 const size_t block = lists_slab_bytes(HT);
-                const long cap = 1024;
+                const long cap = tune_.hybrid_wgs;
                 auto share = [&](const LsJob& J) -> long {
                     if (J.nover <= 0) return 0L;
                     const long want = std::min(J.nover, 1024);
@@ -689,7 +704,7 @@ void Lockstep::step() {
                 BT.ehcap = 1;
                 while (BT.ehcap < 2 * (3 * BT.maxbf + BT.maxbe)) BT.ehcap <<= 1;
                 const size_t block = grow_slab_bytes(BT);
-                const long cap = 256;
+                const long cap = tune_.global_wgs;
                 auto share = [&](const LsJob& J) -> long {
                     if (J.nbig <= 0) return 0L;
                     const long want = std::min(J.nbig, 1024);
@@ -709,7 +724,7 @@ void Lockstep::step() {
     each(L, [&](LsJob& J) {
         Engine& E = *J.E;
         J.ncl = std::min(J.ncl_final, E.PL.cap_cl);
-        J.small_sel = J.ncl > 0 && J.ncl <= MIS_SMALL && J.ncand <= MIS_SMALL;
+        J.small_sel = J.ncl > 0 && J.ncl <= tune_.select_one_wg && J.ncand <= tune_.select_one_wg;
         J.sel_done = false;
         J.passes = 0;
     });
@@ -799,58 +814,18 @@ void Lockstep::step() {
     compact();
 }
 
-// One lockstep group: its instances (indices `mine`) on stream s, driven by
-// the calling thread.  A failure that ends the whole group (a HIP error)
-// lands in gcode/gmsg; per-instance failures in codes/msgs.
-void run_lockstep_group(hipStream_t s, const std::vector<int>& mine, const qm_plc* plcs, const qm_mesh* meshes,
-                        const qm_options* opts, qm_result** outs, int32_t* codes, std::vector<std::string>& msgs,
-                        int& gcode, std::string& gmsg) {
-    try {
-        Lockstep B(s);
-        auto collect = [&]() {
-            for (auto& d : B.take_done()) {
-                outs[d.tag] = d.res;
-                codes[d.tag] = d.code;
-                msgs[d.tag] = d.msg;
-            }
-        };
-        for (int i : mine) B.add(&plcs[i], &meshes[i], &opts[i], (uint64_t)i);
-        collect();
-        while (B.live() > 0) {
-            B.step();
-            collect();
-        }
-    } catch (const QmError& e) {
-        gcode = e.code;
-        gmsg = e.what();
-    } catch (const std::exception& e) {
-        gcode = QM_EINTERNAL;
-        gmsg = e.what();
-    }
-}
-
-}  // namespace
-
-extern "C" {
-
-int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
-                       void* hip_stream, int32_t ngroups, qm_result** outs, int32_t* codes) {
-    g_err.clear();
-    if (n < 0 || (n > 0 && (!plcs || !meshes || !opts || !outs || !codes)) || ngroups < 1 || ngroups > 64) {
-        g_err = "bad batch arguments";
-        return QM_EINVAL;
-    }
+// A whole lockstep batch: instances dealt, largest input first in snake
+// order, to `groups` groups (one on `s`, or each on a stream and host thread
+// of its own).  Returns 0 or the first group failure (message in err).
+int lockstep_run(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts, hipStream_t s,
+                 const LsTune& tune, int groups, qm_result** outs, int32_t* codes, std::vector<std::string>& msgs,
+                 std::string& err) {
     for (int i = 0; i < n; ++i) { outs[i] = nullptr; codes[i] = QM_EINTERNAL; }
-    std::vector<std::string> msgs(n);
-    const int G = std::max(1, std::min<int>(ngroups, n));
-    // instances dealt to the groups in decreasing input size (snake order),
-    // so that the groups carry similar work
+    msgs.assign(n, std::string());
+    const int G = std::max(1, std::min<int>(groups, n));
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const int na = meshes[a].nt, nb = meshes[b].nt;
-        return na > nb;
-    });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return meshes[a].nt > meshes[b].nt; });
     std::vector<std::vector<int>> part(G);
     for (int k = 0; k < n; ++k) {
         const int r = k / G, c = k % G;
@@ -858,11 +833,35 @@ int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, con
     }
     std::vector<int> gcode(G, QM_OK);
     std::vector<std::string> gmsg(G);
+    auto run = [&](int g, hipStream_t st) {
+        try {
+            Lockstep B(st, tune);
+            auto collect = [&]() {
+                for (auto& d : B.take_done()) {
+                    outs[d.tag] = d.res;
+                    codes[d.tag] = d.code;
+                    msgs[d.tag] = d.msg;
+                }
+            };
+            for (int i : part[g]) B.add(&plcs[i], &meshes[i], &opts[i], (uint64_t)i);
+            collect();
+            while (B.live() > 0) {
+                B.step();
+                collect();
+            }
+        } catch (const QmError& e) {
+            gcode[g] = e.code;
+            gmsg[g] = e.what();
+        } catch (const std::exception& e) {
+            gcode[g] = QM_EINTERNAL;
+            gmsg[g] = e.what();
+        }
+    };
     if (G == 1) {
-        run_lockstep_group((hipStream_t)hip_stream, part[0], plcs, meshes, opts, outs, codes, msgs, gcode[0], gmsg[0]);
+        run(0, s);
     } else {                      // one stream (default priority) and one host thread per group
         int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) { g_err = "no HIP device"; return QM_EDEVICE; }
+        if (hipGetDevice(&dev) != hipSuccess) { err = "no HIP device"; return QM_EDEVICE; }
         std::vector<std::thread> th;
         for (int g = 0; g < G; ++g)
             th.emplace_back([&, g]() {
@@ -872,7 +871,7 @@ int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, con
                     gmsg[g] = "no stream for a lockstep group";
                     return;
                 }
-                run_lockstep_group(st, part[g], plcs, meshes, opts, outs, codes, msgs, gcode[g], gmsg[g]);
+                run(g, st);
                 (void)hipStreamSynchronize(st);
                 (void)hipStreamDestroy(st);
             });
@@ -880,14 +879,131 @@ int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, con
     }
     for (int g = 0; g < G; ++g)
         if (gcode[g] != QM_OK) {
-            g_err = gmsg[g];
+            err = gmsg[g];
             return gcode[g];
         }
     for (int i = 0; i < n; ++i)
         if (codes[i] != QM_OK && codes[i] != QM_EROUNDS) {
-            g_err = "instance " + std::to_string(i) + ": " + msgs[i];
+            err = "instance " + std::to_string(i) + ": " + msgs[i];
             return codes[i];
         }
+    return QM_OK;
+}
+
+// the library's knobs from the caller's struct (NULL: defaults), checked
+int tune_from(const qm_lockstep_tune* t, LsTune& out, int& groups) {
+    out = LsTune();
+    groups = 1;
+    if (!t) return QM_OK;
+    if (t->groups < 1 || t->groups > 64 || t->classify_tiles < 1 || t->classify_tiles > 64 || t->rank_max < SORT_SMALL ||
+        t->rank_max > LS_ORDER_CAP || t->select_one_wg < 0 || t->select_one_wg > (1 << 20) || t->hybrid_wgs < 16 ||
+        t->hybrid_wgs > 4096 || t->global_wgs < 4 || t->global_wgs > 1024)
+        return QM_EINVAL;
+    groups = t->groups;
+    out.classify_tiles = t->classify_tiles;
+    out.rank_max = t->rank_max;
+    out.select_one_wg = t->select_one_wg;
+    out.hybrid_wgs = t->hybrid_wgs;
+    out.global_wgs = t->global_wgs;
+    return QM_OK;
+}
+
+void tune_to(const LsTune& t, int groups, qm_lockstep_tune* out) {
+    out->groups = groups;
+    out->classify_tiles = t.classify_tiles;
+    out->rank_max = t.rank_max;
+    out->select_one_wg = t.select_one_wg;
+    out->hybrid_wgs = t.hybrid_wgs;
+    out->global_wgs = t.global_wgs;
+}
+
+}  // namespace
+
+extern "C" {
+
+int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                       void* hip_stream, const qm_lockstep_tune* tune, qm_result** outs, int32_t* codes) {
+    g_err.clear();
+    LsTune t;
+    int groups = 1;
+    if (n < 0 || (n > 0 && (!plcs || !meshes || !opts || !outs || !codes)) || tune_from(tune, t, groups) != QM_OK) {
+        g_err = "bad batch arguments";
+        return QM_EINVAL;
+    }
+    std::vector<std::string> msgs;
+    std::string err;
+    const int rc = lockstep_run(n, plcs, meshes, opts, (hipStream_t)hip_stream, t, groups, outs, codes, msgs, err);
+    if (rc != QM_OK) g_err = err;
+    return rc;
+}
+
+// Coordinate descent over the knobs on a probe batch (instances evenly
+// spaced in input size): each knob in turn takes the value whose run of the
+// probe is fastest (a change must gain 3%); the results of the probe runs
+// are freed.
+int qm_lockstep_autotune(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
+                         int32_t probe, qm_lockstep_tune* best, double* best_seconds) {
+    g_err.clear();
+    if (n < 1 || !plcs || !meshes || !opts || !best || probe < 1) {
+        g_err = "bad tuning arguments";
+        return QM_EINVAL;
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return meshes[a].nt < meshes[b].nt; });
+    const int p = std::min<int>(probe, n);
+    std::vector<qm_plc> P(p);
+    std::vector<qm_mesh> Mh(p);
+    std::vector<qm_options> O(p);
+    for (int k = 0; k < p; ++k) {
+        const int i = order[p == 1 ? n - 1 : (int)((long)k * (n - 1) / (p - 1))];
+        P[k] = plcs[i]; Mh[k] = meshes[i]; O[k] = opts[i];
+    }
+    std::vector<qm_result*> outs(p, nullptr);
+    std::vector<int32_t> codes(p, 0);
+    std::vector<std::string> msgs;
+    auto timed = [&](const LsTune& t, int groups, double& sec) -> int {
+        std::string err;
+        const auto a = std::chrono::steady_clock::now();
+        const int rc = lockstep_run(p, P.data(), Mh.data(), O.data(), nullptr, t, groups, outs.data(), codes.data(),
+                                    msgs, err);
+        sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - a).count();
+        for (auto*& r : outs) { qm_result_free(r); r = nullptr; }
+        if (rc != QM_OK) g_err = "probe batch failed: " + err;
+        return rc;
+    };
+    LsTune cur;
+    int groups = 4;
+    double cur_s = 0;
+    int rc = timed(cur, groups, cur_s);
+    if (rc != QM_OK) return rc;
+    auto consider = [&](LsTune t, int g) -> int {
+        double sec = 0;
+        const int r = timed(t, g, sec);
+        if (r != QM_OK) return r;
+        if (sec < 0.97 * cur_s) { cur = t; groups = g; cur_s = sec; }
+        return QM_OK;
+    };
+    for (int g : {1, 2, 8})
+        if ((rc = consider(cur, g)) != QM_OK) return rc;
+    for (int v : {256, 512, 2048}) {
+        LsTune t = cur; t.hybrid_wgs = v;
+        if (v != cur.hybrid_wgs && (rc = consider(t, groups)) != QM_OK) return rc;
+    }
+    for (int v : {2, 32}) {
+        LsTune t = cur; t.classify_tiles = v;
+        if (v != cur.classify_tiles && (rc = consider(t, groups)) != QM_OK) return rc;
+    }
+    for (int v : {8192, 262144}) {
+        LsTune t = cur; t.select_one_wg = v;
+        if (v != cur.select_one_wg && (rc = consider(t, groups)) != QM_OK) return rc;
+    }
+    {
+        LsTune t = cur; t.rank_max = 1024;
+        if ((rc = consider(t, groups)) != QM_OK) return rc;
+    }
+    tune_to(cur, groups, best);
+    if (best_seconds) *best_seconds = cur_s;
     return QM_OK;
 }
 

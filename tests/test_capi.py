@@ -66,3 +66,12 @@ def test_binding_constants_match_the_header():
         assert int(defs[flag].rstrip("u")) == getattr(qm, flag), flag
     codes = {int(v): k for k, v in defs.items() if k.startswith("QM_E") and v.startswith("-")}
     assert codes == qm.ERRORS
+
+
+@pytest.mark.skipif(not os.path.exists(qm._SO), reason="libqm.so not built")
+def test_lockstep_knobs_are_checked_before_any_device_call():
+    """Out-of-range lockstep knobs are refused with QM_EINVAL (host check)."""
+    for bad in ({"groups": 0}, {"classify_tiles": 65}, {"rank_max": 5000}, {"hybrid_wgs": 8},
+                {"select_one_wg": -1}, {"global_wgs": 2000}):
+        with pytest.raises(qm.QmError, match="EINVAL"):
+            qm.refine_lockstep([], tune=bad)

@@ -70,6 +70,23 @@ def test_lockstep_groups_match_single_instances(mix):
     assert codes == [0, -1, 0, 0] and got[1] is None
 
 
+def test_lockstep_knobs_do_not_change_results(mix):
+    """Launch-shape knobs at their extremes (one classification tile per
+    workgroup, radix sorts from 257 candidates, every selection over many
+    workgroups, the fewest hybrid and global workgroups) and the knobs the
+    autotuner picks give the single runs' results."""
+    alone = [qm.refine_workload(w) for w in mix]
+    extreme = {"groups": 2, "classify_tiles": 1, "rank_max": 256, "select_one_wg": 0, "hybrid_wgs": 16,
+               "global_wgs": 4}
+    for k, g in enumerate(qm.refine_lockstep(mix, tune=extreme)):
+        assert same(g, alone[k]), ("extreme", mix[k].name)
+    tune, sec = qm.lockstep_autotune(mix, probe=6)
+    print(f"[lockstep] autotuned knobs {tune} ({sec:.2f}s for the probe)", flush=True)
+    assert 1 <= tune["groups"] <= 8 and 256 <= tune["rank_max"] <= 4096
+    for k, g in enumerate(qm.refine_lockstep(mix, tune=tune)):
+        assert same(g, alone[k]), ("tuned", mix[k].name)
+
+
 def test_lockstep_small_instances_match_oracle(mix):
     small = [w for w in mix if len(w.xyz) <= 1300]
     got = qm.refine_lockstep(small)
