@@ -265,6 +265,10 @@ def main():
     ap.add_argument("--no-quality", action="store_true", help="skip the output quality report")
     ap.add_argument("--early-stop", action="store_true",
                     help="the early-stop blasting mode (not a parity mode: timing decides which points win)")
+    ap.add_argument("--no-fast-modes", action="store_true",
+                    help="skip the comparison run of the three-sub-phase mode in the single-instance line")
+    ap.add_argument("--subphases", action="store_true",
+                    help="three-sub-phase rounds (not a parity mode: each round runs SS, SF and TET in turn)")
     ap.add_argument("--batch", type=int, default=0,
                     help="instead of the single-instance line: the first N instances of the batched "
                          "workload (config 4), batched jobs/s against one-at-a-time jobs/s")
@@ -309,7 +313,7 @@ def main():
     def step(profile=False):
         return qm.refine(d["xyz"], d["tets"], d["sf"], d["sf_facet"], d["ss"], d["ss_seg"], d["ftri"],
                          d["ftri_facet"], w.B, stream=stream, profile=profile, verbose=True,
-                         early_stop=args.early_stop)
+                         early_stop=args.early_stop, subphases=args.subphases)
 
     # The first untimed step runs with every kernel family timed and the
     # region counters on (the algorithmic bytes and the phase split come from
@@ -363,8 +367,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name + ("_early_stop" if args.early_stop else ""),
-                   "mode": "early-stop blasting (not a parity mode)" if args.early_stop else "parity",
+        "config": {"workload": w.name + ("_early_stop" if args.early_stop else "")
+                   + ("_subphases" if args.subphases else ""),
+                   "mode": ", ".join(m for m, on in (("early-stop blasting (not a parity mode)", args.early_stop),
+                                                     ("three-sub-phase rounds (not a parity mode)", args.subphases))
+                                     if on) or "parity",
                    "input_vertices": int(len(w.xyz)), "input_tets": int(len(w.tets)),
                    "plc_triangles": int(len(w.ftri)), "segments": int(len(w.seg)), "B": w.B,
                    "parallelism": "single instance, one GPU"},
@@ -389,6 +396,21 @@ def main():
         "whole_step_model": {"bytes": sbytes, "frac_of_hbm_over_step": sbytes / sec / (HBM_PEAK_GBS * 1e9),
                              **{k: round(v, 2) for k, v in smodel.items()}},
     }
+    if not (args.no_fast_modes or args.early_stop or args.subphases):
+        # the non-parity three-sub-phase mode on the same resident inputs, for
+        # comparison (one refinement, host clock; not `value`)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        f = qm.refine(d["xyz"], d["tets"], d["sf"], d["sf_facet"], d["ss"], d["ss_seg"], d["ftri"], d["ftri_facet"],
+                      w.B, stream=stream, subphases=True)
+        torch.cuda.synchronize()
+        fs = time.perf_counter() - a
+        print(f"[bench] three-sub-phase rounds: {f.rounds} rounds, {f.steiner} Steiner, {fs:.2f}s",
+              file=sys.stderr, flush=True)
+        out["fast_modes"] = {"three_sub_phase_rounds": {
+            "note": "not a parity mode (insertion order differs from the oracle's); a CDT of the same kind",
+            "seconds": fs, "steiner_per_s": f.steiner / fs, "tets_per_s": len(f.tets) / fs, "rounds": f.rounds,
+            "steiner": f.steiner, "tets": int(len(f.tets))}}
     if not args.no_quality:
         from paper_1903_03406_amd import quality
         print("[bench] quality report ...", file=sys.stderr, flush=True)

@@ -83,6 +83,16 @@ typedef struct qm_mesh {
                                 claim sets and full validation, so the output is a CDT of the
                                 same kind, but which points win depends on timing: the result
                                 is not reproducible and not the oracle's. */
+#define QM_SUBPHASE_ROUNDS 1024u   /* a non-parity mode: each round runs three sub-phases in the
+                                     paper's order (Section 2: subsegments, then subfaces, then bad
+                                     tets), each the usual round restricted to its class (that
+                                     class classified alone, so a later class no longer waits for
+                                     the earlier ones to run out); a sub-phase without candidates
+                                     is skipped and not counted as a round, and the refinement
+                                     ends after three empty sub-phases in a row.  Encroachment of
+                                     constraints by a later class's points is rejected and queued
+                                     as usual.  Reproducible, a CDT of the same kind, but not the
+                                     oracle's result (the insertion order differs) */
 #define QM_OUTPUT_DEVICE 512u   /* the result's output arrays stay on the device (same device):
                                    qm_result_view returns device pointers, valid until
                                    qm_result_free; records and statistics stay on the host */
@@ -203,9 +213,9 @@ typedef struct {
    4096, select_one_wg 65536, hybrid_wgs 1024, global_wgs 256; with
    tune->groups > 1 the groups run on streams of the library.  QM_EINVAL for
    knobs out of range.  Options may not ask for profiling (QM_PROFILE,
-   QM_PROFILE_GROW), QM_EARLY_STOP or max_kept > 0: such an instance ends with
-   QM_EINVAL and the others go on.  Every instance's mesh stays on the device
-   until it finishes. */
+   QM_PROFILE_GROW), a non-parity mode (QM_EARLY_STOP, QM_SUBPHASE_ROUNDS) or
+   max_kept > 0: such an instance ends with QM_EINVAL and the others go on.
+   Every instance's mesh stays on the device until it finishes. */
 int qm_refine_lockstep(int32_t n, const qm_plc* plcs, const qm_mesh* meshes, const qm_options* opts,
                        void* hip_stream, const qm_lockstep_tune* tune, qm_result** outs, int32_t* codes);
 
@@ -313,8 +323,8 @@ size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options*
    server is stepped: admitted jobs form one lockstep batch (as
    qm_refine_lockstep) on a stream of the server, stay resident on the
    device between rounds and advance only through qm_server_step; their
-   options may not ask for profiling, QM_EARLY_STOP or max_kept > 0 (such a
-   job ends with QM_EINVAL).  `hbm_budget_bytes` bounds
+   options may not ask for profiling, a non-parity mode or max_kept > 0
+   (such a job ends with QM_EINVAL).  `hbm_budget_bytes` bounds
    the summed estimates of admitted, unfinished jobs.  *out is freed with
    qm_server_destroy. */
 int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out);

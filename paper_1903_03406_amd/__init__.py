@@ -31,6 +31,7 @@ QM_PROFILE_GROW = 8   # time only the small-tile grow launches (family grow_vali
 QM_VERBOSE = 4
 QM_EARLY_STOP = 256       # non-parity mode: early-stop blasting (timing-dependent result)
 QM_OUTPUT_DEVICE = 512    # the result's arrays stay on the device
+QM_SUBPHASE_ROUNDS = 1024  # non-parity mode: three sub-phase rounds (SS, SF, TET in turn)
 QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through its own error word
 QM_TEST_TIER1 = 32        # tests only: every region grown with the medium tiles (or larger)
 QM_TEST_TIER2 = 64        # tests only: every region grown with the global-memory tiles
@@ -170,7 +171,7 @@ def _arr(a, dtype):
 
 def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None, hmin_factor=0.5,
            max_rounds=100000, max_kept=0, stream=None, profile=False, verbose=False,
-           extra_flags=0, early_stop=False) -> RefineResult:
+           extra_flags=0, early_stop=False, subphases=False) -> RefineResult:
     """Refine a CDT.  Arrays are numpy (host) or torch CUDA tensors (device);
     ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle."""
     lib = _load()
@@ -204,7 +205,8 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
     mesh = _Mesh(nv, pxyz, nt, ptet, nsf, psf, psff, nss, pss, pssg)
     opts = _Opts(float(B), float(hmin_factor), int(max_rounds), int(max_kept),
                  (QM_INPUT_DEVICE if dev else 0) | (_prof_flag(profile))
-                 | (QM_VERBOSE if verbose else 0) | (QM_EARLY_STOP if early_stop else 0) | int(extra_flags))
+                 | (QM_VERBOSE if verbose else 0) | (QM_EARLY_STOP if early_stop else 0)
+                 | (QM_SUBPHASE_ROUNDS if subphases else 0) | int(extra_flags))
     if stream is None:
         hs = None
     elif hasattr(stream, "cuda_stream"):

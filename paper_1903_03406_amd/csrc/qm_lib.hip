@@ -1005,6 +1005,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     const bool verbose = (opt->flags & QM_VERBOSE) != 0;
     const int min_tier = (opt->flags & QM_TEST_TIER2) ? 2 : (opt->flags & QM_TEST_TIER1) ? 1 : 0;
     const bool early_stop = (opt->flags & QM_EARLY_STOP) != 0;
+    // three-sub-phase rounds: the class is forced in turn (SS, SF, TET); a
+    // sub-phase without candidates is skipped and is not a round
+    const bool subphases = (opt->flags & QM_SUBPHASE_ROUNDS) != 0;
+    int sub = CLS_SS, empty_subphases = 0;
     const unsigned long long key_mask = (opt->flags & QM_TEST_KEY_COLLIDE) ? 0xE000000000000000ull : ~0ull;
     E.verbose = verbose;
     auto last_note = std::chrono::steady_clock::now();
@@ -1031,9 +1035,12 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         E.c_elem0.ensure(std::max((size_t)E.M.nss, 4 * (size_t)E.M.nt), s, false);
         k_round_reset<<<1, 64, 0, s>>>(E.ctr.p);
         E.pbegin();
-        if (E.M.nss) k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
-        k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
-        k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
+        // (a sub-phase classifies its class alone: the earlier classes' counts
+        // stay zero, so its kernel does not skip)
+        if (E.M.nss && (!subphases || sub == CLS_SS))
+            k_classify_ss<<<nblk(E.M.nss), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
+        if (!subphases || sub == CLS_SF) k_classify_sf<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
+        if (!subphases || sub == CLS_TET) k_classify_tet<<<nblk(E.M.nt), 256, 0, s>>>(E.M, E.c_elem0.p, cnt_d);
         E.pend(0);
         sync_counters();
         patch_last_record();
@@ -1041,6 +1048,16 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
         for (int c = CLS_SS; c <= CLS_TET && cls == CLS_NONE; ++c)
             if (hc[8 + c] > 0) { cls = c; ncand = hc[8 + c]; }
         if (hc[8 + CLS_SS] == 0 && hc[8 + CLS_SF] == 0) { scan_tets += E.M.nt; scan_verts += E.M.nv; }
+        if (subphases) {
+            if (cls == CLS_NONE) {
+                if (++empty_subphases == 3) break;      // a whole round without work
+                sub = (sub + 1) % 3;
+                --round;
+                continue;
+            }
+            empty_subphases = 0;
+            sub = (sub + 1) % 3;
+        }
         if (cls == CLS_NONE) break;
         E.ensure_cands(ncand);
         // step 2: splitting points and priorities, then priority order

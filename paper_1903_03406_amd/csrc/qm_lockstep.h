@@ -396,8 +396,8 @@ public:
             if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
                 throw QmError(QM_EINVAL, "bad counts");
             if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
-            if (opt->flags & (QM_PROFILE | QM_PROFILE_GROW | QM_EARLY_STOP) || opt->max_kept > 0)
-                throw QmError(QM_EINVAL, "the lockstep form takes no profiling, early stop or insertion cap");
+            if (opt->flags & (QM_PROFILE | QM_PROFILE_GROW | QM_EARLY_STOP | QM_SUBPHASE_ROUNDS) || opt->max_kept > 0)
+                throw QmError(QM_EINVAL, "the lockstep form takes no profiling, non-parity mode or insertion cap");
             J->opt_copy = *opt;
             J->opt = &J->opt_copy;
             J->key_mask = (opt->flags & QM_TEST_KEY_COLLIDE) ? 0xE000000000000000ull : ~0ull;

@@ -62,7 +62,7 @@ def test_binding_constants_match_the_header():
     assert int(defs["QM_ROUND_FIELDS"]) == qm.ROUND_FIELDS
     assert int(defs["QM_PROF_FAMILIES"]) == len(qm.PROF_FAMILIES)
     for flag in ("QM_INPUT_DEVICE", "QM_VERBOSE", "QM_EARLY_STOP", "QM_TEST_ERROR_WORD", "QM_TEST_TIER1",
-                 "QM_TEST_TIER2", "QM_TEST_KEY_COLLIDE", "QM_OUTPUT_DEVICE"):
+                 "QM_TEST_TIER2", "QM_TEST_KEY_COLLIDE", "QM_OUTPUT_DEVICE", "QM_SUBPHASE_ROUNDS"):
         assert int(defs[flag].rstrip("u")) == getattr(qm, flag), flag
     codes = {int(v): k for k, v in defs.items() if k.startswith("QM_E") and v.startswith("-")}
     assert codes == qm.ERRORS

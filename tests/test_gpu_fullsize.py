@@ -100,3 +100,16 @@ def test_config3_full_properties(cfg3):
     a1 = oracle.facet_areas(g.xyz, g.sf, g.sf_facet)
     assert set(a0) == set(a1)
     assert max(abs(a0[k] - a1[k]) / a0[k] for k in a0) < 1e-9
+
+
+def test_config3_subphase_rounds_properties(cfg3):
+    """The three-sub-phase mode (not a parity mode) at full size: converges
+    and is a CDT conforming to the PLC and a valid tetrahedralisation."""
+    g = qm.refine_workload(cfg3, subphases=True)
+    print(f"[fullsize] config3 sub-phase rounds: rounds={g.rounds} steiner={g.steiner} tets={len(g.tets)} "
+          f"{g.seconds_refine:.2f}s", flush=True)
+    assert g.status == 0
+    assert_cdt(g, cfg3, "config3 sub-phase rounds")
+    a0 = oracle.facet_areas(cfg3.xyz, cfg3.ftri, cfg3.ftri_facet)
+    a1 = oracle.facet_areas(g.xyz, g.sf, g.sf_facet)
+    assert set(a0) == set(a1) and max(abs(a0[k] - a1[k]) / a0[k] for k in a0) < 1e-9
