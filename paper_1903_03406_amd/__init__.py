@@ -644,3 +644,120 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+class PipelinedServer:
+    """Served refinement with the input preparation pipelined, as the
+    paper's gQM3D+ splits the work (Section 3): the host builds each job's
+    initial Delaunay tetrahedralisation and CDT while the device refines
+    other jobs.  submit(prep, *args) runs prep(*args) (which returns a
+    workload) on a pool of `prep_threads` host threads; a dispatcher thread
+    hands each prepared workload to an underlying Server (`nworkers` device
+    workers, `budget` bytes) in the order the preparations finish, waiting
+    while the budget has no room.  poll/result give the result with the
+    preparation, queueing and total seconds of the job."""
+
+    def __init__(self, budget, nworkers=8, prep_threads=8):
+        import collections
+        import threading
+        from concurrent.futures import ThreadPoolExecutor
+        self._srv = Server(budget, nworkers=nworkers)
+        self._pool = ThreadPoolExecutor(max_workers=prep_threads)
+        self._mu = threading.Condition()
+        self._ready = collections.deque()       # (handle, workload or exception, t_prepared)
+        self._jobs = {}                         # handle -> dict(t0, t_prep, ticket, error)
+        self._next = 1
+        self._stop = False
+        self._thread = threading.Thread(target=self._dispatch, daemon=True)
+        self._thread.start()
+
+    def submit(self, prep, *args) -> int:
+        import time
+        with self._mu:
+            h = self._next
+            self._next += 1
+            self._jobs[h] = {"t0": time.perf_counter(), "t_prep": None, "ticket": None, "error": None}
+        fut = self._pool.submit(prep, *args)
+
+        def done(f, h=h):
+            import time
+            try:
+                item = f.result()
+            except Exception as e:          # the preparation failed: the job ends with it
+                item = e
+            with self._mu:
+                self._ready.append((h, item, time.perf_counter()))
+                self._mu.notify_all()
+        fut.add_done_callback(done)
+        return h
+
+    def _dispatch(self):
+        import time
+        while True:
+            with self._mu:
+                while not self._ready and not self._stop:
+                    self._mu.wait()
+                if self._stop:
+                    return
+                h, item, t_prep = self._ready[0]
+            job = self._jobs[h]
+            if isinstance(item, Exception):
+                tk, err = None, item
+            else:
+                try:
+                    tk, err = self._srv.submit(item), None
+                except QmError as e:
+                    tk, err = None, e
+                if tk is None and err is None:    # no room yet: wait for completions
+                    time.sleep(0.0005)
+                    continue
+            with self._mu:
+                self._ready.popleft()
+                job["t_prep"] = t_prep - job["t0"]
+                job["ticket"], job["error"] = tk, err
+                self._mu.notify_all()
+
+    def poll(self, handle, wait_ms=0):
+        """None while the job is being prepared, queued or refined; else
+        (result or None, code, message, preparation s, total s)."""
+        import time
+        deadline = None if wait_ms < 0 else time.perf_counter() + wait_ms / 1000.0
+        while True:
+            with self._mu:
+                job = self._jobs[handle]
+                if job["error"] is not None:
+                    del self._jobs[handle]
+                    e = job["error"]
+                    return None, getattr(e, "code", -1), str(e), job["t_prep"] or 0.0, \
+                        time.perf_counter() - job["t0"]
+                tk = job["ticket"]
+            if tk is not None:
+                got = self._srv.poll(tk, wait_ms=0)
+                if got is not None:
+                    res, code, msg, _, _ = got
+                    with self._mu:
+                        del self._jobs[handle]
+                    return res, code, msg, job["t_prep"], time.perf_counter() - job["t0"]
+            if deadline is not None and time.perf_counter() >= deadline:
+                return None
+            time.sleep(0.0005)
+
+    def result(self, handle):
+        out, code, msg, _, _ = self.poll(handle, wait_ms=-1)
+        if code not in (0, -4):
+            raise QmError(code, msg)
+        return out
+
+    def close(self):
+        with self._mu:
+            self._stop = True
+            self._mu.notify_all()
+        self._thread.join()
+        self._pool.shutdown(wait=True)
+        self._srv.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -19,6 +19,8 @@
  * always the newest and a tie means "outside".  The corner triangulation is
  * the perturbed Delaunay triangulation of the 8 corners, found by brute force.
  */
+/* The builder's working state is thread-local: independent calls may run
+   on several host threads at once. */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -88,7 +90,7 @@ static void g_mul(gint* r, const gint* a, const gint* b) {
 static int64_t lat(double x) { return (int64_t)ldexp(x, 53); }
 
 /* ---------------- predicates ------------------------------------------- */
-static const double* P;   /* coordinates, 3 per point */
+static _Thread_local const double* P;   /* coordinates, 3 per point */
 
 /* orient3d(a,b,c,d) = sign det[b-a; c-a; d-a] */
 static int orient_exact(int a, int b, int c, int d) {
@@ -214,14 +216,14 @@ static int insphere_sos(int a, int b, int c, int d, int e) {
 
 /* ---------------- triangulation ---------------------------------------- */
 typedef struct { int v[4]; int adj[4]; } Tet;
-static Tet* T; static int nT, capT;
-static int* freel; static int nfree, capfree;
-static int* dead;   /* 1 if slot is free */
+static _Thread_local Tet* T; static _Thread_local int nT, capT;
+static _Thread_local int* freel; static _Thread_local int nfree, capfree;
+static _Thread_local int* dead;   /* 1 if slot is free */
 
 /* inward face triples: orient3d(face, opposite vertex) > 0 */
 static const int FI[4][3] = {{1, 3, 2}, {0, 2, 3}, {0, 3, 1}, {0, 1, 2}};
 
-static unsigned char* mark;            /* per tet: 1 in cavity, 2 tested outside */
+static _Thread_local unsigned char* mark;            /* per tet: 1 in cavity, 2 tested outside */
 
 static int new_tet(void) {
     if (nfree) { int t = freel[--nfree]; dead[t] = 0; return t; }
@@ -300,9 +302,9 @@ static int corner_dt(void) {
 }
 
 /* cavity work buffers */
-static int *cav, ncav, capcav;
-static int *bnd, nbnd, capbnd;          /* boundary faces (t<<2|f) */
-static int* touched; static int ntouched, captouched;
+static _Thread_local int *cav, ncav, capcav;
+static _Thread_local int *bnd, nbnd, capbnd;          /* boundary faces (t<<2|f) */
+static _Thread_local int* touched; static _Thread_local int ntouched, captouched;
 
 static void push(int** arr, int* n, int* cap, int v) {
     if (*n == *cap) { *cap = *cap ? 2 * *cap : 256; *arr = (int*)realloc(*arr, sizeof(int) * (size_t)*cap); }
@@ -311,7 +313,7 @@ static void push(int** arr, int* n, int* cap, int v) {
 
 /* edge hash for internal linking of new tets */
 typedef struct { uint64_t k; int tf; } EH;
-static EH* eh; static int ehcap;
+static _Thread_local EH* eh; static _Thread_local int ehcap;
 
 static int insert_point(int p, int* start) {
     /* visibility walk */

@@ -193,3 +193,22 @@ def test_stepped_server_advances_one_round_per_step(jobs):
         while srv2.step():
             pass
         assert same(srv2.result(t), alone[jobs[4].name])
+
+
+def test_pipelined_server_matches_single_runs(jobs):
+    """PipelinedServer: inputs built on host threads while others refine;
+    each result equals the job refined alone, and a failing preparation
+    ends only its own job."""
+    specs = [(300 + i, n, B) for i, (n, B) in enumerate([(7000, 2.0), (400, 1.4), (2500, 2.0), (1200, 1.4)])]
+
+    def bad():
+        raise ValueError("no input")
+
+    with qm.PipelinedServer(8 * GiB, nworkers=2, prep_threads=3) as srv:
+        hs = [srv.submit(ellipsoid_instance, *sp) for sp in specs]
+        hb = srv.submit(bad)
+        got = [srv.result(h) for h in hs]
+        res, code, msg, prep_s, total_s = srv.poll(hb, wait_ms=-1)
+        assert res is None and "no input" in msg
+    for g, w in zip(got, jobs[:4]):
+        assert same(g, qm.refine_workload(w)), w.name
