@@ -346,7 +346,7 @@ struct LsJob {
     qm_stats ST{};
     int round = 0, status = 0, last_ncand = 0;
     int cls = CLS_NONE, ncand = 0, ncl = 0, nkept = 0, newt = 0, newss = 0, nover = 0, nbig = 0;
-    int passes = 0, ncl_final = 0, pool_pass = 0, attempt = 0;
+    int passes = 0, ncl_final = 0;
     int undecided = 0;              // selection: undecided candidates after the last batch
     bool small_sel = false, pool_done = false, sel_done = false;
     unsigned long long key_mask = ~0ull;
@@ -622,7 +622,6 @@ void Lockstep::step() {
         E.ensure_cands(J.ncand);
         E.ensure_pools(E.pool_need(1, J.ncand, J.cls), E.pool_need(2, J.ncand, J.cls), E.pool_need(3, J.ncand, J.cls),
                        E.pool_need(4, J.ncand, J.cls));
-        J.pool_pass = 0;
         J.pool_done = false;
         J.nover = J.nbig = 0;
     });
