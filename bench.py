@@ -28,15 +28,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCES = ("qm_geom.h", "qm_kernels.h", "qm_grow.h", "qm_round.h", "qm_insert.h", "qm_setup.h", "qm_lib.hip")
+
+
 def kernel_source_sha256():
-    """Digest of the HIP sources: measured traffic is only valid for the
-    kernels it was measured on."""
-    import glob
+    """Digest of the sources of the single-instance kernels and their
+    launches (the batched and served forms' host code excluded): measured
+    traffic is only valid for the kernels it was measured on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1903_03406_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
-        h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
 
 
@@ -254,6 +257,76 @@ def bench_serve(args, qm):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve_stepped(args, qm):
+    """Served workload on the stepped server (continuous batching): the
+    resident jobs are one lockstep batch; the loop submits the jobs that have
+    arrived, runs one step (one round of every resident job, each phase one
+    launch over all of them) and collects finished jobs.  Inputs prepared
+    before timing, as in --serve.  Latency: arrival to completion."""
+    import numpy as np
+    import qm_inputs as qi
+    t0 = time.time()
+    pool = [qi.serve_job(i, max_points=args.serve_max_points) for i in range(args.serve_pool)]
+    npts = [len(w.xyz) - 8 for w in pool]
+    print(f"[bench] serve pool: {len(pool)} jobs, {min(npts)}..{max(npts)} points, "
+          f"built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    rng = np.random.Generator(np.random.PCG64(55))
+    per_rate = []
+    with qm.Server(budget, nworkers=0) as srv:
+        t = srv.submit(pool[0])                          # warm-up
+        while srv.step():
+            pass
+        srv.result(t)
+        for rate in rates:
+            arrive = np.cumsum(rng.exponential(1.0 / rate, size=args.serve_jobs))
+            jobs = [pool[k % len(pool)] for k in range(args.serve_jobs)]
+            lat, fails, steiner, steps, resident_sum = [], 0, 0, 0, 0
+            pending = {}
+            nxt = 0
+            start = time.perf_counter()
+            while nxt < len(jobs) or pending:
+                now = time.perf_counter() - start
+                while nxt < len(jobs) and arrive[nxt] <= now:
+                    tk = srv.submit(jobs[nxt])
+                    if tk is None:                     # no room: completions first
+                        break
+                    pending[tk] = arrive[nxt]
+                    nxt += 1
+                if not pending:
+                    time.sleep(0.0005)
+                    continue
+                resident_sum += srv.step()
+                steps += 1
+                for tk in list(pending):
+                    got = srv.poll(tk, wait_ms=0)
+                    if got is None:
+                        continue
+                    res, code = got[0], got[1]
+                    lat.append(time.perf_counter() - start - pending.pop(tk))
+                    if res is None or code not in (0, -4):
+                        fails += 1
+                    else:
+                        steiner += res.steiner
+            span = time.perf_counter() - start
+            per_rate.append({"rate_jobs_per_s": rate, "jobs": len(jobs), "failed": fails,
+                             "jobs_per_s": len(jobs) / span, "steiner_per_s": steiner / span,
+                             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                             "steps": steps, "mean_resident": resident_sum / max(steps, 1)})
+            print(f"[bench] stepped, rate {rate:g}/s: {per_rate[-1]}", file=sys.stderr, flush=True)
+    best = max(per_rate, key=lambda r: r["jobs_per_s"])
+    out = {
+        "metric": "served jobs/sec, stepped server (continuous batching, Poisson arrivals)",
+        "value": best["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "higher_is_better": True,
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"served_pool{len(pool)}_max{args.serve_max_points}", "form": "stepped",
+                   "budget_gib": args.serve_budget_gib, "points": [int(min(npts)), int(max(npts))]},
+        "rates": per_rate,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve_pipelined(args, qm):
     """Served workload with each job's input preparation in the latency: a
     job arrives as a generator index; its CDT is built on the host, then it
@@ -359,6 +432,8 @@ def main():
     ap.add_argument("--pipelined", action="store_true",
                     help="with --serve: jobs arrive unprepared; serial against pipelined input preparation")
     ap.add_argument("--prep-threads", type=int, default=8, help="host threads preparing jobs (--pipelined)")
+    ap.add_argument("--stepped", action="store_true",
+                    help="with --serve: the stepped server (continuous batching in one lockstep batch)")
     ap.add_argument("--dump-rounds", default=None,
                     help="write the last step's per-round records and per-round kernel-family ms (JSON)")
     args = ap.parse_args()
@@ -374,6 +449,8 @@ def main():
     if args.serve:
         if args.pipelined:
             bench_serve_pipelined(args, qm)
+        elif args.stepped:
+            bench_serve_stepped(args, qm)
         else:
             bench_serve(args, qm)
         return

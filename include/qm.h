@@ -320,9 +320,11 @@ size_t qm_estimate_bytes(const qm_plc* plc, const qm_mesh* in, const qm_options*
 /* Create a server on the calling thread's current device with `nworkers`
    (1..64) worker threads, each owning a HIP stream (non-blocking, default
    priority) on which it runs one job at a time.  With nworkers = 0 the
-   server is stepped: admitted jobs form one lockstep batch (as
-   qm_refine_lockstep) on a stream of the server, stay resident on the
-   device between rounds and advance only through qm_server_step; their
+   server is stepped: admitted jobs form four lockstep batches (as
+   qm_refine_lockstep; a new job joins the batch with the fewest resident
+   input tets), each on a stream and a host thread of the server, stay
+   resident on the device between rounds and advance only through
+   qm_server_step; their
    options may not ask for profiling, a non-parity mode or max_kept > 0
    (such a job ends with QM_EINVAL).  `hbm_budget_bytes` bounds
    the summed estimates of admitted, unfinished jobs.  *out is freed with
@@ -350,10 +352,10 @@ int qm_server_poll(qm_server* srv, uint64_t ticket, int32_t wait_ms, qm_result**
                    double* seconds);
 
 /* Stepped server only (continuous batching): jobs admitted since the last
-   step are set up on the device and join the batch, then every resident
-   job runs one round of the paper's round loop (Section 2), each phase of
-   the round one launch over all resident jobs; returns when the round is
-   complete.  Jobs that finish (no work left, or their round guard) hand
+   step are set up on the device and join a batch, then every resident job
+   runs one round of the paper's round loop (Section 2), each phase of the
+   round one launch over all resident jobs of a batch, the batches at the
+   same time; returns when the round is complete.  Jobs that finish (no work left, or their round guard) hand
    their result to qm_server_poll.  *nresident receives the number of jobs
    still resident.  Calls take turns.  QM_EINVAL on a server with workers. */
 int qm_server_step(qm_server* srv, int32_t* nresident);

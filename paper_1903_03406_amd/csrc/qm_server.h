@@ -11,11 +11,13 @@
 // a finished job's estimate is released before its result is handed out.
 //
 // Stepped form (created with no workers): continuous batching.  The jobs
-// form one lockstep batch on the server's stream: each qm_server_step sets
-// up the jobs admitted since the last step, then runs one round of every
-// resident job, each phase of the round one launch over all of them; jobs
-// join and leave the batch at round boundaries and their meshes stay on the
-// device in between.
+// form SRV_GROUPS lockstep batches, each on a stream and a persistent host
+// thread of its own (a new job joins the batch with the fewest resident
+// input tets): each qm_server_step sets up the jobs admitted since the last
+// step, then every batch runs one round of each of its resident jobs, each
+// phase of the round one launch over all of them, the batches at the same
+// time; jobs join and leave at round boundaries and their meshes stay on
+// the device in between.
 #pragma once
 
 #include <chrono>
@@ -74,14 +76,63 @@ struct qm_server {
     int64_t admitted = 0, refused = 0, completed = 0;
     std::vector<std::thread> workers;
     bool stepped = false;                                  // no workers: qm_server_step drives the jobs
-    // stepped form: the lockstep batch of resident jobs on `step_stream`, and
-    // what the server keeps of each resident job (its estimate and times)
-    hipStream_t step_stream = nullptr;
-    std::unique_ptr<Lockstep> batch;
+    // stepped form: lockstep batches of resident jobs, each with its stream,
+    // resident input tets and step thread, and what the server keeps of each
+    // resident job (its estimate, batch and times)
+    struct Group {
+        hipStream_t st = nullptr;
+        std::unique_ptr<Lockstep> batch;
+        int64_t load = 0;
+        int code = 0;
+        std::string msg;
+    };
+    std::vector<Group> groups;
+    std::vector<std::thread> group_threads;
+    std::mutex gmu;
+    std::condition_variable gcv, gdone;
+    uint64_t gen = 0;
+    int gpending = 0;
+    bool gstop = false;
     std::unordered_map<uint64_t, std::unique_ptr<SrvJob>> in_batch;
     std::unordered_map<uint64_t, srv_clock::time_point> t_added;
+    std::unordered_map<uint64_t, int> group_of;
     std::mutex step_mu;                                    // steps take turns
+    int live_jobs() const {
+        int n = 0;
+        for (auto& g : groups) n += g.batch ? g.batch->live() : 0;
+        return n;
+    }
 };
+
+namespace {
+constexpr int SRV_GROUPS = 4;      // lockstep batches of the stepped form
+
+// a step thread: runs its batch's round whenever the step counter moves on
+void srv_group_run(qm_server* S, int g) {
+    (void)hipSetDevice(S->dev);
+    uint64_t seen = 0;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(S->gmu);
+            S->gcv.wait(lk, [&] { return S->gstop || S->gen != seen; });
+            if (S->gstop) return;
+            seen = S->gen;
+        }
+        auto& G = S->groups[g];
+        try {
+            if (G.batch->live() > 0) G.batch->step();
+        } catch (const QmError& e) {
+            G.code = e.code;
+            G.msg = e.what();
+        } catch (const std::exception& e) {
+            G.code = QM_EINTERNAL;
+            G.msg = e.what();
+        }
+        std::lock_guard<std::mutex> lk(S->gmu);
+        if (--S->gpending == 0) S->gdone.notify_all();
+    }
+}
+}  // namespace
 
 namespace {
 
@@ -155,11 +206,17 @@ int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out)
     S->stepped = nworkers == 0;
     try {
         if (S->stepped) {
-            if (hipStreamCreateWithFlags(&S->step_stream, hipStreamNonBlocking) != hipSuccess) {
-                g_err = "no HIP stream for the stepped server";
-                return QM_EDEVICE;
+            S->groups.resize(SRV_GROUPS);
+            for (auto& G : S->groups) {
+                if (hipStreamCreateWithFlags(&G.st, hipStreamNonBlocking) != hipSuccess) {
+                    for (auto& H : S->groups)
+                        if (H.st) (void)hipStreamDestroy(H.st);
+                    g_err = "no HIP stream for the stepped server";
+                    return QM_EDEVICE;
+                }
+                G.batch = std::make_unique<Lockstep>(G.st);
             }
-            S->batch = std::make_unique<Lockstep>(S->step_stream);
+            for (int g = 0; g < SRV_GROUPS; ++g) S->group_threads.emplace_back(srv_group_run, S.get(), g);
         }
         for (int i = 0; i < nworkers; ++i) S->workers.emplace_back(srv_worker, S.get());
     } catch (const std::exception& e) {
@@ -169,6 +226,16 @@ int qm_server_create(size_t hbm_budget_bytes, int32_t nworkers, qm_server** out)
         }
         S->cv_work.notify_all();
         for (auto& t : S->workers) t.join();
+        {
+            std::lock_guard<std::mutex> lk(S->gmu);
+            S->gstop = true;
+        }
+        S->gcv.notify_all();
+        for (auto& t : S->group_threads) t.join();
+        for (auto& G : S->groups) {
+            G.batch.reset();
+            if (G.st) (void)hipStreamDestroy(G.st);
+        }
         g_err = e.what();
         return QM_ENOMEM;
     }
@@ -265,15 +332,41 @@ int qm_server_step(qm_server* S, int32_t* nresident) {
         }
         for (auto& J : fresh) {
             const uint64_t t = J->ticket;
+            int g = 0;
+            for (int k = 1; k < (int)S->groups.size(); ++k)
+                if (S->groups[k].load < S->groups[g].load) g = k;
             S->t_added[t] = srv_clock::now();
-            S->batch->add(&J->plc, &J->mesh, &J->opt, t);
+            S->groups[g].load += J->mesh.nt;
+            S->group_of[t] = g;
+            S->groups[g].batch->add(&J->plc, &J->mesh, &J->opt, t);
             S->in_batch[t] = std::move(J);
         }
-        // one round of every resident job, each phase one launch over all
-        if (S->batch->live() > 0) S->batch->step();
+        // one round of every resident job: the batches at the same time, each
+        // phase one launch over a batch's jobs
+        {
+            std::unique_lock<std::mutex> lk(S->gmu);
+            S->gpending = (int)S->groups.size();
+            ++S->gen;
+            S->gcv.notify_all();
+            S->gdone.wait(lk, [&] { return S->gpending == 0; });
+        }
+        for (auto& G : S->groups)
+            if (G.code) {
+                const int c = G.code;
+                G.code = 0;
+                throw QmError(c, G.msg);
+            }
         const auto now = srv_clock::now();
-        for (auto& d : S->batch->take_done()) {
+        std::vector<LsDone> finished;
+        for (auto& G : S->groups)
+            for (auto& d : G.batch->take_done()) finished.push_back(std::move(d));
+        for (auto& d : finished) {
             auto it = S->in_batch.find(d.tag);
+            auto go = S->group_of.find(d.tag);
+            if (go != S->group_of.end()) {
+                if (it != S->in_batch.end()) S->groups[go->second].load -= it->second->mesh.nt;
+                S->group_of.erase(go);
+            }
             SrvDone out;
             out.res = d.res;
             out.code = d.code;
@@ -292,10 +385,10 @@ int qm_server_step(qm_server* S, int32_t* nresident) {
         }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            S->running = S->batch->live();
+            S->running = S->live_jobs();
         }
         S->cv_done.notify_all();
-        if (nresident) *nresident = (int32_t)S->batch->live();
+        if (nresident) *nresident = (int32_t)S->live_jobs();
         return QM_OK;
     } catch (const QmError& e) {
         g_err = e.what();
@@ -330,11 +423,19 @@ void qm_server_destroy(qm_server* S) {
     }
     S->cv_work.notify_all();
     for (auto& t : S->workers) t.join();
-    if (S->batch) {                          // stepped form: resident jobs end with the batch
+    if (S->stepped) {                        // stepped form: resident jobs end with their batches
+        {
+            std::lock_guard<std::mutex> lk(S->gmu);
+            S->gstop = true;
+        }
+        S->gcv.notify_all();
+        for (auto& t : S->group_threads) t.join();
         (void)hipSetDevice(S->dev);
-        S->batch.reset();
+        for (auto& G : S->groups) {
+            G.batch.reset();
+            if (G.st) (void)hipStreamDestroy(G.st);
+        }
     }
-    if (S->step_stream) (void)hipStreamDestroy(S->step_stream);
     for (auto& kv : S->done) qm_result_free(kv.second.res);
     delete S;
 }
