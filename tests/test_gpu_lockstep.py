@@ -167,3 +167,17 @@ def test_lockstep_repeated_small_batches(mix):
         assert codes == [0] * len(small)
         for w, g, s in zip(small, got, alone):
             assert same(g, s), (rep, w.name)
+
+
+def test_lockstep_many_parts_and_chunked_launches():
+    """300 small instances in one group: launches of more than 64 parts
+    (the second ballot of the part search) and of more than 256 (split into
+    several launches per phase); and the same in two groups."""
+    ws = [qi.uniform_cube(12 + (7 * i) % 40, seed=1000 + i, B=2.0, spheres=((0.3,) if i % 3 == 0 else ()))
+          for i in range(300)]
+    alone = [qm.refine_workload(w) for w in ws]
+    for groups in (1, 2):
+        got = qm.refine_lockstep(ws, groups=groups)
+        bad = [w.name for w, g, s in zip(ws, got, alone) if not same(g, s)]
+        print(f"[lockstep] 300 instances, {groups} group(s): {len(bad)} differ", flush=True)
+        assert not bad, bad[:5]
