@@ -83,7 +83,7 @@ typedef struct qm_mesh {
                                 claim sets and full validation, so the output is a CDT of the
                                 same kind, but which points win depends on timing: the result
                                 is not reproducible and not the oracle's. */
-#define QM_SUBPHASE_ROUNDS 1024u   /* a non-parity mode: each round runs three sub-phases in the
+#define QM_SUBPHASE_ROUNDS 1024u   /* the other class-order reading: each round runs three sub-phases in the
                                      paper's order (Section 2: subsegments, then subfaces, then bad
                                      tets), each the usual round restricted to its class (that
                                      class classified alone, so a later class no longer waits for
@@ -91,8 +91,9 @@ typedef struct qm_mesh {
                                      is skipped and not counted as a round, and the refinement
                                      ends after three empty sub-phases in a row.  Encroachment of
                                      constraints by a later class's points is rejected and queued
-                                     as usual.  Reproducible, a CDT of the same kind, but not the
-                                     oracle's result (the insertion order differs) */
+                                     as usual.  Reproducible, a CDT of the same kind; it equals
+                                     the oracle refined with the same reading, not the paper-order
+                                     refinement (the insertion order differs) */
 #define QM_OUTPUT_DEVICE 512u   /* the result's output arrays stay on the device (same device):
                                    qm_result_view returns device pointers, valid until
                                    qm_result_free; records and statistics stay on the host */

@@ -84,12 +84,16 @@ class OracleResult:
 
 
 def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
-           round_checks=False, dump_round=None, key_mask=None) -> OracleResult:
+           round_checks=False, dump_round=None, key_mask=None, subphases=False) -> OracleResult:
     """Run the oracle on a workload (qm_inputs.Workload or compatible).
     round_checks: run check() on the mesh at the end of every round.
     dump_round: record that round's candidates (result.dump, see dump()).
-    key_mask: AND every priority key with this mask (forces equal keys)."""
+    key_mask: AND every priority key with this mask (forces equal keys).
+    subphases: the sub-phase reading of the class order (every round takes
+    the three classes in turn)."""
     lib = _load()
+    lib.qmo_set_subphases.argtypes = [ctypes.c_int]
+    lib.qmo_set_subphases(1 if subphases else 0)
     lib.qmo_set_dump_round.argtypes = [ctypes.c_int]
     lib.qmo_set_dump_round(-1 if dump_round is None else int(dump_round))
     lib.qmo_set_key_mask.argtypes = [ctypes.c_uint64]
@@ -107,6 +111,8 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
                         float(w.B if B is None else B), float(hmin_factor), int(max_rounds),
                         int(max_kept), ctypes.byref(res))
     if rc != 0:
+        lib.qmo_set_key_mask((1 << 64) - 1)
+        lib.qmo_set_subphases(0)
         raise ValueError(f"oracle rejected the input (code {rc})")
     cnt = np.zeros(6, dtype=np.int32)
     lib.qmo_result_counts(res, _ptr(cnt))
@@ -132,6 +138,7 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
         lib.qmo_result_lastc(res, _ptr(out.last_cands))
     lib.qmo_result_free(res)
     lib.qmo_set_key_mask((1 << 64) - 1)
+    lib.qmo_set_subphases(0)
     if dump_round is not None:
         out.dump = _take_dump(lib)
         lib.qmo_set_dump_round(-1)

@@ -709,8 +709,12 @@ static int sf_encroached(const Mesh* M, const int* g, int flags) {
     return 0;
 }
 
-static int classify(Mesh* M, CandList* L) {
+/* `only` = CLS_NONE: the round class is the first class with candidates
+   (Section 2, "in this order"); otherwise that class alone is classified
+   (the sub-phase reading, qmo_set_subphases). */
+static int classify(Mesh* M, CandList* L, int only) {
     L->n = 0;
+    if (only == CLS_NONE || only == CLS_SS)
     for (size_t i = 0; i < M->ss.cap; ++i) {
         HE* e = &M->ss.e[i];
         if (e->st != 1 || (e->v[1] & FL_EXEMPT)) continue;
@@ -718,6 +722,7 @@ static int classify(Mesh* M, CandList* L) {
         Cand* c = cl_push(L); c->cls = CLS_SS; c->ntup = 2; c->tup[0] = e->k[0]; c->tup[1] = e->k[1];
     }
     if (L->n) return CLS_SS;
+    if (only == CLS_NONE || only == CLS_SF)
     for (size_t i = 0; i < M->sf.cap; ++i) {
         HE* e = &M->sf.e[i];
         if (e->st != 1 || (e->v[1] & FL_EXEMPT)) continue;
@@ -725,6 +730,7 @@ static int classify(Mesh* M, CandList* L) {
         Cand* c = cl_push(L); c->cls = CLS_SF; c->ntup = 3; memcpy(c->tup, e->k, 3 * sizeof(int));
     }
     if (L->n) return CLS_SF;
+    if (only == CLS_NONE || only == CLS_TET)
     for (int t = 0; t < M->nt; ++t) {
         const OTet* T = &M->T[t];
         if (!T->alive || T->exempt) continue;
@@ -785,6 +791,14 @@ static int insert_point(Mesh* M, Cand* c, int pid) {
 #define QMO_NCHECK 9
 int qmo_check(int nv, const double* xyz, int nt, const int* tets, int nsf, const int* sf,
               int nss, const int* ss, const int* ss_seg, double B, int* out, double* vol);
+
+/* The sub-phase reading of Section 2's "in this order": every round takes
+   the three classes in turn (subsegments, subfaces, bad tets), each as a
+   round of its own with that class classified alone; a class without
+   candidates is passed over without counting a round, and the refinement
+   ends when the three classes in a row have none. */
+static int g_subphases = 0;
+void qmo_set_subphases(int on) { g_subphases = on; }
 
 /* When set, every round ends with qmo_check on the current mesh, and its
    counts are kept per round (qmo_result_round_checks). */
@@ -959,9 +973,18 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
     clock_gettime(CLOCK_MONOTONIC, &t0);
     int round = 0;
     R->status = 0;
+    int sub = CLS_SS, empty_turns = 0;
     for (;;) {
         if (round >= max_rounds) { R->status = 1; break; }
-        int cls = classify(M, &L);
+        int cls = classify(M, &L, g_subphases ? sub : CLS_NONE);
+        if (g_subphases) {
+            sub = (sub + 1) % 3;
+            if (cls == CLS_NONE) {
+                if (++empty_turns == 3) break;
+                continue;
+            }
+            empty_turns = 0;
+        }
         if (cls == CLS_NONE) break;
         for (int i = 0; i < L.n; ++i) {
             Cand* c = &L.c[i];

@@ -31,7 +31,7 @@ QM_PROFILE_GROW = 8   # time only the small-tile grow launches (family grow_vali
 QM_VERBOSE = 4
 QM_EARLY_STOP = 256       # non-parity mode: early-stop blasting (timing-dependent result)
 QM_OUTPUT_DEVICE = 512    # the result's arrays stay on the device
-QM_SUBPHASE_ROUNDS = 1024  # non-parity mode: three sub-phase rounds (SS, SF, TET in turn)
+QM_SUBPHASE_ROUNDS = 1024  # other class-order reading: three sub-phase rounds (SS, SF, TET in turn)
 QM_TEST_ERROR_WORD = 16   # tests only: the call ends with QM_EINTERNAL through its own error word
 QM_TEST_TIER1 = 32        # tests only: every region grown with the medium tiles (or larger)
 QM_TEST_TIER2 = 64        # tests only: every region grown with the global-memory tiles

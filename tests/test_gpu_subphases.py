@@ -1,7 +1,9 @@
-"""Three-sub-phase rounds (QM_SUBPHASE_ROUNDS, not a parity mode): each
+"""Three-sub-phase rounds (QM_SUBPHASE_ROUNDS, the other reading of the class order): each
 round runs a subsegment, a subface and a bad-tet sub-phase in turn, so the
-insertion order differs from the oracle's and the output is not compared
-with it bit for bit.  It must be reproducible, converge, and be a CDT
+insertion order differs from the paper-order refinement.  It equals, bit
+for bit, the oracle refined with the same reading of the class order
+(``oracle.refine(..., subphases=True)``) on inputs the oracle finishes in
+seconds; at larger sizes it must be reproducible, converge, and be a CDT
 conforming to the PLC (every non-subface face locally Delaunay, every
 subface a face, every subsegment an edge, segment chains intact, facet areas
 kept) and a valid tetrahedralisation of the cube (orientation, face use,
@@ -52,3 +54,24 @@ def test_subphase_output_is_a_conforming_cdt(make):
     g2 = qm.refine_workload(w, subphases=True)
     assert g2.rounds == g.rounds and np.array_equal(g2.xyz.view(np.uint64), g.xyz.view(np.uint64))
     assert np.array_equal(canon(g2.tets), canon(g.tets))
+
+
+def canon_tri(tri, fid):
+    a = np.concatenate([np.sort(np.asarray(tri), axis=1), np.asarray(fid).reshape(-1, 1)], axis=1)
+    return a[np.lexsort(a.T[::-1])]
+
+
+@pytest.mark.parametrize("make", [lambda: qi.uniform_cube(600, seed=5, B=1.6, spheres=(0.25,)),
+                                  lambda: qi.uniform_cube(900, seed=4, B=1.5, spheres=(0.3,)), lambda: qi.config(1)])
+def test_subphase_mode_matches_the_oracle_reading(make):
+    w = make()
+    g = qm.refine_workload(w, subphases=True)
+    o = oracle.refine(w, subphases=True)
+    print(f"[subphases] {w.name}: rounds {g.rounds} (oracle {o.rounds}), steiner {g.steiner} "
+          f"(oracle {len(o.xyz) - len(w.xyz)})", flush=True)
+    assert g.status == o.status == 0
+    assert g.rounds == o.rounds and np.array_equal(g.rstats, o.rstats)
+    assert np.array_equal(g.xyz.view(np.uint64), o.xyz.view(np.uint64))
+    assert np.array_equal(canon(g.tets), canon(o.tets))
+    assert np.array_equal(canon_tri(g.sf, g.sf_facet), canon_tri(o.sf, o.sf_facet))
+    assert np.array_equal(canon_tri(g.ss, g.ss_seg), canon_tri(o.ss, o.ss_seg))

@@ -527,3 +527,28 @@ def test_equal_keys_are_ordered_by_tuple(n, seed, B, spheres):
     keys = [c["key"] for c in d]
     assert all(k & ~mask == 0 for k in keys) and len(set(keys)) < len(keys)
     assert [(-c["key"], c["tup"]) for c in d] == sorted((-c["key"], c["tup"]) for c in d)
+
+
+def test_subphase_reading_keeps_a_cdt_after_every_round():
+    """The sub-phase reading of the class order (every round takes the
+    three classes in turn) on surface inputs: after every round the mesh is
+    a conforming CDT and a valid tetrahedralisation (the independently
+    pinned mesh checks), the refinement converges, and its first round is
+    the paper-order first round (both begin with the encroached
+    subsegments)."""
+    for w in (qi.uniform_cube(250, seed=8, B=1.5, spheres=(0.3,)), qi.uniform_cube(400, seed=3, B=2.0,
+                                                                                  spheres=(0.2, 0.35))):
+        a = oracle.refine(w, subphases=True, round_checks=True)
+        b = oracle.refine(w, max_rounds=1)
+        assert a.status == 0 and a.rounds > 0
+        rc = a.round_checks
+        for k, name in enumerate(oracle.CHECK_FIELDS):
+            if name == "euler":
+                assert (rc[:, k] == 1).all(), name
+            elif name != "bad_tets":
+                assert (rc[:, k] == 0).all(), (w.name, name)
+        assert np.array_equal(a.rstats[0], b.rstats[0])
+        # the classes of consecutive rounds follow the cyclic order SS, SF, TET
+        # (a class without candidates is passed over)
+        cls = a.rstats[:, 0]
+        assert cls[0] == 0 and set(np.unique(cls)) <= {0, 1, 2}
