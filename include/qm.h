@@ -257,6 +257,43 @@ int qm_result_round_profile(const qm_result* r, double* buf, int32_t cap);
 
 void qm_result_free(qm_result* r);
 
+/* ---- Checkpoint and resume ----------------------------------------------
+   The round rule (paper, Section 2) carries, from one round to the next,
+   the mesh and a few flags per element: a subsegment or subface queued by a
+   rejected point (it is split in a later round although no vertex encroaches
+   it) or exempted (its point was filtered away for good), and a bad tet
+   exempted the same way.  h_min is fixed by the first input mesh's shortest
+   edge.  A refinement stopped by max_rounds therefore resumes exactly from
+   its output mesh and this state. */
+typedef struct qm_state {
+    double hmin2;              /* h_min^2 of the refinement (from its first call) */
+    int32_t rounds;            /* rounds run so far, over every call */
+    int32_t next_class;        /* QM_SUBPHASE_ROUNDS: the sub-phase run next (0 SS, 1 SF,
+                                  2 TET); 0 otherwise */
+    int32_t nt, nsf, nss;      /* lengths of the flag arrays: the mesh's counts */
+    const uint8_t* tet_flags;  /* [nt] bit0 exempt; aligned with the mesh's tets */
+    const uint8_t* sf_flags;   /* [nsf] bit0 queued, bit1 exempt; aligned with its subfaces */
+    const uint8_t* ss_flags;   /* [nss] bit0 queued, bit1 exempt; aligned with its subsegments */
+} qm_state;
+
+/* The state after a refinement, aligned with qm_result_view's mesh arrays
+   (host arrays, also for QM_OUTPUT_DEVICE results; valid until
+   qm_result_free).  QM_EINVAL for a null argument. */
+int qm_result_state(const qm_result* r, qm_state* out);
+
+/* Continue a refinement: `in` is the mesh a call returned and `st` its
+   state (qm_result_state; its arrays are host memory, the mesh's follow
+   QM_INPUT_DEVICE as in qm_refine).  opt->hmin_factor is not used (st->hmin2
+   is); opt->max_rounds bounds this call's rounds.  In the deterministic modes
+   (the paper-order rounds and QM_SUBPHASE_ROUNDS) the output mesh and the
+   round records of the calls together equal one uninterrupted qm_refine with
+   the same options; with QM_EARLY_STOP the result is a valid refinement of
+   the same kind.  QM_EINVAL when the state's counts differ from the mesh's,
+   a flag has bits outside those listed, next_class is out of range or hmin2
+   is negative or not finite; otherwise as qm_refine. */
+int qm_refine_resume(const qm_plc* plc, const qm_mesh* in, const qm_state* st, const qm_options* opt,
+                     void* hip_stream, qm_result** out);
+
 /* ---- Without allocation ------------------------------------------------ */
 
 /* Bytes of the static device scratch array used by qm_refine_noalloc (per

@@ -72,6 +72,12 @@ class _Mesh(ctypes.Structure):
                 ("ss_seg", ctypes.c_void_p)]
 
 
+class _State(ctypes.Structure):
+    _fields_ = [("hmin2", ctypes.c_double), ("rounds", ctypes.c_int32), ("next_class", ctypes.c_int32),
+                ("nt", ctypes.c_int32), ("nsf", ctypes.c_int32), ("nss", ctypes.c_int32),
+                ("tet_flags", ctypes.c_void_p), ("sf_flags", ctypes.c_void_p), ("ss_flags", ctypes.c_void_p)]
+
+
 class _Opts(ctypes.Structure):
     _fields_ = [("B", ctypes.c_double), ("hmin_factor", ctypes.c_double),
                 ("max_rounds", ctypes.c_int32), ("max_kept", ctypes.c_int32), ("flags", ctypes.c_uint32)]
@@ -117,7 +123,7 @@ def _load():
     return _lib
 
 
-EXPORTS = ("qm_refine", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_refine_lockstep", "qm_lockstep_autotune", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
+EXPORTS = ("qm_refine", "qm_refine_resume", "qm_result_state", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_refine_lockstep", "qm_lockstep_autotune", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
            "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_step", "qm_server_poll",
            "qm_server_info",
@@ -151,10 +157,25 @@ class RefineResult:
     last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
     deferred: int = 0               # QM_EARLY_STOP: evaluations stopped early
     device_bytes_peak: int = 0      # most device memory the call held at once
+    state: "RefineState" = None     # checkpoint: flags and h_min to resume from (qm_result_state)
 
     @property
     def steiner(self) -> int:
         return int(sum(self.inserted))
+
+
+@dataclass
+class RefineState:
+    """The refinement state beyond the mesh (qm_state): per output tet an
+    exempt bit, per subface and subsegment queued (bit0) and exempt (bit1)
+    bits, aligned with the result's arrays; h_min^2 of the first call; rounds
+    run over every call; the next sub-phase (three-sub-phase mode)."""
+    hmin2: float
+    rounds: int
+    next_class: int
+    tet_flags: np.ndarray
+    sf_flags: np.ndarray
+    ss_flags: np.ndarray
 
 
 def _prof_flag(profile):
@@ -171,9 +192,11 @@ def _arr(a, dtype):
 
 def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None, hmin_factor=0.5,
            max_rounds=100000, max_kept=0, stream=None, profile=False, verbose=False,
-           extra_flags=0, early_stop=False, subphases=False) -> RefineResult:
+           extra_flags=0, early_stop=False, subphases=False, state=None) -> RefineResult:
     """Refine a CDT.  Arrays are numpy (host) or torch CUDA tensors (device);
-    ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle."""
+    ``stream`` is a torch.cuda.Stream or a raw hipStream_t handle.
+    ``state``: a RefineState to resume from (qm_refine_resume); the mesh is
+    then the output the state belongs to."""
     lib = _load()
     dev = False
     keep = []
@@ -214,7 +237,18 @@ def refine(xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, B, *, seg=None
     else:
         hs = int(stream)
     res = ctypes.c_void_p()
-    rc = lib.qm_refine(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), hs, ctypes.byref(res))
+    if state is None:
+        rc = lib.qm_refine(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), hs, ctypes.byref(res))
+    else:
+        fl = [_arr(a, np.uint8) for a in (state.tet_flags, state.sf_flags, state.ss_flags)]
+        keep.extend(fl)
+        cst = _State(float(state.hmin2), int(state.rounds), int(state.next_class), len(fl[0]), len(fl[1]),
+                     len(fl[2]), fl[0].ctypes.data, fl[1].ctypes.data, fl[2].ctypes.data)
+        lib.qm_refine_resume.restype = ctypes.c_int
+        lib.qm_refine_resume.argtypes = [ctypes.POINTER(_Plc), ctypes.POINTER(_Mesh), ctypes.POINTER(_State),
+                                         ctypes.POINTER(_Opts), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+        rc = lib.qm_refine_resume(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(cst), ctypes.byref(opts),
+                                  hs, ctypes.byref(res))
     if rc not in (0, -4):
         raise QmError(rc, lib.qm_last_error().decode())
     return _take_result(lib, res, profile)
@@ -249,6 +283,16 @@ def _take_result(lib, res, profile) -> RefineResult:
             round_ms = np.zeros((max(npr, 0), len(PROF_FAMILIES)), dtype=np.float64)
             if npr:
                 lib.qm_result_round_profile(res, round_ms.ctypes.data, npr)
+        cs = _State()
+        lib.qm_result_state.restype = ctypes.c_int
+        lib.qm_result_state.argtypes = [P_, ctypes.POINTER(_State)]
+        lib.qm_result_state(res, ctypes.byref(cs))
+
+        def flags(p, n):
+            return (np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint8)), shape=(n,)).copy()
+                    if n else np.zeros(0, np.uint8))
+        state = RefineState(float(cs.hmin2), int(cs.rounds), int(cs.next_class), flags(cs.tet_flags, cs.nt),
+                            flags(cs.sf_flags, cs.nsf), flags(cs.ss_flags, cs.nss))
         nr = lib.qm_result_rounds(res, None, 0)
         rs = np.zeros((max(nr, 0), ROUND_FIELDS), dtype=np.int32)
         if nr:
@@ -269,7 +313,7 @@ def _take_result(lib, res, profile) -> RefineResult:
                               "tiers": [dict(zip(TIER_FIELDS, [int(x) for x in st.prof_tier[k]]))
                                         for k in range(3)],
                               "round_ms": round_ms}
-                             if profile else None), last, int(st.deferred), int(st.device_bytes_peak))
+                             if profile else None), last, int(st.deferred), int(st.device_bytes_peak), state)
     finally:
         lib.qm_result_free(res)
 
@@ -466,6 +510,17 @@ def refine_workload(w, **kw) -> RefineResult:
     (xyz, tets, sf, sf_facet, ss, ss_seg, ftri, ftri_facet, seg, B)."""
     return refine(w.xyz, w.tets, w.sf, w.sf_facet, w.ss, w.ss_seg, w.ftri, w.ftri_facet,
                   kw.pop("B", w.B), seg=w.seg, **kw)
+
+
+def resume(w, r, **kw) -> RefineResult:
+    """Continue the refinement of workload ``w`` from result ``r`` (a run cut
+    by max_rounds): its output mesh and state, ``w``'s PLC and bound.  In the
+    deterministic modes the rounds of ``r`` and of this call together equal
+    one uninterrupted refinement."""
+    if r.state is None:
+        raise ValueError("the result carries no refinement state")
+    return refine(r.xyz, r.tets, r.sf, r.sf_facet, r.ss, r.ss_seg, w.ftri, w.ftri_facet,
+                  kw.pop("B", w.B), seg=w.seg, state=r.state, **kw)
 
 
 def test_geometry(op, tuples, param=0.0):

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <stdexcept>
@@ -161,6 +162,11 @@ struct qm_result {
     std::vector<int32_t> last;     // last round's candidates, 9 per candidate
     std::vector<double> round_ms;  // QM_PROFILE: QM_PROF_FAMILIES device ms per round
     qm_stats stats;
+    // refinement state of the output (qm_result_state), host arrays aligned
+    // with the output mesh
+    std::vector<uint8_t> st_tfl, st_sfl, st_ssl;
+    double st_hmin2 = 0.0;
+    int32_t st_rounds = 0, st_next = 0;
 };
 
 namespace qm {
@@ -710,7 +716,7 @@ using namespace qm;
 // projection axes, the h_min bound.  Input errors become QmError.  `e0`
 // (optional) is recorded when the setup kernels start.
 static void setup_mesh(Engine& E, const qm_plc* plc, const qm_mesh* in, const qm_options* opt, Arena* ar,
-                       hipEvent_t e0) {
+                       hipEvent_t e0, const qm_state* st = nullptr) {
     const hipStream_t s = E.s;
     const bool noalloc = ar != nullptr;
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
@@ -725,7 +731,7 @@ static void setup_mesh(Engine& E, const qm_plc* plc, const qm_mesh* in, const qm
     };
     // staged copies (unused with device inputs), freed on the stream when setup ends
     struct Staged {
-        DBuf<char> b[8];
+        DBuf<char> b[11];
         hipStream_t s;
         ~Staged() { for (auto& x : b) x.release(s); }
     } stg;
@@ -741,6 +747,16 @@ static void setup_mesh(Engine& E, const qm_plc* plc, const qm_mesh* in, const qm
     const int* d_ssg = (const int*)stage(in->ss_seg, sizeof(int) * (size_t)nss, b_ssg);
     const int* d_ft = (const int*)stage(plc->ftri, sizeof(int) * 3 * (size_t)nftri, b_ft);
     const int* d_ftf = (const int*)stage(plc->ftri_facet, sizeof(int) * (size_t)nftri, b_ftf);
+    // a resumed refinement's flags (host arrays whatever the mesh's kind)
+    auto stage_h = [&](const uint8_t* p, size_t bytes, DBuf<char>& buf) -> const unsigned char* {
+        if (!st || bytes == 0) return nullptr;
+        buf.ensure(bytes, s, false);
+        HIPCK(hipMemcpyAsync(buf.p, p, bytes, hipMemcpyHostToDevice, s));
+        return (const unsigned char*)buf.p;
+    };
+    const unsigned char* d_tfl = stage_h(st ? st->tet_flags : nullptr, (size_t)nt, stg.b[8]);
+    const unsigned char* d_sfl = stage_h(st ? st->sf_flags : nullptr, (size_t)nsf, stg.b[9]);
+    const unsigned char* d_ssl = stage_h(st ? st->ss_flags : nullptr, (size_t)nss, stg.b[10]);
     E.ctr.ensure(64, s, false, 0);
     // number of facets = 1 + max facet id over PLC triangles and subfaces
     if (nftri) k_count_ids<<<nblk(nftri), 256, 0, s>>>(nftri, d_ftf, E.ctr.p + 49);
@@ -758,7 +774,7 @@ static void setup_mesh(Engine& E, const qm_plc* plc, const qm_mesh* in, const qm
     if (e0) HIPCK(hipEventRecord(e0, s));
     // ---- device setup
     k_setup_verts<<<nblk(nv), 256, 0, s>>>(nv, d_xyz, E.X.p, err);
-    k_setup_tets<<<nblk(nt), 256, 0, s>>>(nt, nv, d_tet, E.M, err);
+    k_setup_tets<<<nblk(nt), 256, 0, s>>>(nt, nv, d_tet, d_tfl, E.M, err);
     {
         DBuf<unsigned long long> k0, k1;
         DBuf<int> v0, v1;
@@ -769,11 +785,12 @@ static void setup_mesh(Engine& E, const qm_plc* plc, const qm_mesh* in, const qm
         k_face_keys<<<nblk(n4), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
         E.sort_asc(k0.p, k1.p, v0.p, v1.p, (int)n4);
         k_face_match<<<nblk(n4), 256, 0, s>>>((int)n4, k1.p, v1.p, E.TA.p, err);
-        if (nsf) k_mark_subfaces<<<nblk(nsf), 256, 0, s>>>(nsf, nv, nfacet, d_sf, d_sff, k1.p, v1.p, (int)n4, E.TF.p,
-                                                            E.TI.p, err);
+        if (nsf) k_mark_subfaces<<<nblk(nsf), 256, 0, s>>>(nsf, nv, nfacet, d_sf, d_sff, d_sfl, k1.p, v1.p, (int)n4,
+                                                            E.TF.p, E.TI.p, err);
         k_edge_keys<<<nblk(n6), 256, 0, s>>>(nt, E.TV.p, k0.p, v0.p);
         E.sort_asc(k0.p, k1.p, v0.p, v1.p, (int)n6);
-        if (nss) k_mark_subsegs<<<nblk(nss), 256, 0, s>>>(nss, nv, d_ss, d_ssg, k1.p, v1.p, (int)n6, E.M, err);
+        if (nss) k_mark_subsegs<<<nblk(nss), 256, 0, s>>>(nss, nv, d_ss, d_ssg, d_ssl, k1.p, v1.p, (int)n6, E.M,
+                                                           err);
         DBuf<int> first;
         first.ar = ar;
         first.acct = &E.acct;
@@ -795,7 +812,7 @@ static void setup_mesh(Engine& E, const qm_plc* plc, const qm_mesh* in, const qm
         unsigned long long bits = read1(dmin, s);
         double l2;
         std::memcpy(&l2, &bits, sizeof l2);
-        E.M.hmin2 = (opt->hmin_factor * opt->hmin_factor) * l2;
+        E.M.hmin2 = st ? st->hmin2 : (opt->hmin_factor * opt->hmin_factor) * l2;   // fixed by the first call
         E.M.B2 = opt->B * opt->B;
     }
 }
@@ -845,6 +862,23 @@ static int emit_output(Engine& E, qm_result* R, const qm_options* opt, Arena* ar
     E.exscan(ff.p, fs.p, 4 * ntot);
     int a = read1(ts.p + ntot - 1, s) + read1(tf.p + ntot - 1, s);
     int b = read1(fs.p + 4 * ntot - 1, s) + read1(ff.p + 4 * ntot - 1, s);
+    if (!noalloc) {            // the refinement state, aligned with the output mesh (host arrays)
+        const int nss = E.M.nss;
+        const size_t nb = (size_t)a + (size_t)b + (size_t)nss;
+        DBuf<char> ob;
+        ob.acct = &E.acct;
+        ob.ensure(std::max<size_t>(nb, 1), s, false);
+        unsigned char* o = (unsigned char*)ob.p;
+        k_out_state<<<nblk(std::max(ntot, nss)), 256, 0, s>>>(E.M, tf.p, ts.p, ff.p, fs.p, o, o + a, o + a + b);
+        std::vector<uint8_t> h(nb);
+        if (nb) HIPCK(hipMemcpyAsync(h.data(), o, nb, hipMemcpyDeviceToHost, s));
+        HIPCK(hipStreamSynchronize(s));
+        ob.release(s);
+        R->st_tfl.assign(h.begin(), h.begin() + a);
+        R->st_sfl.assign(h.begin() + a, h.begin() + a + b);
+        R->st_ssl.assign(h.begin() + a + b, h.end());
+        R->st_hmin2 = E.M.hmin2;
+    }
     if (noalloc) {
         dout->nv = E.M.nv; dout->nt = a; dout->nsf = b; dout->nss = E.M.nss;
         if (E.M.nv > dout->cap_v || a > dout->cap_t || b > dout->cap_sf || E.M.nss > dout->cap_ss)
@@ -917,7 +951,7 @@ static int emit_output(Engine& E, qm_result* R, const qm_options* opt, Arena* ar
 // *dstats; no qm_result, pinned buffer or event is created.
 static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
                       qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
-                      qm_stats* dstats = nullptr, size_t mem_cap = 0) {
+                      qm_stats* dstats = nullptr, size_t mem_cap = 0, const qm_state* rs = nullptr) {
     auto T0 = std::chrono::steady_clock::now();
     const bool noalloc = ar != nullptr;
     if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
@@ -926,6 +960,21 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
         throw QmError(QM_EINVAL, "bad counts");
     if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
+    if (rs) {                 // a resumed refinement's state must describe this mesh
+        if (rs->nt != in->nt || rs->nsf != in->nsf || rs->nss != in->nss)
+            throw QmError(QM_EINVAL, "the state's counts differ from the mesh's");
+        if ((in->nt && !rs->tet_flags) || (in->nsf && !rs->sf_flags) || (in->nss && !rs->ss_flags))
+            throw QmError(QM_EINVAL, "state flag array missing");
+        if (rs->next_class < 0 || rs->next_class > 2 || rs->rounds < 0 || !(rs->hmin2 >= 0.0) ||
+            !std::isfinite(rs->hmin2))
+            throw QmError(QM_EINVAL, "state: next_class outside 0..2, negative rounds or bad hmin2");
+        for (int i = 0; i < in->nt; ++i)
+            if (rs->tet_flags[i] > 1) throw QmError(QM_EINVAL, "state: tet flag with bits other than bit0");
+        for (int i = 0; i < in->nsf; ++i)
+            if (rs->sf_flags[i] > 3) throw QmError(QM_EINVAL, "state: subface flag with bits other than 0-1");
+        for (int i = 0; i < in->nss; ++i)
+            if (rs->ss_flags[i] > 3) throw QmError(QM_EINVAL, "state: subsegment flag with bits other than 0-1");
+    }
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
     if (noalloc) {
         if (!dev) throw QmError(QM_EINVAL, "the no-alloc entry point takes device arrays (QM_INPUT_DEVICE)");
@@ -953,7 +1002,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     if (!noalloc) {
         HIPCK(hipEventCreate(&e0)); HIPCK(hipEventCreate(&e1)); HIPCK(hipEventCreate(&e2));
     }
-    setup_mesh(E, plc, in, opt, ar, e0);
+    setup_mesh(E, plc, in, opt, ar, e0, rs);
 
     auto T1s = std::chrono::steady_clock::now();
     if (!noalloc) HIPCK(hipEventRecord(e1, s));
@@ -1008,7 +1057,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     // three-sub-phase rounds: the class is forced in turn (SS, SF, TET); a
     // sub-phase without candidates is skipped and is not a round
     const bool subphases = (opt->flags & QM_SUBPHASE_ROUNDS) != 0;
-    int sub = CLS_SS, empty_subphases = 0;
+    int sub = rs ? rs->next_class : CLS_SS, empty_subphases = 0;
     const unsigned long long key_mask = (opt->flags & QM_TEST_KEY_COLLIDE) ? 0xE000000000000000ull : ~0ull;
     E.verbose = verbose;
     auto last_note = std::chrono::steady_clock::now();
@@ -1330,6 +1379,8 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     if (noalloc) *dstats = ST;
     else {
         R->stats = ST;
+        R->st_rounds = (rs ? rs->rounds : 0) + round;
+        R->st_next = subphases ? sub : 0;
         *out = R.release();
     }
     return status == 1 ? QM_EROUNDS : QM_OK;
@@ -1340,10 +1391,10 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
 // other buffers in that many bytes (the served form passes each job's
 // admitted estimate).
 static int refine_within(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
-                         qm_result** out, size_t mem_cap) {
+                         qm_result** out, size_t mem_cap, const qm_state* rs = nullptr) {
     g_err.clear();
     try {
-        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap);
+        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap, rs);
     } catch (const QmError& e) {
         g_err = e.what();
         return e.code;
@@ -1360,6 +1411,22 @@ extern "C" {
 
 int qm_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, void* hip_stream, qm_result** out) {
     return refine_within(plc, in, opt, (hipStream_t)hip_stream, out, 0);
+}
+
+int qm_refine_resume(const qm_plc* plc, const qm_mesh* in, const qm_state* st, const qm_options* opt,
+                     void* hip_stream, qm_result** out) {
+    if (!st) { g_err = "null state"; return QM_EINVAL; }
+    return refine_within(plc, in, opt, (hipStream_t)hip_stream, out, 0, st);
+}
+
+int qm_result_state(const qm_result* r, qm_state* o) {
+    if (!r || !o) { g_err = "null argument"; return QM_EINVAL; }
+    o->hmin2 = r->st_hmin2;
+    o->rounds = r->st_rounds;
+    o->next_class = r->st_next;
+    o->nt = (int32_t)r->st_tfl.size(); o->nsf = (int32_t)r->st_sfl.size(); o->nss = (int32_t)r->st_ssl.size();
+    o->tet_flags = r->st_tfl.data(); o->sf_flags = r->st_sfl.data(); o->ss_flags = r->st_ssl.data();
+    return QM_OK;
 }
 
 }  // extern "C"

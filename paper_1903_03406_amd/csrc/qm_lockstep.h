@@ -547,6 +547,7 @@ void Lockstep::finish(LsJob& J) {
     const auto now = std::chrono::steady_clock::now();
     J.ST.rounds = J.round;
     J.ST.status = J.status;
+    J.R->st_rounds = J.round;
     J.ST.device_bytes_peak = (int64_t)E.acct.peak;
     J.ST.nv_out = E.M.nv;
     J.ST.seconds_setup = std::chrono::duration<double>(J.t_ready - J.t_add).count();

@@ -19,8 +19,9 @@ __global__ void k_setup_verts(int nv, const double* xyz, double4* X, int* err) {
     X[i] = make_double4(x, y, z, 0.0);
 }
 
-// tets: copy, check ids and positive orientation
-__global__ void k_setup_tets(int nt, int nv, const int* tin, Mesh M, int* err) {
+// tets: copy, check ids and positive orientation; `tfl` (resumed
+// refinement, else null): bit0 exempt
+__global__ void k_setup_tets(int nt, int nv, const int* tin, const unsigned char* tfl, Mesh M, int* err) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     int4 v = make_int4(tin[4 * (size_t)t], tin[4 * (size_t)t + 1], tin[4 * (size_t)t + 2], tin[4 * (size_t)t + 3]);
@@ -33,7 +34,7 @@ __global__ void k_setup_tets(int nt, int nv, const int* tin, Mesh M, int* err) {
         if (orient3d_any(A, B, Cc, D, M.err) <= 0) atomicOr(err, 2);
     }
     *reinterpret_cast<int4*>(M.TV + 4 * (size_t)t) = v;
-    M.TI[t] = TI_ALIVE;
+    M.TI[t] = TI_ALIVE | (tfl && (tfl[t] & 1u) ? (unsigned)TI_EXEMPT : 0u);
 }
 
 QMD unsigned long long face_key3(int a, int b, int c) {
@@ -61,9 +62,11 @@ QMD int lower_bound64(const unsigned long long* k, int n, unsigned long long key
     while (lo < hi) { int mid = (lo + hi) >> 1; if (k[mid] < key) lo = mid + 1; else hi = mid; }
     return lo;
 }
+// `sfl` (resumed refinement, else null): bit0 queued, bit1 exempt, set on
+// both tets of the subface as the rounds set them
 __global__ void k_mark_subfaces(int nsf, int nv, int nfacet, const int* sf, const int* sff,
-                                const unsigned long long* k, const int* v, int n, int* TF, unsigned* TI,
-                                int* err) {
+                                const unsigned char* sfl, const unsigned long long* k, const int* v, int n,
+                                int* TF, unsigned* TI, int* err) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsf) return;
     int a = sf[3 * (size_t)i], b = sf[3 * (size_t)i + 1], c = sf[3 * (size_t)i + 2], F = sff[i];
@@ -71,9 +74,11 @@ __global__ void k_mark_subfaces(int nsf, int nv, int nfacet, const int* sf, cons
     unsigned long long key = face_key3(a, b, c);
     int j = lower_bound64(k, n, key);
     if (j >= n || k[j] != key) { atomicOr(err, 8); return; }
+    const unsigned fl = sfl ? sfl[i] : 0u;
     for (; j < n && k[j] == key; ++j) {
+        const int f = v[j] & 3;
         TF[v[j]] = F;
-        atomicOr(&TI[v[j] >> 2], ti_fsub(v[j] & 3));
+        atomicOr(&TI[v[j] >> 2], ti_fsub(f) | ((fl & 1u) << (4 + f)) | (((fl >> 1) & 1u) << (8 + f)));
     }
 }
 __global__ void k_edge_keys(int nt, const int* TV, unsigned long long* keys, int* vals) {
@@ -86,8 +91,9 @@ __global__ void k_edge_keys(int nt, const int* TV, unsigned long long* keys, int
     keys[i] = ((unsigned long long)a << 32) | (unsigned)b;
     vals[i] = i;
 }
-__global__ void k_mark_subsegs(int nss, int nv, const int* ss, const int* ssg, const unsigned long long* k,
-                               const int* v, int n, Mesh M, int* err) {
+// `ssl` (resumed refinement, else null): bit0 queued, bit1 exempt
+__global__ void k_mark_subsegs(int nss, int nv, const int* ss, const int* ssg, const unsigned char* ssl,
+                               const unsigned long long* k, const int* v, int n, Mesh M, int* err) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nss) return;
     int a = ss[2 * (size_t)i], b = ss[2 * (size_t)i + 1];
@@ -98,7 +104,7 @@ __global__ void k_mark_subsegs(int nss, int nv, const int* ss, const int* ssg, c
     if (j >= n || k[j] != key) { atomicOr(err, 16); return; }
     M.STET[i] = v[j] / 6;
     for (; j < n && k[j] == key; ++j) M.TS[v[j]] = i;
-    M.SV[i] = make_int2(a, b); M.SSEG[i] = ssg[i]; M.SFL[i] = 0u;
+    M.SV[i] = make_int2(a, b); M.SSEG[i] = ssg[i]; M.SFL[i] = ssl ? (ssl[i] & 3u) : 0u;
 }
 // projection axis of each facet: the dominant normal component of the
 // 1 + the largest id of ids[0..n) into *out (atomic max; *out starts at 0)
@@ -225,6 +231,20 @@ __global__ void k_out_sf(Mesh M, const int* flag, const int* scan, int* sf, int*
     int o = scan[i];
     sf[3 * (size_t)o] = a; sf[3 * (size_t)o + 1] = b; sf[3 * (size_t)o + 2] = c;
     sff[o] = M.TF[i];
+}
+// the refinement state of the output, aligned with k_out_tets and k_out_sf:
+// a tet's exempt bit, a subface's queued and exempt bits (from the tet that
+// holds its output copy, the one classification reads) and a subsegment's
+__global__ void k_out_state(Mesh M, const int* tflag, const int* tscan, const int* sfflag, const int* sfscan,
+                            unsigned char* tfl, unsigned char* sfl, unsigned char* ssl) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < M.nss) ssl[t] = (unsigned char)(M.SFL[t] & 3u);
+    if (t >= M.nt || !tflag[t]) return;
+    const unsigned ti = M.TI[t];
+    tfl[tscan[t]] = (ti & TI_EXEMPT) ? 1 : 0;
+    for (int f = 0; f < 4; ++f)
+        if (sfflag[4 * (size_t)t + f])
+            sfl[sfscan[4 * (size_t)t + f]] = (unsigned char)(((ti >> (4 + f)) & 1u) | (((ti >> (8 + f)) & 1u) << 1));
 }
 __global__ void k_out_xyz(int nv, const double4* X, double* xyz) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -75,3 +75,27 @@ def test_lockstep_knobs_are_checked_before_any_device_call():
                 {"select_one_wg": -1}, {"global_wgs": 2000}):
         with pytest.raises(qm.QmError, match="EINVAL"):
             qm.refine_lockstep([], tune=bad)
+
+
+@pytest.mark.skipif(not os.path.exists(qm._SO), reason="libqm.so not built")
+def test_resume_state_is_checked_before_any_device_call():
+    """A resume state that does not describe the mesh, or holds flag bits,
+    a sub-phase, a round count or an h_min outside their ranges, is refused
+    with QM_EINVAL (host check)."""
+    import numpy as np
+    import qm_inputs as qi
+    w = qi.uniform_cube(60, seed=2, B=2.0, spheres=(0.3,))
+    nt, nsf, nss = len(w.tets), len(w.sf), len(w.ss)
+    good = dict(hmin2=1e-6, rounds=3, next_class=0, tet_flags=np.zeros(nt, np.uint8),
+                sf_flags=np.zeros(nsf, np.uint8), ss_flags=np.zeros(nss, np.uint8))
+    bads = [dict(tet_flags=np.zeros(nt - 1, np.uint8)), dict(sf_flags=np.zeros(nsf + 1, np.uint8)),
+            dict(ss_flags=np.zeros(max(nss - 1, 0), np.uint8)), dict(next_class=3), dict(next_class=-1),
+            dict(hmin2=-1.0), dict(hmin2=float("nan")), dict(hmin2=float("inf")), dict(rounds=-1),
+            dict(tet_flags=np.full(nt, 2, np.uint8)), dict(sf_flags=np.full(nsf, 4, np.uint8)),
+            dict(ss_flags=np.full(nss, 8, np.uint8))]
+    assert nss > 0 and nsf > 0
+    for b in bads:
+        st = qm.RefineState(**{**good, **b})
+        with pytest.raises(qm.QmError, match="EINVAL"):
+            qm.refine(w.xyz, w.tets, w.sf, w.sf_facet, w.ss, w.ss_seg, w.ftri, w.ftri_facet, w.B, seg=w.seg,
+                      state=st)

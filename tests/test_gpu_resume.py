@@ -1,0 +1,148 @@
+"""Checkpoint and resume (qm_refine_resume, qm_result_state): a refinement
+cut by the round limit continues from its output mesh and state (queued and
+exempt flags, h_min, the next sub-phase).  The calls together must give the
+uninterrupted refinement bit for bit: the same round records, point
+coordinates, tets, subfaces and subsegments, and the same final state; on
+small inputs also the oracle's result."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1903_03406_amd as qm
+import qm_inputs as qi
+
+pytestmark = pytest.mark.gpu
+
+
+def canon(t):
+    t = np.sort(np.asarray(t), axis=1)
+    return t[np.lexsort(t.T[::-1])]
+
+
+def canon_tri(tri, fid):
+    a = np.concatenate([np.sort(np.asarray(tri), axis=1), np.asarray(fid).reshape(-1, 1)], axis=1)
+    return a[np.lexsort(a.T[::-1])]
+
+
+def state_map(r):
+    """The state keyed by element (sorted vertex ids), so that results whose
+    arrays list the elements in different orders compare."""
+    st = r.state
+    m = {}
+    for tup, f in zip(np.sort(r.tets, axis=1), st.tet_flags):
+        if f:
+            m[("t",) + tuple(tup)] = int(f)
+    for tup, f in zip(np.sort(r.sf, axis=1), st.sf_flags):
+        if f:
+            m[("f",) + tuple(tup)] = int(f)
+    for tup, f in zip(np.sort(r.ss, axis=1), st.ss_flags):
+        if f:
+            m[("s",) + tuple(tup)] = int(f)
+    return m
+
+
+def same_mesh(a, b):
+    return (np.array_equal(a.xyz.view(np.uint64), b.xyz.view(np.uint64))
+            and np.array_equal(canon(a.tets), canon(b.tets))
+            and np.array_equal(canon_tri(a.sf, a.sf_facet), canon_tri(b.sf, b.sf_facet))
+            and np.array_equal(canon_tri(a.ss, a.ss_seg), canon_tri(b.ss, b.ss_seg)))
+
+
+CASES = [lambda: qi.uniform_cube(900, seed=4, B=1.5, spheres=(0.3,)),
+         lambda: qi.uniform_cube(600, seed=5, B=1.6, spheres=(0.25,)),
+         lambda: qi.config(1)]
+
+
+@pytest.mark.parametrize("make", CASES)
+@pytest.mark.parametrize("subphases", [False, True])
+def test_resume_equals_uninterrupted(make, subphases):
+    w = make()
+    full = qm.refine_workload(w, subphases=subphases)
+    assert full.status == 0 and full.state.rounds == full.rounds
+    flagged = 0
+    for k in sorted({1, 2, 7, full.rounds // 3, full.rounds // 2, full.rounds - 1}):
+        a = qm.refine_workload(w, subphases=subphases, max_rounds=k)
+        assert a.status == 1 and a.rounds == k and a.state.rounds == k
+        assert len(a.state.tet_flags) == len(a.tets) and len(a.state.sf_flags) == len(a.sf)
+        assert len(a.state.ss_flags) == len(a.ss)
+        flagged += bool(state_map(a))
+        b = qm.resume(w, a, subphases=subphases)
+        print(f"[resume] {w.name} subphases={subphases} cut {k}: next class {a.state.next_class}, "
+              f"{len(state_map(a))} flagged elements; resumed {b.rounds} rounds (total {b.state.rounds}, "
+              f"uninterrupted {full.rounds})", flush=True)
+        assert b.status == 0 and b.state.rounds == full.rounds
+        assert np.array_equal(np.concatenate([a.rstats, b.rstats]), full.rstats), k
+        assert same_mesh(b, full), k
+        assert state_map(b) == state_map(full), k
+        assert b.state.hmin2 == full.state.hmin2
+    assert flagged, "no checkpoint carried a flag"
+
+
+def test_resume_in_short_calls_and_against_the_oracle():
+    """Ten rounds per call until the refinement converges; the last call's
+    mesh equals the oracle's."""
+    w = CASES[0]()
+    o = oracle.refine(w)
+    r = qm.refine_workload(w, max_rounds=10)
+    recs = [r.rstats]
+    calls = 1
+    while r.status == 1:
+        r = qm.resume(w, r, max_rounds=10)
+        recs.append(r.rstats)
+        calls += 1
+    print(f"[resume] {w.name}: {calls} calls, {r.state.rounds} rounds (oracle {o.rounds})", flush=True)
+    assert r.status == 0 and r.state.rounds == o.rounds
+    assert np.array_equal(np.concatenate(recs), o.rstats)
+    assert same_mesh(r, o)
+
+
+def test_the_flags_carry_the_rounds():
+    """Resuming with the flags cleared is not the same refinement on at least
+    one checkpoint that holds queued or exempt elements: the state is part of
+    the round rule, not a cache."""
+    w = CASES[0]()
+    full = qm.refine_workload(w)
+    differ = 0
+    for k in range(5, full.rounds, max(1, full.rounds // 12)):
+        a = qm.refine_workload(w, max_rounds=k)
+        if not state_map(a):
+            continue
+        st = a.state
+        a.state = qm.RefineState(st.hmin2, st.rounds, st.next_class, np.zeros_like(st.tet_flags),
+                                 np.zeros_like(st.sf_flags), np.zeros_like(st.ss_flags))
+        b = qm.resume(w, a)
+        differ += not (same_mesh(b, full) and np.array_equal(np.concatenate([a.rstats, b.rstats]), full.rstats))
+    print(f"[resume] cleared flags changed the refinement at {differ} checkpoints", flush=True)
+    assert differ > 0
+
+
+def test_lockstep_results_carry_the_same_state():
+    ws = [CASES[0](), CASES[1]()]
+    got = qm.refine_lockstep(ws, max_rounds=[9, 14])
+    for w, g, k in zip(ws, got, (9, 14)):
+        s = qm.refine_workload(w, max_rounds=k)
+        assert g.state.rounds == k and state_map(g) == state_map(s) and g.state.hmin2 == s.state.hmin2
+        b = qm.resume(w, g)
+        assert same_mesh(b, qm.refine_workload(w))
+
+
+def test_resume_rejects_a_state_of_another_mesh():
+    w = CASES[0]()
+    a = qm.refine_workload(w, max_rounds=5)
+    st = a.state
+    bad = [
+        qm.RefineState(st.hmin2, st.rounds, st.next_class, st.tet_flags[:-1], st.sf_flags, st.ss_flags),
+        qm.RefineState(st.hmin2, st.rounds, 3, st.tet_flags, st.sf_flags, st.ss_flags),
+        qm.RefineState(-1.0, st.rounds, 0, st.tet_flags, st.sf_flags, st.ss_flags),
+        qm.RefineState(float("nan"), st.rounds, 0, st.tet_flags, st.sf_flags, st.ss_flags),
+        qm.RefineState(st.hmin2, st.rounds, 0, st.tet_flags | 2, st.sf_flags, st.ss_flags),
+        qm.RefineState(st.hmin2, st.rounds, 0, st.tet_flags, st.sf_flags | 4, st.ss_flags),
+        qm.RefineState(st.hmin2, -1, 0, st.tet_flags, st.sf_flags, st.ss_flags),
+    ]
+    for s in bad:
+        a.state = s
+        with pytest.raises(qm.QmError) as e:
+            qm.resume(w, a)
+        assert e.value.code == -1            # QM_EINVAL
+    a.state = st                                   # the good state still resumes
+    assert qm.resume(w, a).status == 0
