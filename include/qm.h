@@ -345,6 +345,8 @@ typedef struct qm_server_stats {
     int32_t queued;          /* admitted jobs not started */
     int32_t running;         /* jobs being refined */
     int64_t admitted, refused, completed;   /* since creation; refused = QM_EAGAIN */
+    int64_t evictions;       /* jobs taken off the device by qm_server_evict, since creation */
+    int32_t parked;          /* evicted jobs not yet readmitted */
 } qm_server_stats;
 
 /* Device bytes the library budgets for refining this instance: 16 KB per
@@ -397,6 +399,24 @@ int qm_server_poll(qm_server* srv, uint64_t ticket, int32_t wait_ms, qm_result**
    their result to qm_server_poll.  *nresident receives the number of jobs
    still resident.  Calls take turns.  QM_EINVAL on a server with workers. */
 int qm_server_step(qm_server* srv, int32_t* nresident);
+
+/* Take a job off the device (a server's HBM budget is then free for other
+   jobs): a queued job leaves the queue; a running one ends at its next round
+   boundary (the worker form waits for it; the stepped form evicts between
+   steps), and its output mesh and refinement state (qm_result_state) become
+   a host checkpoint.  Its estimate leaves the budget.  QM_OK when the job is
+   evicted; QM_EAGAIN when it finished first (its result is ready to poll);
+   QM_EINVAL for an unknown, collected, finished or already evicted ticket.
+   qm_server_poll on an evicted job returns QM_EAGAIN at once. */
+int qm_server_evict(qm_server* srv, uint64_t ticket);
+
+/* Admit an evicted job again against the budget (QM_EAGAIN while it does
+   not fit; it stays evicted).  It resumes from its checkpoint
+   (qm_refine_resume) with the rounds left of its round limit.  The result it
+   finally gives holds the round records and summed statistics of every
+   segment, and its mesh and records equal the uninterrupted refinement's.
+   QM_EINVAL when the ticket is not an evicted job. */
+int qm_server_readmit(qm_server* srv, uint64_t ticket);
 
 /* Counters of the server (a consistent snapshot). */
 int qm_server_info(qm_server* srv, qm_server_stats* info);

@@ -126,7 +126,7 @@ def _load():
 EXPORTS = ("qm_refine", "qm_refine_resume", "qm_result_state", "qm_refine_noalloc", "qm_test_geometry", "qm_refine_batch", "qm_refine_lockstep", "qm_lockstep_autotune", "qm_result_view", "qm_result_rounds", "qm_result_last_round",
            "qm_result_round_profile", "qm_result_free", "qm_last_error", "qm_version",
            "qm_estimate_bytes", "qm_server_create", "qm_server_submit", "qm_server_step", "qm_server_poll",
-           "qm_server_info",
+           "qm_server_info", "qm_server_evict", "qm_server_readmit",
            "qm_server_destroy")
 
 
@@ -592,7 +592,7 @@ def estimate_bytes(w, *, hmin_factor=0.5) -> int:
 class _SrvStats(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_size_t), ("resident", ctypes.c_size_t), ("queued", ctypes.c_int32),
                 ("running", ctypes.c_int32), ("admitted", ctypes.c_int64), ("refused", ctypes.c_int64),
-                ("completed", ctypes.c_int64)]
+                ("completed", ctypes.c_int64), ("evictions", ctypes.c_int64), ("parked", ctypes.c_int32)]
 
 
 class Server:
@@ -675,11 +675,40 @@ class Server:
         return out, int(code.value), msg, float(sec[0]), float(sec[1])
 
     def result(self, ticket):
-        """Wait for a job and return its RefineResult (QmError if it failed)."""
-        out, code, msg, _, _ = self.poll(ticket, wait_ms=-1)
+        """Wait for a job and return its RefineResult (QmError if it failed
+        or is evicted)."""
+        got = self.poll(ticket, wait_ms=-1)
+        if got is None:
+            raise QmError(-8, self._lib.qm_last_error().decode())
+        out, code, msg, _, _ = got
         if code not in (0, -4):
             raise QmError(code, msg)
         return out
+
+    def evict(self, ticket) -> bool:
+        """Take a job off the device at a round boundary, its mesh and state
+        kept on the host (qm_server_evict).  True when evicted, False when it
+        finished first."""
+        self._lib.qm_server_evict.restype = ctypes.c_int
+        self._lib.qm_server_evict.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        rc = self._lib.qm_server_evict(self._h, int(ticket))
+        if rc == -8:
+            return False
+        if rc:
+            raise QmError(rc, self._lib.qm_last_error().decode())
+        return True
+
+    def readmit(self, ticket) -> bool:
+        """Admit an evicted job again (qm_server_readmit): True when admitted,
+        False while the budget has no room."""
+        self._lib.qm_server_readmit.restype = ctypes.c_int
+        self._lib.qm_server_readmit.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        rc = self._lib.qm_server_readmit(self._h, int(ticket))
+        if rc == -8:
+            return False
+        if rc:
+            raise QmError(rc, self._lib.qm_last_error().decode())
+        return True
 
     def info(self) -> dict:
         st = _SrvStats()

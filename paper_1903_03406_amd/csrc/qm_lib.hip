@@ -9,6 +9,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -949,9 +950,30 @@ static int emit_output(Engine& E, qm_result* R, const qm_options* opt, Arena* ar
 // buffer is carved from the arena, inputs are device arrays, the output mesh
 // is written into the caller's device arrays `dout` and the statistics into
 // *dstats; no qm_result, pinned buffer or event is created.
+// A resumed refinement's state must describe its mesh (host check, before
+// any device call).
+static void check_state(const qm_mesh* in, const qm_state* rs) {
+    if (rs->nt != in->nt || rs->nsf != in->nsf || rs->nss != in->nss)
+        throw QmError(QM_EINVAL, "the state's counts differ from the mesh's");
+    if ((in->nt && !rs->tet_flags) || (in->nsf && !rs->sf_flags) || (in->nss && !rs->ss_flags))
+        throw QmError(QM_EINVAL, "state flag array missing");
+    if (rs->next_class < 0 || rs->next_class > 2 || rs->rounds < 0 || !(rs->hmin2 >= 0.0) || !std::isfinite(rs->hmin2))
+        throw QmError(QM_EINVAL, "state: next_class outside 0..2, negative rounds or bad hmin2");
+    for (int i = 0; i < in->nt; ++i)
+        if (rs->tet_flags[i] > 1) throw QmError(QM_EINVAL, "state: tet flag with bits other than bit0");
+    for (int i = 0; i < in->nsf; ++i)
+        if (rs->sf_flags[i] > 3) throw QmError(QM_EINVAL, "state: subface flag with bits other than 0-1");
+    for (int i = 0; i < in->nss; ++i)
+        if (rs->ss_flags[i] > 3) throw QmError(QM_EINVAL, "state: subsegment flag with bits other than 0-1");
+}
+
+// `stop` (served jobs, else null): when it is set, the refinement ends at the
+// next round boundary with status 2 and its output and state on the host, a
+// checkpoint to resume from.
 static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
                       qm_result** out, Arena* ar = nullptr, qm_mesh_buf* dout = nullptr,
-                      qm_stats* dstats = nullptr, size_t mem_cap = 0, const qm_state* rs = nullptr) {
+                      qm_stats* dstats = nullptr, size_t mem_cap = 0, const qm_state* rs = nullptr,
+                      const std::atomic<bool>* stop = nullptr) {
     auto T0 = std::chrono::steady_clock::now();
     const bool noalloc = ar != nullptr;
     if (!plc || !in || !opt || (noalloc ? (!dout || !dstats) : !out)) throw QmError(QM_EINVAL, "null argument");
@@ -960,21 +982,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0 || plc->nseg < 0)
         throw QmError(QM_EINVAL, "bad counts");
     if (in->nv >= (1 << 21)) throw QmError(QM_EINVAL, "input vertex count must be below 2^21");
-    if (rs) {                 // a resumed refinement's state must describe this mesh
-        if (rs->nt != in->nt || rs->nsf != in->nsf || rs->nss != in->nss)
-            throw QmError(QM_EINVAL, "the state's counts differ from the mesh's");
-        if ((in->nt && !rs->tet_flags) || (in->nsf && !rs->sf_flags) || (in->nss && !rs->ss_flags))
-            throw QmError(QM_EINVAL, "state flag array missing");
-        if (rs->next_class < 0 || rs->next_class > 2 || rs->rounds < 0 || !(rs->hmin2 >= 0.0) ||
-            !std::isfinite(rs->hmin2))
-            throw QmError(QM_EINVAL, "state: next_class outside 0..2, negative rounds or bad hmin2");
-        for (int i = 0; i < in->nt; ++i)
-            if (rs->tet_flags[i] > 1) throw QmError(QM_EINVAL, "state: tet flag with bits other than bit0");
-        for (int i = 0; i < in->nsf; ++i)
-            if (rs->sf_flags[i] > 3) throw QmError(QM_EINVAL, "state: subface flag with bits other than 0-1");
-        for (int i = 0; i < in->nss; ++i)
-            if (rs->ss_flags[i] > 3) throw QmError(QM_EINVAL, "state: subsegment flag with bits other than 0-1");
-    }
+    if (rs) check_state(in, rs);
     const bool dev = (opt->flags & QM_INPUT_DEVICE) != 0;
     if (noalloc) {
         if (!dev) throw QmError(QM_EINVAL, "the no-alloc entry point takes device arrays (QM_INPUT_DEVICE)");
@@ -1069,6 +1077,7 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     };
     for (;; ++round) {
         if (round >= opt->max_rounds) { status = 1; break; }
+        if (stop && stop->load(std::memory_order_relaxed)) { status = 2; break; }
         E.cur_round = round;
         E.arena_round();
         // slots appended since the last renumbering are in priority order,
@@ -1342,7 +1351,9 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
     const int gerr = read1(E.M.err, s);
     if (gerr) throw QmError(QM_EINTERNAL, "exact predicate precondition failed (code " + std::to_string(gerr) + ")");
     // ---- output: live tets and subfaces compacted in slot order
-    ST.nt_out = emit_output(E, R.get(), opt, ar, dout);
+    qm_options opt_out = *opt;
+    if (status == 2) opt_out.flags &= ~QM_OUTPUT_DEVICE;   // a checkpoint is kept on the host
+    ST.nt_out = emit_output(E, R.get(), &opt_out, ar, dout);
     float ms_setup = 0, ms_ref = 0;
     if (noalloc) {            // host clock: the call's stream was synchronised at both points
         ms_setup = (float)std::chrono::duration<double, std::milli>(T1s - T0).count();
@@ -1391,10 +1402,11 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
 // other buffers in that many bytes (the served form passes each job's
 // admitted estimate).
 static int refine_within(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, hipStream_t s,
-                         qm_result** out, size_t mem_cap, const qm_state* rs = nullptr) {
+                         qm_result** out, size_t mem_cap, const qm_state* rs = nullptr,
+                         const std::atomic<bool>* stop = nullptr) {
     g_err.clear();
     try {
-        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap, rs);
+        return run_refine(plc, in, opt, s, out, nullptr, nullptr, nullptr, mem_cap, rs, stop);
     } catch (const QmError& e) {
         g_err = e.what();
         return e.code;

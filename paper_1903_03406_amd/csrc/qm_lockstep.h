@@ -345,6 +345,7 @@ struct LsJob {
     std::unique_ptr<qm_result> R;
     qm_stats ST{};
     int round = 0, status = 0, last_ncand = 0;
+    int round0 = 0;                 // rounds run before this set-up (a resumed refinement)
     int cls = CLS_NONE, ncand = 0, ncl = 0, nkept = 0, newt = 0, newss = 0, nover = 0, nbig = 0;
     int passes = 0, ncl_final = 0;
     int undecided = 0;              // selection: undecided candidates after the last batch
@@ -383,9 +384,11 @@ public:
         (void)hipStreamSynchronize(s_);
     }
     int live() const { return (int)jobs_.size(); }
-    // Set an instance up on the device; it takes part from the next step.
-    // A failing set-up (or refused options) ends it at once, in take_done().
-    void add(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, uint64_t tag) {
+    // Set an instance up on the device (resumed from `st` when given); it
+    // takes part from the next step.  A failing set-up (or refused options)
+    // ends it at once, in take_done().
+    void add(const qm_plc* plc, const qm_mesh* in, const qm_options* opt, uint64_t tag,
+             const qm_state* st = nullptr) {
         auto J = std::make_unique<LsJob>();
         J->tag = tag;
         J->t_add = std::chrono::steady_clock::now();
@@ -402,9 +405,11 @@ public:
             J->opt = &J->opt_copy;
             J->key_mask = (opt->flags & QM_TEST_KEY_COLLIDE) ? 0xE000000000000000ull : ~0ull;
             J->min_tier = (opt->flags & QM_TEST_TIER2) ? 2 : (opt->flags & QM_TEST_TIER1) ? 1 : 0;
+            if (st) check_state(in, st);
+            J->round0 = st ? st->rounds : 0;
             J->E = std::make_unique<Engine>(s_);
             J->R = std::make_unique<qm_result>();
-            setup_mesh(*J->E, plc, in, J->opt, nullptr, nullptr);
+            setup_mesh(*J->E, plc, in, J->opt, nullptr, nullptr, st);
             J->t_ready = std::chrono::steady_clock::now();
             jobs_.push_back(std::move(J));
         } catch (const QmError& e) {
@@ -416,6 +421,26 @@ public:
     // One round of every live instance; instances that finish (no candidate
     // left, round limit, failure) move to take_done().
     void step();
+    // Between steps: take instance `tag` off the device.  Its mesh and state
+    // go to a host result with status 2 in take_done(), a checkpoint that
+    // add() resumes from.  False when no live instance has that tag.
+    bool evict_now(uint64_t tag) {
+        for (auto& P : jobs_) {
+            if (!P->E || P->tag != tag) continue;
+            LsJob& J = *P;
+            int hc[48];
+            HIPCK(hipMemcpyAsync(hc, J.E->ctr.p, sizeof hc, hipMemcpyDeviceToHost, s_));
+            HIPCK(hipStreamSynchronize(s_));
+            J.hc = hc;
+            patch_last_record(J);
+            J.hc = nullptr;
+            J.status = 2;
+            finish(J);
+            compact();
+            return true;
+        }
+        return false;
+    }
     std::vector<LsDone> take_done() { return std::exchange(done_, {}); }
 
 private:
@@ -543,11 +568,12 @@ void Lockstep::finish(LsJob& J) {
     if (J.last_ncand > 0) read_last_round(E, J.R.get(), J.last_ncand);
     const int gerr = read1(E.M.err, s_);
     if (gerr) throw QmError(QM_EINTERNAL, "exact predicate precondition failed (code " + std::to_string(gerr) + ")");
+    if (J.status == 2) J.opt_copy.flags &= ~QM_OUTPUT_DEVICE;   // a checkpoint is kept on the host
     J.ST.nt_out = emit_output(E, J.R.get(), J.opt, nullptr, nullptr);
     const auto now = std::chrono::steady_clock::now();
     J.ST.rounds = J.round;
     J.ST.status = J.status;
-    J.R->st_rounds = J.round;
+    J.R->st_rounds = J.round0 + J.round;
     J.ST.device_bytes_peak = (int64_t)E.acct.peak;
     J.ST.nv_out = E.M.nv;
     J.ST.seconds_setup = std::chrono::duration<double>(J.t_ready - J.t_add).count();

@@ -18,8 +18,16 @@
 // phase of the round one launch over all of them, the batches at the same
 // time; jobs join and leave at round boundaries and their meshes stay on
 // the device in between.
+//
+// Eviction (both forms): qm_server_evict takes a job off the device at a
+// round boundary.  Its output mesh and refinement state (qm_result_state)
+// become a host checkpoint, and its estimate leaves the budget.
+// qm_server_readmit admits it again, and it resumes from the checkpoint
+// (qm_refine_resume).  The result it finally returns holds the round records
+// and statistics of every segment, and equals the uninterrupted refinement.
 #pragma once
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -40,7 +48,74 @@ struct SrvJob {
     qm_mesh mesh{};
     qm_options opt{};
     srv_clock::time_point t_sub;
+    // eviction: the checkpoint (the mesh above is then the output it
+    // resumes from), and what the job's earlier segments recorded
+    std::vector<uint8_t> tfl, sfl, ssl;
+    qm_state state{};
+    bool has_state = false;
+    std::vector<int32_t> hist_rounds;
+    qm_stats hist{};
+    int segments = 0;
+    std::atomic<bool> stop{false};     // worker form: end at the next round boundary
+    double wait_s = -1.0;              // queued time before the first segment started
 };
+
+// the job's options for its next segment: the round limit less the rounds
+// its earlier segments ran
+qm_options srv_seg_opt(const SrvJob& J) {
+    qm_options o = J.opt;
+    if (J.has_state) o.max_rounds = std::max(0, J.opt.max_rounds - J.state.rounds);
+    return o;
+}
+
+void srv_add_stats(qm_stats& a, const qm_stats& b) {
+    a.rounds += b.rounds;
+    for (int c = 0; c < 3; ++c) a.inserted[c] += b.inserted[c];
+    a.candidates += b.candidates;
+    a.mis_passes += b.mis_passes;
+    a.deferred += b.deferred;
+    a.device_bytes_peak = std::max(a.device_bytes_peak, b.device_bytes_peak);
+    a.seconds_setup += b.seconds_setup;
+    a.seconds_refine += b.seconds_refine;
+    a.seconds_total += b.seconds_total;
+}
+
+// an evicted segment's host result becomes the job's checkpoint
+void srv_checkpoint(SrvJob& J, qm_result* r) {
+    J.xyz = std::move(r->xyz); J.tet = std::move(r->tets);
+    J.sf = std::move(r->sf); J.sff = std::move(r->sff);
+    J.ss = std::move(r->ss); J.ssg = std::move(r->ssg);
+    J.tfl = std::move(r->st_tfl); J.sfl = std::move(r->st_sfl); J.ssl = std::move(r->st_ssl);
+    J.mesh = qm_mesh{(int32_t)(J.xyz.size() / 3), J.xyz.data(), (int32_t)(J.tet.size() / 4), J.tet.data(),
+                     (int32_t)J.sff.size(), J.sf.data(), J.sff.data(), (int32_t)J.ssg.size(), J.ss.data(),
+                     J.ssg.data()};
+    J.state = qm_state{r->st_hmin2, r->st_rounds, r->st_next, (int32_t)J.tfl.size(), (int32_t)J.sfl.size(),
+                       (int32_t)J.ssl.size(), J.tfl.data(), J.sfl.data(), J.ssl.data()};
+    J.has_state = true;
+    J.hist_rounds.insert(J.hist_rounds.end(), r->rounds.begin(), r->rounds.end());
+    srv_add_stats(J.hist, r->stats);
+    ++J.segments;
+    qm_result_free(r);
+}
+
+// the last segment's result completed with the earlier segments' records
+void srv_merge(const SrvJob& J, qm_result* r) {
+    if (!r || !J.segments) return;
+    r->rounds.insert(r->rounds.begin(), J.hist_rounds.begin(), J.hist_rounds.end());
+    // counters summed over the segments; the output's own figures are the
+    // last segment's
+    qm_stats s = J.hist;
+    srv_add_stats(s, r->stats);
+    r->stats.rounds = s.rounds;
+    for (int c = 0; c < 3; ++c) r->stats.inserted[c] = s.inserted[c];
+    r->stats.candidates = s.candidates;
+    r->stats.mis_passes = s.mis_passes;
+    r->stats.deferred = s.deferred;
+    r->stats.device_bytes_peak = s.device_bytes_peak;
+    r->stats.seconds_setup = s.seconds_setup;
+    r->stats.seconds_refine = s.seconds_refine;
+    r->stats.seconds_total = s.seconds_total;
+}
 
 struct SrvDone {
     qm_result* res = nullptr;
@@ -73,7 +148,9 @@ struct qm_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     int running = 0;
-    int64_t admitted = 0, refused = 0, completed = 0;
+    int64_t admitted = 0, refused = 0, completed = 0, evictions = 0;
+    std::unordered_map<uint64_t, SrvJob*> running_jobs;             // worker form: jobs being refined
+    std::unordered_map<uint64_t, std::unique_ptr<SrvJob>> parked;   // evicted jobs (host checkpoints)
     std::vector<std::thread> workers;
     bool stepped = false;                                  // no workers: qm_server_step drives the jobs
     // stepped form: lockstep batches of resident jobs, each with its stream,
@@ -149,25 +226,40 @@ void srv_worker(qm_server* S) {
             J = std::move(S->queue.front());
             S->queue.pop_front();
             ++S->running;
+            S->running_jobs[J->ticket] = J.get();
         }
         const auto t_start = srv_clock::now();
+        if (J->wait_s < 0) J->wait_s = std::chrono::duration<double>(t_start - J->t_sub).count();
         SrvDone d;
         if (ok) {
-            d.code = refine_within(&J->plc, &J->mesh, &J->opt, st, &d.res, J->est);
+            const qm_options o = srv_seg_opt(*J);
+            d.code = refine_within(&J->plc, &J->mesh, &o, st, &d.res, J->est, J->has_state ? &J->state : nullptr,
+                                   &J->stop);
             if (d.code != QM_OK && d.code != QM_EROUNDS) d.msg = qm_last_error();
         } else {
             d.code = QM_EDEVICE;
             d.msg = "server worker has no HIP stream";
         }
+        const bool evicted = d.code == QM_OK && d.res && d.res->stats.status == 2;
+        if (evicted) srv_checkpoint(*J, d.res);
+        else srv_merge(*J, d.res);
         const auto t_end = srv_clock::now();
-        d.wait_s = std::chrono::duration<double>(t_start - J->t_sub).count();
+        d.wait_s = J->wait_s;
         d.total_s = std::chrono::duration<double>(t_end - J->t_sub).count();
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->resident -= J->est;
             --S->running;
-            ++S->completed;
-            S->done[J->ticket] = std::move(d);
+            S->running_jobs.erase(J->ticket);
+            if (evicted) {
+                J->stop = false;
+                ++S->evictions;
+                const uint64_t t = J->ticket;
+                S->parked[t] = std::move(J);
+            } else {
+                ++S->completed;
+                S->done[J->ticket] = std::move(d);
+            }
         }
         S->cv_done.notify_all();
     }
@@ -297,12 +389,15 @@ int qm_server_poll(qm_server* S, uint64_t ticket, int32_t wait_ms, qm_result** o
     if (!S || !out || !code) { g_err = "null argument"; return QM_EINVAL; }
     std::unique_lock<std::mutex> lk(S->mu);
     if (!S->live.count(ticket)) { g_err = "unknown ticket"; return QM_EINVAL; }
-    auto ready = [&] { return S->done.count(ticket) > 0; };
+    auto ready = [&] { return S->done.count(ticket) > 0 || S->parked.count(ticket) > 0; };
     if (!ready()) {
         if (wait_ms < 0) S->cv_done.wait(lk, ready);
         else if (wait_ms > 0) S->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), ready);
     }
-    if (!ready()) return QM_EAGAIN;
+    if (!S->done.count(ticket)) {
+        if (S->parked.count(ticket)) g_err = "the job is evicted (qm_server_readmit brings it back)";
+        return QM_EAGAIN;
+    }
     auto it = S->done.find(ticket);
     SrvDone d = std::move(it->second);
     S->done.erase(it);
@@ -311,6 +406,139 @@ int qm_server_poll(qm_server* S, uint64_t ticket, int32_t wait_ms, qm_result** o
     *code = d.code;
     if (seconds) { seconds[0] = d.wait_s; seconds[1] = d.total_s; }
     g_err = d.msg;
+    return QM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// stepped form: jobs that left their batches (finished, failed, or evicted
+// with a checkpoint) leave the budget; called with step_mu held
+void srv_collect(qm_server* S, std::vector<LsDone>& finished) {
+    const auto now = srv_clock::now();
+    for (auto& d : finished) {
+        auto it = S->in_batch.find(d.tag);
+        auto go = S->group_of.find(d.tag);
+        if (go != S->group_of.end()) {
+            if (it != S->in_batch.end()) S->groups[go->second].load -= it->second->mesh.nt;
+            S->group_of.erase(go);
+        }
+        std::unique_ptr<SrvJob> J;
+        if (it != S->in_batch.end()) {
+            J = std::move(it->second);
+            S->in_batch.erase(it);
+        }
+        const bool evicted = J && d.code == QM_OK && d.res && d.res->stats.status == 2;
+        SrvDone out;
+        if (J && !evicted) {
+            srv_merge(*J, d.res);
+            out.wait_s = J->wait_s;
+            out.total_s = std::chrono::duration<double>(now - J->t_sub).count();
+        }
+        if (evicted) srv_checkpoint(*J, d.res);
+        out.res = evicted ? nullptr : d.res;
+        out.code = d.code;
+        out.msg = d.msg;
+        const size_t est = J ? J->est : 0;
+        S->t_added.erase(d.tag);
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->resident -= est;
+        if (evicted) {
+            ++S->evictions;
+            S->parked[d.tag] = std::move(J);
+        } else {
+            ++S->completed;
+            S->done[d.tag] = std::move(out);
+        }
+    }
+}
+
+// a job waiting in the queue leaves it for the parked set (called with mu
+// held); false when it is not queued
+bool srv_park_queued(qm_server* S, uint64_t t) {
+    for (auto q = S->queue.begin(); q != S->queue.end(); ++q) {
+        if ((*q)->ticket != t) continue;
+        S->resident -= (*q)->est;
+        ++S->evictions;
+        S->parked[t] = std::move(*q);
+        S->queue.erase(q);
+        return true;
+    }
+    return false;
+}
+}  // namespace
+
+extern "C" {
+
+int qm_server_evict(qm_server* S, uint64_t t) {
+    g_err.clear();
+    if (!S) { g_err = "null argument"; return QM_EINVAL; }
+    auto known = [&]() {
+        if (!S->live.count(t) || S->done.count(t) || S->parked.count(t)) {
+            g_err = "unknown, finished or already evicted ticket";
+            return false;
+        }
+        return true;
+    };
+    try {
+        if (S->stepped) {
+            std::lock_guard<std::mutex> step_lock(S->step_mu);   // the batches are idle between steps
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (!known()) return QM_EINVAL;
+                if (srv_park_queued(S, t)) { S->cv_done.notify_all(); return QM_OK; }
+            }
+            auto go = S->group_of.find(t);
+            if (go == S->group_of.end()) { g_err = "the job is not resident"; return QM_EINVAL; }
+            if (hipSetDevice(S->dev) != hipSuccess) throw QmError(QM_EDEVICE, "cannot select the server's device");
+            auto& G = S->groups[go->second];
+            G.batch->evict_now(t);
+            std::vector<LsDone> finished = G.batch->take_done();
+            srv_collect(S, finished);
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->running = S->live_jobs();
+            }
+            S->cv_done.notify_all();
+            std::lock_guard<std::mutex> lk(S->mu);
+            return S->parked.count(t) ? QM_OK : QM_EAGAIN;
+        }
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (!known()) return QM_EINVAL;
+        if (srv_park_queued(S, t)) { S->cv_done.notify_all(); return QM_OK; }
+        auto r = S->running_jobs.find(t);
+        if (r == S->running_jobs.end()) { g_err = "the job is not resident"; return QM_EINVAL; }
+        r->second->stop = true;                   // the worker ends the job at its next round boundary
+        S->cv_done.wait(lk, [&] { return S->parked.count(t) > 0 || S->done.count(t) > 0; });
+        if (S->parked.count(t)) return QM_OK;
+        g_err = "the job finished before it could be evicted";
+        return QM_EAGAIN;
+    } catch (const QmError& e) {
+        g_err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return QM_EINTERNAL;
+    }
+}
+
+int qm_server_readmit(qm_server* S, uint64_t t) {
+    g_err.clear();
+    if (!S) { g_err = "null argument"; return QM_EINVAL; }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->parked.find(t);
+        if (it == S->parked.end()) { g_err = "the ticket is not an evicted job"; return QM_EINVAL; }
+        if (S->resident + it->second->est > S->budget) {
+            ++S->refused;
+            g_err = "over the server budget (resident " + std::to_string(S->resident) + " B)";
+            return QM_EAGAIN;
+        }
+        S->resident += it->second->est;
+        S->queue.push_back(std::move(it->second));
+        S->parked.erase(it);
+    }
+    S->cv_work.notify_one();
     return QM_OK;
 }
 
@@ -336,9 +564,11 @@ int qm_server_step(qm_server* S, int32_t* nresident) {
             for (int k = 1; k < (int)S->groups.size(); ++k)
                 if (S->groups[k].load < S->groups[g].load) g = k;
             S->t_added[t] = srv_clock::now();
+            if (J->wait_s < 0) J->wait_s = std::chrono::duration<double>(S->t_added[t] - J->t_sub).count();
             S->groups[g].load += J->mesh.nt;
             S->group_of[t] = g;
-            S->groups[g].batch->add(&J->plc, &J->mesh, &J->opt, t);
+            const qm_options o = srv_seg_opt(*J);
+            S->groups[g].batch->add(&J->plc, &J->mesh, &o, t, J->has_state ? &J->state : nullptr);
             S->in_batch[t] = std::move(J);
         }
         // one round of every resident job: the batches at the same time, each
@@ -356,33 +586,10 @@ int qm_server_step(qm_server* S, int32_t* nresident) {
                 G.code = 0;
                 throw QmError(c, G.msg);
             }
-        const auto now = srv_clock::now();
         std::vector<LsDone> finished;
         for (auto& G : S->groups)
             for (auto& d : G.batch->take_done()) finished.push_back(std::move(d));
-        for (auto& d : finished) {
-            auto it = S->in_batch.find(d.tag);
-            auto go = S->group_of.find(d.tag);
-            if (go != S->group_of.end()) {
-                if (it != S->in_batch.end()) S->groups[go->second].load -= it->second->mesh.nt;
-                S->group_of.erase(go);
-            }
-            SrvDone out;
-            out.res = d.res;
-            out.code = d.code;
-            out.msg = d.msg;
-            if (it != S->in_batch.end()) {
-                out.wait_s = std::chrono::duration<double>(S->t_added[d.tag] - it->second->t_sub).count();
-                out.total_s = std::chrono::duration<double>(now - it->second->t_sub).count();
-            }
-            const size_t est = it != S->in_batch.end() ? it->second->est : 0;
-            S->in_batch.erase(d.tag);
-            S->t_added.erase(d.tag);
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->resident -= est;
-            ++S->completed;
-            S->done[d.tag] = std::move(out);
-        }
+        srv_collect(S, finished);
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->running = S->live_jobs();
@@ -410,6 +617,8 @@ int qm_server_info(qm_server* S, qm_server_stats* info) {
     info->admitted = S->admitted;
     info->refused = S->refused;
     info->completed = S->completed;
+    info->evictions = S->evictions;
+    info->parked = (int32_t)S->parked.size();
     return QM_OK;
 }
 
