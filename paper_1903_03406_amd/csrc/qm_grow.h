@@ -55,6 +55,7 @@ struct GrowShared {
     int nrt, nrf, nbf, nbe, nq, ncx, hcount;
     int over, fail, reason, accepted, lost;
     int base_reg, base_bf, base_be, base_cl, base_q;
+    int take;                                   // next candidate of a shared-counter loop
     unsigned long long prof[4 + GROW_PHASES];   // region counters and phase clocks of this workgroup
     unsigned long long tlast;                   // (flushed at exit)
 };
@@ -939,10 +940,13 @@ inline size_t lists_slab_bytes(const GrowTiles& T) {
 // atomic-heavy structures) in LDS, the region list, face records and edge
 // table in the workgroup's block of a global slab.  `list` holds the
 // candidate ids; T carries the capacities (hcap = HCAP, ...).
-// (`block`: this workgroup's block of the slab)
+// (`block`: this workgroup's block of the slab).  With `next` (a counter
+// zeroed before the launch) each workgroup takes the next candidate of the
+// list when it is done with one, so that regions of very different sizes even
+// out over the workgroups; without it, workgroup bid takes every gdim-th.
 template <int NT, int HCAP, int RFHCAP, int QHCAP>
 QMD void d_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP, const int* list, int nlist,
-                       const GrowTiles& T, char* block, const int bid, const int gdim) {
+                       const GrowTiles& T, char* block, const int bid, const int gdim, int* next = nullptr) {
     __shared__ unsigned H[HCAP];
     __shared__ unsigned RFH[RFHCAP];
     __shared__ unsigned long long QH[QHCAP];
@@ -952,7 +956,13 @@ QMD void d_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP, const int*
     W.H = H; W.RFH = RFH; W.QH = QH;
     W.hcap = HCAP; W.rfhcap = RFHCAP; W.qhcap = QHCAP;
     prof_begin(S);
-    for (int i = bid; i < nlist; i += gdim) {
+    for (int i = bid;; i += gdim) {
+        if (next) {
+            if (threadIdx.x == 0) S.take = atomicAdd(next, 1);
+            __syncthreads();
+            i = S.take;                   // every lane reads it before the barriers of grow_one
+        }
+        if (i >= nlist) break;
         grow_one<NT>(M, cls, C, PL, BP, list[i], W, S);
         __syncthreads();
         tier_count(S, BP, 1);
@@ -962,9 +972,9 @@ QMD void d_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP, const int*
 template <int NT, int HCAP, int RFHCAP, int QHCAP>
 __global__ __launch_bounds__(NT) void k_grow_hybrid(Mesh M, int cls, Cands C, Pools PL, BfPool BP,
                                                     const int* list, int nlist, GrowTiles T, char* slab,
-                                                    size_t slab_per_block) {
+                                                    size_t slab_per_block, int* next) {
     d_grow_hybrid<NT, HCAP, RFHCAP, QHCAP>(M, cls, C, PL, BP, list, nlist, T, slab + slab_per_block * blockIdx.x,
-                                           blockIdx.x, gridDim.x);
+                                           blockIdx.x, gridDim.x, next);
 }
 
 // re-run of the candidates that overflowed the LDS tiles (or a pool), with

@@ -1185,14 +1185,18 @@ static int run_refine(const qm_plc* plc, const qm_mesh* in, const qm_options* op
                 if (nover + nbig == 0) break;
                 if (attempt >= 64) throw QmError(QM_EINTERNAL, "regions kept outgrowing the tiles");
                 const BfPool BPr = E.BPnoprof();
-                if (nover > 0) {             // hybrid tier (a grid-stride loop: any grid)
+                if (nover > 0) {             // hybrid tier (a shared-counter loop: any grid)
                     E.pbegin(8);
                     const GrowTiles HT = hybrid_tiles();
                     const size_t block = lists_slab_bytes(HT);
-                    const int grid = E.slab_grid(std::min(nover, noalloc ? 4 : 1024), block, E.hslab.cap);
+                    // the workgroups that stay resident (two per CU): they take the
+                    // candidates from a shared counter, so more would only add slab
+                    const int grid = E.slab_grid(std::min(nover, noalloc ? 4 : 512), block, E.hslab.cap);
                     E.hslab.ensure_exact(block * grid, s);
+                    int* const next = E.ctr.p + 56;      // the shared candidate counter
+                    HIPCK(hipMemsetAsync(next, 0, sizeof(int), s));
                     k_grow_hybrid<H_LANES, H_HCAP, H_RFHCAP, H_QHCAP><<<grid, H_LANES, 0, s>>>(
-                        E.M, cls, E.C, E.PL, BPr, E.olist.p, nover, HT, E.hslab.p, block);
+                        E.M, cls, E.C, E.PL, BPr, E.olist.p, nover, HT, E.hslab.p, block, next);
                     E.pend(8);
                 }
                 if (nbig > 0) {              // global-memory tiles
