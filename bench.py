@@ -112,6 +112,15 @@ def make_workload(name):
         return qi.config(2)
     if name == "cfg1":
         return qi.config(1)
+    if name.split(":")[0] == "rect":
+        # rect[:n[:gamma[:dist[:B]]]]: a rectangle PLC like the paper's experiments
+        # (Table 1: n points, gamma * n rectangles), each rectangle split in advance
+        f = name.split(":")[1:]
+        n = int(f[0]) if f else 200000
+        gamma = float(f[1]) if len(f) > 1 else 0.1
+        dist = f[2] if len(f) > 2 else "uniform"
+        B = float(f[3]) if len(f) > 3 else 1.4
+        return qi.rectangles_plc(n, gamma, seed=12, dist=dist, B=B)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -405,7 +414,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--workload", default="cfg3",
+                    help="cfg1, cfg2, cfg3, or rect[:n[:gamma[:uniform|gauss[:B]]]] (rectangle PLC)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-quality", action="store_true", help="skip the output quality report")

@@ -15,7 +15,9 @@ data model used throughout):
 * the PLC always contains the six cube faces as facets 0..5 (facet
   ``2*axis + side``), each given by its two hull triangles, and the twelve
   cube edges as segments 0..11; internal constraint surfaces add one facet
-  per Delaunay face and one segment per distinct edge of those faces;
+  per Delaunay face and one segment per distinct edge of those faces, and
+  rectangle PLCs (``rectangles_plc``) one facet per rectangle and one segment
+  per Delaunay edge along its sides;
 * the initial CDT is the Delaunay tetrahedralisation itself: its subfaces are
   the PLC triangles and its subsegments the PLC segments.
 """
@@ -324,3 +326,165 @@ def serve_job(i: int, max_points: int = 500000, seed: int = 5) -> Workload:
         fns = [ellipsoid_inside(axes, rot)]
         kind = "ellipsoid"
     return make_workload(f"serve_job{i}_{kind}{n}", pts, B, fns, {"n": n, "job": i, "kind": kind})
+
+
+def rectangles_plc(n: int, gamma: float, seed: int, B: float = 1.4, dist: str = "uniform",
+                   lattice: int = 3, name=None) -> Workload:
+    """A PLC of the kind the paper's experiments use (Section 3, Table 1):
+    n points, of which round(gamma * n) polygons are axis-aligned rectangles
+    whose four corners are PLC points; the other points are uniform
+    (``dist="uniform"``) or from the Gaussian mixture of workload 3
+    (``dist="gauss"``).
+
+    The paper's inputs are made a CDT by TetGen's constraint recovery, which
+    is not built here.  Instead each rectangle is split in advance so that
+    the Delaunay tetrahedralisation of all points conforms to it:
+
+    * the cube is cut into k^3 cells (k^3 >= the number of rectangles); each
+      rectangle lies in a cell of its own, chosen at random, in a plane
+      normal to a random axis, with a random size and position inside the
+      cell;
+    * every rectangle carries a (lattice+1) x (lattice+1) grid of points,
+      exactly in its plane and on its sides (coordinates on the 2^-53 grid).
+      The grid points inside the rectangle are moved by up to 15% of the
+      spacing within the plane, and those on a side are moved along it, so
+      that no four are cocircular;
+    * no other point lies within twice the grid spacing of the rectangle's
+      plane over the rectangle grown by that margin.  A Delaunay triangle of
+      the grid then has an empty equatorial ball in 3D, so the rectangle is
+      a union of Delaunay faces and its sides unions of Delaunay edges.
+
+    Both facts are checked on the result: the Delaunay faces with all three
+    vertices on one rectangle cover its area, and every pair of consecutive
+    points of a side is a Delaunay edge.  Each rectangle is one facet (id 6 +
+    its index); each edge between consecutive side points is a segment.
+    The grid points are Steiner points of the recovery, so gamma counts the
+    rectangles against the PLC's own points (corners and others)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nrect = int(round(gamma * n))
+    nother = n - 4 * nrect
+    if nrect < 0 or nother < 0 or lattice < 3:
+        raise ValueError("need 4 * round(gamma * n) <= n and lattice >= 3")
+    k = max(1, int(np.ceil(nrect ** (1.0 / 3.0) - 1e-9)))
+    while k ** 3 < nrect:
+        k += 1
+    cell = 1.0 / k
+    cells = rng.choice(k ** 3, size=nrect, replace=False)
+    boxes = np.zeros((nrect, 2, 3))
+    rect = []                                          # (axis, plane, lo(2), hi(2)) per rectangle
+    pts = []
+    sides = []                                         # per rectangle: 4 lists of point indices along its sides
+    base = 0
+    for r, c in enumerate(cells):
+        ci = np.array([c % k, (c // k) % k, c // (k * k)], dtype=np.float64)
+        lo_cell, hi_cell = ci * cell, (ci + 1) * cell
+        axis = int(rng.integers(0, 3))
+        u, v = [a for a in range(3) if a != axis]
+        size = rng.uniform(0.2, 0.35, size=2) * cell     # size (1 + 4 / lattice) <= cell for lattice >= 3
+        h = float(np.max(size)) / lattice
+        m = 2.0 * h                                    # slab margin
+        # rectangle and its slab inside the cell (away from the cube faces)
+        lo = np.empty(2)
+        for j, a in enumerate((u, v)):
+            lo[j] = rng.uniform(lo_cell[a] + m, hi_cell[a] - m - size[j])
+        plane = snap(rng.uniform(lo_cell[axis] + m, hi_cell[axis] - m))
+        lo = snap(lo)
+        hi = snap(lo + size)
+        # grid with in-plane jitter (sides move along themselves, corners stay)
+        gi = np.arange(lattice + 1)
+        I, J = np.meshgrid(gi, gi, indexing="ij")
+        I, J = I.reshape(-1), J.reshape(-1)
+        su, sv = (hi[0] - lo[0]) / lattice, (hi[1] - lo[1]) / lattice
+        pu = lo[0] + I * su + rng.uniform(-0.15, 0.15, size=len(I)) * su
+        pv = lo[1] + J * sv + rng.uniform(-0.15, 0.15, size=len(J)) * sv
+        on_u = (I == 0) | (I == lattice)
+        on_v = (J == 0) | (J == lattice)
+        pu = np.where(I == 0, lo[0], np.where(I == lattice, hi[0], pu))
+        pv = np.where(J == 0, lo[1], np.where(J == lattice, hi[1], pv))
+        # a point on a side keeps that side's coordinate; pu/pv already hold it
+        p = np.empty((len(I), 3))
+        p[:, axis] = plane
+        p[:, u] = snap(pu)
+        p[:, v] = snap(pv)
+        p[:, u] = np.where(on_u, np.where(I == 0, lo[0], hi[0]), p[:, u])
+        p[:, v] = np.where(on_v, np.where(J == 0, lo[1], hi[1]), p[:, v])
+        pts.append(p)
+        idx = base + np.arange(len(I))
+        sides.append([idx[(I == 0)][np.argsort(J[I == 0])], idx[(I == lattice)][np.argsort(J[I == lattice])],
+                      idx[(J == 0)][np.argsort(I[J == 0])], idx[(J == lattice)][np.argsort(I[J == lattice])]])
+        rect.append((axis, plane, lo.copy(), hi.copy(), base, len(I)))
+        base += len(I)
+        box_lo = np.empty(3); box_hi = np.empty(3)
+        box_lo[axis], box_hi[axis] = plane - m, plane + m
+        box_lo[u], box_hi[u] = lo[0] - m, hi[0] + m
+        box_lo[v], box_hi[v] = lo[1] - m, hi[1] + m
+        boxes[r] = (box_lo, box_hi)
+    rect_pts = np.concatenate(pts) if pts else np.zeros((0, 3))
+    # the other points, outside every slab
+    other = np.zeros((0, 3))
+    while len(other) < nother:
+        want = nother - len(other)
+        if dist == "uniform":
+            q = uniform_interior(rng, want)
+        elif dist == "gauss":
+            q = gaussmix_interior(rng, want)
+        else:
+            raise ValueError("dist is 'uniform' or 'gauss'")
+        q = snap(q)
+        cidx = np.minimum((q / cell).astype(np.int64), k - 1)
+        cid = cidx[:, 0] + k * cidx[:, 1] + k * k * cidx[:, 2]
+        slot = np.full(k ** 3, -1, dtype=np.int64)
+        slot[cells] = np.arange(nrect)
+        rr = slot[cid]
+        inside = np.zeros(len(q), dtype=bool)
+        has = rr >= 0
+        if has.any():
+            bl, bh = boxes[rr[has], 0], boxes[rr[has], 1]
+            inside[has] = np.all((q[has] >= bl) & (q[has] <= bh), axis=1)
+        ok = ~inside & np.all((q > 0.0) & (q < 1.0), axis=1)
+        other = np.concatenate([other, q[ok]])
+    allp = np.concatenate([rect_pts, other[:nother]])
+    if len(np.unique(allp, axis=0)) != len(allp):
+        raise RuntimeError("coincident points")
+    order = np.argsort(_morton(allp), kind="stable")
+    xyz = np.concatenate([corners(), allp[order]], axis=0)
+    vid = np.empty(len(allp), dtype=np.int64)
+    vid[order] = 8 + np.arange(len(allp))
+    tets, adj = delaunay(xyz)
+    ftri, ftri_facet, seg = build_plc(xyz, tets, adj)
+    # Delaunay faces (each once) and edges
+    t, f, nb = _faces_of(tets, adj)
+    once = (nb < 0) | (t < (nb >> 2))
+    fv = np.sort(tets[t[once][:, None], FACE[f[once]]], axis=1)
+    owner = np.full(len(xyz), -1, dtype=np.int64)
+    for r, (_, _, _, _, b0, cnt) in enumerate(rect):
+        owner[vid[b0:b0 + cnt]] = r
+    o = owner[fv]
+    same = (o[:, 0] >= 0) & (o[:, 0] == o[:, 1]) & (o[:, 0] == o[:, 2])
+    tri, tri_rect = fv[same], o[same, 0]
+    # coverage: the faces on each rectangle tile its area
+    a, b_, c_ = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(b_ - a, c_ - a), axis=1)
+    cover = np.bincount(tri_rect, weights=area, minlength=nrect)
+    want = np.array([(hi[0] - lo[0]) * (hi[1] - lo[1]) for (_, _, lo, hi, _, _) in rect])
+    if nrect and np.max(np.abs(cover - want) / want) > 1e-9:
+        raise RuntimeError("a rectangle is not a union of Delaunay faces")
+    e6 = np.concatenate([tets[:, [0, 1]], tets[:, [0, 2]], tets[:, [0, 3]], tets[:, [1, 2]], tets[:, [1, 3]],
+                         tets[:, [2, 3]]]).astype(np.int64)
+    e6.sort(axis=1)
+    ekeys = np.unique(e6[:, 0] * (1 << 32) + e6[:, 1])
+    sseg = []
+    for r in range(nrect):
+        for side in sides[r]:
+            ids = vid[side]
+            sseg.append(np.stack([ids[:-1], ids[1:]], axis=1))
+    sseg = np.sort(np.concatenate(sseg), axis=1) if sseg else np.zeros((0, 2), dtype=np.int64)
+    if len(sseg) and not np.all(np.isin(sseg[:, 0] * (1 << 32) + sseg[:, 1], ekeys)):
+        raise RuntimeError("a rectangle side is not a union of Delaunay edges")
+    order_t = np.lexsort((tri[:, 2], tri[:, 1], tri[:, 0], tri_rect))
+    ftri = np.concatenate([ftri, tri[order_t]]).astype(np.int32)
+    ftri_facet = np.concatenate([ftri_facet, 6 + tri_rect[order_t]]).astype(np.int32)
+    seg = np.concatenate([seg, sseg]).astype(np.int32)
+    return Workload(name or f"rect{n}_g{gamma}_{dist}_s{seed}", xyz, tets, adj, ftri, ftri_facet, seg, float(B),
+                    {"n": n, "gamma": gamma, "rectangles": nrect, "dist": dist, "seed": seed,
+                     "grid_points": int(len(rect_pts)), "lattice": lattice})

@@ -44,3 +44,33 @@ def test_configs_are_seeded():
     a, b = qi.config(1), qi.config(1)
     assert a.sha256() == b.sha256()
     assert len(a.xyz) == 1008
+
+
+@pytest.mark.parametrize("n,gamma,dist", [(200, 0.1, "uniform"), (400, 0.25, "uniform"), (1500, 0.05, "gauss")])
+def test_rectangle_plc_is_a_cdt(n, gamma, dist):
+    """Rectangle PLCs (the kind of input of the paper's Table 1): gamma * n
+    rectangles whose corners are PLC points, each split in advance by a
+    jittered grid so that the Delaunay tetrahedralisation conforms.  A grid of
+    (L+1)^2 points triangulates into exactly 2 L^2 Delaunay triangles and its
+    sides into 4 L edges; the input is a Delaunay tetrahedralisation (global
+    empty-sphere check), a valid CDT of its PLC (every subface a face, every
+    subsegment an edge), and each rectangle's triangles tile its area."""
+    w = qi.rectangles_plc(n, gamma, seed=5, dist=dist)
+    L = w.meta["lattice"]
+    nr = w.meta["rectangles"]
+    assert nr == round(gamma * n)
+    assert len(w.xyz) == 8 + (n - 4 * nr) + nr * (L + 1) ** 2
+    assert len(w.ftri) == 12 + nr * 2 * L * L and len(w.seg) == 12 + nr * 4 * L
+    for r in range(nr):
+        assert np.count_nonzero(w.ftri_facet == 6 + r) == 2 * L * L
+    assert oracle.check_global(w.xyz, w.tets) == 0
+    c = oracle.check(w.xyz, w.tets, w.sf, w.ss, w.ss_seg, w.B)
+    for k in ("neg_orient", "face_overuse", "hull_not_subface", "nonlocal_delaunay", "sf_missing", "ss_missing",
+              "chain_broken"):
+        assert c[k] == 0, (k, c)
+    assert c["euler"] == 1 and abs(c["volume"] - 1.0) < 1e-12
+    # every rectangle is planar (one coordinate shared by its triangles)
+    for r in range(nr):
+        p = w.xyz[w.ftri[w.ftri_facet == 6 + r]].reshape(-1, 3)
+        assert sum(np.all(p[:, a] == p[0, a]) for a in range(3)) == 1
+    assert qi.rectangles_plc(n, gamma, seed=5, dist=dist).sha256() == w.sha256()

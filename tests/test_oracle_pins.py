@@ -552,3 +552,22 @@ def test_subphase_reading_keeps_a_cdt_after_every_round():
         # (a class without candidates is passed over)
         cls = a.rstats[:, 0]
         assert cls[0] == 0 and set(np.unique(cls)) <= {0, 1, 2}
+
+
+def test_rectangle_plc_refinement_keeps_a_cdt_every_round():
+    """The oracle on a rectangle PLC (large planar facets of many triangles,
+    collinear segment chains): after every round the mesh is a conforming
+    CDT and a valid tetrahedralisation (the independently pinned mesh
+    checks); the refinement converges and keeps every facet's area."""
+    w = qi.rectangles_plc(200, 0.1, seed=11, B=1.4)
+    o = oracle.refine(w, round_checks=True)
+    assert o.status == 0 and o.rounds > 0
+    rc = o.round_checks
+    for k, name in enumerate(oracle.CHECK_FIELDS):
+        if name == "euler":
+            assert (rc[:, k] == 1).all()
+        elif name != "bad_tets":
+            assert (rc[:, k] == 0).all(), name
+    a0 = oracle.facet_areas(w.xyz, w.ftri, w.ftri_facet)
+    a1 = oracle.facet_areas(o.xyz, o.sf, o.sf_facet)
+    assert set(a0) == set(a1) and max(abs(a0[k] - a1[k]) / a0[k] for k in a0) < 1e-12
