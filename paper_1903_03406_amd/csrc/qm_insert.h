@@ -62,7 +62,9 @@ __global__ __launch_bounds__(256) void k_verdicts(Mesh M, int cls, Cands C, Pool
 
 // ------------------------------------------------------------- selection
 // Iterated local maxima with fixed priorities: in each pass every undecided
-// candidate marks its claim set with its priority (atomic max); a candidate
+// candidate marks its claim set with its priority (atomic max, skipped when
+// the mark already read is as high: marks only grow, and the pass number in
+// their high bits makes every earlier mark lower); a candidate
 // owning all its marks is kept, one touching a kept claim is dropped.  The
 // result is exactly the greedy maximal disjoint set in priority order.
 // Passes are launched in batches without waiting: every kernel of a pass
@@ -77,7 +79,9 @@ QMD void d_mis_mark(int ncl, const int* cl, const int* clc, const int* state,
     int c = clc[e];
     if (c < 0) return;                 // void range (reservation that did not fit)
     if (state[c] != 0) return;
-    atomicMax(&mark[cl[e]], mis_val(pass, c));
+    const unsigned long long v = mis_val(pass, c);
+    unsigned long long* const p = &mark[cl[e]];
+    if (*p < v) atomicMax(p, v);       // marks only grow: one as high already leaves the atomic nothing to do
 }
 __global__ void k_mis_mark(int ncl, const int* cl, const int* clc, const int* state,
                            unsigned long long* mark, unsigned pass, const int* prev) {
@@ -137,7 +141,10 @@ QMD void d_mis_mark_list(const int* u_in, const int* nu_in, Cands C, const int* 
     for (int i = bid * 4 + (threadIdx.x >> 6); i < n; i += gdim * 4) {
         const int c = u_in[i], off = C.cl_off[c], m = C.cl_n[c];
         const unsigned long long v = mis_val(pass, c);
-        for (int j = lane; j < m; j += 64) atomicMax(&mark[cl[off + j]], v);
+        for (int j = lane; j < m; j += 64) {
+            unsigned long long* const p = &mark[cl[off + j]];
+            if (*p < v) atomicMax(p, v);
+        }
     }
 }
 __global__ __launch_bounds__(256) void k_mis_mark_list(const int* u_in, const int* nu_in, Cands C, const int* cl,
@@ -222,7 +229,11 @@ QMD void d_mis_small(int ncl, const int* cl, const int* clc, int n, int* state,
         const unsigned pass = pass0 + (unsigned)k;
         for (int e = threadIdx.x; e < ncl; e += blockDim.x) {          // mark
             int c = clc[e];
-            if (c >= 0 && state[c] == 0) atomicMax(&mark[cl[e]], mis_val(pass, c));
+            if (c >= 0 && state[c] == 0) {
+                const unsigned long long v = mis_val(pass, c);
+                unsigned long long* const p = &mark[cl[e]];
+                if (*p < v) atomicMax(p, v);
+            }
         }
         if (threadIdx.x == 0) undecided = 0;
         __syncthreads();
