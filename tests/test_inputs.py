@@ -74,3 +74,19 @@ def test_rectangle_plc_is_a_cdt(n, gamma, dist):
         p = w.xyz[w.ftri[w.ftri_facet == 6 + r]].reshape(-1, 3)
         assert sum(np.all(p[:, a] == p[0, a]) for a in range(3)) == 1
     assert qi.rectangles_plc(n, gamma, seed=5, dist=dist).sha256() == w.sha256()
+
+
+def test_rectangle_plc_edge_cases():
+    """No rectangles (gamma = 0: the cube PLC alone), every point a corner
+    (gamma = 0.25), and refused parameters."""
+    w = qi.rectangles_plc(100, 0.0, seed=3)
+    assert w.meta["rectangles"] == 0 and len(w.xyz) == 108 and len(w.ftri) == 12 and len(w.seg) == 12
+    w = qi.rectangles_plc(40, 0.25, seed=3)
+    assert w.meta["rectangles"] == 10 and len(w.xyz) == 8 + 10 * 16
+    assert oracle.check_global(w.xyz, w.tets) == 0
+    with pytest.raises(ValueError):
+        qi.rectangles_plc(10, 0.3, seed=3)             # more corners than points
+    with pytest.raises(ValueError):
+        qi.rectangles_plc(100, 0.1, seed=3, lattice=2)
+    with pytest.raises(ValueError):
+        qi.rectangles_plc(100, 0.1, seed=3, dist="ball")
