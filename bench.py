@@ -79,7 +79,7 @@ def tier_bytes(t):
             + 8 * max(t["acc_claims"] - t["acc_region"], 0))
 
 
-def survey_bytes(r, prof):
+def insertion_model_bytes(r, prof):
     """The whole refinement's algorithmic bytes by the per-insertion model:
     a kept point moves 36(k+s) + 24u + 36f + 4s + 24 + 16(k+s)P bytes, every
     other candidate 36(k+s) + 16(k+s) + 44, with k region tets, f new tets
@@ -517,7 +517,7 @@ def main():
     mean_us = kms * 1e3 / t_launches
     achieved = (nbytes / launches) / (mean_us * 1e-6) / 1e9 if kms > 0 else 0.0
     dominant = max(prof["ms"], key=lambda k: prof["ms"][k])
-    sbytes, smodel = survey_bytes(r, prof)
+    sbytes, smodel = insertion_model_bytes(r, prof)
     npts = len(w.xyz) - 8
     size = f"{npts // 1000000}M" if npts >= 1000000 else f"{npts // 1000}K"
     out = {
