@@ -81,16 +81,34 @@ class OracleResult:
     last_cands: np.ndarray = None   # last round: tuple(4), status, reason, kept, region, bfaces
     dump: list = None               # dump_round's candidates (see _take_dump)
     round_checks: np.ndarray = None  # (rounds, len(CHECK_FIELDS)): check() after every round
+    state: "OracleState" = None     # the flags and h_min the rounds carry (see OracleState)
+
+
+@dataclass
+class OracleState:
+    """What the round rule carries beyond the mesh (Section 2's filtering):
+    per tet an exempt bit, per subface and subsegment queued (bit0) and
+    exempt (bit1) bits, aligned with the result's arrays; h_min^2 of the
+    first input; rounds run over every call; the sub-phase due next (the
+    sub-phase reading)."""
+    hmin2: float
+    rounds: int
+    next_class: int
+    tet_flags: np.ndarray
+    sf_flags: np.ndarray
+    ss_flags: np.ndarray
 
 
 def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
-           round_checks=False, dump_round=None, key_mask=None, subphases=False) -> OracleResult:
+           round_checks=False, dump_round=None, key_mask=None, subphases=False, state=None) -> OracleResult:
     """Run the oracle on a workload (qm_inputs.Workload or compatible).
     round_checks: run check() on the mesh at the end of every round.
     dump_round: record that round's candidates (result.dump, see dump()).
     key_mask: AND every priority key with this mask (forces equal keys).
     subphases: the sub-phase reading of the class order (every round takes
-    the three classes in turn)."""
+    the three classes in turn).
+    state: resume from it (an OracleState, or any object with its fields);
+    w then holds the mesh that state belongs to."""
     lib = _load()
     lib.qmo_set_subphases.argtypes = [ctypes.c_int]
     lib.qmo_set_subphases(1 if subphases else 0)
@@ -105,11 +123,24 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
     sf = c(w.sf, np.int32); sff = c(w.sf_facet, np.int32)
     ss = c(w.ss, np.int32); sss = c(w.ss_seg, np.int32)
     ft = c(w.ftri, np.int32); ftf = c(w.ftri_facet, np.int32)
+    lib.qmo_clear_resume.argtypes = []
+    if state is not None:
+        fl = [c(state.tet_flags, np.uint8), c(state.sf_flags, np.uint8), c(state.ss_flags, np.uint8)]
+        if (len(fl[0]), len(fl[1]), len(fl[2])) != (len(tets), len(sf), len(ss)):
+            lib.qmo_set_key_mask((1 << 64) - 1)
+            lib.qmo_set_subphases(0)
+            lib.qmo_set_round_check(0)
+            lib.qmo_set_dump_round(-1)
+            raise ValueError("the state does not describe this mesh")
+        lib.qmo_set_resume.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                       ctypes.c_int]
+        lib.qmo_set_resume(_ptr(fl[0]), _ptr(fl[1]), _ptr(fl[2]), float(state.hmin2), int(state.next_class))
     res = ctypes.c_void_p()
     rc = lib.qmo_refine(len(xyz), _ptr(xyz), len(tets), _ptr(tets), len(sf), _ptr(sf), _ptr(sff),
                         len(ss), _ptr(ss), _ptr(sss), len(ft), _ptr(ft), _ptr(ftf),
                         float(w.B if B is None else B), float(hmin_factor), int(max_rounds),
                         int(max_kept), ctypes.byref(res))
+    lib.qmo_clear_resume()
     if rc != 0:
         lib.qmo_set_key_mask((1 << 64) - 1)
         lib.qmo_set_subphases(0)
@@ -130,6 +161,13 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
         if rounds:
             lib.qmo_result_round_checks(res, _ptr(out.round_checks))
         lib.qmo_set_round_check(0)
+    tfl, sfl, ssl = np.zeros(nt, np.uint8), np.zeros(nsf, np.uint8), np.zeros(nss, np.uint8)
+    h2 = ctypes.c_double()
+    lib.qmo_result_state.restype = ctypes.c_int
+    lib.qmo_result_state.argtypes = [ctypes.c_void_p] * 4 + [ctypes.POINTER(ctypes.c_double)]
+    nxt = lib.qmo_result_state(res, _ptr(tfl), _ptr(sfl), _ptr(ssl), ctypes.byref(h2))
+    out.state = OracleState(float(h2.value), (int(state.rounds) if state is not None else 0) + rounds, int(nxt),
+                            tfl, sfl, ssl)
     lib.qmo_result_lastc.restype = ctypes.c_int
     lib.qmo_result_lastc.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     nl = lib.qmo_result_lastc(res, None)

@@ -800,6 +800,22 @@ int qmo_check(int nv, const double* xyz, int nt, const int* tets, int nsf, const
 static int g_subphases = 0;
 void qmo_set_subphases(int on) { g_subphases = on; }
 
+/* Resuming a refinement that the round guard stopped.  What the rounds
+   carry beyond the mesh is a flag pair per subsegment and subface (queued by
+   a rejected point, exempted by the filtering of Section 2), an exempt flag
+   per bad tet whose point was filtered away, and h_min, fixed by the first
+   input's shortest edge.  With a resume state set, qmo_refine takes these
+   (aligned with its input arrays) instead of starting from clear flags, and
+   the sub-phase reading starts at `next_class`. */
+static const unsigned char *g_res_tfl = NULL, *g_res_sfl = NULL, *g_res_ssl = NULL;
+static double g_res_hmin2 = 0.0;
+static int g_res_on = 0, g_res_next = 0;
+void qmo_set_resume(const unsigned char* tfl, const unsigned char* sfl, const unsigned char* ssl, double hmin2,
+                    int next_class) {
+    g_res_tfl = tfl; g_res_sfl = sfl; g_res_ssl = ssl; g_res_hmin2 = hmin2; g_res_next = next_class; g_res_on = 1;
+}
+void qmo_clear_resume(void) { g_res_on = 0; g_res_tfl = g_res_sfl = g_res_ssl = NULL; }
+
 /* When set, every round ends with qmo_check on the current mesh, and its
    counts are kept per round (qmo_result_round_checks). */
 static int g_round_check = 0;
@@ -849,6 +865,8 @@ static void dump_round(const Mesh* M, const CandList* L) {
 }
 
 typedef struct qmo_result {
+    unsigned char *tfl, *sfl, *ssl;   /* state after the run, aligned with tets, sf, ss */
+    double hmin2; int next_class;     /* h_min^2 used; sub-phase due next (sub-phase reading) */
     int* rcheck;                  /* QMO_NCHECK ints per round (round checks on) */
     int* lastc; int nlastc;       /* last round: 9 ints per candidate */
     int nv, nt, nsf, nss, rounds, status;
@@ -930,20 +948,22 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
         const int* v = &tets[4 * t];
         for (int k = 0; k < 4; ++k) if (v[k] < 0 || v[k] >= nv) return -1;
         if (qmo_orient3d(X(M, v[0]), X(M, v[1]), X(M, v[2]), X(M, v[3])) <= 0) return -2;
-        if (add_tet(M, v) < 0) return -3;
+        int ti = add_tet(M, v);
+        if (ti < 0) return -3;
+        if (g_res_on && g_res_tfl) M->T[ti].exempt = g_res_tfl[t] & 1;
         for (int e = 0; e < 6; ++e) { double d = qmo_d2(X(M, v[EDGE[e][0]]), X(M, v[EDGE[e][1]])); if (d < l2) l2 = d; }
     }
     for (int i = 0; i < nsf; ++i) {
         int k[4]; key3(k, sf[3 * i], sf[3 * i + 1], sf[3 * i + 2]);
         if (!hm_get(&M->faces, k)) return -4;
-        HE* e = hm_put(&M->sf, k); e->v[0] = sf_facet[i]; e->v[1] = 0;
+        HE* e = hm_put(&M->sf, k); e->v[0] = sf_facet[i]; e->v[1] = g_res_on && g_res_sfl ? (g_res_sfl[i] & 3) : 0;
     }
     for (int i = 0; i < nss; ++i) {
         int k[4]; key2(k, ss[2 * i], ss[2 * i + 1]);
         IV et = {0}; edge_tets(M, k[0], k[1], &et);
         int n = et.n; iv_free(&et);
         if (!n) return -5;
-        HE* e = hm_put(&M->ss, k); e->v[0] = ss_seg[i]; e->v[1] = 0;
+        HE* e = hm_put(&M->ss, k); e->v[0] = ss_seg[i]; e->v[1] = g_res_on && g_res_ssl ? (g_res_ssl[i] & 3) : 0;
     }
     int nfacet = 0;
     for (int i = 0; i < nftri; ++i) if (ftri_facet[i] + 1 > nfacet) nfacet = ftri_facet[i] + 1;
@@ -963,7 +983,7 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
     }
     M->nfacet = nfacet;
     M->B2 = B * B;
-    M->hmin2 = (hmin_factor * hmin_factor) * l2;
+    M->hmin2 = g_res_on ? g_res_hmin2 : (hmin_factor * hmin_factor) * l2;
 
     qmo_result* R = (qmo_result*)calloc(1, sizeof *R);
     int rcap = 256;
@@ -973,7 +993,7 @@ int qmo_refine(int nv, const double* xyz, int nt, const int* tets,
     clock_gettime(CLOCK_MONOTONIC, &t0);
     int round = 0;
     R->status = 0;
-    int sub = CLS_SS, empty_turns = 0;
+    int sub = g_res_on ? g_res_next : CLS_SS, empty_turns = 0;
     for (;;) {
         if (round >= max_rounds) { R->status = 1; break; }
         int cls = classify(M, &L, g_subphases ? sub : CLS_NONE);
@@ -1063,17 +1083,29 @@ finish:
     int live = 0; for (int t = 0; t < M->nt; ++t) live += M->T[t].alive;
     R->nt = live;
     R->tets = (int*)malloc(sizeof(int) * 4 * (size_t)(live ? live : 1));
-    for (int t = 0, j = 0; t < M->nt; ++t) if (M->T[t].alive) memcpy(&R->tets[4 * j++], M->T[t].v, 4 * sizeof(int));
+    R->tfl = (unsigned char*)malloc((size_t)(live ? live : 1));
+    for (int t = 0, j = 0; t < M->nt; ++t)
+        if (M->T[t].alive) { R->tfl[j] = M->T[t].exempt; memcpy(&R->tets[4 * j++], M->T[t].v, 4 * sizeof(int)); }
     R->nsf = (int)M->sf.n;
     R->sf = (int*)malloc(sizeof(int) * 3 * (size_t)(R->nsf + 1));
     R->sf_facet = (int*)malloc(sizeof(int) * (size_t)(R->nsf + 1));
+    R->sfl = (unsigned char*)malloc((size_t)(R->nsf + 1));
     for (size_t i = 0, j = 0; i < M->sf.cap; ++i)
-        if (M->sf.e[i].st == 1) { memcpy(&R->sf[3 * j], M->sf.e[i].k, 3 * sizeof(int)); R->sf_facet[j] = M->sf.e[i].v[0]; j++; }
+        if (M->sf.e[i].st == 1) {
+            memcpy(&R->sf[3 * j], M->sf.e[i].k, 3 * sizeof(int)); R->sf_facet[j] = M->sf.e[i].v[0];
+            R->sfl[j] = (unsigned char)(M->sf.e[i].v[1] & 3); j++;
+        }
     R->nss = (int)M->ss.n;
     R->ss = (int*)malloc(sizeof(int) * 2 * (size_t)(R->nss + 1));
     R->ss_seg = (int*)malloc(sizeof(int) * (size_t)(R->nss + 1));
+    R->ssl = (unsigned char*)malloc((size_t)(R->nss + 1));
     for (size_t i = 0, j = 0; i < M->ss.cap; ++i)
-        if (M->ss.e[i].st == 1) { memcpy(&R->ss[2 * j], M->ss.e[i].k, 2 * sizeof(int)); R->ss_seg[j] = M->ss.e[i].v[0]; j++; }
+        if (M->ss.e[i].st == 1) {
+            memcpy(&R->ss[2 * j], M->ss.e[i].k, 2 * sizeof(int)); R->ss_seg[j] = M->ss.e[i].v[0];
+            R->ssl[j] = (unsigned char)(M->ss.e[i].v[1] & 3); j++;
+        }
+    R->hmin2 = M->hmin2;
+    R->next_class = g_subphases ? sub : 0;
     hm_free(&M->faces); hm_free(&M->sf); hm_free(&M->ss);
     free(M->V); free(M->vt); free(M->T); free(M->inR); free(M->tested); free(M->claimed); free(M->instar); free(M->faxis);
     *out = R;
@@ -1098,13 +1130,22 @@ int qmo_result_round_checks(const qmo_result* R, int* buf) {
     if (buf) memcpy(buf, R->rcheck, sizeof(int) * QMO_NCHECK * (size_t)R->nrstats);
     return R->nrstats;
 }
+/* the state after the run, aligned with the arrays of qmo_result_copy;
+   returns the sub-phase due next */
+int qmo_result_state(const qmo_result* R, unsigned char* tfl, unsigned char* sfl, unsigned char* ssl, double* hmin2) {
+    memcpy(tfl, R->tfl, (size_t)R->nt);
+    memcpy(sfl, R->sfl, (size_t)R->nsf);
+    memcpy(ssl, R->ssl, (size_t)R->nss);
+    *hmin2 = R->hmin2;
+    return R->next_class;
+}
 int qmo_result_lastc(const qmo_result* R, int* buf) {
     if (buf) memcpy(buf, R->lastc, sizeof(int) * 9 * (size_t)R->nlastc);
     return R->nlastc;
 }
 void qmo_result_free(qmo_result* R) {
     if (!R) return;
-    free(R->lastc); free(R->rcheck);
+    free(R->lastc); free(R->rcheck); free(R->tfl); free(R->sfl); free(R->ssl);
     free(R->xyz); free(R->tets); free(R->sf); free(R->sf_facet); free(R->ss); free(R->ss_seg); free(R->rstats);
     free(R);
 }

@@ -146,3 +146,27 @@ def test_resume_rejects_a_state_of_another_mesh():
         assert e.value.code == -1            # QM_EINVAL
     a.state = st                                   # the good state still resumes
     assert qm.resume(w, a).status == 0
+
+
+@pytest.mark.parametrize("subphases", [False, True])
+def test_checkpoint_state_matches_the_oracle(subphases):
+    """At a checkpoint the GPU's state (flags of every element, h_min, the
+    sub-phase due next) equals the oracle's at the same round."""
+    w = CASES[1]()
+    for k in (1, 7, 40, 100):
+        g = qm.refine_workload(w, subphases=subphases, max_rounds=k)
+        o = oracle.refine(w, subphases=subphases, max_rounds=k)
+        om = {}
+        for tup, f in zip(np.sort(o.tets, axis=1), o.state.tet_flags):
+            if f:
+                om[("t",) + tuple(tup)] = int(f)
+        for tup, f in zip(np.sort(o.sf, axis=1), o.state.sf_flags):
+            if f:
+                om[("f",) + tuple(tup)] = int(f)
+        for tup, f in zip(np.sort(o.ss, axis=1), o.state.ss_flags):
+            if f:
+                om[("s",) + tuple(tup)] = int(f)
+        print(f"[resume] {w.name} subphases={subphases} round {k}: {len(om)} flagged elements", flush=True)
+        assert state_map(g) == om, k
+        assert g.state.hmin2 == o.state.hmin2 and g.state.next_class == o.state.next_class
+        assert g.state.rounds == o.state.rounds == k

@@ -571,3 +571,38 @@ def test_rectangle_plc_refinement_keeps_a_cdt_every_round():
     a0 = oracle.facet_areas(w.xyz, w.ftri, w.ftri_facet)
     a1 = oracle.facet_areas(o.xyz, o.sf, o.sf_facet)
     assert set(a0) == set(a1) and max(abs(a0[k] - a1[k]) / a0[k] for k in a0) < 1e-12
+
+
+def test_resume_from_the_state_equals_the_uninterrupted_run():
+    """What the round rule carries beyond the mesh is exactly the queued and
+    exempt flags and h_min: a run stopped by the round guard and started
+    again from its output mesh and that state gives the uninterrupted run
+    (round records, point bits, tets), in both readings of the class order;
+    with the flags cleared it is a different refinement at some cut."""
+    import types
+
+    def canon(t):
+        t = np.sort(np.asarray(t), axis=1)
+        return t[np.lexsort(t.T[::-1])]
+
+    w = qi.uniform_cube(400, seed=3, B=2.0, spheres=(0.2, 0.35))
+    differ = 0
+    for sub in (False, True):
+        full = oracle.refine(w, subphases=sub)
+        assert full.state.rounds == full.rounds
+        for k in (1, 9, full.rounds // 2, full.rounds - 1):
+            a = oracle.refine(w, max_rounds=k, subphases=sub)
+            assert a.status == 1 and a.state.rounds == k
+            m = types.SimpleNamespace(xyz=a.xyz, tets=a.tets, sf=a.sf, sf_facet=a.sf_facet, ss=a.ss,
+                                      ss_seg=a.ss_seg, ftri=w.ftri, ftri_facet=w.ftri_facet, B=w.B)
+            b = oracle.refine(m, state=a.state, subphases=sub)
+            assert b.status == 0 and b.state.rounds == full.rounds
+            assert np.array_equal(np.concatenate([a.rstats, b.rstats]), full.rstats), (sub, k)
+            assert np.array_equal(b.xyz.view(np.uint64), full.xyz.view(np.uint64))
+            assert np.array_equal(canon(b.tets), canon(full.tets))
+            st = a.state
+            clear = oracle.OracleState(st.hmin2, st.rounds, st.next_class, np.zeros_like(st.tet_flags),
+                                       np.zeros_like(st.sf_flags), np.zeros_like(st.ss_flags))
+            c = oracle.refine(m, state=clear, subphases=sub)
+            differ += not (c.rounds == b.rounds and np.array_equal(c.xyz.view(np.uint64), b.xyz.view(np.uint64)))
+    assert differ > 0
