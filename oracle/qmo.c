@@ -31,6 +31,12 @@
  * Every decision depends only on vertex ids and coordinates, never on array
  * slots.  The readings taken where the paper is silent are spelled out at the
  * functions that implement them.
+ *
+ * Options set before a run: the sub-phase reading of the class order
+ * (qmo_set_subphases), a check of the mesh after every round
+ * (qmo_set_round_check), a recorded round (qmo_set_dump_round), forced equal
+ * priorities (qmo_set_key_mask), and resuming from a refinement state
+ * (qmo_set_resume; every result exports its state, qmo_result_state).
  */
 #define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
