@@ -449,7 +449,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the refinement of one instance runs on a single "
-              "MI355X (no multi-GPU path in this build)", file=sys.stderr)
+              "MI355X (the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
