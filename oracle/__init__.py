@@ -145,6 +145,34 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
         lib.qmo_set_key_mask((1 << 64) - 1)
         lib.qmo_set_subphases(0)
         raise ValueError(f"oracle rejected the input (code {rc})")
+    out = _collect(lib, res, round_checks, int(state.rounds) if state is not None else 0)
+    lib.qmo_set_key_mask((1 << 64) - 1)
+    lib.qmo_set_subphases(0)
+    if dump_round is not None:
+        out.dump = _take_dump(lib)
+        lib.qmo_set_dump_round(-1)
+    return out
+
+
+def refine_call(plc, mesh, opts):
+    """qm_oracle_refine: the oracle behind the GPU library's call layout.
+    plc, mesh and opts are ctypes structures laid out as qm_plc, qm_mesh
+    and qm_options (host arrays).  Returns (code, OracleResult or None) with
+    the library's codes: 0, -4 (round guard; result returned), -1 (invalid
+    argument), -2 (not a conforming tetrahedralisation), -6."""
+    lib = _load()
+    lib.qm_oracle_refine.restype = ctypes.c_int
+    lib.qm_oracle_refine.argtypes = [ctypes.c_void_p] * 3 + [ctypes.POINTER(ctypes.c_void_p)]
+    res = ctypes.c_void_p()
+    rc = lib.qm_oracle_refine(ctypes.addressof(plc), ctypes.addressof(mesh), ctypes.addressof(opts),
+                              ctypes.byref(res))
+    if rc not in (0, -4) and rc != -6:
+        return rc, None
+    return rc, _collect(lib, res, False, 0)
+
+
+def _collect(lib, res, round_checks, rounds_before):
+    """Copy a qmo_result into an OracleResult and free it."""
     cnt = np.zeros(6, dtype=np.int32)
     lib.qmo_result_counts(res, _ptr(cnt))
     nv, nt, nsf, nss, rounds, status = (int(x) for x in cnt)
@@ -166,8 +194,7 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
     lib.qmo_result_state.restype = ctypes.c_int
     lib.qmo_result_state.argtypes = [ctypes.c_void_p] * 4 + [ctypes.POINTER(ctypes.c_double)]
     nxt = lib.qmo_result_state(res, _ptr(tfl), _ptr(sfl), _ptr(ssl), ctypes.byref(h2))
-    out.state = OracleState(float(h2.value), (int(state.rounds) if state is not None else 0) + rounds, int(nxt),
-                            tfl, sfl, ssl)
+    out.state = OracleState(float(h2.value), rounds_before + rounds, int(nxt), tfl, sfl, ssl)
     lib.qmo_result_lastc.restype = ctypes.c_int
     lib.qmo_result_lastc.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     nl = lib.qmo_result_lastc(res, None)
@@ -175,11 +202,6 @@ def refine(w, B=None, hmin_factor=0.5, max_rounds=100000, max_kept=0,
     if nl:
         lib.qmo_result_lastc(res, _ptr(out.last_cands))
     lib.qmo_result_free(res)
-    lib.qmo_set_key_mask((1 << 64) - 1)
-    lib.qmo_set_subphases(0)
-    if dump_round is not None:
-        out.dump = _take_dump(lib)
-        lib.qmo_set_dump_round(-1)
     return out
 
 

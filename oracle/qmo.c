@@ -1156,6 +1156,55 @@ void qmo_result_free(qmo_result* R) {
     free(R);
 }
 
+/* --- the library's call layout ---------------------------------------- */
+/* qm_oracle_refine takes its arguments in the layout of the GPU library's
+   refine call: a PLC, a mesh and options, each a struct with the same field
+   order and types, and it answers with the library's return codes.  A test
+   can then marshal one set of arguments and hand it to either engine.  The
+   structs are declared here again (a call layout is an interface, not shared
+   code).  Of the option flags, the sub-phase reading (1024) and forced equal
+   priorities (128) change the run; early-stop blasting (256, timing-decided)
+   and device arrays (1) are refused; the others only concern the GPU
+   (profiling, device output, tier tests) and are ignored. */
+typedef struct {
+    int32_t nv; int32_t nseg; const int32_t* seg;
+    int32_t nftri; const int32_t* ftri; const int32_t* ftri_facet;
+} qmo_call_plc;
+typedef struct {
+    int32_t nv; const double* xyz; int32_t nt; const int32_t* tet;
+    int32_t nsf; const int32_t* sf; const int32_t* sf_facet;
+    int32_t nss; const int32_t* ss; const int32_t* ss_seg;
+} qmo_call_mesh;
+typedef struct { double B; double hmin_factor; int32_t max_rounds; int32_t max_kept; uint32_t flags; } qmo_call_options;
+
+enum { QMO_CALL_INPUT_DEVICE = 1u, QMO_CALL_KEY_COLLIDE = 128u, QMO_CALL_EARLY_STOP = 256u,
+       QMO_CALL_SUBPHASES = 1024u };
+
+int qm_oracle_refine(const qmo_call_plc* plc, const qmo_call_mesh* in, const qmo_call_options* opt,
+                     qmo_result** out) {
+    if (!plc || !in || !opt || !out) return -1;                       /* invalid argument */
+    if (opt->flags & (QMO_CALL_INPUT_DEVICE | QMO_CALL_EARLY_STOP)) return -1;
+    if (!(opt->B > 0.0) || !(opt->hmin_factor >= 0.0) || opt->max_rounds < 0) return -1;
+    if (in->nv < 8 || in->nt < 1 || in->nsf < 0 || in->nss < 0 || plc->nftri < 0) return -1;
+    for (int i = 0; i < 3 * in->nv; ++i) {        /* coordinates in the cube, on the 2^-53 lattice */
+        const double c = in->xyz[i], s = ldexp(c, 53);
+        if (!(c >= 0.0 && c <= 1.0) || rint(s) != s) return -1;
+    }
+    const int sub0 = g_subphases;
+    const uint64_t mask0 = g_key_mask;
+    g_subphases = (opt->flags & QMO_CALL_SUBPHASES) != 0;
+    if (opt->flags & QMO_CALL_KEY_COLLIDE) g_key_mask = 0xE000000000000000ull;
+    int rc = qmo_refine(in->nv, in->xyz, in->nt, in->tet, in->nsf, in->sf, in->sf_facet, in->nss, in->ss,
+                        in->ss_seg, plc->nftri, plc->ftri, plc->ftri_facet, opt->B, opt->hmin_factor,
+                        opt->max_rounds, opt->max_kept, out);
+    g_subphases = sub0;
+    g_key_mask = mask0;
+    if (rc == -1) return -1;                  /* ids out of range */
+    if (rc < 0) return -2;                    /* not a conforming tetrahedralisation of the PLC */
+    if ((*out)->status < 0) return -6;        /* an insertion failed: impossible state */
+    return (*out)->status == 1 ? -4 : 0;      /* round guard reached: the result is still returned */
+}
+
 /* --- predicate entry points for the oracle's own pin tests ------------- */
 int qmo_p_orient3d(const double* a, const double* b, const double* c, const double* d) { return qmo_orient3d(a, b, c, d); }
 int qmo_p_insphere(const double* a, const double* b, const double* c, const double* d, const double* e) { return qmo_insphere(a, b, c, d, e); }

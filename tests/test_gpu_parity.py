@@ -210,3 +210,29 @@ def test_invalid_inputs_fail_cleanly():
     # the library is still usable afterwards
     g, o = run_both(w)
     assert_same(g, o, "after errors")
+
+
+@pytest.mark.parametrize("flags,max_rounds", [(0, 100000), (qm.QM_SUBPHASE_ROUNDS, 100000), (0, 20)])
+def test_one_argument_set_to_both_engines(flags, max_rounds):
+    """The same marshalled qm_plc, qm_mesh and qm_options go to the GPU
+    library (qm_refine) and to the oracle behind the same call layout
+    (qm_oracle_refine): the return codes and the results are equal."""
+    import ctypes
+    w = qi.uniform_cube(700, seed=9, B=1.5, spheres=(0.25, 0.4))
+    keep = []
+    plc, mesh = qm._marshal(w, keep)
+    opts = qm._Opts(float(w.B), 0.5, int(max_rounds), 0, int(flags))
+    lib = qm._load()
+    res = ctypes.c_void_p()
+    rc_g = lib.qm_refine(ctypes.byref(plc), ctypes.byref(mesh), ctypes.byref(opts), None, ctypes.byref(res))
+    g = qm._take_result(lib, res, False)
+    rc_o, o = oracle.refine_call(plc, mesh, opts)
+    print(f"[engines] flags={flags} max_rounds={max_rounds}: codes {rc_g}/{rc_o}, rounds {g.rounds}/{o.rounds}",
+          flush=True)
+    assert rc_g == rc_o and rc_g in (0, -4)
+    assert g.rounds == o.rounds and g.status == o.status and np.array_equal(g.rstats, o.rstats)
+    assert np.array_equal(g.xyz.view(np.uint64), o.xyz.view(np.uint64))
+    t1, t2 = np.sort(g.tets, axis=1), np.sort(o.tets, axis=1)
+    assert np.array_equal(t1[np.lexsort(t1.T[::-1])], t2[np.lexsort(t2.T[::-1])])
+    s1, s2 = np.sort(g.sf, axis=1), np.sort(o.sf, axis=1)
+    assert np.array_equal(s1[np.lexsort(s1.T[::-1])], s2[np.lexsort(s2.T[::-1])])

@@ -606,3 +606,39 @@ def test_resume_from_the_state_equals_the_uninterrupted_run():
             c = oracle.refine(m, state=clear, subphases=sub)
             differ += not (c.rounds == b.rounds and np.array_equal(c.xyz.view(np.uint64), b.xyz.view(np.uint64)))
     assert differ > 0
+
+
+def test_oracle_behind_the_library_call_layout():
+    """qm_oracle_refine takes the arguments the GPU library's refine call
+    takes (qm_plc, qm_mesh, qm_options, marshalled once by the binding) and
+    answers with its codes, so a test can hand one argument set to either
+    engine.  Its results equal the oracle's own runs, option flags included,
+    and its refusals are the library's."""
+    import paper_1903_03406_amd as qm
+    w = qi.uniform_cube(300, seed=2, B=1.6, spheres=(0.3,))
+    keep = []
+    plc, mesh = qm._marshal(w, keep)
+
+    def run(flags=0, max_rounds=100000, B=None):
+        return oracle.refine_call(plc, mesh, qm._Opts(float(w.B if B is None else B), 0.5, max_rounds, 0, flags))
+
+    for flags, ref in ((0, oracle.refine(w)), (qm.QM_SUBPHASE_ROUNDS, oracle.refine(w, subphases=True)),
+                       (qm.QM_TEST_KEY_COLLIDE, oracle.refine(w, key_mask=0xE000000000000000)),
+                       (qm.QM_PROFILE | qm.QM_OUTPUT_DEVICE, oracle.refine(w))):
+        rc, o = run(flags)
+        assert rc == 0 and o.rounds == ref.rounds and np.array_equal(o.rstats, ref.rstats)
+        assert np.array_equal(o.xyz.view(np.uint64), ref.xyz.view(np.uint64))
+        assert np.array_equal(np.sort(o.tets, axis=1), np.sort(ref.tets, axis=1))
+    rc, o = run(max_rounds=5)
+    assert rc == -4 and o.status == 1 and o.rounds == 5            # QM_EROUNDS, result returned
+    assert run(qm.QM_EARLY_STOP)[0] == -1 and run(qm.QM_INPUT_DEVICE)[0] == -1 and run(B=0.0)[0] == -1
+    flipped = w.tets.copy()
+    flipped[0, [0, 1]] = flipped[0, [1, 0]]
+    k2 = []
+    p2, m2 = qm._marshal(qi.Workload(w.name, w.xyz, flipped, w.adj, w.ftri, w.ftri_facet, w.seg, w.B), k2)
+    assert oracle.refine_call(p2, m2, qm._Opts(w.B, 0.5, 100, 0, 0))[0] == -2      # QM_ENONCONFORM
+    xyz = w.xyz.copy()
+    xyz[9, 0] = 0.1                                                  # off the 2^-53 lattice
+    k3 = []
+    p3, m3 = qm._marshal(qi.Workload(w.name, xyz, w.tets, w.adj, w.ftri, w.ftri_facet, w.seg, w.B), k3)
+    assert oracle.refine_call(p3, m3, qm._Opts(w.B, 0.5, 100, 0, 0))[0] == -1      # QM_EINVAL
