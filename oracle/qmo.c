@@ -37,6 +37,8 @@
  * (qmo_set_round_check), a recorded round (qmo_set_dump_round), forced equal
  * priorities (qmo_set_key_mask), and resuming from a refinement state
  * (qmo_set_resume; every result exports its state, qmo_result_state).
+ * qm_oracle_refine takes the GPU library's call layout and return codes, so
+ * that a test can hand one marshalled argument set to either engine.
  */
 #define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
